@@ -1,0 +1,266 @@
+"""Multigrid reduction (MGR) setup and V-cycle, FP64 on the CPU (test infrastructure, see
+the package docstring).
+
+Follows Sec. 5 of the paper:
+  * C/F splitting of the rows into disjoint sets (Sec. 5.1), chosen per level by unknown
+    type (Sec. 5.3);
+  * approximate interpolation P~ = [W_p; I] and restriction R~ = [W_r, I] (eq. RPoperator1)
+    with injection W_r = 0 and Jacobi interpolation W_p = -D_FF^{-1} A_FC, D_FF = diag(A_FF)
+    (eq. injective_rp);
+  * coarse grid R~ A P~ = A_CC - A_CF D_FF^{-1} A_FC (Sec. 5.2), made sparse by the dropping
+    operator G, which keeps the N_max largest entries per row of the correction term plus
+    the diagonals of its sub-blocks (eq. drop_operator);
+  * the multi-level V-cycle with global relaxation, F-relaxation, restriction, recursion,
+    interpolation and correction (Algorithm 2, the recursive form of Algorithm 1).
+
+Readings where the paper is silent (each also listed in the design notes):
+  * F and C index lists are ascending, so interleaved orderings stay interleaved;
+  * a zero or structurally missing D_FF entry is an error (ZeroPivot);
+  * "diagonals of the sub-blocks": entries (i, j) of the correction term whose coarse
+    points i and j have the same rank among the coarse points of their own label (the same
+    cell); they are kept in addition to the N_max largest;
+  * ranking is by |value|, ties to the smaller column; dropped entries are discarded;
+  * N_max < 0 means no dropping (Galerkin coarse grid);
+  * the residual in the F-relaxation step of Algorithm 2 uses the level's own matrix A_l;
+  * the global smoother is block Jacobi over the same-cell blocks (a stand-in for the
+    ILU/Gauss-Seidel smoothers of Sec. 5.3): first sweep z = D_B^{-1} v, later sweeps
+    z += omega D_B^{-1} (v - A z).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import amg as amg_mod
+from .sparse import CSR, diagonal, merge_sub, spgemm, submatrix
+
+
+class ZeroPivot(ArithmeticError):
+    pass
+
+
+@dataclass
+class LevelPlan:
+    f_labels: tuple                  # labels that are F-points at this level
+    interp: str = "jacobi"           # 'jacobi' (eq. injective_rp) | 'zero' | 'ideal' (dense)
+    nmax: int = -1                   # N_max of G; < 0: no dropping
+    frelax: str = "jacobi"           # 'jacobi' | 'amg' | 'exact' (dense)
+    frelax_sweeps: int = 1
+    frelax_omega: float = 1.0
+    frelax_block: int = 1            # 3: nodal AMG on the F block
+    global_smoother: str = "none"    # 'none' | 'block_jacobi'
+    global_sweeps: int = 1
+    global_omega: float = 1.0
+
+
+@dataclass
+class Plan:
+    levels: list
+    coarse: str = "dense"            # 'dense' | 'amg'
+    amg_frelax: amg_mod.AMGOptions = field(default_factory=lambda: amg_mod.AMGOptions(block=3))
+    amg_coarse: amg_mod.AMGOptions = field(default_factory=amg_mod.AMGOptions)
+
+
+@dataclass
+class Level:
+    A: CSR
+    labels: np.ndarray
+    F: np.ndarray
+    C: np.ndarray
+    dFF: np.ndarray
+    A_FF: CSR
+    A_FC: CSR
+    A_CF: CSR
+    A_CC: CSR
+    Wp: CSR                     # W_p (F rows x C cols)
+    Acor: CSR                   # A_CF D_FF^{-1} A_FC (before dropping)
+    G: CSR                      # G(A_cor)
+    plan: LevelPlan
+    amg: object = None          # F-relaxation AMG hierarchy
+    ff_lu: tuple | None = None  # F-relaxation dense LU ('exact')
+    blocks: tuple | None = None # global smoother: (rows per block, block inverses)
+
+
+@dataclass
+class Hierarchy:
+    levels: list
+    coarse_A: CSR
+    coarse_labels: np.ndarray
+    coarse_lu: tuple | None = None
+    coarse_amg: object = None
+    plan: Plan | None = None
+
+
+def cf_split(labels: np.ndarray, f_labels) -> tuple:
+    """F = rows whose label is in f_labels, C = the rest; both ascending."""
+    isF = np.isin(labels, np.asarray(f_labels, dtype=labels.dtype))
+    return np.flatnonzero(isF), np.flatnonzero(~isF)
+
+
+def label_rank(labels: np.ndarray) -> np.ndarray:
+    """rank[x] = number of points before x that carry the same label as x."""
+    rank = np.empty(labels.shape[0], dtype=np.int64)
+    for lab in np.unique(labels):
+        idx = np.flatnonzero(labels == lab)
+        rank[idx] = np.arange(idx.shape[0])
+    return rank
+
+
+def blocks_of(A: CSR, F, C):
+    n = A.shape[0]
+    fmap = np.full(n, -1, dtype=np.int64)
+    cmap = np.full(n, -1, dtype=np.int64)
+    fmap[F] = np.arange(F.shape[0])
+    cmap[C] = np.arange(C.shape[0])
+    nF, nC = F.shape[0], C.shape[0]
+    return (submatrix(A, F, fmap, nF), submatrix(A, F, cmap, nC),
+            submatrix(A, C, fmap, nF), submatrix(A, C, cmap, nC))
+
+
+def jacobi_interpolation(A_FC: CSR, dFF: np.ndarray) -> tuple:
+    """M = D_FF^{-1} A_FC entrywise (m_kj = a_kj / d_k) and W_p = -M (eq. injective_rp)."""
+    r = A_FC.row_ids()
+    m = A_FC.data / dFF[r]
+    M = CSR(A_FC.indptr, A_FC.indices, m, A_FC.shape)
+    Wp = CSR(A_FC.indptr, A_FC.indices, -m, A_FC.shape)
+    return M, Wp
+
+
+def drop(Acor: CSR, labels_c: np.ndarray, nmax: int) -> CSR:
+    """The dropping operator G of eq. drop_operator: per row, keep the entries on the
+    diagonals of the sub-blocks (same per-label rank) and the nmax largest |values| among
+    the rest (ties to the smaller column).  nmax < 0 keeps everything."""
+    if nmax < 0:
+        return Acor
+    rank = label_rank(labels_c)
+    r = Acor.row_ids()
+    c = Acor.indices
+    prot = rank[c] == rank[r]
+    idx = np.flatnonzero(~prot)
+    keep = prot.copy()
+    if idx.shape[0]:
+        order = np.lexsort((c[idx], -np.abs(Acor.data[idx]), r[idx]))
+        srt = idx[order]
+        rs = r[srt]
+        first = np.r_[True, rs[1:] != rs[:-1]]
+        start_of = np.maximum.accumulate(np.where(first, np.arange(rs.shape[0]), 0))
+        pos_in_row = np.arange(rs.shape[0]) - start_of
+        keep[srt[pos_in_row < nmax]] = True
+    kr = r[keep]
+    indptr = np.zeros(Acor.shape[0] + 1, dtype=np.int64)
+    np.cumsum(np.bincount(kr, minlength=Acor.shape[0]), out=indptr[1:])
+    return CSR(indptr, c[keep], Acor.data[keep], Acor.shape)
+
+
+def same_cell_blocks(A: CSR, labels: np.ndarray):
+    """Global-smoother blocks: rows grouped by their per-label rank (one block per cell).
+    Returns (rows, inverses): rows[e] lists block e's rows ascending, inverses[e] is the
+    dense inverse of the diagonal block A[rows[e], rows[e]]."""
+    rank = label_rank(labels)
+    nblk = int(rank.max()) + 1
+    sizes = np.bincount(rank, minlength=nblk)
+    if np.any(sizes != sizes[0]):
+        raise ValueError("same-cell blocks of unequal size")
+    nb = int(sizes[0])
+    order = np.lexsort((np.arange(rank.shape[0]), rank))
+    rows = order.reshape(nblk, nb)
+    slot = np.empty(rank.shape[0], dtype=np.int64)
+    slot[rows] = np.arange(nb)[None, :]
+    r = A.row_ids()
+    c = A.indices
+    m = rank[r] == rank[c]
+    D = np.zeros((nblk, nb, nb))
+    D[rank[r[m]], slot[r[m]], slot[c[m]]] = A.data[m]
+    return rows, np.linalg.inv(D)
+
+
+def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
+    """Level loop of Sec. 5.2: A_{l+1} = A_CC - G(A_CF D_FF^{-1} A_FC) with labels_{l+1} =
+    labels_l[C]; then the coarsest-grid solver (dense LU or AMG)."""
+    levels = []
+    cur, lab = A, np.asarray(labels)
+    for lp in plan.levels:
+        F, C = cf_split(lab, lp.f_labels)
+        if F.shape[0] == 0 or C.shape[0] == 0:
+            raise ValueError("empty F or C set")
+        A_FF, A_FC, A_CF, A_CC = blocks_of(cur, F, C)
+        d = diagonal(A_FF)
+        if np.any(~np.isfinite(d)) or np.any(d == 0.0):
+            raise ZeroPivot("zero or missing diagonal in A_FF")
+        if lp.interp == "jacobi":
+            M, Wp = jacobi_interpolation(A_FC, d)
+        elif lp.interp == "zero":
+            M = CSR(np.zeros(F.shape[0] + 1, dtype=np.int64), [], [], A_FC.shape)
+            Wp = M
+        elif lp.interp == "ideal":          # dense W_p = -A_FF^{-1} A_FC, tiny inputs only
+            Md = np.linalg.solve(A_FF.to_dense(), A_FC.to_dense())
+            M = CSR.from_dense(Md, np.ones_like(Md, dtype=bool))
+            Wp = CSR(M.indptr, M.indices, -M.data, M.shape)
+        else:
+            raise ValueError(lp.interp)
+        Acor = spgemm(A_CF, M)
+        G = drop(Acor, lab[C], lp.nmax)
+        S = merge_sub(A_CC, G)
+        L = Level(A=cur, labels=lab, F=F, C=C, dFF=d, A_FF=A_FF, A_FC=A_FC, A_CF=A_CF,
+                  A_CC=A_CC, Wp=Wp, Acor=Acor, G=G, plan=lp)
+        if lp.frelax == "amg":
+            opts = amg_mod.AMGOptions(**{**plan.amg_frelax.__dict__, "block": lp.frelax_block})
+            L.amg = amg_mod.setup(A_FF, opts)
+        elif lp.frelax == "exact":
+            L.ff_lu = sla.lu_factor(A_FF.to_dense())
+        if lp.global_smoother == "block_jacobi":
+            L.blocks = same_cell_blocks(cur, lab)
+        levels.append(L)
+        cur, lab = S, lab[C]
+    H = Hierarchy(levels=levels, coarse_A=cur, coarse_labels=lab, plan=plan)
+    if plan.coarse == "dense":
+        H.coarse_lu = sla.lu_factor(cur.to_dense())
+    else:
+        H.coarse_amg = amg_mod.setup(cur, plan.amg_coarse)
+    return H
+
+
+def _block_jacobi(L: Level, v: np.ndarray) -> np.ndarray:
+    rows, inv = L.blocks
+    z = np.zeros_like(v)
+    z[rows] = np.einsum("eij,ej->ei", inv, v[rows])
+    return z
+
+
+def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
+    """z = M^{-1} v by Algorithm 2 (presmoothing form, eq. MGR-pre)."""
+    if lvl == len(H.levels):
+        if H.coarse_lu is not None:
+            return sla.lu_solve(H.coarse_lu, v)
+        return amg_mod.vcycle(H.coarse_amg, v)
+    L = H.levels[lvl]
+    lp = L.plan
+    A = L.A
+    # global relaxation
+    if lp.global_smoother == "block_jacobi":
+        z = _block_jacobi(L, v)
+        for _ in range(lp.global_sweeps - 1):
+            z = z + lp.global_omega * _block_jacobi(L, v - A.matvec(z))
+    else:
+        z = np.zeros_like(v)
+    # F-relaxation: z <- z + Q M_FF^{-1} Q^T (v - A z)
+    if lp.frelax == "jacobi":
+        for _ in range(lp.frelax_sweeps):
+            r = v - A.matvec(z)
+            z[L.F] = z[L.F] + lp.frelax_omega * (r[L.F] / L.dFF)
+    elif lp.frelax == "amg":
+        r = v - A.matvec(z)
+        z[L.F] = z[L.F] + amg_mod.vcycle(L.amg, r[L.F])
+    elif lp.frelax == "exact":
+        r = v - A.matvec(z)
+        z[L.F] = z[L.F] + sla.lu_solve(L.ff_lu, r[L.F])
+    else:
+        raise ValueError(lp.frelax)
+    # restrict the residual by injection, recurse, interpolate, correct
+    r = v - A.matvec(z)
+    eC = apply(H, r[L.C], lvl + 1)
+    z[L.F] = z[L.F] + L.Wp.matvec(eC)
+    z[L.C] = z[L.C] + eC
+    return z

@@ -1,0 +1,292 @@
+"""Pins of the oracle's MGR setup and V-cycle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a hand-worked example,
+the block LDU factorisation and the MGR identities of Sec. 5.1, the closed form of the
+Galerkin coarse grid with injection restriction and Jacobi interpolation (Sec. 5.2), a
+brute-force sort for the dropping operator, exactness of the two-grid and multi-level
+V-cycle with ideal components, and the block-triangular special case W_p = W_r = 0.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import krylov, mgr
+from oracle.sparse import CSR, spgemm, transpose
+
+
+def csr_from_dense(D):
+    return CSR.from_dense(np.asarray(D, dtype=np.float64))
+
+
+def random_system(rng, labels, density=0.4, diag_ff=False, dominance=3.0):
+    """Random sparse nonsymmetric matrix with a dominant diagonal; if diag_ff, the F block of
+    label 0 is diagonal."""
+    n = len(labels)
+    D = rng.standard_normal((n, n)) * (rng.random((n, n)) < density)
+    if diag_ff:
+        f = np.flatnonzero(np.asarray(labels) == 0)
+        D[np.ix_(f, f)] = 0.0
+    D[np.arange(n), np.arange(n)] = dominance * (np.abs(D).sum(axis=1) + 1.0)
+    return D
+
+
+# ---------------------------------------------------------------------------------------
+def test_golden_hand_worked(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "mgr_two_level_6x6.json")))
+    A = csr_from_dense(g["dense_A"])
+    labels = np.array(g["labels"], dtype=np.int8)
+    F, C = mgr.cf_split(labels, g["f_labels"])
+    assert F.tolist() == g["F"] and C.tolist() == g["C"]
+    for nmax_s, exp in g["S"].items():
+        plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=tuple(g["f_labels"]), nmax=int(nmax_s))])
+        H = mgr.setup(A, labels, plan)
+        L = H.levels[0]
+        assert np.array_equal(L.Wp.to_dense(), np.array(g["Wp_dense"], dtype=float))
+        assert np.array_equal(L.Acor.to_dense(), np.array(g["Acor_dense"], dtype=float))
+        S = H.coarse_A
+        for i in range(4):
+            cols, vals = S.row(i)
+            assert cols.tolist() == exp["rows"][i], (nmax_s, i)
+            assert vals.tolist() == [float(v) for v in exp["vals"][i]], (nmax_s, i)
+
+
+def test_cf_split_and_label_rank():
+    labels = np.array([0, 0, 0, 1, 2, 1, 2, 0, 1, 2], dtype=np.int8)
+    F, C = mgr.cf_split(labels, (0,))
+    assert F.tolist() == [0, 1, 2, 7]
+    assert C.tolist() == [3, 4, 5, 6, 8, 9]
+    assert mgr.label_rank(labels[C]).tolist() == [0, 0, 1, 1, 2, 2]
+
+
+def test_ldu_and_ideal_schur():
+    """Block LDU factorisation (Sec. 5.1): A = L diag(A_FF, S) U with the Schur complement;
+    the oracle's 'ideal' mode must produce exactly that S (up to rounding)."""
+    rng = np.random.default_rng(0)
+    labels = np.array([0, 1, 0, 1, 0, 1, 1, 0, 1], dtype=np.int8)
+    D = random_system(rng, labels, density=0.6)
+    A = csr_from_dense(D)
+    F, C = mgr.cf_split(labels, (0,))
+    Aff, Afc, Acf, Acc = D[np.ix_(F, F)], D[np.ix_(F, C)], D[np.ix_(C, F)], D[np.ix_(C, C)]
+    S = Acc - Acf @ np.linalg.solve(Aff, Afc)
+    nF, nC = len(F), len(C)
+    Lm = np.block([[np.eye(nF), np.zeros((nF, nC))], [Acf @ np.linalg.inv(Aff), np.eye(nC)]])
+    Dm = np.block([[Aff, np.zeros((nF, nC))], [np.zeros((nC, nF)), S]])
+    Um = np.block([[np.eye(nF), np.linalg.solve(Aff, Afc)], [np.zeros((nC, nF)), np.eye(nC)]])
+    perm = np.concatenate([F, C])
+    assert np.allclose(Lm @ Dm @ Um, D[np.ix_(perm, perm)], rtol=1e-13, atol=1e-12)
+    H = mgr.setup(A, labels, mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), interp="ideal")]))
+    assert np.allclose(H.coarse_A.to_dense(), S, rtol=1e-12, atol=1e-12)
+
+
+def test_mgr_identities_ideal_operators():
+    """A^{-1} = P (RAP)^{-1} R + Q (Q^T A Q)^{-1} Q^T and RAQ = Q^T AP = 0 (Sec. 5.1), and the
+    oracle's two-grid V-cycle with ideal interpolation and exact F-relaxation equals A^{-1}
+    (eq. MGR-mul1 with exact factors)."""
+    rng = np.random.default_rng(1)
+    labels = np.array([0, 1, 1, 0, 0, 1, 0, 1], dtype=np.int8)
+    D = random_system(rng, labels, density=0.5)
+    F, C = mgr.cf_split(labels, (0,))
+    perm = np.concatenate([F, C])
+    Ap = D[np.ix_(perm, perm)]
+    nF, nC = len(F), len(C)
+    Aff, Afc, Acf = Ap[:nF, :nF], Ap[:nF, nF:], Ap[nF:, :nF]
+    P = np.vstack([-np.linalg.solve(Aff, Afc), np.eye(nC)])
+    R = np.hstack([-Acf @ np.linalg.inv(Aff), np.eye(nC)])
+    Q = np.vstack([np.eye(nF), np.zeros((nC, nF))])
+    inv = P @ np.linalg.inv(R @ Ap @ P) @ R + Q @ np.linalg.inv(Q.T @ Ap @ Q) @ Q.T
+    assert np.allclose(inv, np.linalg.inv(Ap), atol=1e-12)
+    assert np.allclose(R @ Ap @ Q, 0.0, atol=1e-12)
+    assert np.allclose(Q.T @ Ap @ P, 0.0, atol=1e-12)
+    plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), interp="ideal", frelax="exact")])
+    H = mgr.setup(csr_from_dense(D), labels, plan)
+    Minv = np.column_stack([mgr.apply(H, e) for e in np.eye(len(labels))])
+    assert np.linalg.norm(Minv @ D - np.eye(len(labels))) <= 1e-12
+
+
+def test_rap_closed_form_and_dense_triple_product():
+    """With W_r = 0 and W_p = -D_FF^{-1} A_FC, R~ A P~ = A_CC - A_CF D_FF^{-1} A_FC (Sec. 5.2);
+    checked against a dense triple product built from the definitions of eq. RPoperator1."""
+    rng = np.random.default_rng(2)
+    labels = rng.integers(0, 3, size=40).astype(np.int8)
+    D = random_system(rng, labels, density=0.15)
+    A = csr_from_dense(D)
+    H = mgr.setup(A, labels, mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), nmax=-1)]))
+    F, C = mgr.cf_split(labels, (0,))
+    perm = np.concatenate([F, C])
+    Ap = D[np.ix_(perm, perm)]
+    nF, nC = len(F), len(C)
+    dff = np.diag(Ap[:nF, :nF])
+    Wp = -Ap[:nF, nF:] / dff[:, None]
+    Pt = np.vstack([Wp, np.eye(nC)])
+    Rt = np.hstack([np.zeros((nC, nF)), np.eye(nC)])
+    rap = Rt @ Ap @ Pt
+    closed = Ap[nF:, nF:] - Ap[nF:, :nF] @ np.diag(1.0 / dff) @ Ap[:nF, nF:]
+    S = H.coarse_A.to_dense()
+    assert np.allclose(S, rap, rtol=1e-14, atol=1e-13)
+    assert np.allclose(S, closed, rtol=1e-14, atol=1e-13)
+    # pattern: union of A_CC and the boolean product pattern
+    pat = (Ap[nF:, nF:] != 0) | ((Ap[nF:, :nF] != 0).astype(int) @ (Ap[:nF, nF:] != 0).astype(int) > 0)
+    Spat = np.zeros((nC, nC), dtype=bool)
+    Spat[H.coarse_A.row_ids(), H.coarse_A.indices] = True
+    assert np.array_equal(Spat, pat)
+
+
+def test_zero_interpolation_gives_acc():
+    """W_p = W_r = 0 gives R A P = A_CC (Sec. 5.1, the first extreme)."""
+    rng = np.random.default_rng(3)
+    labels = rng.integers(0, 2, size=30).astype(np.int8)
+    D = random_system(rng, labels, density=0.2)
+    H = mgr.setup(csr_from_dense(D), labels,
+                  mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), interp="zero")]))
+    F, C = mgr.cf_split(labels, (0,))
+    assert np.array_equal(H.coarse_A.to_dense(), D[np.ix_(C, C)])
+
+
+def test_block_lower_triangular_special_case():
+    """W_p = W_r = 0 with exact F and coarse solves makes M the block lower-triangular part
+    [[A_FF, 0], [A_CF, A_CC]] (Algorithm 1 with z_C = 0 before the correction)."""
+    rng = np.random.default_rng(4)
+    labels = rng.integers(0, 2, size=24).astype(np.int8)
+    D = random_system(rng, labels, density=0.3)
+    plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), interp="zero", frelax="exact")])
+    H = mgr.setup(csr_from_dense(D), labels, plan)
+    F, C = mgr.cf_split(labels, (0,))
+    Mb = D.copy()
+    Mb[np.ix_(F, C)] = 0.0
+    v = rng.standard_normal(len(labels))
+    assert np.allclose(mgr.apply(H, v), np.linalg.solve(Mb, v), rtol=1e-12, atol=1e-14)
+
+
+def _brute_drop(Acor: CSR, labels_c, nmax):
+    rank = mgr.label_rank(labels_c)
+    out = {}
+    for i in range(Acor.shape[0]):
+        cols, vals = Acor.row(i)
+        prot = [(c, v) for c, v in zip(cols, vals) if rank[c] == rank[i]]
+        rest = sorted([(c, v) for c, v in zip(cols, vals) if rank[c] != rank[i]],
+                      key=lambda cv: (-abs(cv[1]), cv[0]))
+        kept = sorted(prot + (rest[:nmax] if nmax >= 0 else rest))
+        out[i] = kept
+    return out
+
+
+@pytest.mark.parametrize("nmax", [0, 1, 2, 4, 100, -1])
+def test_drop_bruteforce(nmax):
+    """Dropping operator G (eq. drop_operator) against a brute-force sort, with many ties."""
+    rng = np.random.default_rng(10 + max(nmax, 0))
+    nC = 60
+    labels_c = np.tile(np.array([1, 2], dtype=np.int8), nC // 2)
+    D = rng.integers(-3, 4, size=(nC, nC)).astype(float) * (rng.random((nC, nC)) < 0.3)
+    mask = (D != 0) | (rng.random((nC, nC)) < 0.05)       # some explicit zeros
+    Acor = CSR.from_dense(D, mask)
+    G = mgr.drop(Acor, labels_c, nmax)
+    bf = _brute_drop(Acor, labels_c, nmax)
+    for i in range(nC):
+        cols, vals = G.row(i)
+        assert list(zip(cols.tolist(), vals.tolist())) == [(int(c), float(v)) for c, v in bf[i]]
+
+
+def test_drop_extremes_block_diagonal():
+    """N_max = 0 leaves a 2x2 block matrix whose sub-blocks are diagonal (Sec. 5.2);
+    N_max = infinity leaves A_cor unchanged."""
+    rng = np.random.default_rng(5)
+    nC = 40
+    labels_c = np.tile(np.array([1, 2], dtype=np.int8), nC // 2)
+    D = rng.standard_normal((nC, nC))
+    Acor = CSR.from_dense(D)
+    G0 = mgr.drop(Acor, labels_c, 0).to_dense()
+    s = np.arange(0, nC, 2)
+    p = np.arange(1, nC, 2)
+    for bi in (s, p):
+        for bj in (s, p):
+            blk = G0[np.ix_(bi, bj)]
+            assert np.array_equal(blk, np.diag(np.diag(blk)))
+            assert np.all(np.diag(blk) == np.diag(D[np.ix_(bi, bj)]))
+    assert np.array_equal(mgr.drop(Acor, labels_c, 10 ** 6).to_dense(), D)
+
+
+def test_spgemm_pinned_order_by_hand():
+    """Products are summed in ascending k from +0.0: (0 + 1e16) + 1 + (-1e16) = 0 in binary64
+    (1e16 + 1 rounds back to 1e16), whereas summing the last two first would give 1."""
+    A = CSR([0, 3], [0, 1, 2], [1.0, 1.0, 1.0], (1, 3))
+    B = CSR([0, 1, 2, 3], [0, 0, 0], [1e16, 1.0, -1e16], (3, 1))
+    C = spgemm(A, B)
+    assert C.indices.tolist() == [0] and C.data.tolist() == [0.0]
+    B2 = CSR([0, 1, 2, 3], [0, 0, 0], [1.0, 1e16, -1e16], (3, 1))
+    assert spgemm(A, B2).data.tolist() == [0.0]      # (1 + 1e16) - 1e16 = 0 as well
+    B3 = CSR([0, 1, 2, 3], [0, 0, 0], [1e16, -1e16, 1.0], (3, 1))
+    assert spgemm(A, B3).data.tolist() == [1.0]
+
+
+def test_spgemm_and_transpose_against_dense():
+    rng = np.random.default_rng(6)
+    Da = rng.standard_normal((30, 25)) * (rng.random((30, 25)) < 0.2)
+    Db = rng.standard_normal((25, 35)) * (rng.random((25, 35)) < 0.2)
+    A, B = CSR.from_dense(Da), CSR.from_dense(Db)
+    C = spgemm(A, B)
+    assert np.allclose(C.to_dense(), Da @ Db, rtol=1e-14, atol=1e-14)
+    pat = ((Da != 0).astype(int) @ (Db != 0).astype(int)) > 0
+    Cp = np.zeros(pat.shape, dtype=bool)
+    Cp[C.row_ids(), C.indices] = True
+    assert np.array_equal(Cp, pat)
+    At = transpose(A)
+    assert np.array_equal(At.to_dense(), Da.T)
+    assert all(np.all(np.diff(At.row(i)[0]) > 0) for i in range(At.shape[0]))
+
+
+def test_exactness_two_level_and_fgmres_one_iteration():
+    """With A_FF diagonal, Jacobi interpolation is the ideal one and one Jacobi sweep with
+    omega = 1 is an exact F-relaxation; with no dropping and an exact coarse solve the
+    presmoothed two-grid operator is A^{-1}, so FGMRES converges in one iteration."""
+    rng = np.random.default_rng(7)
+    labels = rng.integers(0, 2, size=50).astype(np.int8)
+    D = random_system(rng, labels, density=0.2, diag_ff=True)
+    A = csr_from_dense(D)
+    plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), nmax=-1, frelax="jacobi")], coarse="dense")
+    H = mgr.setup(A, labels, plan)
+    Minv = np.column_stack([mgr.apply(H, e) for e in np.eye(50)])
+    assert np.linalg.norm(Minv @ D - np.eye(50)) <= 1e-12
+    F, C = mgr.cf_split(labels, (0,))
+    S = D[np.ix_(C, C)] - D[np.ix_(C, F)] @ np.linalg.solve(D[np.ix_(F, F)], D[np.ix_(F, C)])
+    assert np.allclose(H.coarse_A.to_dense(), S, rtol=1e-13, atol=1e-13)
+    b = rng.standard_normal(50)
+    res = krylov.fgmres(A.matvec, lambda v: mgr.apply(H, v), b, restart=30, rtol=1e-10)
+    assert res.converged and res.iters == 1
+
+
+def test_exactness_multilevel_by_induction():
+    """Three labels, two reductions with ideal interpolation and exact F-relaxation, dense
+    coarsest solve: the multi-level V-cycle of Algorithm 2 is exactly A^{-1}."""
+    rng = np.random.default_rng(8)
+    labels = rng.integers(0, 3, size=36).astype(np.int8)
+    D = random_system(rng, labels, density=0.3)
+    plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,), interp="ideal", frelax="exact"),
+                            mgr.LevelPlan(f_labels=(1,), interp="ideal", frelax="exact")])
+    H = mgr.setup(csr_from_dense(D), labels, plan)
+    Minv = np.column_stack([mgr.apply(H, e) for e in np.eye(36)])
+    assert np.linalg.norm(Minv @ D - np.eye(36)) <= 1e-11
+
+
+def test_global_smoother_blocks_exact_on_block_diagonal():
+    """Block Jacobi over same-cell blocks inverts a matrix that is block diagonal by cells."""
+    rng = np.random.default_rng(9)
+    ncell = 12
+    labels = np.tile(np.array([1, 2], dtype=np.int8), ncell)
+    D = np.zeros((2 * ncell, 2 * ncell))
+    for c in range(ncell):
+        D[2 * c:2 * c + 2, 2 * c:2 * c + 2] = rng.standard_normal((2, 2)) + 3 * np.eye(2)
+    rows, inv = mgr.same_cell_blocks(csr_from_dense(D), labels)
+    v = rng.standard_normal(2 * ncell)
+    z = np.zeros_like(v)
+    z[rows] = np.einsum("eij,ej->ei", inv, v[rows])
+    assert np.allclose(D @ z, v, rtol=1e-13, atol=1e-13)
+
+
+def test_zero_pivot_detected():
+    """A zero on the diagonal of A_FF is reported, not skipped."""
+    D = np.array([[0.0, 1.0], [1.0, 2.0]])
+    A = CSR.from_dense(D, np.ones((2, 2), dtype=bool))
+    with pytest.raises(mgr.ZeroPivot):
+        mgr.setup(A, np.array([0, 1], dtype=np.int8), mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,))]))
