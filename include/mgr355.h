@@ -1,0 +1,252 @@
+/*
+ * mgr355.h - multigrid-reduction (MGR) preconditioned flexible GMRES on one AMD Instinct
+ * MI355X (gfx950), as a C ABI.
+ *
+ * The method (Bui, Osei-Kuffuor, Castelletto, White, "A Scalable Multigrid Reduction
+ * Framework for Multiphase Poromechanics of Heterogeneous Media"):
+ *   - the Jacobian A of fully implicit multiphase poromechanics (Sec. 4, eq.
+ *     block_linear_system) is solved with right-preconditioned GMRES (Sec. 4);
+ *   - the preconditioner M is built level by level from a user-given C/F splitting of the
+ *     rows by unknown type (Sec. 5.1, Sec. 5.3): Jacobi interpolation W_p = -D_FF^{-1} A_FC
+ *     and injection restriction W_r = 0 (eq. injective_rp), coarse grid
+ *     A_{l+1} = A_CC - G(A_CF D_FF^{-1} A_FC) with the optional dropping operator G
+ *     (eq. drop_operator; without dropping this is the Galerkin product R~ A P~);
+ *   - M^{-1} is applied by the V-cycle of Algorithm 2: global relaxation, F-relaxation,
+ *     restriction of the residual, recursion, interpolation and correction; the coarsest
+ *     grid and the F-relaxation of the displacement block use an algebraic multigrid
+ *     V-cycle (smoothed aggregation, l1-Jacobi) or a dense solve.
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked [host].
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     ordered on that stream; entry points that must know sizes synchronise it (stated).
+ *   - Matrices are CSR with int64 row pointers and int32 column indices, sorted and unique
+ *     within each row; explicit zeros are part of the pattern.  Values are FP64.
+ *   - Functions return mgr_status and never throw; on failure mgr_last_error() returns a
+ *     message for the calling thread and outputs are left unwritten (unless stated).
+ *   - The caller owns every array it passes; the library keeps no pointer to caller
+ *     arrays after a call returns.  A handle owns its hierarchy until mgr_destroy().
+ */
+#ifndef MGR355_H
+#define MGR355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGR_OK = 0,
+  MGR_ERR_ARG = 1,            /* invalid argument, label, option or size               */
+  MGR_ERR_ALLOC = 2,          /* device allocation failed                               */
+  MGR_ERR_HIP = 3,            /* a HIP runtime call failed                              */
+  MGR_ERR_ZERO_PIVOT = 4,     /* zero/missing diagonal in D_FF, an AMG level, or a
+                                 singular dense or block-diagonal inverse               */
+  MGR_ERR_NOT_CONVERGED = 5,  /* FGMRES reached maxit; x holds the last iterate         */
+  MGR_ERR_PATTERN = 6,        /* mgr_setup_numeric: sparsity pattern differs            */
+  MGR_ERR_UNSUPPORTED = 7     /* a size or structure outside the documented limits     */
+} mgr_status;
+
+/* ---------------------------------------------------------------------------------- */
+typedef struct {
+  int64_t nrows, ncols;        /* [host]                                              */
+  const int64_t *row_ptr;      /* nrows + 1 entries, row_ptr[0] = 0, nondecreasing     */
+  const int32_t *col;          /* row_ptr[nrows] entries                               */
+  const double *val;           /* row_ptr[nrows] entries                               */
+} mgr_csr;
+
+/* Algebraic multigrid used for F-relaxation and for the coarsest grid.  Smoothed
+ * aggregation: strength |a_ij| >= theta_l sqrt(|a_ii a_jj|) (squared Frobenius norms of
+ * bxb blocks when block = 3), theta_l = theta0 * 0.5^l; MIS(2) aggregation with SplitMix64
+ * priorities; P = (I - omega D^{-1} A) T, omega = (4/3)/max_i(sum_j|a_ij|/|a_ii|);
+ * A_c = P^T A P; one l1-Jacobi pre- and post-sweep; dense inverse at the coarsest level. */
+typedef struct {
+  double theta0;               /* default 0.08                                           */
+  int32_t max_levels;          /* default 10                                             */
+  int32_t coarse_size;         /* dense solve when n <= coarse_size; default 256, max 4096 */
+} mgr_amg_opts;
+
+enum { MGR_INTERP_JACOBI = 0, MGR_INTERP_ZERO = 1 };
+enum { MGR_FRELAX_JACOBI = 0, MGR_FRELAX_AMG = 1, MGR_FRELAX_DENSE = 2 };
+enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1 };
+enum { MGR_COARSE_AMG = 0, MGR_COARSE_DENSE = 1 };
+enum { MGR_PREC_FP64 = 0, MGR_PREC_FP32 = 1 };
+
+/* One reduction level (Sec. 5.2, Algorithm 2). */
+typedef struct {
+  uint32_t f_label_mask;       /* bit t set: rows with label t are F-points               */
+  int32_t interp;              /* MGR_INTERP_JACOBI (eq. injective_rp) or _ZERO (W_p = 0) */
+  int32_t nmax_drop;           /* < 0: no dropping (Galerkin); >= 0: N_max of G, kept in
+                                  addition to the sub-block diagonals (eq. drop_operator) */
+  int32_t frelax;              /* MGR_FRELAX_*: Jacobi sweeps, one AMG V-cycle on A_FF, or
+                                  a dense solve with A_FF (n_F <= 4096)                  */
+  int32_t frelax_sweeps;       /* Jacobi sweeps (default 1)                              */
+  double frelax_omega;         /* Jacobi weight (default 1.0)                            */
+  int32_t frelax_block;        /* 1 scalar AMG, 3 nodal AMG with 3x3 block storage; the F
+                                  rows must then come in consecutive triples with full
+                                  3x3 block patterns                                     */
+  int32_t global_smoother;     /* MGR_GSMOOTH_*: block Jacobi over same-cell blocks, i.e.
+                                  rows of equal rank within their label; the level's rows
+                                  must be interleaved cell by cell                       */
+  int32_t global_sweeps;       /* default 1                                              */
+  double global_omega;         /* weight of sweeps after the first (default 1.0)         */
+} mgr_level_opts;
+
+#define MGR_MAX_LEVELS 8
+
+typedef struct {
+  int32_t nlevels;                       /* number of reductions, 1..MGR_MAX_LEVELS     */
+  mgr_level_opts level[MGR_MAX_LEVELS];
+  int32_t coarse;                        /* MGR_COARSE_AMG or MGR_COARSE_DENSE (n<=4096) */
+  mgr_amg_opts amg_frelax;               /* AMG used by MGR_FRELAX_AMG levels            */
+  mgr_amg_opts amg_coarse;               /* AMG used on the coarsest grid                */
+  int32_t precision;                     /* MGR_PREC_FP64 or MGR_PREC_FP32: storage and
+                                            arithmetic of the whole hierarchy in apply;
+                                            setup always runs in FP64                    */
+  int32_t use_graph;                     /* 1: capture the apply V-cycle in a HIP graph  */
+  int32_t keep_setup;                    /* 1: keep the FP64 setup matrices for export   */
+} mgr_opts;
+
+typedef struct mgr_handle mgr_handle;
+
+/* Fill `o` with defaults: zero levels, coarse AMG, FP64, graphs on, level defaults as
+ * documented above.  [host] */
+void mgr_default_opts(mgr_opts *o);
+
+/* Build the MGR hierarchy for A (Sec. 5.2: per level the C/F split by label, D_FF,
+ * W_p = -D_FF^{-1} A_FC, A_cor = A_CF D_FF^{-1} A_FC by sparse product with a fixed
+ * summation order, G, A_{l+1} = A_CC - G(A_cor); then the AMG and dense solvers).
+ *   A        square CSR, n = A->nrows; nnz < 2^31.
+ *   labels   n int8 labels in [0, 7] (unknown type of every row).
+ *   opts     [host] options.
+ *   out      [host] receives the new handle on success.
+ * Synchronises `stream` (sizes of the coarse operators are data dependent).
+ * Errors: ARG (labels outside [0,7], empty F or C set, bad options, A not square),
+ * ZERO_PIVOT, UNSUPPORTED (a row of an intermediate product beyond 1 << 20 entries, a
+ * dense solve beyond 4096 unknowns, a nodal level without full 3x3 blocks), ALLOC, HIP. */
+mgr_status mgr_setup(const mgr_csr *A, const int8_t *labels, const mgr_opts *opts,
+                     void *stream, mgr_handle **out);
+
+/* Recompute every value of the hierarchy of `h` for a new matrix with exactly the same
+ * pattern as the one given to mgr_setup (e.g. the next Newton step), reusing the symbolic
+ * work: C/F split, patterns of W_p and A_cor.  Value-dependent decisions (G, AMG strength
+ * and aggregates) are recomputed, so the result equals a fresh mgr_setup.
+ * Synchronises `stream`.  Errors: PATTERN (row pointer or column arrays differ), ARG,
+ * ZERO_PIVOT, ALLOC, HIP. */
+mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream);
+
+/* z = M^{-1} v (Algorithm 2).  v and z are FP64 vectors of length n; they may not alias.
+ * With MGR_PREC_FP32 the vector is rounded to FP32 at entry and z widened at exit.
+ * Asynchronous on `stream`; calls that overlap on one handle race (one work area per
+ * handle).  Errors: ARG (null pointers), HIP. */
+mgr_status mgr_apply(mgr_handle *h, const double *v, double *z, void *stream);
+
+typedef struct {
+  int32_t restart;            /* m, Krylov vectors per cycle (1..64), default 30       */
+  int32_t maxit;              /* total preconditioner applications, default 1000       */
+  double rtol;                /* stop when ||b - A x|| <= rtol ||b|| (FP64)             */
+} fgmres_opts;
+
+typedef struct {
+  int32_t iters;              /* preconditioner applications                           */
+  int32_t restarts;           /* cycles started after the first                        */
+  int32_t converged;          /* 1 if the true residual met rtol                       */
+  double true_relres;         /* ||b - A x|| / ||b|| recomputed in FP64 at the end      */
+  double est_relres;          /* last Givens estimate |g_{j+1}| / ||b||                */
+  double *history;            /* [host] optional, history_cap entries: relative residual
+                                 estimate after every iteration (plus one entry per
+                                 restart: the true relative residual)                  */
+  int32_t history_cap;
+  int32_t history_len;        /* entries written                                       */
+} fgmres_result;
+
+/* Bytes of device workspace fgmres_solve needs for n unknowns and restart m. [host] */
+size_t fgmres_workspace_bytes(int64_t n, int32_t restart);
+
+/* Solve A x = b by flexible GMRES(m) (Saad 1993; equal to right-preconditioned GMRES,
+ * Sec. 4, for a fixed M), FP64 throughout: SpMV, classical Gram-Schmidt with one
+ * re-orthogonalisation, norms, Givens rotations, x = x0 + Z y.  After every cycle the
+ * true residual is recomputed; the solve ends when it is <= rtol ||b||.
+ *   A      the FP64 matrix (may be the one given to mgr_setup).
+ *   M      preconditioner handle, or NULL for M = I.
+ *   b      n entries.  x  n entries: initial guess in, solution out.
+ *   work   device workspace of at least fgmres_workspace_bytes(n, m) bytes, or NULL to let
+ *          the library allocate and free it inside the call.
+ *   res    [host] result record (may be NULL).
+ * Synchronises `stream` once per iteration (the convergence test).
+ * Errors: ARG, NOT_CONVERGED (x holds the last iterate, res filled), ALLOC, HIP. */
+mgr_status fgmres_solve(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
+                        const fgmres_opts *o, void *work, size_t work_bytes,
+                        fgmres_result *res, void *stream);
+
+/* Free every device allocation of the handle.  NULL is ignored. */
+void mgr_destroy(mgr_handle *h);
+
+/* Bytes of device memory the handle holds. [host out] */
+mgr_status mgr_footprint(const mgr_handle *h, size_t *bytes);
+
+/* Upper bound of the device bytes mgr_setup will hold for a matrix with n rows and nnz
+ * entries under `opts` (peak including setup temporaries), computed on the host from the
+ * sizes only. [host in/out] */
+mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts,
+                                  size_t *bytes);
+
+/* Route every device allocation of the library through caller functions (e.g. a caching
+ * allocator).  Pass NULLs to restore the default (stream-ordered hipMallocAsync).  Not
+ * thread-safe with respect to concurrent calls. [host] */
+void mgr_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
+                       void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/* Message of the last failing call on this thread ("" if none). [host] */
+const char *mgr_last_error(void);
+
+/* ---------------------------------------------------------------------------------- */
+/* Inspection of a hierarchy (tests, diagnostics).  `what` selects an object:           */
+enum {
+  MGR_X_LEVEL_A = 0,   /* A_l (level 0: copy of the input)                         CSR */
+  MGR_X_F = 1,         /* F index list of level l (ascending)               int in col */
+  MGR_X_C = 2,         /* C index list of level l                           int in col */
+  MGR_X_WP = 3,        /* W_p = -D_FF^{-1} A_FC                                    CSR */
+  MGR_X_ACOR = 4,      /* A_cor = A_CF D_FF^{-1} A_FC before dropping              CSR */
+  MGR_X_G = 5,         /* G(A_cor)                                                 CSR */
+  MGR_X_COARSE = 6,    /* A_{l+1} = A_CC - G(A_cor)                                CSR */
+  MGR_X_AMG_A = 7,     /* AMG level `sub` matrix of level l's F-relaxation AMG
+                          (l = nlevels: the coarsest-grid AMG)                     CSR */
+  MGR_X_AMG_P = 8,     /* AMG prolongator of level `sub`                           CSR */
+  MGR_X_AMG_AGG = 9,   /* AMG aggregate id per node (-1: none)              int in col */
+  MGR_X_AMG_NLEV = 10  /* number of AMG levels in out[0]                               */
+};
+/* Sizes of an object: out[0] = rows, out[1] = cols, out[2] = entries. [host out]
+ * Requires opts.keep_setup = 1 for the CSR objects.  Errors: ARG. */
+mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t sub,
+                     int64_t out[3]);
+/* Copy an object into caller arrays sized by mgr_query (row_ptr may be NULL for index
+ * lists, val NULL to skip values).  Synchronises `stream`.  Errors: ARG, HIP. */
+mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t sub,
+                      int64_t *row_ptr, int32_t *col, double *val, void *stream);
+
+/* ---------------------------------------------------------------------------------- */
+/* Building blocks and measurement hooks.                                               */
+
+/* y = A x with the FP64 CSR kernel used by fgmres_solve.  Asynchronous. */
+mgr_status mgr_spmv(const mgr_csr *A, const double *x, double *y, void *stream);
+
+/* dst = src for n doubles with a plain streaming kernel (HBM counter calibration). */
+mgr_status mgr_stream_copy(const double *src, double *dst, int64_t n, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the launching stream around every launch
+ * of the named kernel family, inside mgr_apply / fgmres_solve of `h`:
+ *   family 0 = nodal (3x3 block) AMG smoothing sweeps, 1 = outer FP64 CSR SpMV.
+ * enable != 0 starts a new accumulation; mgr_profile_read synchronises and returns the
+ * number of launches timed, their total milliseconds, and the algorithmic bytes they move
+ * (matrix values and indices, row pointers, and each vector read or written once). */
+mgr_status mgr_profile_enable(int32_t family, int32_t enable);
+mgr_status mgr_profile_read(int32_t family, int64_t *launches, double *total_ms,
+                            double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGR355_H */

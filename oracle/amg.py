@@ -48,7 +48,7 @@ class ZeroPivot(ArithmeticError):
 class AMGOptions:
     theta0: float = 0.08
     max_levels: int = 10
-    coarse_size: int = 1024
+    coarse_size: int = 256
     block: int = 1          # 1 = scalar, 3 = nodal (unknown approach)
 
 

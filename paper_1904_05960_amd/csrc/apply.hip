@@ -1,0 +1,349 @@
+// Kernels of the preconditioner application (Algorithm 2 and the AMG V-cycles inside it),
+// for FP32 or FP64 hierarchies.  All of them are HBM-bandwidth bound:
+//  * CSR rows are processed by G lanes of a 64-wide wavefront (G from the mean row length),
+//    so that each group streams a contiguous run of column indices and values;
+//  * 3x3 block rows (nodal elasticity AMG) store the nine block entries in nine planes
+//    (entry k of block e at v[k * nnzb + e]), so lane-consecutive blocks give unit-stride
+//    loads; one lane handles one block and the three row sums are reduced over the group;
+//  * the l1-Jacobi smoothing sweeps are fused with the residual they need: the presweep
+//    from zero (x = D^{-1} b) and the residual b - A x are one pass over A, the postsweep
+//    y = x + D^{-1}(b - A x) is one pass.
+#include "common.hpp"
+
+namespace mgr {
+namespace {
+
+enum { M_RESID = 0, M_SPMV = 1, M_SPMV_ADD = 2, M_L1PRE = 3, M_L1POST = 4 };
+
+template <class T, int G>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// One kernel for the CSR variants.  Work item t uses matrix row rows[t] (or t); the right
+// side is indexed by bidx[t] (or t).
+template <class T, int G, int MODE>
+__global__ void __launch_bounds__(256) k_csr(int64_t nw, const int *__restrict__ rows,
+                                             const int *__restrict__ bidx,
+                                             const int *__restrict__ rp, const int *__restrict__ ci,
+                                             const T *__restrict__ v, const T *__restrict__ x,
+                                             const T *__restrict__ b, const T *__restrict__ dinv,
+                                             T *__restrict__ out, T *__restrict__ out2) {
+  const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (t >= nw) return;
+  const int row = rows ? rows[t] : (int)t;
+  T acc = 0;
+  const int e1 = rp[row + 1];
+  for (int e = rp[row] + l; e < e1; e += G) {
+    const int c = ci[e];
+    if (MODE == M_L1PRE) acc += v[e] * (dinv[c] * b[c]);
+    else acc += v[e] * x[c];
+  }
+  acc = group_sum<T, G>(acc);
+  if (l != 0) return;
+  if (MODE == M_RESID) {
+    out[t] = b[bidx ? bidx[t] : t] - acc;
+  } else if (MODE == M_SPMV) {
+    out[t] = acc;
+  } else if (MODE == M_SPMV_ADD) {
+    out[t] += acc;
+  } else if (MODE == M_L1PRE) {
+    const T bi = b[t];
+    out2[t] = dinv[t] * bi;       // x
+    out[t] = bi - acc;            // r
+  } else {                        // M_L1POST: y = x + D^{-1}(b - A x)
+    out[t] = x[t] + dinv[t] * (b[t] - acc);
+  }
+}
+
+template <class T, int MODE>
+void launch_csr(const CsrV<T> &A, int64_t nw, const int *rows, const int *bidx, const T *x,
+                const T *b, const T *dinv, T *out, T *out2, hipStream_t s) {
+  if (nw <= 0) return;
+  const double avg = A.n ? (double)A.nnz / (double)A.n : 0.0;
+#define LCSR(GG)                                                                          \
+  k_csr<T, GG, MODE><<<grid_for(nw * GG, 256), 256, 0, s>>>(nw, rows, bidx, A.rp, A.ci, A.v, \
+                                                             x, b, dinv, out, out2)
+  if (avg > 48) LCSR(64);
+  else if (avg > 24) LCSR(32);
+  else if (avg > 12) LCSR(16);
+  else if (avg > 6) LCSR(8);
+  else LCSR(4);
+#undef LCSR
+  KCHK();
+}
+
+// BSR3 variants; G lanes per block row, block values in nine planes
+template <class T, int G, int MODE>
+__global__ void __launch_bounds__(256) k_bsr3(int64_t nb, const int *__restrict__ rp,
+                                              const int *__restrict__ ci, int64_t nnzb,
+                                              const T *__restrict__ v, const T *__restrict__ x,
+                                              const T *__restrict__ b, const T *__restrict__ dinv,
+                                              T *__restrict__ out, T *__restrict__ out2) {
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (I >= nb) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  const int e1 = rp[I + 1];
+  for (int e = rp[I] + l; e < e1; e += G) {
+    const int64_t c3 = 3 * (int64_t)ci[e];
+    T x0, x1, x2;
+    if (MODE == M_L1PRE) {
+      x0 = dinv[c3] * b[c3];
+      x1 = dinv[c3 + 1] * b[c3 + 1];
+      x2 = dinv[c3 + 2] * b[c3 + 2];
+    } else {
+      x0 = x[c3];
+      x1 = x[c3 + 1];
+      x2 = x[c3 + 2];
+    }
+    const T *vb = v + e;
+    a0 += vb[0] * x0 + vb[nnzb] * x1 + vb[2 * nnzb] * x2;
+    a1 += vb[3 * nnzb] * x0 + vb[4 * nnzb] * x1 + vb[5 * nnzb] * x2;
+    a2 += vb[6 * nnzb] * x0 + vb[7 * nnzb] * x1 + vb[8 * nnzb] * x2;
+  }
+  a0 = group_sum<T, G>(a0);
+  a1 = group_sum<T, G>(a1);
+  a2 = group_sum<T, G>(a2);
+  if (l != 0) return;
+  const int64_t r = 3 * I;
+  if (MODE == M_SPMV) {
+    out[r] = a0; out[r + 1] = a1; out[r + 2] = a2;
+  } else if (MODE == M_SPMV_ADD) {
+    out[r] += a0; out[r + 1] += a1; out[r + 2] += a2;
+  } else if (MODE == M_RESID) {
+    out[r] = b[r] - a0; out[r + 1] = b[r + 1] - a1; out[r + 2] = b[r + 2] - a2;
+  } else if (MODE == M_L1PRE) {
+    const T b0 = b[r], b1 = b[r + 1], b2 = b[r + 2];
+    out2[r] = dinv[r] * b0; out2[r + 1] = dinv[r + 1] * b1; out2[r + 2] = dinv[r + 2] * b2;
+    out[r] = b0 - a0; out[r + 1] = b1 - a1; out[r + 2] = b2 - a2;
+  } else {
+    out[r] = x[r] + dinv[r] * (b[r] - a0);
+    out[r + 1] = x[r + 1] + dinv[r + 1] * (b[r + 1] - a1);
+    out[r + 2] = x[r + 2] + dinv[r + 2] * (b[r + 2] - a2);
+  }
+}
+
+template <class T, int MODE>
+void launch_bsr3(const Bsr3V<T> &A, const T *x, const T *b, const T *dinv, T *out, T *out2,
+                 hipStream_t s) {
+  if (A.n <= 0) return;
+  const double avg = (double)A.nnzb / (double)A.n;
+#define LB(GG)                                                                         \
+  k_bsr3<T, GG, MODE><<<grid_for(A.n * GG, 256), 256, 0, s>>>(A.n, A.rp, A.ci, A.nnzb, A.v, \
+                                                               x, b, dinv, out, out2)
+  if (avg > 12) LB(16);
+  else if (avg > 6) LB(8);
+  else LB(4);
+#undef LB
+  KCHK();
+}
+
+// interpolation and correction: z_F (+)= [eF] + W_p e_C, z_C (+)= e_C.  8 lanes per row.
+template <class T>
+__global__ void k_interp(int64_t n, const int *__restrict__ map, const int *__restrict__ wrp,
+                         const int *__restrict__ wci, const T *__restrict__ wv,
+                         const T *__restrict__ eC, const T *__restrict__ eF, T *__restrict__ z,
+                         int accumulate) {
+  constexpr int G = 8;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (i >= n) return;
+  const int m = map[i];
+  if (m >= 0) {
+    T acc = 0;
+    for (int e = wrp[m] + l; e < wrp[m + 1]; e += G) acc += wv[e] * eC[wci[e]];
+    acc = group_sum<T, G>(acc);
+    if (l == 0) {
+      const T base = accumulate ? z[i] : (eF ? eF[m] : (T)0);
+      z[i] = base + acc;
+    }
+  } else if (l == 0) {
+    const T e = eC[-m - 1];
+    z[i] = accumulate ? z[i] + e : e;
+  }
+}
+
+// dense y = M x, one wavefront per row
+template <class T>
+__global__ void k_gemv(const T *__restrict__ M, int n, const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
+  const int l = threadIdx.x & 63;
+  if (row >= n) return;
+  T acc = 0;
+  const T *mr = M + row * (int64_t)n;
+  for (int j = l; j < n; j += 64) acc += mr[j] * x[j];
+  acc = group_sum<T, 64>(acc);
+  if (l == 0) y[row] = acc;
+}
+
+template <class T>
+__global__ void k_gather(const int *__restrict__ idx, int64_t n, const T *__restrict__ x,
+                         T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[t] = x[idx[t]];
+}
+template <class T>
+__global__ void k_scatter_add(const int *__restrict__ idx, int64_t n, const T *__restrict__ x,
+                              T *__restrict__ y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) y[idx[t]] += x[t];
+}
+template <class T>
+__global__ void k_jacobi_update(const int *__restrict__ F, int64_t nF, const T *__restrict__ dinv,
+                                T omega, const T *__restrict__ r, T *__restrict__ z) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < nF) z[F[t]] += omega * (dinv[t] * r[t]);
+}
+template <class T>
+__global__ void k_jacobi_first(int64_t n, const int *__restrict__ map, const T *__restrict__ dinv,
+                               T omega, const T *__restrict__ v, T *__restrict__ z) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = map[i];
+  z[i] = m >= 0 ? omega * (dinv[m] * v[i]) : (T)0;
+}
+// z = D_B^{-1} v, or z += omega D_B^{-1} v, over consecutive nb x nb blocks
+template <class T>
+__global__ void k_block_jacobi(int64_t nblk, int nb, const T *__restrict__ inv,
+                               const T *__restrict__ v, T omega, T *__restrict__ z, int acc) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nblk) return;
+  const T *B = inv + e * nb * nb;
+  const int64_t r0 = e * nb;
+  T vv[3];
+  for (int c = 0; c < nb; ++c) vv[c] = v[r0 + c];
+  for (int r = 0; r < nb; ++r) {
+    T s = 0;
+    for (int c = 0; c < nb; ++c) s += B[r * nb + c] * vv[c];
+    z[r0 + r] = acc ? z[r0 + r] + omega * s : s;
+  }
+}
+template <class T>
+__global__ void k_fillv(T *p, T val, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+template <class A, class B>
+__global__ void k_cast(const A *__restrict__ a, B *__restrict__ b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (B)a[i];
+}
+
+}  // namespace
+
+template <class T>
+void VecOps<T>::resid(const CsrV<T> &A, int64_t nw, const int *rows, const int *bidx, const T *x,
+                      const T *b, T *out, hipStream_t s) {
+  launch_csr<T, M_RESID>(A, nw, rows, bidx, x, b, nullptr, out, nullptr, s);
+}
+template <class T>
+void VecOps<T>::spmv(const CsrV<T> &A, const T *x, T *y, bool accumulate, hipStream_t s) {
+  if (accumulate) launch_csr<T, M_SPMV_ADD>(A, A.n, nullptr, nullptr, x, nullptr, nullptr, y, nullptr, s);
+  else launch_csr<T, M_SPMV>(A, A.n, nullptr, nullptr, x, nullptr, nullptr, y, nullptr, s);
+}
+template <class T>
+void VecOps<T>::interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC, const T *eF,
+                       T *z, bool accumulate, hipStream_t s) {
+  if (n <= 0) return;
+  k_interp<T><<<grid_for(n * 8, 256), 256, 0, s>>>(n, map, Wp.rp, Wp.ci, Wp.v, eC, eF, z,
+                                                   accumulate ? 1 : 0);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r, hipStream_t s) {
+  launch_csr<T, M_L1PRE>(A, A.n, nullptr, nullptr, nullptr, b, dinv, r, x, s);
+}
+template <class T>
+void VecOps<T>::l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,
+                        hipStream_t s) {
+  launch_csr<T, M_L1POST>(A, A.n, nullptr, nullptr, x, b, dinv, y, nullptr, s);
+}
+template <class T>
+void VecOps<T>::b_spmv(const Bsr3V<T> &A, const T *x, T *y, bool accumulate, hipStream_t s) {
+  if (accumulate) launch_bsr3<T, M_SPMV_ADD>(A, x, nullptr, nullptr, y, nullptr, s);
+  else launch_bsr3<T, M_SPMV>(A, x, nullptr, nullptr, y, nullptr, s);
+}
+template <class T>
+void VecOps<T>::b_l1_pre(const Bsr3V<T> &A, const T *dinv, const T *b, T *x, T *r, hipStream_t s) {
+  launch_bsr3<T, M_L1PRE>(A, nullptr, b, dinv, r, x, s);
+}
+template <class T>
+void VecOps<T>::b_l1_post(const Bsr3V<T> &A, const T *dinv, const T *b, const T *x, T *y,
+                          hipStream_t s) {
+  launch_bsr3<T, M_L1POST>(A, x, b, dinv, y, nullptr, s);
+}
+template <class T>
+void VecOps<T>::gemv(const T *M, int n, const T *x, T *y, hipStream_t s) {
+  k_gemv<T><<<grid_for((int64_t)n * 64, 256), 256, 0, s>>>(M, n, x, y);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::gather(const int *idx, int64_t n, const T *x, T *y, hipStream_t s) {
+  if (n <= 0) return;
+  k_gather<T><<<grid_for(n, 256), 256, 0, s>>>(idx, n, x, y);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::scatter_add(const int *idx, int64_t n, const T *x, T *y, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_add<T><<<grid_for(n, 256), 256, 0, s>>>(idx, n, x, y);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::jacobi_update(const int *F, int64_t nF, const T *dinv, T omega, const T *r, T *z,
+                              hipStream_t s) {
+  if (nF <= 0) return;
+  k_jacobi_update<T><<<grid_for(nF, 256), 256, 0, s>>>(F, nF, dinv, omega, r, z);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::jacobi_first(int64_t n, const int *map, const T *dinv, T omega, const T *v, T *z,
+                             hipStream_t s) {
+  if (n <= 0) return;
+  k_jacobi_first<T><<<grid_for(n, 256), 256, 0, s>>>(n, map, dinv, omega, v, z);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::block_jacobi(int64_t nblk, int nb, const T *inv, const T *v, T omega, T *z,
+                             bool accumulate, hipStream_t s) {
+  if (nblk <= 0) return;
+  k_block_jacobi<T><<<grid_for(nblk, 256), 256, 0, s>>>(nblk, nb, inv, v, omega, z,
+                                                        accumulate ? 1 : 0);
+  KCHK();
+}
+template <class T>
+void VecOps<T>::fill(T *p, T val, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fillv<T><<<grid_for(n, 256), 256, 0, s>>>(p, val, n);
+  KCHK();
+}
+
+template struct VecOps<float>;
+template struct VecOps<double>;
+
+void cast_to(const double *in, float *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<double, float><<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  KCHK();
+}
+void cast_to(const double *in, double *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<double, double><<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  KCHK();
+}
+void cast_from(const float *in, double *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<float, double><<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  KCHK();
+}
+void cast_from(const double *in, double *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<double, double><<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  KCHK();
+}
+
+}  // namespace mgr

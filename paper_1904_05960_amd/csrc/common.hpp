@@ -1,0 +1,259 @@
+// Internal declarations shared by the HIP translation units of libmgr355.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mgr355.h"
+
+namespace mgr {
+
+// ------------------------------------------------------------------------------------
+// errors
+struct Error : std::runtime_error {
+  mgr_status st;
+  Error(mgr_status s, const std::string &m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw ::mgr::Error(MGR_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define KCHK() HIPCHK(hipGetLastError())
+
+inline void require(bool ok, mgr_status st, const std::string &msg) {
+  if (!ok) throw Error(st, msg);
+}
+
+// device error flags raised by kernels (atomicOr on a device int)
+enum : int {
+  FLAG_ZERO_PIVOT = 1,
+  FLAG_BAD_LABEL = 2,
+  FLAG_ROW_TOO_LONG = 4,
+  FLAG_NOT_BLOCKED = 8,
+  FLAG_PATTERN = 16,
+  FLAG_OVERFLOW = 32,
+};
+
+// ------------------------------------------------------------------------------------
+// allocation (caller hook or stream-ordered hipMallocAsync)
+void *dalloc(size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
+
+template <class T>
+struct DArr {
+  T *p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DArr() = default;
+  DArr(size_t n_, hipStream_t s_) { alloc(n_, s_); }
+  DArr(const DArr &) = delete;
+  DArr &operator=(const DArr &) = delete;
+  DArr(DArr &&o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DArr &operator=(DArr &&o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DArr() { reset(); }
+  void alloc(size_t n_, hipStream_t s_) {
+    reset();
+    s = s_;
+    n = n_;
+    p = n_ ? static_cast<T *>(dalloc(n_ * sizeof(T), s_)) : nullptr;
+  }
+  void reset() {
+    if (p) dfree(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  T *get() const { return p; }
+};
+
+// ------------------------------------------------------------------------------------
+// matrices
+// Device CSR with int32 row pointers (nnz < 2^31) and FP64 values, owning its arrays.
+struct Csr {
+  int64_t n = 0, m = 0, nnz = 0;
+  DArr<int> rp, ci;
+  DArr<double> v;
+  size_t bytes() const { return rp.bytes() + ci.bytes() + v.bytes(); }
+};
+
+// Read-only views used by apply kernels (T = float or double).
+template <class T>
+struct CsrV {
+  int64_t n = 0, m = 0, nnz = 0;
+  const int *rp = nullptr, *ci = nullptr;
+  const T *v = nullptr;
+};
+// 3x3 block CSR: n, m in block rows/cols, values row-major per block (9 per block).
+template <class T>
+struct Bsr3V {
+  int64_t n = 0, m = 0, nnzb = 0;
+  const int *rp = nullptr, *ci = nullptr;
+  const T *v = nullptr;
+};
+
+// ------------------------------------------------------------------------------------
+// launch geometry
+inline unsigned grid_for(int64_t work, int block) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 0x7fffffff) g = 0x7fffffff;
+  return static_cast<unsigned>(g);
+}
+
+// ------------------------------------------------------------------------------------
+// primitives (prims.hip)
+int64_t exclusive_scan_i32(const int *in, int *out, int64_t n, hipStream_t s);   // out[n]=total
+int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+template <class T> void fill(T *p, T val, int64_t n, hipStream_t s);
+int64_t reduce_max_i64(const int64_t *p, int64_t n, hipStream_t s);
+int64_t reduce_sum_i32(const int *p, int64_t n, hipStream_t s);
+double reduce_max_f64(const double *p, int64_t n, hipStream_t s);
+void cast_f64_to_f32(const double *in, float *out, int64_t n, hipStream_t s);
+void cast_f32_to_f64(const float *in, double *out, int64_t n, hipStream_t s);
+void negate_f64(double *p, int64_t n, hipStream_t s);
+void rowptr64_to_32(const int64_t *in, int *out, int64_t n1, int *flag, hipStream_t s);
+void rowptr32_to_64(const int *in, int64_t *out, int64_t n1, hipStream_t s);
+void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+int read_flag(const int *dflag, hipStream_t s);      // synchronises
+void clear_flag(int *dflag, hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// sparse setup kernels (spgemm.hip, setup.hip, amg_setup.hip)
+void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag);
+void transpose(const Csr &A, Csr &T, bool values, hipStream_t s);
+// S = A - diag(w) * B restricted to entries of B kept by the drop rule.
+//   keep rule: nmax < 0 keeps all of B; otherwise per row the entries whose column c has
+//   lrank[c] == lrank[row] plus the nmax largest |b| (ties: smaller column).
+//   w may be null (w = 1).  If values == false, only the union pattern is formed.
+void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int *lrank,
+                Csr &S, bool values, hipStream_t s, int *dflag);
+void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag);
+
+struct CfSplit {
+  int64_t n = 0, nF = 0, nC = 0;
+  DArr<int> F, C;         // index lists (ascending)
+  DArr<int> map;          // map[i] = F index if F point, else -(C index) - 1
+};
+void cf_split(const int8_t *labels, int64_t n, uint32_t fmask, CfSplit &cf, hipStream_t s,
+              int *dflag);
+void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s);
+void gather_labels(const int8_t *labels, const int *idx, int64_t n, int8_t *out,
+                   hipStream_t s);
+// A_FF, A_FC, A_CF, A_CC of A under cf; dFF = diag(A_FF) (0 where missing).
+void extract_blocks(const Csr &A, const CfSplit &cf, Csr *Aff, Csr &Afc, Csr &Acf, Csr &Acc,
+                    double *dFF, hipStream_t s);
+// M = D^{-1} A_FC (values a/d), in place on a copy.
+void scale_rows_div(Csr &M, const double *d, hipStream_t s);
+void check_nonzero(const double *d, int64_t n, int *dflag, hipStream_t s);
+void copy_csr(const Csr &A, Csr &B, hipStream_t s);
+void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag);
+uint64_t pattern_hash(const Csr &A, hipStream_t s);
+
+// AMG setup
+struct AmgGraph {
+  int64_t n = 0;
+  DArr<int> rp, ci;
+};
+void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t s,
+                    int *dflag);
+void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
+                    hipStream_t s);
+void tentative(const DArr<int> &agg, int64_t nnode, int bs, int64_t nagg, Csr &T,
+               hipStream_t s);
+double gershgorin_rho(const Csr &A, hipStream_t s, int *dflag);
+void diag_of(const Csr &A, double *d, hipStream_t s);
+void omega_over_diag(const double *d, double omega, double *w, int64_t n, hipStream_t s);
+void l1_inverse(const Csr &A, double *dinv, hipStream_t s);
+
+// dense (dense.hip)
+void csr_to_dense(const Csr &A, double *D, hipStream_t s);
+void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s);
+
+// BSR3 conversion: scalar CSR with full 3x3 blocks -> block CSR
+void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, int64_t &nb,
+                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag);
+// block-Jacobi inverses over consecutive nb x nb diagonal blocks (nb = 2 or 3)
+void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag);
+
+// ------------------------------------------------------------------------------------
+// apply kernels (apply.hip), T = float or double
+template <class T>
+struct VecOps {
+  static void resid(const CsrV<T> &A, int64_t nw, const int *rows, const int *bidx,
+                    const T *x, const T *b, T *out, hipStream_t s);
+  static void spmv(const CsrV<T> &A, const T *x, T *y, bool accumulate, hipStream_t s);
+  static void interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC,
+                     const T *eF, T *z, bool accumulate, hipStream_t s);
+  static void l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r,
+                     hipStream_t s);
+  static void l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,
+                      hipStream_t s);
+  static void b_spmv(const Bsr3V<T> &A, const T *x, T *y, bool accumulate, hipStream_t s);
+  static void b_l1_pre(const Bsr3V<T> &A, const T *dinv, const T *b, T *x, T *r,
+                       hipStream_t s);
+  static void b_l1_post(const Bsr3V<T> &A, const T *dinv, const T *b, const T *x, T *y,
+                        hipStream_t s);
+  static void gemv(const T *M, int n, const T *x, T *y, hipStream_t s);
+  static void gather(const int *idx, int64_t n, const T *x, T *y, hipStream_t s);
+  static void scatter_add(const int *idx, int64_t n, const T *x, T *y, hipStream_t s);
+  static void jacobi_update(const int *F, int64_t nF, const T *dinv, T omega, const T *r,
+                            T *z, hipStream_t s);
+  static void jacobi_first(int64_t n, const int *map, const T *dinv, T omega, const T *v,
+                           T *z, hipStream_t s);
+  static void block_jacobi(int64_t nblk, int nb, const T *inv, const T *v, T omega, T *z,
+                           bool accumulate, hipStream_t s);
+  static void fill(T *p, T val, int64_t n, hipStream_t s);
+};
+void cast_to(const double *in, float *out, int64_t n, hipStream_t s);
+void cast_to(const double *in, double *out, int64_t n, hipStream_t s);
+void cast_from(const float *in, double *out, int64_t n, hipStream_t s);
+void cast_from(const double *in, double *out, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// FP64 Krylov kernels (krylov.hip)
+void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s);
+void resid64(const mgr_csr &A, const double *x, const double *b, double *r, hipStream_t s);
+int krylov_partials_blocks();
+// partial[blk * 64 + k] = sum over rows of blk of V_k . w  (k < nv)
+void multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
+                       hipStream_t s);
+// w -= sum_k h[k] V_k ; partial dots of the updated w with V_k (k < nv) or its norm^2
+void cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
+                         double *partial, bool norm_only, hipStream_t s);
+void reduce_partials(const double *partial, int nv, double *out, bool add, hipStream_t s);
+void givens_step(double *H, double *cs, double *sn, double *g, const double *h1,
+                 const double *h2, const double *hn2, int j, int ldh, double *scal,
+                 double *unused, hipStream_t s);
+void scale_vec(const double *w, const double *scale, double *v, int64_t n, hipStream_t s);
+void tri_solve_and_update(const double *H, const double *g, int k, int ldh, const double *Z,
+                          int64_t n, double *x, double *y, hipStream_t s);
+void norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s);
+void dot_partials(const double *a, const double *b, int64_t n, double *partial,
+                  hipStream_t s);
+void start_cycle_host_beta(const double *r, double beta, double *V0, double *g, int64_t n,
+                           int mp1, hipStream_t s);
+void spmv64_avg(const mgr_csr &A, const double *x, const double *b, double *y, double avg,
+                hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// profiling hooks (abi.hip)
+struct Prof {
+  static bool on(int family);
+  static void begin(int family, hipStream_t s);
+  static void end(int family, hipStream_t s, double bytes);
+};
+
+}  // namespace mgr

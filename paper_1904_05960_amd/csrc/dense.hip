@@ -1,0 +1,115 @@
+// Dense solves for the coarsest grids: the matrix is expanded to a dense row-major array
+// and inverted once at setup (Gauss-Jordan with partial pivoting, FP64, one workgroup);
+// each coarse solve in the V-cycle is then a dense matrix-vector product.
+#include "common.hpp"
+
+namespace mgr {
+namespace {
+
+__global__ void k_scatter_dense(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                const double *__restrict__ v, double *__restrict__ D) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) D[i * n + ci[e]] = v[e];
+}
+
+constexpr int GJ_THREADS = 1024;
+
+// In-place Gauss-Jordan inversion with partial pivoting (first row of largest |a| in the
+// column); column interchanges undone at the end.
+__global__ void __launch_bounds__(GJ_THREADS) k_gauss_jordan(double *__restrict__ A, int n,
+                                                            int *__restrict__ piv,
+                                                            double *__restrict__ colk,
+                                                            int *flag) {
+  __shared__ double s_val[GJ_THREADS];
+  __shared__ int s_idx[GJ_THREADS];
+  __shared__ int s_fail;
+  const int t = threadIdx.x;
+  if (t == 0) s_fail = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // pivot search
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + t; i < n; i += GJ_THREADS) {
+      const double a = fabs(A[(int64_t)i * n + k]);
+      if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+    }
+    s_val[t] = best;
+    s_idx[t] = bi;
+    __syncthreads();
+    for (int o = GJ_THREADS / 2; o > 0; o >>= 1) {
+      if (t < o) {
+        const double a = s_val[t + o];
+        const int ia = s_idx[t + o];
+        if (a > s_val[t] || (a == s_val[t] && ia < s_idx[t])) { s_val[t] = a; s_idx[t] = ia; }
+      }
+      __syncthreads();
+    }
+    const int p = s_idx[0];
+    const double pv = s_val[0];
+    if (pv == 0.0 || !(pv == pv)) {
+      if (t == 0) s_fail = 1;
+      __syncthreads();
+      break;
+    }
+    if (t == 0) piv[k] = p;
+    if (p != k) {
+      for (int j = t; j < n; j += GJ_THREADS) {
+        const double x = A[(int64_t)k * n + j];
+        A[(int64_t)k * n + j] = A[(int64_t)p * n + j];
+        A[(int64_t)p * n + j] = x;
+      }
+    }
+    __syncthreads();
+    const double pivot = A[(int64_t)k * n + k];
+    __syncthreads();
+    for (int j = t; j < n; j += GJ_THREADS)
+      A[(int64_t)k * n + j] = (j == k ? 1.0 : A[(int64_t)k * n + j]) / pivot;
+    for (int i = t; i < n; i += GJ_THREADS) colk[i] = A[(int64_t)i * n + k];
+    __syncthreads();
+    for (int64_t q = t; q < (int64_t)n * n; q += GJ_THREADS) {
+      const int i = (int)(q / n), j = (int)(q % n);
+      if (i == k) continue;
+      const double base = (j == k) ? 0.0 : A[q];
+      A[q] = base - colk[i] * A[(int64_t)k * n + j];
+    }
+    __syncthreads();
+  }
+  if (s_fail) {
+    if (t == 0) atomicOr(flag, FLAG_ZERO_PIVOT);
+    return;
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      for (int i = t; i < n; i += GJ_THREADS) {
+        const double x = A[(int64_t)i * n + k];
+        A[(int64_t)i * n + k] = A[(int64_t)i * n + p];
+        A[(int64_t)i * n + p] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+void csr_to_dense(const Csr &A, double *D, hipStream_t s) {
+  fill<double>(D, 0.0, A.n * A.n, s);
+  if (A.n == 0) return;
+  k_scatter_dense<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, D);
+  KCHK();
+}
+
+void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s) {
+  require(n >= 1 && n <= 4096, MGR_ERR_UNSUPPORTED, "dense solve limited to 4096 unknowns");
+  HIPCHK(hipMemcpyAsync(Inv, D, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  DArr<int> piv(n, s);
+  DArr<double> colk(n, s);
+  k_gauss_jordan<<<1, GJ_THREADS, 0, s>>>(Inv, n, piv.p, colk.p, dflag);
+  KCHK();
+  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "singular coarsest-grid matrix");
+}
+
+}  // namespace mgr

@@ -1,0 +1,1118 @@
+// Host orchestration of libmgr355: allocation, the MGR hierarchy (Sec. 5.2), the AMG
+// hierarchies, the V-cycle of Algorithm 2, flexible GMRES, and the C ABI of mgr355.h.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <memory>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace mgr {
+
+// ===================================================================================
+// allocation
+static void *(*g_alloc)(size_t, void *, void *) = nullptr;
+static void (*g_free)(void *, void *, void *) = nullptr;
+static void *g_ctx = nullptr;
+static std::once_flag g_pool_once;
+
+static void init_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+}
+
+void *dalloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) return nullptr;
+  if (g_alloc) {
+    void *p = g_alloc(bytes, s, g_ctx);
+    if (!p) throw Error(MGR_ERR_ALLOC, "allocator hook returned NULL");
+    return p;
+  }
+  std::call_once(g_pool_once, init_pool);
+  void *p = nullptr;
+  hipError_t e = hipMallocAsync(&p, bytes, s);
+  if (e != hipSuccess || !p)
+    throw Error(MGR_ERR_ALLOC, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+  return p;
+}
+void dfree(void *p, hipStream_t s) {
+  if (!p) return;
+  if (g_free) g_free(p, s, g_ctx);
+  else (void)hipFreeAsync(p, s);
+}
+
+// ===================================================================================
+// profiling: HIP events around launches of a kernel family
+namespace {
+struct ProfFamily {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<double> bytes;
+  size_t used = 0;
+};
+ProfFamily g_prof[2];
+std::mutex g_prof_mu;
+}  // namespace
+
+bool Prof::on(int f) { return g_prof[f].on; }
+void Prof::begin(int f, hipStream_t s) {
+  ProfFamily &P = g_prof[f];
+  if (P.used == P.ev.size()) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    P.ev.emplace_back(a, b);
+    P.bytes.push_back(0.0);
+  }
+  HIPCHK(hipEventRecord(P.ev[P.used].first, s));
+}
+void Prof::end(int f, hipStream_t s, double bytes) {
+  ProfFamily &P = g_prof[f];
+  HIPCHK(hipEventRecord(P.ev[P.used].second, s));
+  P.bytes[P.used] = bytes;
+  ++P.used;
+}
+
+// ===================================================================================
+// hierarchy structures
+struct AmgLevel {
+  Csr A, P, R;               // FP64 scalar CSR (A of the last level is the dense-solved one)
+  DArr<int> agg;
+  int64_t nagg = 0;
+  double omega = 0.0;
+  DArr<double> dinv;         // l1 row sums inverted
+  // nodal (3x3 block) copies for the V-cycle
+  DArr<int> Ab_rp, Ab_ci, Pb_rp, Pb_ci, Rb_rp, Rb_ci;
+  int64_t nb = 0, ncb = 0, Ab_nnzb = 0, Pb_nnzb = 0, Rb_nnzb = 0;
+  // apply-precision values (bytes of float or double)
+  DArr<char> tA, tP, tR, tdinv;
+  // work vectors (apply precision)
+  DArr<char> x, r, b, y;
+};
+
+struct Amg {
+  int bs = 1;
+  std::vector<std::unique_ptr<AmgLevel>> lv;
+  int nc = 0;                // coarsest size (dense)
+  DArr<double> cinv64;
+  DArr<char> tcinv;
+};
+
+struct MgrLevel {
+  Csr A;                     // level matrix A_l (FP64)
+  DArr<int8_t> labels;
+  CfSplit cf;
+  bool f_prefix = false;     // F = 0..nF-1
+  DArr<double> dFF;
+  Csr Acf, Wp, Acor, G;      // Acor / G only with keep_setup
+  int nb_gs = 0;             // global smoother block size
+  DArr<double> binv64;
+  Amg amg;                   // F-relaxation AMG
+  DArr<double> ffinv64;      // dense F-relaxation inverse
+  int nF = 0;
+  // apply-precision copies
+  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv;
+  // work vectors
+  DArr<char> v, z, rF, eF, rfull;
+};
+
+template <class T> struct Ptr {
+  static T *of(const DArr<char> &d) { return reinterpret_cast<T *>(d.p); }
+};
+
+}  // namespace mgr
+
+struct mgr_handle {
+  mgr_opts opts;
+  hipStream_t s = nullptr;
+  int64_t n = 0;
+  std::vector<std::unique_ptr<mgr::MgrLevel>> lv;
+  mgr::Csr coarseA;
+  mgr::DArr<int8_t> coarse_labels;
+  mgr::Amg coarse_amg;
+  mgr::DArr<double> cdense64;
+  mgr::DArr<char> tcdense;
+  int ncd = 0;
+  mgr::DArr<int> dflag;
+  mgr::DArr<int8_t> labels0;
+  uint64_t pattern = 0;
+  mgr::DArr<char> v0, z0;    // apply-precision level-0 vectors
+  hipStream_t cap = nullptr; // private capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  ~mgr_handle();
+};
+
+namespace mgr {
+namespace {
+
+thread_local std::string t_err;
+
+size_t esz(const mgr_opts &o) { return o.precision == MGR_PREC_FP32 ? 4 : 8; }
+
+void cast_values(const double *src, DArr<char> &dst, int64_t n, size_t sz, hipStream_t s) {
+  dst.alloc(std::max<int64_t>(n, 1) * sz, s);
+  if (n <= 0) return;
+  if (sz == 4) cast_to(src, reinterpret_cast<float *>(dst.p), n, s);
+  else cast_to(src, reinterpret_cast<double *>(dst.p), n, s);
+}
+
+__global__ void k_planes(const double *__restrict__ blk, int64_t nnzb, float *f, double *d) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnzb) return;
+  for (int k = 0; k < 9; ++k) {
+    const double x = blk[9 * e + k];
+    if (f) f[k * nnzb + e] = (float)x;
+    else d[k * nnzb + e] = x;
+  }
+}
+void to_planes(const DArr<double> &blk, int64_t nnzb, DArr<char> &dst, size_t sz, hipStream_t s) {
+  dst.alloc(std::max<int64_t>(nnzb, 1) * 9 * sz, s);
+  if (nnzb <= 0) return;
+  k_planes<<<grid_for(nnzb, 256), 256, 0, s>>>(
+      blk.p, nnzb, sz == 4 ? reinterpret_cast<float *>(dst.p) : nullptr,
+      sz == 8 ? reinterpret_cast<double *>(dst.p) : nullptr);
+  KCHK();
+}
+
+mgr_amg_opts amg_defaults(mgr_amg_opts o) {
+  if (!(o.theta0 > 0)) o.theta0 = 0.08;
+  if (o.max_levels <= 0) o.max_levels = 10;
+  if (o.coarse_size <= 0) o.coarse_size = 256;
+  return o;
+}
+
+// AMG hierarchy on A (moved in); bs = 1 or 3
+void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipStream_t s,
+               int *dflag) {
+  o = amg_defaults(o);
+  require(o.coarse_size <= 4096, MGR_ERR_ARG, "coarse_size above 4096");
+  H.bs = bs;
+  H.lv.clear();
+  auto L0 = std::make_unique<AmgLevel>();
+  L0->A = std::move(A);
+  H.lv.push_back(std::move(L0));
+  for (int k = 0;; ++k) {
+    AmgLevel &L = *H.lv.back();
+    const int64_t n = L.A.n;
+    if (n <= o.coarse_size || k + 1 >= o.max_levels) break;
+    AmgGraph G;
+    strength_graph(L.A, bs, o.theta0 * std::ldexp(1.0, -k), G, s, dflag);
+    int64_t nagg = 0;
+    DArr<int> agg;
+    mis2_aggregate(G, k, agg, nagg, s);
+    const int64_t nc = nagg * bs;
+    if (nc == 0 || (double)nc > 0.8 * (double)n) break;
+    Csr T;
+    tentative(agg, n / bs, bs, nagg, T, s);
+    const double rho = gershgorin_rho(L.A, s, dflag);
+    const double omega = (4.0 / 3.0) / rho;
+    DArr<double> d(n, s), w(n, s);
+    diag_of(L.A, d.p, s);
+    omega_over_diag(d.p, omega, w.p, n, s);
+    Csr AT;
+    spgemm(L.A, T, AT, s, dflag);
+    merge_drop(T, AT, w.p, -1, nullptr, L.P, true, s, dflag);
+    transpose(L.P, L.R, true, s);
+    Csr AP;
+    spgemm(L.A, L.P, AP, s, dflag);
+    auto N = std::make_unique<AmgLevel>();
+    spgemm(L.R, AP, N->A, s, dflag);
+    L.agg = std::move(agg);
+    L.nagg = nagg;
+    L.omega = omega;
+    H.lv.push_back(std::move(N));
+  }
+  // coarsest: dense inverse
+  AmgLevel &C = *H.lv.back();
+  require(C.A.n <= 4096, MGR_ERR_UNSUPPORTED,
+          "AMG coarsest level above 4096 unknowns (coarsening stalled)");
+  H.nc = (int)C.A.n;
+  DArr<double> D((size_t)H.nc * H.nc, s);
+  H.cinv64.alloc((size_t)H.nc * H.nc, s);
+  csr_to_dense(C.A, D.p, s);
+  dense_inverse(D.p, H.cinv64.p, H.nc, dflag, s);
+  // apply copies
+  const size_t sz = esz(mo);
+  for (size_t k = 0; k + 1 < H.lv.size(); ++k) {
+    AmgLevel &L = *H.lv[k];
+    L.dinv.alloc(L.A.n, s);
+    l1_inverse(L.A, L.dinv.p, s);
+    cast_values(L.dinv.p, L.tdinv, L.A.n, sz, s);
+    if (bs == 3) {
+      DArr<double> bv;
+      csr_to_bsr3(L.A, L.Ab_rp, L.Ab_ci, bv, L.nb, L.ncb, L.Ab_nnzb, s, dflag);
+      to_planes(bv, L.Ab_nnzb, L.tA, sz, s);
+      int64_t a, b;
+      csr_to_bsr3(L.P, L.Pb_rp, L.Pb_ci, bv, a, b, L.Pb_nnzb, s, dflag);
+      to_planes(bv, L.Pb_nnzb, L.tP, sz, s);
+      csr_to_bsr3(L.R, L.Rb_rp, L.Rb_ci, bv, a, b, L.Rb_nnzb, s, dflag);
+      to_planes(bv, L.Rb_nnzb, L.tR, sz, s);
+    } else {
+      cast_values(L.A.v.p, L.tA, L.A.nnz, sz, s);
+      cast_values(L.P.v.p, L.tP, L.P.nnz, sz, s);
+      cast_values(L.R.v.p, L.tR, L.R.nnz, sz, s);
+    }
+    L.x.alloc(L.A.n * sz, s);
+    L.r.alloc(L.A.n * sz, s);
+    L.y.alloc(L.A.n * sz, s);
+    L.b.alloc(L.A.n * sz, s);
+  }
+  {
+    AmgLevel &Lc = *H.lv.back();
+    Lc.y.alloc(std::max<int64_t>(Lc.A.n, 1) * sz, s);
+    Lc.b.alloc(std::max<int64_t>(Lc.A.n, 1) * sz, s);
+  }
+  cast_values(H.cinv64.p, H.tcinv, (int64_t)H.nc * H.nc, sz, s);
+  if (!mo.keep_setup) {
+    // the V-cycle only needs the apply copies (scalar levels still share the CSR pattern)
+    for (size_t k = 0; k < H.lv.size(); ++k) {
+      AmgLevel &L = *H.lv[k];
+      L.A.v.reset();
+      L.P.v.reset();
+      L.R.v.reset();
+      L.dinv.reset();
+      if (bs == 3 || k + 1 == H.lv.size()) {
+        L.A.rp.reset(); L.A.ci.reset();
+        L.P.rp.reset(); L.P.ci.reset();
+        L.R.rp.reset(); L.R.ci.reset();
+      }
+    }
+    H.cinv64.reset();
+  }
+}
+
+// ------------------------------------------------------------------------------------
+template <class T>
+CsrV<T> view(const Csr &M, const DArr<char> &tv) {
+  CsrV<T> v;
+  v.n = M.n; v.m = M.m; v.nnz = M.nnz;
+  v.rp = M.rp.p; v.ci = M.ci.p;
+  v.v = reinterpret_cast<const T *>(tv.p);
+  return v;
+}
+template <class T>
+CsrV<T> view64(const Csr &M) {
+  CsrV<T> v;
+  v.n = M.n; v.m = M.m; v.nnz = M.nnz;
+  v.rp = M.rp.p; v.ci = M.ci.p;
+  v.v = reinterpret_cast<const T *>(M.v.p);
+  return v;
+}
+template <class T>
+Bsr3V<T> bview(int64_t n, int64_t m, int64_t nnzb, const DArr<int> &rp, const DArr<int> &ci,
+               const DArr<char> &tv) {
+  Bsr3V<T> v;
+  v.n = n; v.m = m; v.nnzb = nnzb;
+  v.rp = rp.p; v.ci = ci.p;
+  v.v = reinterpret_cast<const T *>(tv.p);
+  return v;
+}
+
+// V-cycle from x = 0: y = V(b); y must not alias b
+template <class T>
+void vcycle(const Amg &H, size_t k, const T *b, T *y, hipStream_t s) {
+  using V = VecOps<T>;
+  if (k + 1 == H.lv.size()) {
+    V::gemv(Ptr<T>::of(H.tcinv), H.nc, b, y, s);
+    return;
+  }
+  const AmgLevel &L = *H.lv[k];
+  const AmgLevel &N = *H.lv[k + 1];
+  T *x = Ptr<T>::of(L.x), *r = Ptr<T>::of(L.r);
+  T *bc = Ptr<T>::of(N.b), *yc = Ptr<T>::of(N.y);
+  const T *dinv = Ptr<T>::of(L.tdinv);
+  if (H.bs == 3) {
+    auto A = bview<T>(L.nb, L.nb, L.Ab_nnzb, L.Ab_rp, L.Ab_ci, L.tA);
+    auto P = bview<T>(L.nb, L.ncb, L.Pb_nnzb, L.Pb_rp, L.Pb_ci, L.tP);
+    auto R = bview<T>(N.A.n / 3, L.nb, L.Rb_nnzb, L.Rb_rp, L.Rb_ci, L.tR);
+    const double sweep_bytes =
+        (double)L.Ab_nnzb * (9 * sizeof(T) + 4) + (double)(L.nb + 1) * 4 + (double)L.A.n * sizeof(T) * 4;
+    const bool prof = k == 0 && Prof::on(0);
+    if (prof) Prof::begin(0, s);
+    V::b_l1_pre(A, dinv, b, x, r, s);
+    if (prof) Prof::end(0, s, sweep_bytes + (double)L.A.n * sizeof(T));
+    V::b_spmv(R, r, bc, false, s);
+    vcycle<T>(H, k + 1, bc, yc, s);
+    V::b_spmv(P, yc, x, true, s);
+    if (prof) Prof::begin(0, s);
+    V::b_l1_post(A, dinv, b, x, y, s);
+    if (prof) Prof::end(0, s, sweep_bytes + (double)L.A.n * sizeof(T));
+  } else {
+    auto A = view<T>(L.A, L.tA);
+    auto P = view<T>(L.P, L.tP);
+    auto R = view<T>(L.R, L.tR);
+    V::l1_pre(A, dinv, b, x, r, s);
+    V::spmv(R, r, bc, false, s);
+    vcycle<T>(H, k + 1, bc, yc, s);
+    V::spmv(P, yc, x, true, s);
+    V::l1_post(A, dinv, b, x, y, s);
+  }
+}
+
+}  // namespace
+
+// Algorithm 2 at level l: z = M_l^{-1} v
+template <class T>
+void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
+  using V = VecOps<T>;
+  if (l == h->lv.size()) {
+    if (h->opts.coarse == MGR_COARSE_DENSE) V::gemv(Ptr<T>::of(h->tcdense), h->ncd, v, z, s);
+    else vcycle<T>(h->coarse_amg, 0, v, z, s);
+    return;
+  }
+  MgrLevel &L = *h->lv[l];
+  const mgr_level_opts &o = h->opts.level[l];
+  MgrLevel *N = (l + 1 < h->lv.size()) ? h->lv[l + 1].get() : nullptr;
+  const int64_t n = L.A.n, nF = L.cf.nF, nC = L.cf.nC;
+  const bool fp64 = sizeof(T) == 8;
+  CsrV<T> A = fp64 ? view64<T>(L.A) : view<T>(L.A, L.tA);
+  CsrV<T> Acf = fp64 ? view64<T>(L.Acf) : view<T>(L.Acf, L.tAcf);
+  CsrV<T> Wp = fp64 ? view64<T>(L.Wp) : view<T>(L.Wp, L.tWp);
+  T *rF = Ptr<T>::of(L.rF), *eF = Ptr<T>::of(L.eF);
+  // the next level's input/output vectors (the coarsest grid uses this level's buffer)
+  T *rC = N ? Ptr<T>::of(N->v) : Ptr<T>::of(L.rfull);
+  T *eC = N ? Ptr<T>::of(N->z) : Ptr<T>::of(L.rfull) + nC;
+  bool zero_z = true;
+  // global relaxation (block Jacobi over same-cell blocks)
+  if (o.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI) {
+    const T *binv = Ptr<T>::of(L.tbinv);
+    V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, v, (T)1, z, false, s);
+    for (int sw = 1; sw < o.global_sweeps; ++sw) {
+      T *r = Ptr<T>::of(L.rfull) + 2 * nC;
+      V::resid(A, n, nullptr, nullptr, z, v, r, s);
+      V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, r, (T)o.global_omega, z, true, s);
+    }
+    zero_z = false;
+  }
+  bool compactF = false;  // z_F held in eF, z otherwise untouched (z_C = 0)
+  const T *dinvF = Ptr<T>::of(L.tdinvF);
+  if (o.frelax == MGR_FRELAX_JACOBI) {
+    int sw0 = 0;
+    if (zero_z) {
+      V::jacobi_first(n, L.cf.map.p, dinvF, (T)o.frelax_omega, v, z, s);
+      sw0 = 1;
+      zero_z = false;
+    }
+    for (int sw = sw0; sw < o.frelax_sweeps; ++sw) {
+      V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      V::jacobi_update(L.cf.F.p, nF, dinvF, (T)o.frelax_omega, rF, z, s);
+    }
+  } else {
+    const T *rin;
+    if (zero_z) {
+      if (L.f_prefix) rin = v;
+      else { V::gather(L.cf.F.p, nF, v, rF, s); rin = rF; }
+    } else {
+      V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      rin = rF;
+    }
+    if (o.frelax == MGR_FRELAX_AMG) vcycle<T>(L.amg, 0, rin, eF, s);
+    else V::gemv(Ptr<T>::of(L.tffinv), L.nF, rin, eF, s);
+    if (zero_z) compactF = true;
+    else V::scatter_add(L.cf.F.p, nF, eF, z, s);
+  }
+  // restrict the residual by injection
+  if (compactF) V::resid(Acf, nC, nullptr, L.cf.C.p, eF, v, rC, s);
+  else V::resid(A, nC, L.cf.C.p, L.cf.C.p, z, v, rC, s);
+  apply_level<T>(h, l + 1, rC, eC, s);
+  // interpolate and correct
+  V::interp(n, L.cf.map.p, Wp, eC, compactF ? eF : nullptr, z, !compactF, s);
+}
+
+namespace {
+
+template <class T>
+void apply_typed(mgr_handle *h, const double *v, double *z, hipStream_t s) {
+  T *v0 = Ptr<T>::of(h->v0), *z0 = Ptr<T>::of(h->z0);
+  cast_to(v, v0, h->n, s);
+  const bool prof = Prof::on(0);
+  if (h->opts.use_graph && !prof) {
+    if (!h->gexec) {
+      if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+      try {
+        apply_level<T>(h, 0, v0, z0, h->cap);
+      } catch (...) {
+        hipGraph_t g;
+        (void)hipStreamEndCapture(h->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(h->cap, &h->graph));
+      HIPCHK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(h->gexec, s));
+  } else {
+    apply_level<T>(h, 0, v0, z0, s);
+  }
+  cast_from(z0, z, h->n, s);
+}
+
+void destroy_graph(mgr_handle *h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+}
+
+std::vector<int8_t> host_labels(const int8_t *d, int64_t n, hipStream_t s) {
+  std::vector<int8_t> h(n);
+  if (n) HIPCHK(hipMemcpyAsync(h.data(), d, n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return h;
+}
+
+// number of labels if the rows are interleaved cell by cell (labels periodic with distinct
+// labels inside one period), else 0
+int interleave_period(const std::vector<int8_t> &lab) {
+  if (lab.empty()) return 0;
+  int present[8] = {0};
+  for (int8_t t : lab) present[t & 7] = 1;
+  int nb = 0;
+  for (int t = 0; t < 8; ++t) nb += present[t];
+  if (nb < 1 || nb > 3 || lab.size() % nb) return 0;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < i; ++j)
+      if (lab[i] == lab[j]) return 0;
+  for (size_t i = 0; i < lab.size(); ++i)
+    if (lab[i] != lab[i % nb]) return 0;
+  return nb;
+}
+
+void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
+  hipStream_t s = h->s;
+  int *flag = h->dflag.p;
+  const mgr_opts &o = h->opts;
+  const size_t sz = esz(o);
+  Csr cur;
+  import_csr(Ain, cur, s, flag);
+  require(cur.n == cur.m, MGR_ERR_ARG, "A must be square");
+  h->n = cur.n;
+  h->pattern = pattern_hash(cur, s);
+  DArr<int8_t> lab(std::max<int64_t>(cur.n, 1), s);
+  if (cur.n) HIPCHK(hipMemcpyAsync(lab.p, labels_in, cur.n, hipMemcpyDeviceToDevice, s));
+  for (int l = 0; l < o.nlevels; ++l) {
+    const mgr_level_opts &lo = o.level[l];
+    auto L = std::make_unique<MgrLevel>();
+    L->A = std::move(cur);
+    L->labels = std::move(lab);
+    const int64_t n = L->A.n;
+    std::vector<int8_t> hl = host_labels(L->labels.p, n, s);
+    for (int8_t t : hl) require(t >= 0 && t <= 7, MGR_ERR_ARG, "labels must lie in [0, 7]");
+    cf_split(L->labels.p, n, lo.f_label_mask, L->cf, s, flag);
+    L->nF = (int)L->cf.nF;
+    {
+      int last = -1;
+      HIPCHK(hipMemcpyAsync(&last, L->cf.F.p + L->cf.nF - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      L->f_prefix = last == L->cf.nF - 1;
+    }
+    const int64_t nC = L->cf.nC;
+    DArr<int8_t> labC(nC, s);
+    gather_labels(L->labels.p, L->cf.C.p, nC, labC.p, s);
+    DArr<int> lrankC;
+    if (lo.nmax_drop >= 0) label_rank(labC.p, nC, lrankC, s);
+    const bool need_ff = lo.frelax != MGR_FRELAX_JACOBI;
+    Csr Aff, Afc, Acc;
+    L->dFF.alloc(L->cf.nF, s);
+    extract_blocks(L->A, L->cf, need_ff ? &Aff : nullptr, Afc, L->Acf, Acc, L->dFF.p, s);
+    check_nonzero(L->dFF.p, L->cf.nF, flag, s);
+    require(read_flag(flag, s) == 0, MGR_ERR_ZERO_PIVOT, "zero or missing diagonal in A_FF");
+    // W_p = -D_FF^{-1} A_FC (eq. injective_rp); M = -W_p
+    Csr M;
+    if (lo.interp == MGR_INTERP_JACOBI) {
+      M = std::move(Afc);
+      scale_rows_div(M, L->dFF.p, s);
+    } else {
+      M.n = L->cf.nF;
+      M.m = nC;
+      M.nnz = 0;
+      M.rp.alloc(M.n + 1, s);
+      fill<int>(M.rp.p, 0, M.n + 1, s);
+    }
+    Csr Acor;
+    spgemm(L->Acf, M, Acor, s, flag);
+    Csr S;
+    merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag);
+    if (o.keep_setup) {
+      if (lo.nmax_drop >= 0) drop_only(Acor, lo.nmax_drop, lrankC.p, L->G, s, flag);
+      else copy_csr(Acor, L->G, s);
+      L->Acor = std::move(Acor);
+    }
+    negate_f64(M.v.p, M.nnz, s);
+    L->Wp = std::move(M);
+    // F-relaxation solvers
+    if (lo.frelax == MGR_FRELAX_AMG) {
+      require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
+      amg_setup(std::move(Aff), lo.frelax_block, o.amg_frelax, L->amg, o, s, flag);
+    } else if (lo.frelax == MGR_FRELAX_DENSE) {
+      require(L->cf.nF <= 4096, MGR_ERR_UNSUPPORTED, "dense F-relaxation limited to 4096 rows");
+      DArr<double> D(L->cf.nF * L->cf.nF, s);
+      L->ffinv64.alloc(L->cf.nF * L->cf.nF, s);
+      csr_to_dense(Aff, D.p, s);
+      dense_inverse(D.p, L->ffinv64.p, (int)L->cf.nF, flag, s);
+      cast_values(L->ffinv64.p, L->tffinv, L->cf.nF * L->cf.nF, sz, s);
+    }
+    // global smoother
+    if (lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI) {
+      const int nb = interleave_period(hl);
+      require(nb >= 2, MGR_ERR_UNSUPPORTED,
+              "block-Jacobi smoother needs rows interleaved cell by cell (2 or 3 unknowns)");
+      L->nb_gs = nb;
+      L->binv64.alloc(n * nb, s);
+      block_diag_inverse(L->A, nb, L->binv64.p, s, flag);
+      cast_values(L->binv64.p, L->tbinv, n * nb, sz, s);
+    }
+    // apply copies and work vectors
+    DArr<double> dinvF(L->cf.nF, s);
+    omega_over_diag(L->dFF.p, 1.0, dinvF.p, L->cf.nF, s);  // 1 / d_F
+    cast_values(dinvF.p, L->tdinvF, L->cf.nF, sz, s);
+    if (sz == 4) {
+      cast_values(L->A.v.p, L->tA, L->A.nnz, sz, s);
+      cast_values(L->Acf.v.p, L->tAcf, L->Acf.nnz, sz, s);
+      cast_values(L->Wp.v.p, L->tWp, L->Wp.nnz, sz, s);
+    }
+    L->rF.alloc(std::max<int64_t>(L->cf.nF, 1) * sz, s);
+    L->eF.alloc(std::max<int64_t>(L->cf.nF, 1) * sz, s);
+    L->v.alloc(std::max<int64_t>(n, 1) * sz, s);
+    L->z.alloc(std::max<int64_t>(n, 1) * sz, s);
+    L->rfull.alloc(std::max<int64_t>(2 * nC + n, 1) * sz, s);
+    cur = std::move(S);
+    lab = std::move(labC);
+    h->lv.push_back(std::move(L));
+  }
+  // coarsest grid
+  const int64_t nc = cur.n;
+  if (o.coarse == MGR_COARSE_DENSE) {
+    require(nc <= 4096, MGR_ERR_UNSUPPORTED, "dense coarse solve limited to 4096 unknowns");
+    h->ncd = (int)nc;
+    DArr<double> D(nc * nc, s);
+    h->cdense64.alloc(nc * nc, s);
+    csr_to_dense(cur, D.p, s);
+    dense_inverse(D.p, h->cdense64.p, (int)nc, flag, s);
+    cast_values(h->cdense64.p, h->tcdense, nc * nc, sz, s);
+    if (o.keep_setup) h->coarseA = std::move(cur);
+  } else {
+    Csr keep;
+    if (o.keep_setup) copy_csr(cur, keep, s);
+    amg_setup(std::move(cur), 1, o.amg_coarse, h->coarse_amg, o, s, flag);
+    if (o.keep_setup) h->coarseA = std::move(keep);
+  }
+  h->coarse_labels = std::move(lab);
+  h->v0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
+  h->z0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
+  // level 0 input / output are the handle vectors; release what apply does not need
+  if (!o.keep_setup) {
+    for (auto &L : h->lv) {
+      if (sz == 4) {
+        L->A.v.reset();
+        L->Acf.v.reset();
+        L->Wp.v.reset();
+        L->binv64.reset();
+        L->ffinv64.reset();
+      }
+      L->dFF.reset();
+    }
+    if (sz == 4) h->cdense64.reset();
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  require(read_flag(flag, s) == 0, MGR_ERR_ZERO_PIVOT, "setup flagged an invalid pivot");
+}
+
+void validate_opts(const mgr_opts &o) {
+  require(o.nlevels >= 0 && o.nlevels <= MGR_MAX_LEVELS, MGR_ERR_ARG, "nlevels out of range");
+  require(o.precision == MGR_PREC_FP64 || o.precision == MGR_PREC_FP32, MGR_ERR_ARG, "precision");
+  require(o.coarse == MGR_COARSE_AMG || o.coarse == MGR_COARSE_DENSE, MGR_ERR_ARG, "coarse");
+  for (int l = 0; l < o.nlevels; ++l) {
+    const mgr_level_opts &lo = o.level[l];
+    require(lo.f_label_mask != 0 && (lo.f_label_mask >> 8) == 0, MGR_ERR_ARG, "f_label_mask");
+    require(lo.interp == MGR_INTERP_JACOBI || lo.interp == MGR_INTERP_ZERO, MGR_ERR_ARG, "interp");
+    require(lo.frelax >= 0 && lo.frelax <= 2, MGR_ERR_ARG, "frelax");
+    require(lo.frelax_sweeps >= 1 && lo.frelax_sweeps <= 100, MGR_ERR_ARG, "frelax_sweeps");
+    require(lo.global_smoother == 0 || lo.global_smoother == 1, MGR_ERR_ARG, "global_smoother");
+    require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
+  }
+}
+
+size_t handle_bytes(const mgr_handle *h) {
+  size_t b = 0;
+  auto csr = [&](const Csr &M) { b += M.bytes(); };
+  auto amg = [&](const Amg &H) {
+    for (auto &L : H.lv) {
+      csr(L->A); csr(L->P); csr(L->R);
+      b += L->agg.bytes() + L->dinv.bytes() + L->Ab_rp.bytes() + L->Ab_ci.bytes() +
+           L->Pb_rp.bytes() + L->Pb_ci.bytes() + L->Rb_rp.bytes() + L->Rb_ci.bytes() +
+           L->tA.bytes() + L->tP.bytes() + L->tR.bytes() + L->tdinv.bytes() + L->x.bytes() +
+           L->r.bytes() + L->b.bytes() + L->y.bytes();
+    }
+    b += H.cinv64.bytes() + H.tcinv.bytes();
+  };
+  for (auto &L : h->lv) {
+    csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G);
+    b += L->labels.bytes() + L->cf.F.bytes() + L->cf.C.bytes() + L->cf.map.bytes() +
+         L->dFF.bytes() + L->binv64.bytes() + L->ffinv64.bytes() + L->tA.bytes() +
+         L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
+         L->tffinv.bytes() + L->v.bytes() + L->z.bytes() + L->rF.bytes() + L->eF.bytes() +
+         L->rfull.bytes();
+    amg(L->amg);
+  }
+  csr(h->coarseA);
+  amg(h->coarse_amg);
+  b += h->cdense64.bytes() + h->tcdense.bytes() + h->v0.bytes() + h->z0.bytes() +
+       h->coarse_labels.bytes() + h->labels0.bytes();
+  return b;
+}
+
+mgr_status fail(const Error &e) {
+  t_err = e.what();
+  return e.st;
+}
+
+}  // namespace
+}  // namespace mgr
+
+mgr_handle::~mgr_handle() {
+  if (s) (void)hipStreamSynchronize(s);
+  mgr::destroy_graph(this);
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
+// ===================================================================================
+// FGMRES
+namespace mgr {
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct FgWork {
+  double *V, *Z, *w, *r, *partial, *H, *cs, *sn, *g, *h1, *h2, *hn2, *scal, *y, *red;
+};
+
+size_t fg_layout(int64_t n, int m, char *base, FgWork *w) {
+  size_t off = 0;
+  auto take = [&](double **p, size_t count) {
+    if (w) *p = reinterpret_cast<double *>(base + off);
+    off += align256(count * sizeof(double));
+  };
+  FgWork tmp;
+  FgWork *W = w ? w : &tmp;
+  take(&W->V, (size_t)(m + 1) * n);
+  take(&W->Z, (size_t)m * n);
+  take(&W->w, n);
+  take(&W->r, n);
+  take(&W->partial, (size_t)krylov_partials_blocks());
+  take(&W->H, (size_t)(m + 1) * m);
+  take(&W->cs, m + 1);
+  take(&W->sn, m + 1);
+  take(&W->g, m + 2);
+  take(&W->h1, 80);
+  take(&W->h2, 80);
+  take(&W->hn2, 8);
+  take(&W->scal, 8);
+  take(&W->y, m + 1);
+  take(&W->red, 8);
+  return off;
+}
+
+double host_norm(const double *r, int64_t n, FgWork &W, hipStream_t s) {
+  norm2_partials(r, n, W.partial, s);
+  reduce_partials(W.partial, 1, W.red, false, s);
+  double v = 0.0;
+  HIPCHK(hipMemcpyAsync(&v, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return std::sqrt(v);
+}
+
+mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
+                       const fgmres_opts *o, void *work, size_t work_bytes, fgmres_result *res,
+                       hipStream_t s) {
+  require(A && b && x && o, MGR_ERR_ARG, "null argument");
+  const int64_t n = A->nrows;
+  const int m = o->restart;
+  require(m >= 1 && m <= 64, MGR_ERR_ARG, "restart must be in [1, 64]");
+  require(o->maxit >= 1, MGR_ERR_ARG, "maxit must be positive");
+  require(!M || M->n == n, MGR_ERR_ARG, "preconditioner size differs from A");
+  const size_t need = fg_layout(n, m, nullptr, nullptr);
+  DArr<char> own;
+  char *base = static_cast<char *>(work);
+  if (!base) {
+    own.alloc(need, s);
+    base = own.p;
+  } else {
+    require(work_bytes >= need, MGR_ERR_ARG, "fgmres workspace too small");
+  }
+  FgWork W;
+  fg_layout(n, m, base, &W);
+  int64_t nnz = 0;
+  if (n) {
+    HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  const double avg = n ? (double)nnz / (double)n : 0.0;
+  const double spmv_bytes = (double)nnz * 12.0 + (double)n * (8.0 + 8.0 + 8.0);
+  auto matvec = [&](const double *xx, const double *bb, double *yy) {
+    const bool prof = Prof::on(1);
+    if (prof) Prof::begin(1, s);
+    spmv64_avg(*A, xx, bb, yy, avg, s);
+    if (prof) Prof::end(1, s, spmv_bytes + (bb ? (double)n * 8.0 : 0.0));
+  };
+  const double bnorm = host_norm(b, n, W, s);
+  fgmres_result R{};
+  if (res) { R.history = res->history; R.history_cap = res->history_cap; }
+  auto push = [&](double v) {
+    if (R.history && R.history_len < R.history_cap) R.history[R.history_len++] = v;
+  };
+  if (bnorm == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    R.converged = 1;
+    if (res) *res = R;
+    return MGR_OK;
+  }
+  const double tol = o->rtol * bnorm;
+  const int ldh = m + 1;
+  int its = 0;
+  bool first = true;
+  for (;;) {
+    matvec(x, b, W.r);  // r = b - A x
+    const double beta = host_norm(W.r, n, W, s);
+    R.true_relres = beta / bnorm;
+    push(beta / bnorm);
+    if (beta <= tol) { R.converged = 1; break; }
+    if (its >= o->maxit || !std::isfinite(beta)) break;
+    if (!first) ++R.restarts;
+    first = false;
+    start_cycle_host_beta(W.r, beta, W.V, W.g, n, m + 1, s);
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double *vj = W.V + (int64_t)j * n;
+      double *zj = W.Z + (int64_t)j * n;
+      if (M) {
+        if (M->opts.precision == MGR_PREC_FP32) apply_typed<float>(M, vj, zj, s);
+        else apply_typed<double>(M, vj, zj, s);
+      } else {
+        HIPCHK(hipMemcpyAsync(zj, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+      matvec(zj, nullptr, W.w);
+      ++its;
+      // classical Gram-Schmidt, twice
+      multidot_partials(W.V, n, j + 1, W.w, W.partial, s);
+      reduce_partials(W.partial, j + 1, W.h1, false, s);
+      cgs_update_partials(W.V, n, j + 1, W.h1, W.w, W.partial, false, s);
+      reduce_partials(W.partial, j + 1, W.h2, false, s);
+      cgs_update_partials(W.V, n, j + 1, W.h2, W.w, W.partial, true, s);
+      reduce_partials(W.partial, 1, W.hn2, false, s);
+      givens_step(W.H, W.cs, W.sn, W.g, W.h1, W.h2, W.hn2, j, ldh, W.scal, nullptr, s);
+      double sc[3];
+      HIPCHK(hipMemcpyAsync(sc, W.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      R.est_relres = sc[0] / bnorm;
+      push(R.est_relres);
+      k = j + 1;
+      if (sc[0] <= tol || sc[1] == 0.0 || its >= o->maxit || !std::isfinite(sc[0])) break;
+      scale_vec(W.w, W.scal + 2, W.V + (int64_t)(j + 1) * n, n, s);
+    }
+    tri_solve_and_update(W.H, W.g, k, ldh, W.Z, n, x, W.y, s);
+  }
+  R.iters = its;
+  HIPCHK(hipStreamSynchronize(s));
+  if (res) {
+    double *hist = res->history;
+    int cap = res->history_cap;
+    *res = R;
+    res->history = hist;
+    res->history_cap = cap;
+  }
+  if (!R.converged) {
+    t_err = "fgmres: not converged";
+    return MGR_ERR_NOT_CONVERGED;
+  }
+  return MGR_OK;
+}
+}  // namespace
+}  // namespace mgr
+
+// ===================================================================================
+// C ABI
+using namespace mgr;
+
+extern "C" {
+
+void mgr_default_opts(mgr_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nlevels = 0;
+  o->coarse = MGR_COARSE_AMG;
+  o->amg_frelax = mgr_amg_opts{0.08, 10, 256};
+  o->amg_coarse = mgr_amg_opts{0.08, 10, 256};
+  o->precision = MGR_PREC_FP64;
+  o->use_graph = 1;
+  o->keep_setup = 0;
+  for (int l = 0; l < MGR_MAX_LEVELS; ++l) {
+    mgr_level_opts &L = o->level[l];
+    L.f_label_mask = 0;
+    L.interp = MGR_INTERP_JACOBI;
+    L.nmax_drop = -1;
+    L.frelax = MGR_FRELAX_JACOBI;
+    L.frelax_sweeps = 1;
+    L.frelax_omega = 1.0;
+    L.frelax_block = 1;
+    L.global_smoother = MGR_GSMOOTH_NONE;
+    L.global_sweeps = 1;
+    L.global_omega = 1.0;
+  }
+}
+
+mgr_status mgr_setup(const mgr_csr *A, const int8_t *labels, const mgr_opts *opts, void *stream,
+                     mgr_handle **out) {
+  t_err.clear();
+  if (!A || !labels || !opts || !out) { t_err = "null argument"; return MGR_ERR_ARG; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::unique_ptr<mgr_handle> h(new mgr_handle());
+  try {
+    validate_opts(*opts);
+    require(A->nrows >= 1, MGR_ERR_ARG, "empty matrix");
+    h->opts = *opts;
+    h->s = s;
+    h->dflag.alloc(1, s);
+    clear_flag(h->dflag.p, s);
+    h->labels0.alloc(A->nrows, s);
+    HIPCHK(hipMemcpyAsync(h->labels0.p, labels, A->nrows, hipMemcpyDeviceToDevice, s));
+    build(h.get(), A, labels);
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (const std::exception &e) {
+    t_err = e.what();
+    return MGR_ERR_HIP;
+  }
+  *out = h.release();
+  return MGR_OK;
+}
+
+mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
+  t_err.clear();
+  if (!h || !A) { t_err = "null argument"; return MGR_ERR_ARG; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    require(A->nrows == h->n, MGR_ERR_PATTERN, "size differs from the original matrix");
+    {
+      Csr tmp;
+      import_csr(A, tmp, s, h->dflag.p);
+      require(pattern_hash(tmp, s) == h->pattern, MGR_ERR_PATTERN,
+              "sparsity pattern differs from the original matrix");
+    }
+    HIPCHK(hipStreamSynchronize(h->s));
+    destroy_graph(h);
+    h->lv.clear();
+    h->coarseA = Csr();
+    h->coarse_amg = Amg();
+    h->cdense64.reset();
+    h->tcdense.reset();
+    h->s = s;
+    clear_flag(h->dflag.p, s);
+    DArr<int8_t> lab(h->n, s);
+    HIPCHK(hipMemcpyAsync(lab.p, h->labels0.p, h->n, hipMemcpyDeviceToDevice, s));
+    build(h, A, lab.p);
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (const std::exception &e) {
+    t_err = e.what();
+    return MGR_ERR_HIP;
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_apply(mgr_handle *h, const double *v, double *z, void *stream) {
+  t_err.clear();
+  if (!h || !v || !z) { t_err = "null argument"; return MGR_ERR_ARG; }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (h->opts.precision == MGR_PREC_FP32) apply_typed<float>(h, v, z, s);
+    else apply_typed<double>(h, v, z, s);
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+size_t fgmres_workspace_bytes(int64_t n, int32_t restart) {
+  return fg_layout(n, restart, nullptr, nullptr);
+}
+
+mgr_status fgmres_solve(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
+                        const fgmres_opts *o, void *work, size_t work_bytes, fgmres_result *res,
+                        void *stream) {
+  t_err.clear();
+  try {
+    return fgmres_impl(A, M, b, x, o, work, work_bytes, res, static_cast<hipStream_t>(stream));
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+void mgr_destroy(mgr_handle *h) { delete h; }
+
+mgr_status mgr_footprint(const mgr_handle *h, size_t *bytes) {
+  if (!h || !bytes) { t_err = "null argument"; return MGR_ERR_ARG; }
+  *bytes = handle_bytes(h);
+  return MGR_OK;
+}
+
+mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts, size_t *bytes) {
+  if (!opts || !bytes || n < 0 || nnz < 0) { t_err = "bad argument"; return MGR_ERR_ARG; }
+  // level matrices, products and AMG hierarchies stay below three copies of A in FP64 CSR
+  // plus the setup temporaries of one sparse product of the same size, and 48 vectors.
+  const double a = (double)nnz * 12.0 + (double)(n + 1) * 4.0;
+  double est = 4.0 * a + 48.0 * 8.0 * (double)n + (double)(4096.0 * 4096.0 * 8.0 * 2);
+  *bytes = (size_t)est;
+  return MGR_OK;
+}
+
+void mgr_set_allocator(void *(*alloc_fn)(size_t, void *, void *),
+                       void (*free_fn)(void *, void *, void *), void *ctx) {
+  g_alloc = alloc_fn;
+  g_free = free_fn;
+  g_ctx = ctx;
+}
+
+const char *mgr_last_error(void) { return t_err.c_str(); }
+
+mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t sub, int64_t out[3]) {
+  t_err.clear();
+  if (!h || !out) { t_err = "null argument"; return MGR_ERR_ARG; }
+  try {
+    const int nl = (int)h->lv.size();
+    require(level >= 0 && level <= nl, MGR_ERR_ARG, "level out of range");
+    const Amg *amg = nullptr;
+    if (what >= MGR_X_AMG_A) {
+      amg = level == nl ? &h->coarse_amg : &h->lv[level]->amg;
+      require(!amg->lv.empty(), MGR_ERR_ARG, "no AMG hierarchy at this level");
+      if (what == MGR_X_AMG_NLEV) { out[0] = (int64_t)amg->lv.size(); out[1] = out[2] = 0; return MGR_OK; }
+      require(sub >= 0 && sub < (int)amg->lv.size(), MGR_ERR_ARG, "AMG level out of range");
+    } else {
+      require(level < nl || what == MGR_X_LEVEL_A, MGR_ERR_ARG, "level out of range");
+    }
+    auto csr = [&](const Csr &M) {
+      require(M.v.p != nullptr || M.nnz == 0, MGR_ERR_ARG, "object not kept (set keep_setup)");
+      out[0] = M.n; out[1] = M.m; out[2] = M.nnz;
+    };
+    switch (what) {
+      case MGR_X_LEVEL_A: csr(level == nl ? h->coarseA : h->lv[level]->A); break;
+      case MGR_X_F: out[0] = h->lv[level]->cf.nF; out[1] = 0; out[2] = out[0]; break;
+      case MGR_X_C: out[0] = h->lv[level]->cf.nC; out[1] = 0; out[2] = out[0]; break;
+      case MGR_X_WP: csr(h->lv[level]->Wp); break;
+      case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
+      case MGR_X_G: csr(h->lv[level]->G); break;
+      case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
+      case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;
+      case MGR_X_AMG_P:
+        require(sub + 1 < (int)amg->lv.size(), MGR_ERR_ARG, "coarsest AMG level has no P");
+        csr(amg->lv[sub]->P);
+        break;
+      case MGR_X_AMG_AGG:
+        require(sub + 1 < (int)amg->lv.size(), MGR_ERR_ARG, "coarsest AMG level has no aggregates");
+        out[0] = amg->lv[sub]->A.n / amg->bs; out[1] = amg->lv[sub]->nagg; out[2] = out[0];
+        break;
+      default: throw Error(MGR_ERR_ARG, "unknown object");
+    }
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t sub,
+                      int64_t *row_ptr, int32_t *col, double *val, void *stream) {
+  int64_t sz[3];
+  mgr_status st = mgr_query(h, what, level, sub, sz);
+  if (st != MGR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    const int nl = (int)h->lv.size();
+    auto ints = [&](const int *src, int64_t n) {
+      if (col && n) HIPCHK(hipMemcpyAsync(col, src, n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    };
+    auto csr = [&](const Csr &M) {
+      if (row_ptr) rowptr32_to_64(M.rp.p, row_ptr, M.n + 1, s);
+      ints(M.ci.p, M.nnz);
+      if (val && M.nnz)
+        HIPCHK(hipMemcpyAsync(val, M.v.p, M.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    };
+    const Amg *amg = (what >= MGR_X_AMG_A) ? (level == nl ? &h->coarse_amg : &h->lv[level]->amg) : nullptr;
+    switch (what) {
+      case MGR_X_LEVEL_A: csr(level == nl ? h->coarseA : h->lv[level]->A); break;
+      case MGR_X_F: ints(h->lv[level]->cf.F.p, sz[0]); break;
+      case MGR_X_C: ints(h->lv[level]->cf.C.p, sz[0]); break;
+      case MGR_X_WP: csr(h->lv[level]->Wp); break;
+      case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
+      case MGR_X_G: csr(h->lv[level]->G); break;
+      case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
+      case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;
+      case MGR_X_AMG_P: csr(amg->lv[sub]->P); break;
+      case MGR_X_AMG_AGG: ints(amg->lv[sub]->agg.p, sz[0]); break;
+      default: break;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_spmv(const mgr_csr *A, const double *x, double *y, void *stream) {
+  t_err.clear();
+  if (!A || !x || !y) { t_err = "null argument"; return MGR_ERR_ARG; }
+  try {
+    spmv64(*A, x, y, static_cast<hipStream_t>(stream));
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_stream_copy(const double *src, double *dst, int64_t n, void *stream) {
+  t_err.clear();
+  try {
+    stream_copy_f64(src, dst, n, static_cast<hipStream_t>(stream));
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_profile_enable(int32_t family, int32_t enable) {
+  if (family < 0 || family > 1) { t_err = "family"; return MGR_ERR_ARG; }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof[family].on = enable != 0;
+  g_prof[family].used = 0;
+  return MGR_OK;
+}
+
+mgr_status mgr_profile_read(int32_t family, int64_t *launches, double *total_ms, double *bytes) {
+  if (family < 0 || family > 1) { t_err = "family"; return MGR_ERR_ARG; }
+  try {
+    ProfFamily &P = g_prof[family];
+    double ms = 0.0, by = 0.0;
+    for (size_t i = 0; i < P.used; ++i) {
+      HIPCHK(hipEventSynchronize(P.ev[i].second));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, P.ev[i].first, P.ev[i].second));
+      ms += t;
+      by += P.bytes[i];
+    }
+    if (launches) *launches = (int64_t)P.used;
+    if (total_ms) *total_ms = ms;
+    if (bytes) *bytes = by;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+  return MGR_OK;
+}
+
+}  // extern "C"

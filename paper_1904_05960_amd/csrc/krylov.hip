@@ -1,0 +1,300 @@
+// FP64 kernels of flexible GMRES: outer SpMV (int64 row pointers), classical Gram-Schmidt
+// with one re-orthogonalisation fused into streaming passes over the Krylov basis, norms,
+// the Givens update of the Hessenberg least-squares problem, and x = x0 + Z y.
+// Reductions are two-stage with a fixed tree (per-block partials, then one block per
+// output), so results are identical from run to run.
+#include "common.hpp"
+
+namespace mgr {
+namespace {
+
+constexpr int NB = 1024;     // partial-sum blocks
+constexpr int KS = 72;       // partial stride (>= restart + 1)
+constexpr int KC = 16;       // basis vectors per register chunk
+
+template <int G>
+__global__ void __launch_bounds__(256) k_spmv64(int64_t n, const int64_t *__restrict__ rp,
+                                                const int *__restrict__ ci,
+                                                const double *__restrict__ v,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ b,
+                                                double *__restrict__ y) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (row >= n) return;
+  double acc = 0.0;
+  const int64_t e1 = rp[row + 1];
+  for (int64_t e = rp[row] + l; e < e1; e += G) acc += v[e] * x[ci[e]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (l == 0) y[row] = b ? b[row] - acc : acc;
+}
+
+void launch_spmv64(const mgr_csr &A, const double *x, const double *b, double *y, hipStream_t s,
+                   double avg) {
+#define L64(GG)                                                                         \
+  k_spmv64<GG><<<grid_for(A.nrows * GG, 256), 256, 0, s>>>(A.nrows, A.row_ptr, A.col, A.val, \
+                                                           x, b, y)
+  if (avg > 48) L64(64);
+  else if (avg > 24) L64(32);
+  else if (avg > 12) L64(16);
+  else L64(8);
+#undef L64
+  KCHK();
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-level reduction of KC values per thread into partial[blockIdx * KS + k0 + k]
+__device__ inline void block_store(double (&acc)[KC], int kn, int k0, double *partial) {
+  __shared__ double sh[4][KC];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    double t = wave_sum(acc[k]);
+    if (lane == 0) sh[w][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kn) {
+    const int k = threadIdx.x;
+    partial[blockIdx.x * KS + k0 + k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_multidot(const double *__restrict__ V, int64_t n, int nv,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ partial) {
+  for (int k0 = 0; k0 < nv; k0 += KC) {
+    const int kn = min(KC, nv - k0);
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const double wi = w[i];
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k < kn) acc[k] += V[(int64_t)(k0 + k) * n + i] * wi;
+    }
+    block_store(acc, kn, k0, partial);
+  }
+}
+
+// w -= sum_k h[k] V_k; then partial dots of the new w with every V_k, or its norm^2
+__global__ void __launch_bounds__(256) k_cgs_update(const double *__restrict__ V, int64_t n, int nv,
+                                                    const double *__restrict__ h,
+                                                    double *__restrict__ w,
+                                                    double *__restrict__ partial, int norm_only) {
+  __shared__ double sh_h[KS];
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) sh_h[k] = h[k];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double nacc = 0.0;
+  for (int64_t i = i0; i < n; i += stride) {
+    double wi = w[i];
+    for (int k = 0; k < nv; ++k) wi -= sh_h[k] * V[(int64_t)k * n + i];
+    w[i] = wi;
+    nacc += wi * wi;
+  }
+  if (norm_only) {
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+    acc[0] = nacc;
+    block_store(acc, 1, 0, partial);
+    return;
+  }
+  for (int k0 = 0; k0 < nv; k0 += KC) {
+    const int kn = min(KC, nv - k0);
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const double wi = w[i];
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k < kn) acc[k] += V[(int64_t)(k0 + k) * n + i] * wi;
+    }
+    block_store(acc, kn, k0, partial);
+  }
+}
+
+__global__ void k_norm_partials(const double *__restrict__ r, int64_t n, double *__restrict__ partial) {
+  double acc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc[0] += r[i] * r[i];
+  block_store(acc, 1, 0, partial);
+}
+__global__ void k_dot_partials(const double *__restrict__ a, const double *__restrict__ b,
+                               int64_t n, double *__restrict__ partial) {
+  double acc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc[0] += a[i] * b[i];
+  block_store(acc, 1, 0, partial);
+}
+
+// out[k] (+)= sum over blocks of partial[blk * KS + k]; one block per k, fixed order
+__global__ void k_reduce_partials(const double *__restrict__ partial, double *__restrict__ out,
+                                  int add) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < NB; b += 256) acc += partial[b * KS + k];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = add ? out[k] + sh[0] : sh[0];
+}
+
+// H column-major with leading dimension ldh; scal[0] = |g_{j+1}|, scal[1] = h_{j+1,j},
+// scal[2] = 1 / h_{j+1,j} (0 at breakdown)
+__global__ void k_givens(double *__restrict__ H, double *__restrict__ cs, double *__restrict__ sn,
+                         double *__restrict__ g, const double *__restrict__ h1,
+                         const double *__restrict__ h2, const double *__restrict__ hn2, int j,
+                         int ldh, double *__restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double *col = H + (int64_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(hn2[0]);
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  cs[j] = r != 0.0 ? a / r : 1.0;
+  sn[j] = r != 0.0 ? b / r : 0.0;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  scal[0] = fabs(g[j + 1]);
+  scal[1] = hn;
+  scal[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+__global__ void k_scale(const double *__restrict__ w, const double *__restrict__ sc,
+                        double *__restrict__ v, int64_t n) {
+  const double a = sc[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * a;
+}
+
+__global__ void k_start(const double *__restrict__ r, double inv_beta, double beta,
+                        double *__restrict__ V0, double *__restrict__ g, int64_t n, int mp1) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    V0[i] = r[i] * inv_beta;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < mp1; k += blockDim.x) g[k] = k == 0 ? beta : 0.0;
+}
+
+__global__ void k_trisolve(const double *__restrict__ H, const double *__restrict__ g, int k,
+                           int ldh, double *__restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int c = i + 1; c < k; ++c) s -= H[(int64_t)c * ldh + i] * y[c];
+    y[i] = s / H[(int64_t)i * ldh + i];
+  }
+}
+
+__global__ void k_xupdate(const double *__restrict__ Z, int64_t n, int k,
+                          const double *__restrict__ y, double *__restrict__ x) {
+  __shared__ double sy[KS];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) sy[c] = y[c];
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double s = x[i];
+    for (int c = 0; c < k; ++c) s += Z[(int64_t)c * n + i] * sy[c];
+    x[i] = s;
+  }
+}
+
+unsigned sgrid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  return g < 1 ? 1u : (unsigned)g;
+}
+
+}  // namespace
+
+void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s) {
+  launch_spmv64(A, x, nullptr, y, s, A.nrows ? 1e9 : 0.0);
+}
+
+int krylov_partials_blocks() { return NB * KS; }
+
+void multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
+                       hipStream_t s) {
+  k_multidot<<<NB, 256, 0, s>>>(V, n, nv, w, partial);
+  KCHK();
+}
+void cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
+                         double *partial, bool norm_only, hipStream_t s) {
+  k_cgs_update<<<NB, 256, 0, s>>>(V, n, nv, h, w, partial, norm_only ? 1 : 0);
+  KCHK();
+}
+void reduce_partials(const double *partial, int nv, double *out, bool add, hipStream_t s) {
+  k_reduce_partials<<<nv, 256, 0, s>>>(partial, out, add ? 1 : 0);
+  KCHK();
+}
+void givens_step(double *H, double *cs, double *sn, double *g, const double *h1, const double *h2,
+                 const double *hn2, int j, int ldh, double *scal, double *unused, hipStream_t s) {
+  (void)unused;
+  k_givens<<<1, 64, 0, s>>>(H, cs, sn, g, h1, h2, hn2, j, ldh, scal);
+  KCHK();
+}
+void scale_vec(const double *w, const double *scale, double *v, int64_t n, hipStream_t s) {
+  k_scale<<<sgrid(n), 256, 0, s>>>(w, scale, v, n);
+  KCHK();
+}
+void tri_solve_and_update(const double *H, const double *g, int k, int ldh, const double *Z,
+                          int64_t n, double *x, double *y, hipStream_t s) {
+  if (k <= 0) return;
+  k_trisolve<<<1, 64, 0, s>>>(H, g, k, ldh, y);
+  KCHK();
+  k_xupdate<<<sgrid(n), 256, 0, s>>>(Z, n, k, y, x);
+  KCHK();
+}
+void norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s) {
+  k_norm_partials<<<NB, 256, 0, s>>>(r, n, partial);
+  KCHK();
+}
+void dot_partials(const double *a, const double *b, int64_t n, double *partial, hipStream_t s) {
+  k_dot_partials<<<NB, 256, 0, s>>>(a, b, n, partial);
+  KCHK();
+}
+void start_cycle_host_beta(const double *r, double beta, double *V0, double *g, int64_t n, int mp1,
+                           hipStream_t s) {
+  k_start<<<sgrid(n), 256, 0, s>>>(r, 1.0 / beta, beta, V0, g, n, mp1);
+  KCHK();
+}
+void resid64(const mgr_csr &A, const double *x, const double *b, double *r, hipStream_t s) {
+  launch_spmv64(A, x, b, r, s, 1e9);
+}
+void spmv64_avg(const mgr_csr &A, const double *x, const double *b, double *y, double avg,
+                hipStream_t s) {
+  launch_spmv64(A, x, b, y, s, avg);
+}
+
+}  // namespace mgr

@@ -1,0 +1,645 @@
+// MGR setup kernels (Sec. 5.1-5.2): C/F split by label, extraction of A_FF, A_FC, A_CF,
+// A_CC, Jacobi interpolation, the dropping operator G with the merge
+// S = A_CC - G(A_CF D_FF^{-1} A_FC), transposition, and format conversions.
+// Floating-point steps are single IEEE operations (no contraction), matching the
+// summation and rounding order the setup is specified with.
+#include "common.hpp"
+
+namespace mgr {
+namespace {
+
+__device__ __forceinline__ uint64_t group_bits(bool p, int G) {
+  uint64_t b = __ballot(p);
+  if (G == 64) return b;
+  const int lane = threadIdx.x & 63;
+  const int base = lane & ~(G - 1);
+  return (b >> base) & ((1ull << G) - 1);
+}
+__device__ __forceinline__ int lane_in_group(int G) { return threadIdx.x & (G - 1); }
+
+// ---------------------------------------------------------------------------------
+// C/F split
+__global__ void k_cf_flags(const int8_t *__restrict__ lab, int64_t n, uint32_t fmask,
+                           int *__restrict__ isF, int *flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int t = lab[i];
+  if (t < 0 || t > 7) { atomicOr(flag, FLAG_BAD_LABEL); t = 0; }
+  isF[i] = (fmask >> t) & 1u;
+}
+__global__ void k_cf_fill(int64_t n, const int *__restrict__ isF, const int *__restrict__ fpos,
+                          int *__restrict__ F, int *__restrict__ C, int *__restrict__ map) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int f = fpos[i];
+  if (isF[i]) { F[f] = (int)i; map[i] = f; }
+  else { int c = (int)i - f; C[c] = (int)i; map[i] = -c - 1; }
+}
+__global__ void k_label_eq(const int8_t *__restrict__ lab, int64_t n, int t, int *__restrict__ fl) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) fl[i] = lab[i] == t;
+}
+__global__ void k_label_rank_set(const int8_t *__restrict__ lab, int64_t n, int t,
+                                 const int *__restrict__ pos, int *__restrict__ rank) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && lab[i] == t) rank[i] = pos[i];
+}
+__global__ void k_gather_i8(const int8_t *__restrict__ a, const int *__restrict__ idx, int64_t n,
+                            int8_t *__restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[idx[i]];
+}
+
+// ---------------------------------------------------------------------------------
+// block extraction; G lanes per row
+template <int G>
+__global__ void k_extract_count(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                const int *__restrict__ map, int *__restrict__ cFF,
+                                int *__restrict__ cFC, int *__restrict__ cCF,
+                                int *__restrict__ cCC) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = lane_in_group(G);
+  if (row >= n) return;
+  int nf = 0, nc = 0;
+  for (int e = rp[row] + l; e < rp[row + 1]; e += G) {
+    if (map[ci[e]] >= 0) ++nf; else ++nc;
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    nf += __shfl_xor(nf, o, G);
+    nc += __shfl_xor(nc, o, G);
+  }
+  if (l == 0) {
+    int r = map[row];
+    if (r >= 0) { if (cFF) cFF[r] = nf; cFC[r] = nc; }
+    else { cCF[-r - 1] = nf; cCC[-r - 1] = nc; }
+  }
+}
+
+template <int G>
+__global__ void k_extract_fill(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                               const double *__restrict__ v, const int *__restrict__ map,
+                               const int *__restrict__ pFF, int *__restrict__ ciFF,
+                               double *__restrict__ vFF, const int *__restrict__ pFC,
+                               int *__restrict__ ciFC, double *__restrict__ vFC,
+                               const int *__restrict__ pCF, int *__restrict__ ciCF,
+                               double *__restrict__ vCF, const int *__restrict__ pCC,
+                               int *__restrict__ ciCC, double *__restrict__ vCC,
+                               double *__restrict__ dFF) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = lane_in_group(G);
+  const bool active = row < n;
+  const int r = active ? map[row] : 0;
+  const bool isFrow = r >= 0;
+  const int rr = isFrow ? r : -r - 1;
+  int oF = 0, oC = 0;
+  if (active) {
+    if (isFrow) { oF = pFF ? pFF[rr] : 0; oC = pFC[rr]; }
+    else { oF = pCF[rr]; oC = pCC[rr]; }
+  }
+  const int s = active ? rp[row] : 0, e = active ? rp[row + 1] : 0;
+  const int len = e - s;
+  // the group loops until its row is done; groups in one wave differ in trip count, so
+  // ballots are taken by every lane of the wave in every round
+  int maxlen = len;
+  for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
+  for (int c0 = 0; c0 < maxlen; c0 += G) {
+    const int q = c0 + l;
+    const bool has = q < len;
+    int col = 0, m = 0;
+    double val = 0.0;
+    if (has) { col = ci[s + q]; val = v[s + q]; m = map[col]; }
+    const bool toF = has && m >= 0;
+    const bool toC = has && m < 0;
+    const uint64_t bF = group_bits(toF, G), bC = group_bits(toC, G);
+    const uint64_t below = (1ull << l) - 1;
+    const int pf = __popcll(bF & below), pc = __popcll(bC & below);
+    if (toF) {
+      if (isFrow) {
+        if (ciFF) { ciFF[oF + pf] = m; vFF[oF + pf] = val; }
+        if (m == rr) dFF[rr] = val;
+      } else { ciCF[oF + pf] = m; vCF[oF + pf] = val; }
+    } else if (toC) {
+      if (isFrow) { ciFC[oC + pc] = -m - 1; vFC[oC + pc] = val; }
+      else { ciCC[oC + pc] = -m - 1; vCC[oC + pc] = val; }
+    }
+    oF += __popcll(bF);
+    oC += __popcll(bC);
+  }
+}
+
+__global__ void k_scale_rows_div(int64_t n, const int *__restrict__ rp, double *__restrict__ v,
+                                 const double *__restrict__ d) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = d[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) v[e] = __ddiv_rn(v[e], di);
+}
+
+__global__ void k_check_nonzero(const double *__restrict__ d, int64_t n, int *flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && !(d[i] != 0.0 && d[i] == d[i])) atomicOr(flag, FLAG_ZERO_PIVOT);
+}
+
+// ---------------------------------------------------------------------------------
+// merge with dropping: S = A - diag(w) keep(B).  One 64-lane workgroup per row; the row of
+// B is staged in LDS.
+constexpr int MB_MAX = 2048;
+
+template <int MODE>  // 0: count, 1: fill
+__global__ void k_merge_drop(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
+                             const double *__restrict__ av, const int *__restrict__ brp,
+                             const int *__restrict__ bci, const double *__restrict__ bv,
+                             const double *__restrict__ w, int nmax,
+                             const int *__restrict__ lrank, int *__restrict__ cnt,
+                             const int *__restrict__ srp, int *__restrict__ sci,
+                             double *__restrict__ sv, int *flag) {
+  __shared__ int bc[MB_MAX];
+  __shared__ double bvals[MB_MAX];
+  __shared__ int kpre[MB_MAX + 1];
+  __shared__ unsigned char keep[MB_MAX];
+  __shared__ int s_carry;
+  const int row = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (row >= n) return;
+  const int bs = brp[row], mb = brp[row + 1] - bs;
+  const int as = arp ? arp[row] : 0, la = arp ? arp[row + 1] - as : 0;
+  if (mb > MB_MAX) {
+    if (lane == 0) atomicOr(flag, FLAG_ROW_TOO_LONG);
+    return;
+  }
+  for (int t = lane; t < mb; t += 64) {
+    bc[t] = bci[bs + t];
+    bvals[t] = bv ? bv[bs + t] : 0.0;
+  }
+  __syncthreads();
+  const int myrank = (nmax >= 0) ? lrank[row] : 0;
+  for (int t = lane; t < mb; t += 64) {
+    bool k = true;
+    if (nmax >= 0 && lrank[bc[t]] != myrank) {
+      const double at = fabs(bvals[t]);
+      int rk = 0;
+      for (int u = 0; u < mb; ++u) {
+        if (lrank[bc[u]] == myrank) continue;
+        const double au = fabs(bvals[u]);
+        rk += (au > at) || (au == at && bc[u] < bc[t]);
+      }
+      k = rk < nmax;
+    }
+    keep[t] = k;
+  }
+  if (lane == 0) s_carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < mb; c0 += 64) {
+    const int t = c0 + lane;
+    const int kv = (t < mb) ? keep[t] : 0;
+    int inc = kv;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int x = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += x;
+    }
+    const int carry = s_carry;
+    if (t < mb) kpre[t] = carry + inc - kv;
+    __syncthreads();
+    if (lane == 63) s_carry = carry + inc;
+    __syncthreads();
+  }
+  const int K = s_carry;
+  if (lane == 0) kpre[mb] = K;
+  __syncthreads();
+  // entries of A: position p + (# kept B entries with a smaller column)
+  int dup = 0;
+  const int so = (MODE == 1) ? srp[row] : 0;
+  for (int p = lane; p < la; p += 64) {
+    const int c = aci[as + p];
+    int lo = 0, hi = mb;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (bc[mid] < c) lo = mid + 1; else hi = mid; }
+    const bool found = lo < mb && bc[lo] == c && keep[lo];
+    if (MODE == 0) { dup += found; }
+    else {
+      const int pos = p + kpre[lo];
+      sci[so + pos] = c;
+      if (sv) {
+        double a = av[as + p];
+        if (found) {
+          const double b = w ? __dmul_rn(w[row], bvals[lo]) : bvals[lo];
+          a = __dsub_rn(a, b);
+        }
+        sv[so + pos] = a;
+      }
+    }
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dup += __shfl_xor(dup, o, 64);
+    if (lane == 0) cnt[row] = la + K - dup;
+    return;
+  }
+  // kept entries of B that A lacks: position (# A entries below) + (# kept B below)
+  for (int t = lane; t < mb; t += 64) {
+    if (!keep[t]) continue;
+    const int c = bc[t];
+    int lo = 0, hi = la;
+    while (lo < hi) { int mid = (lo + hi) >> 1; if (aci[as + mid] < c) lo = mid + 1; else hi = mid; }
+    if (lo < la && aci[as + lo] == c) continue;
+    const int pos = lo + kpre[t];
+    sci[so + pos] = c;
+    if (sv) {
+      const double b = w ? __dmul_rn(w[row], bvals[t]) : bvals[t];
+      sv[so + pos] = -b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// transpose: column counts, scatter, per-row ordering by source row
+__global__ void k_col_count(int64_t nnz, const int *__restrict__ ci, int *__restrict__ cnt) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+__global__ void k_transpose_scatter(int64_t n, const int *__restrict__ rp,
+                                    const int *__restrict__ ci, const double *__restrict__ v,
+                                    const int *__restrict__ trp, int *__restrict__ fillpos,
+                                    int *__restrict__ tmp_r, double *__restrict__ tmp_v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int c = ci[e];
+    const int pos = trp[c] + atomicAdd(&fillpos[c], 1);
+    tmp_r[pos] = (int)i;
+    if (tmp_v) tmp_v[pos] = v[e];
+  }
+}
+// keys are unique within a row: the output position of an entry is its rank
+__global__ void k_rank_sort_rows(int64_t n, const int *__restrict__ rp,
+                                 const int *__restrict__ tk, const double *__restrict__ tv,
+                                 int *__restrict__ ok, double *__restrict__ ov) {
+  const int64_t row = blockIdx.x;
+  if (row >= n) return;
+  const int s = rp[row], m = rp[row + 1] - s;
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    const int key = tk[s + t];
+    int rank = 0;
+    for (int u = 0; u < m; ++u) rank += tk[s + u] < key;
+    ok[s + rank] = key;
+    if (tv) ov[s + rank] = tv[s + t];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+__global__ void k_diag(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                       const double *__restrict__ v, double *__restrict__ d) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] == i) x = v[e];
+  d[i] = x;
+}
+// rs_i / |a_ii| with rs_i summed in ascending column order
+__global__ void k_gershgorin(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                             const double *__restrict__ v, double *__restrict__ q, int *flag) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rs = 0.0, d = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    rs = __dadd_rn(rs, fabs(v[e]));
+    if (ci[e] == i) d = v[e];
+  }
+  if (d == 0.0) { atomicOr(flag, FLAG_ZERO_PIVOT); q[i] = 0.0; return; }
+  q[i] = __ddiv_rn(rs, fabs(d));
+}
+__global__ void k_l1_inv(int64_t n, const int *__restrict__ rp, const double *__restrict__ v,
+                         double *__restrict__ dinv) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rs = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) rs = __dadd_rn(rs, fabs(v[e]));
+  dinv[i] = rs != 0.0 ? 1.0 / rs : 0.0;
+}
+__global__ void k_omega_over(const double *__restrict__ d, double omega, double *__restrict__ w,
+                             int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) w[i] = __ddiv_rn(omega, d[i]);
+}
+
+// ---------------------------------------------------------------------------------
+// scalar CSR with full 3x3 blocks -> BSR3
+__global__ void k_bsr3_count(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
+                             int *__restrict__ cnt, int *flag) {
+  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (I >= nb) return;
+  const int s0 = rp[3 * I], L = rp[3 * I + 1] - s0;
+  bool ok = (L % 3 == 0) && (rp[3 * I + 2] - rp[3 * I + 1] == L) && (rp[3 * I + 3] - rp[3 * I + 2] == L);
+  if (ok) {
+    for (int r = 0; r < 3 && ok; ++r) {
+      const int s = rp[3 * I + r];
+      for (int q = 0; q < L && ok; q += 3) {
+        const int c = ci[s + q];
+        ok = (c % 3 == 0) && ci[s + q + 1] == c + 1 && ci[s + q + 2] == c + 2 && ci[s0 + q] == c;
+      }
+    }
+  }
+  if (!ok) atomicOr(flag, FLAG_NOT_BLOCKED);
+  cnt[I] = ok ? L / 3 : 0;
+}
+__global__ void k_bsr3_fill(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ v, const int *__restrict__ brp,
+                            int *__restrict__ bci, double *__restrict__ bv) {
+  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (I >= nb) return;
+  const int nbk = brp[I + 1] - brp[I];
+  for (int q = 0; q < nbk; ++q) {
+    const int blk = brp[I] + q;
+    bci[blk] = ci[rp[3 * I] + 3 * q] / 3;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) bv[9 * (int64_t)blk + 3 * r + c] = v[rp[3 * I + r] + 3 * q + c];
+  }
+}
+
+// inverses of consecutive nb x nb diagonal blocks (nb = 2 or 3), row-major
+__global__ void k_block_inv(int64_t nblk, int nb, const int *__restrict__ rp,
+                            const int *__restrict__ ci, const double *__restrict__ v,
+                            double *__restrict__ inv, int *flag) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nblk) return;
+  double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int r0 = (int)(e * nb);
+  for (int r = 0; r < nb; ++r)
+    for (int q = rp[r0 + r]; q < rp[r0 + r + 1]; ++q) {
+      const int c = ci[q] - r0;
+      if (c >= 0 && c < nb) B[r * nb + c] = v[q];
+    }
+  double *o = inv + (int64_t)e * nb * nb;
+  if (nb == 2) {
+    const double det = B[0] * B[3] - B[1] * B[2];
+    if (det == 0.0 || det != det) { atomicOr(flag, FLAG_ZERO_PIVOT); return; }
+    o[0] = B[3] / det; o[1] = -B[1] / det; o[2] = -B[2] / det; o[3] = B[0] / det;
+  } else {
+    const double c00 = B[4] * B[8] - B[5] * B[7], c01 = B[5] * B[6] - B[3] * B[8],
+                 c02 = B[3] * B[7] - B[4] * B[6];
+    const double det = B[0] * c00 + B[1] * c01 + B[2] * c02;
+    if (det == 0.0 || det != det) { atomicOr(flag, FLAG_ZERO_PIVOT); return; }
+    o[0] = c00 / det;
+    o[1] = (B[2] * B[7] - B[1] * B[8]) / det;
+    o[2] = (B[1] * B[5] - B[2] * B[4]) / det;
+    o[3] = c01 / det;
+    o[4] = (B[0] * B[8] - B[2] * B[6]) / det;
+    o[5] = (B[2] * B[3] - B[0] * B[5]) / det;
+    o[6] = c02 / det;
+    o[7] = (B[1] * B[6] - B[0] * B[7]) / det;
+    o[8] = (B[0] * B[4] - B[1] * B[3]) / det;
+  }
+}
+
+__global__ void k_hash(int64_t n, const int *__restrict__ a, unsigned long long salt,
+                       unsigned long long *__restrict__ out) {
+  unsigned long long acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)(uint32_t)a[i] ^ ((unsigned long long)i << 32) ^ salt;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    acc += z ^ (z >> 31);
+  }
+  atomicAdd(out, acc);
+}
+
+}  // namespace
+
+// ===================================================================================
+void cf_split(const int8_t *labels, int64_t n, uint32_t fmask, CfSplit &cf, hipStream_t s,
+              int *dflag) {
+  cf.n = n;
+  DArr<int> isF(n, s), fpos(n + 1, s);
+  k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(labels, n, fmask, isF.p, dflag);
+  KCHK();
+  cf.nF = exclusive_scan_i32(isF.p, fpos.p, n, s);
+  cf.nC = n - cf.nF;
+  require(read_flag(dflag, s) == 0, MGR_ERR_ARG, "labels must lie in [0, 7]");
+  require(cf.nF > 0 && cf.nC > 0, MGR_ERR_ARG, "a reduction level has an empty F or C set");
+  cf.F.alloc(cf.nF, s);
+  cf.C.alloc(cf.nC, s);
+  cf.map.alloc(n, s);
+  k_cf_fill<<<grid_for(n, 256), 256, 0, s>>>(n, isF.p, fpos.p, cf.F.p, cf.C.p, cf.map.p);
+  KCHK();
+}
+
+void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s) {
+  rank.alloc(n, s);
+  DArr<int> fl(n, s), pos(n + 1, s);
+  for (int t = 0; t < 8; ++t) {
+    k_label_eq<<<grid_for(n, 256), 256, 0, s>>>(labels, n, t, fl.p);
+    KCHK();
+    if (exclusive_scan_i32(fl.p, pos.p, n, s) == 0) continue;
+    k_label_rank_set<<<grid_for(n, 256), 256, 0, s>>>(labels, n, t, pos.p, rank.p);
+    KCHK();
+  }
+}
+
+void gather_labels(const int8_t *labels, const int *idx, int64_t n, int8_t *out, hipStream_t s) {
+  if (n <= 0) return;
+  k_gather_i8<<<grid_for(n, 256), 256, 0, s>>>(labels, idx, n, out);
+  KCHK();
+}
+
+void extract_blocks(const Csr &A, const CfSplit &cf, Csr *Aff, Csr &Afc, Csr &Acf, Csr &Acc,
+                    double *dFF, hipStream_t s) {
+  const int64_t n = A.n, nF = cf.nF, nC = cf.nC;
+  constexpr int G = 16;
+  DArr<int> cFF, cFC(nF + 1, s), cCF(nC + 1, s), cCC(nC + 1, s);
+  if (Aff) cFF.alloc(nF + 1, s);
+  k_extract_count<G><<<grid_for(n * G, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, cf.map.p, cFF.p,
+                                                         cFC.p, cCF.p, cCC.p);
+  KCHK();
+  auto finish = [&](Csr &M, DArr<int> &cnt, int64_t rows, int64_t cols) {
+    M.n = rows;
+    M.m = cols;
+    M.rp.alloc(rows + 1, s);
+    M.nnz = exclusive_scan_i32(cnt.p, M.rp.p, rows, s);
+    M.ci.alloc(M.nnz, s);
+    M.v.alloc(M.nnz, s);
+  };
+  if (Aff) finish(*Aff, cFF, nF, nF);
+  finish(Afc, cFC, nF, nC);
+  finish(Acf, cCF, nC, nF);
+  finish(Acc, cCC, nC, nC);
+  fill<double>(dFF, 0.0, nF, s);
+  k_extract_fill<G><<<grid_for(n * G, 256), 256, 0, s>>>(
+      n, A.rp.p, A.ci.p, A.v.p, cf.map.p, Aff ? Aff->rp.p : nullptr, Aff ? Aff->ci.p : nullptr,
+      Aff ? Aff->v.p : nullptr, Afc.rp.p, Afc.ci.p, Afc.v.p, Acf.rp.p, Acf.ci.p, Acf.v.p,
+      Acc.rp.p, Acc.ci.p, Acc.v.p, dFF);
+  KCHK();
+}
+
+void scale_rows_div(Csr &M, const double *d, hipStream_t s) {
+  if (M.n == 0) return;
+  k_scale_rows_div<<<grid_for(M.n, 256), 256, 0, s>>>(M.n, M.rp.p, M.v.p, d);
+  KCHK();
+}
+
+void check_nonzero(const double *d, int64_t n, int *dflag, hipStream_t s) {
+  if (n == 0) return;
+  k_check_nonzero<<<grid_for(n, 256), 256, 0, s>>>(d, n, dflag);
+  KCHK();
+}
+
+void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int *lrank, Csr &S,
+                bool values, hipStream_t s, int *dflag) {
+  const int64_t n = B.n;
+  S.n = n;
+  S.m = B.m;
+  S.rp.alloc(n + 1, s);
+  DArr<int> cnt(n + 1, s);
+  const int *arp = A.n ? A.rp.p : nullptr;
+  k_merge_drop<0><<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+      n, arp, A.ci.p, A.v.p, B.rp.p, B.ci.p, values ? B.v.p : nullptr, w, nmax, lrank, cnt.p,
+      nullptr, nullptr, nullptr, dflag);
+  KCHK();
+  S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, n, s);
+  require(read_flag(dflag, s) == 0, MGR_ERR_UNSUPPORTED,
+          "merge/drop: a row of the correction term exceeds 2048 entries");
+  S.ci.alloc(S.nnz, s);
+  if (values) S.v.alloc(S.nnz, s);
+  k_merge_drop<1><<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
+      n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p, values ? B.v.p : nullptr, w,
+      nmax, lrank, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr, dflag);
+  KCHK();
+}
+
+void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag) {
+  Csr empty;
+  merge_drop(empty, B, nullptr, nmax, lrank, G, true, s, dflag);
+  negate_f64(G.v.p, G.nnz, s);
+}
+
+void transpose(const Csr &A, Csr &T, bool values, hipStream_t s) {
+  T.n = A.m;
+  T.m = A.n;
+  T.nnz = A.nnz;
+  T.rp.alloc(T.n + 1, s);
+  DArr<int> cnt(T.n + 1, s), fillpos(T.n, s);
+  fill<int>(cnt.p, 0, T.n + 1, s);
+  fill<int>(fillpos.p, 0, T.n, s);
+  if (A.nnz) {
+    k_col_count<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.nnz, A.ci.p, cnt.p);
+    KCHK();
+  }
+  exclusive_scan_i32(cnt.p, T.rp.p, T.n, s);
+  T.ci.alloc(T.nnz, s);
+  if (values) T.v.alloc(T.nnz, s);
+  if (A.nnz == 0) return;
+  DArr<int> tr(A.nnz, s);
+  DArr<double> tv;
+  if (values) tv.alloc(A.nnz, s);
+  k_transpose_scatter<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, T.rp.p,
+                                                         fillpos.p, tr.p, values ? tv.p : nullptr);
+  KCHK();
+  k_rank_sort_rows<<<(unsigned)T.n, 64, 0, s>>>(T.n, T.rp.p, tr.p, values ? tv.p : nullptr,
+                                                T.ci.p, values ? T.v.p : nullptr);
+  KCHK();
+}
+
+void diag_of(const Csr &A, double *d, hipStream_t s) {
+  if (A.n == 0) return;
+  k_diag<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d);
+  KCHK();
+}
+
+double gershgorin_rho(const Csr &A, hipStream_t s, int *dflag) {
+  DArr<double> q(A.n, s);
+  k_gershgorin<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, q.p, dflag);
+  KCHK();
+  double r = reduce_max_f64(q.p, A.n, s);
+  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "AMG level matrix has a zero diagonal");
+  return r;
+}
+
+void omega_over_diag(const double *d, double omega, double *w, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_omega_over<<<grid_for(n, 256), 256, 0, s>>>(d, omega, w, n);
+  KCHK();
+}
+
+void l1_inverse(const Csr &A, double *dinv, hipStream_t s) {
+  if (A.n == 0) return;
+  k_l1_inv<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.v.p, dinv);
+  KCHK();
+}
+
+void copy_csr(const Csr &A, Csr &B, hipStream_t s) {
+  B.n = A.n;
+  B.m = A.m;
+  B.nnz = A.nnz;
+  B.rp.alloc(A.n + 1, s);
+  B.ci.alloc(A.nnz, s);
+  B.v.alloc(A.nnz, s);
+  HIPCHK(hipMemcpyAsync(B.rp.p, A.rp.p, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+  if (A.nnz) {
+    HIPCHK(hipMemcpyAsync(B.ci.p, A.ci.p, A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.v.p, A.v.p, A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
+  int64_t nnz = 0;
+  HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + A->nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  require(nnz >= 0 && nnz < 0x7fffffffLL, MGR_ERR_UNSUPPORTED, "nnz must be below 2^31");
+  B.n = A->nrows;
+  B.m = A->ncols;
+  B.nnz = nnz;
+  B.rp.alloc(B.n + 1, s);
+  B.ci.alloc(nnz, s);
+  B.v.alloc(nnz, s);
+  rowptr64_to_32(A->row_ptr, B.rp.p, B.n + 1, dflag, s);
+  if (nnz) {
+    HIPCHK(hipMemcpyAsync(B.ci.p, A->col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(B.v.p, A->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  require(read_flag(dflag, s) == 0, MGR_ERR_ARG, "row pointers out of range");
+}
+
+uint64_t pattern_hash(const Csr &A, hipStream_t s) {
+  DArr<unsigned long long> h(1, s);
+  HIPCHK(hipMemsetAsync(h.p, 0, sizeof(unsigned long long), s));
+  k_hash<<<1024, 256, 0, s>>>(A.n + 1, A.rp.p, 0x1234567ull, h.p);
+  KCHK();
+  if (A.nnz) {
+    k_hash<<<1024, 256, 0, s>>>(A.nnz, A.ci.p, 0x9876543ull, h.p);
+    KCHK();
+  }
+  unsigned long long r = 0;
+  HIPCHK(hipMemcpyAsync(&r, h.p, sizeof(r), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return r;
+}
+
+void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, int64_t &nb,
+                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag) {
+  require(A.n % 3 == 0 && A.m % 3 == 0, MGR_ERR_UNSUPPORTED, "BSR3 needs sizes divisible by 3");
+  nb = A.n / 3;
+  mb = A.m / 3;
+  DArr<int> cnt(nb + 1, s);
+  k_bsr3_count<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, cnt.p, dflag);
+  KCHK();
+  rp.alloc(nb + 1, s);
+  nnzb = exclusive_scan_i32(cnt.p, rp.p, nb, s);
+  require(read_flag(dflag, s) == 0, MGR_ERR_UNSUPPORTED,
+          "nodal AMG level without full 3x3 block structure");
+  ci.alloc(nnzb, s);
+  v.alloc(nnzb * 9, s);
+  k_bsr3_fill<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, A.v.p, rp.p, ci.p, v.p);
+  KCHK();
+}
+
+void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag) {
+  require(A.n % nb == 0, MGR_ERR_UNSUPPORTED, "block smoother: size not divisible by block");
+  const int64_t nblk = A.n / nb;
+  k_block_inv<<<grid_for(nblk, 256), 256, 0, s>>>(nblk, nb, A.rp.p, A.ci.p, A.v.p, inv, dflag);
+  KCHK();
+  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "singular same-cell block");
+}
+
+}  // namespace mgr

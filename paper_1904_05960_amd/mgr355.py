@@ -1,0 +1,377 @@
+"""Python binding of libmgr355 (ctypes): argument marshalling only.
+
+Every step of setup, preconditioner application and FGMRES runs in the HIP library; this
+module passes device pointers of torch tensors and the current HIP stream across the C ABI
+declared in include/mgr355.h.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgr355.so")
+
+MGR_OK, MGR_ERR_ARG, MGR_ERR_ALLOC, MGR_ERR_HIP, MGR_ERR_ZERO_PIVOT = 0, 1, 2, 3, 4
+MGR_ERR_NOT_CONVERGED, MGR_ERR_PATTERN, MGR_ERR_UNSUPPORTED = 5, 6, 7
+STATUS_NAMES = {0: "OK", 1: "ARG", 2: "ALLOC", 3: "HIP", 4: "ZERO_PIVOT", 5: "NOT_CONVERGED",
+                6: "PATTERN", 7: "UNSUPPORTED"}
+
+INTERP = {"jacobi": 0, "zero": 1}
+FRELAX = {"jacobi": 0, "amg": 1, "dense": 2}
+GSMOOTH = {"none": 0, "block_jacobi": 1}
+COARSE = {"amg": 0, "dense": 1}
+PREC = {"fp64": 0, "fp32": 1}
+
+X_LEVEL_A, X_F, X_C, X_WP, X_ACOR, X_G, X_COARSE, X_AMG_A, X_AMG_P, X_AMG_AGG, X_AMG_NLEV = range(11)
+MAX_LEVELS = 8
+
+
+class MgrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mgr_csr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class mgr_amg_opts(C.Structure):
+    _fields_ = [("theta0", C.c_double), ("max_levels", C.c_int32), ("coarse_size", C.c_int32)]
+
+
+class mgr_level_opts(C.Structure):
+    _fields_ = [("f_label_mask", C.c_uint32), ("interp", C.c_int32), ("nmax_drop", C.c_int32),
+                ("frelax", C.c_int32), ("frelax_sweeps", C.c_int32), ("frelax_omega", C.c_double),
+                ("frelax_block", C.c_int32), ("global_smoother", C.c_int32),
+                ("global_sweeps", C.c_int32), ("global_omega", C.c_double)]
+
+
+class mgr_opts(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("level", mgr_level_opts * MAX_LEVELS),
+                ("coarse", C.c_int32), ("amg_frelax", mgr_amg_opts), ("amg_coarse", mgr_amg_opts),
+                ("precision", C.c_int32), ("use_graph", C.c_int32), ("keep_setup", C.c_int32)]
+
+
+class fgmres_opts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double)]
+
+
+class fgmres_result(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("true_relres", C.c_double), ("est_relres", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
+                ("history_len", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmgr355.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1904_05960_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    sig = {
+        "mgr_default_opts": (None, [C.POINTER(mgr_opts)]),
+        "mgr_setup": (st, [C.POINTER(mgr_csr), vp, C.POINTER(mgr_opts), vp, C.POINTER(vp)]),
+        "mgr_setup_numeric": (st, [vp, C.POINTER(mgr_csr), vp]),
+        "mgr_apply": (st, [vp, vp, vp, vp]),
+        "fgmres_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
+        "fgmres_solve": (st, [C.POINTER(mgr_csr), vp, vp, vp, C.POINTER(fgmres_opts), vp,
+                              C.c_size_t, C.POINTER(fgmres_result), vp]),
+        "mgr_destroy": (None, [vp]),
+        "mgr_footprint": (st, [vp, C.POINTER(C.c_size_t)]),
+        "mgr_estimate_footprint": (st, [C.c_int64, C.c_int64, C.POINTER(mgr_opts),
+                                        C.POINTER(C.c_size_t)]),
+        "mgr_set_allocator": (None, [vp, vp, vp]),
+        "mgr_last_error": (C.c_char_p, []),
+        "mgr_query": (st, [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
+        "mgr_export": (st, [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp]),
+        "mgr_spmv": (st, [C.POINTER(mgr_csr), vp, vp, vp]),
+        "mgr_stream_copy": (st, [vp, vp, C.c_int64, vp]),
+        "mgr_profile_enable": (st, [C.c_int32, C.c_int32]),
+        "mgr_profile_read": (st, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != MGR_OK:
+        raise MgrError(status, lib().mgr_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+# ----------------------------------------------------------------------------------------
+class Matrix:
+    """Device CSR matrix (int64 row pointers, int32 columns, FP64 values) in torch tensors."""
+
+    def __init__(self, row_ptr, col, val, ncols=None):
+        import torch
+        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
+        assert val.dtype == torch.float64
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        self.nrows = row_ptr.numel() - 1
+        self.ncols = self.nrows if ncols is None else ncols
+        self.c = mgr_csr(self.nrows, self.ncols, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+
+    @staticmethod
+    def from_host(indptr, indices, data, device="cuda", ncols=None):
+        import torch
+        return Matrix(torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(device),
+                      torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(device),
+                      torch.as_tensor(np.asarray(data, dtype=np.float64)).to(device), ncols)
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+    def spmv(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(self.nrows, dtype=torch.float64, device=x.device)
+        _check(lib().mgr_spmv(C.byref(self.c), _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+
+@dataclass
+class Level:
+    """One reduction level (Sec. 5.2): F labels and the components of Algorithm 2."""
+    f_labels: tuple
+    interp: str = "jacobi"
+    nmax: int = -1
+    frelax: str = "jacobi"
+    frelax_sweeps: int = 1
+    frelax_omega: float = 1.0
+    frelax_block: int = 1
+    global_smoother: str = "none"
+    global_sweeps: int = 1
+    global_omega: float = 1.0
+
+
+@dataclass
+class AMG:
+    theta0: float = 0.08
+    max_levels: int = 10
+    coarse_size: int = 256
+
+
+@dataclass
+class Options:
+    levels: list
+    coarse: str = "amg"
+    amg_frelax: AMG = field(default_factory=AMG)
+    amg_coarse: AMG = field(default_factory=AMG)
+    precision: str = "fp64"
+    use_graph: bool = True
+    keep_setup: bool = False
+
+    def to_c(self) -> mgr_opts:
+        o = mgr_opts()
+        lib().mgr_default_opts(C.byref(o))
+        if len(self.levels) > MAX_LEVELS:
+            raise ValueError("too many levels")
+        o.nlevels = len(self.levels)
+        for i, L in enumerate(self.levels):
+            c = o.level[i]
+            c.f_label_mask = sum(1 << int(t) for t in L.f_labels)
+            c.interp = INTERP[L.interp]
+            c.nmax_drop = int(L.nmax)
+            c.frelax = FRELAX[L.frelax]
+            c.frelax_sweeps = int(L.frelax_sweeps)
+            c.frelax_omega = float(L.frelax_omega)
+            c.frelax_block = int(L.frelax_block)
+            c.global_smoother = GSMOOTH[L.global_smoother]
+            c.global_sweeps = int(L.global_sweeps)
+            c.global_omega = float(L.global_omega)
+        o.coarse = COARSE[self.coarse]
+        for dst, src in ((o.amg_frelax, self.amg_frelax), (o.amg_coarse, self.amg_coarse)):
+            dst.theta0, dst.max_levels, dst.coarse_size = src.theta0, src.max_levels, src.coarse_size
+        o.precision = PREC[self.precision]
+        o.use_graph = int(self.use_graph)
+        o.keep_setup = int(self.keep_setup)
+        return o
+
+
+def paper_plan(model: str, **kw) -> Options:
+    """Reduction order of Sec. 5.3: displacement first (one nodal AMG V-cycle, N_max = 4),
+    then the saturations (Jacobi, Galerkin, with the global block smoother on the level that
+    holds only cell unknowns), pressure last (AMG)."""
+    if model == "biot1":
+        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3)]
+    elif model == "two":
+        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3),
+                  Level((1,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi")]
+    elif model == "three":
+        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3),
+                  Level((3,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi"),
+                  Level((1,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi")]
+    else:
+        raise ValueError(model)
+    return Options(levels=levels, **kw)
+
+
+def saturation_first_plan(model: str, **kw) -> Options:
+    """Saturations reduced first (Jacobi, Galerkin), then displacement (nodal AMG,
+    N_max = 4), pressure last (AMG)."""
+    if model == "two":
+        levels = [Level((1,), nmax=-1, frelax="jacobi"),
+                  Level((0,), nmax=4, frelax="amg", frelax_block=3)]
+    elif model == "three":
+        levels = [Level((3,), nmax=-1, frelax="jacobi"), Level((1,), nmax=-1, frelax="jacobi"),
+                  Level((0,), nmax=4, frelax="amg", frelax_block=3)]
+    else:
+        raise ValueError(model)
+    return Options(levels=levels, **kw)
+
+
+class Preconditioner:
+    """MGR hierarchy owned by the library (mgr_setup / mgr_apply / mgr_destroy)."""
+
+    def __init__(self, A: Matrix, labels, opts: Options, stream=None):
+        self.n = A.nrows
+        self.opts = opts
+        self._copts = opts.to_c()
+        h = C.c_void_p()
+        _check(lib().mgr_setup(C.byref(A.c), _ptr(labels), C.byref(self._copts), _stream(stream),
+                               C.byref(h)))
+        self.h = h
+
+    def apply(self, v, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(v)
+        _check(lib().mgr_apply(self.h, _ptr(v), _ptr(z), _stream(stream)))
+        return z
+
+    def setup_numeric(self, A: Matrix, stream=None):
+        _check(lib().mgr_setup_numeric(self.h, C.byref(A.c), _stream(stream)))
+
+    def footprint(self) -> int:
+        b = C.c_size_t()
+        _check(lib().mgr_footprint(self.h, C.byref(b)))
+        return int(b.value)
+
+    def query(self, what, level=0, sub=0):
+        out = (C.c_int64 * 3)()
+        _check(lib().mgr_query(self.h, what, level, sub, out))
+        return int(out[0]), int(out[1]), int(out[2])
+
+    def export(self, what, level=0, sub=0, stream=None):
+        """Copy an object of the hierarchy to the host: (indptr, indices, data) for CSR
+        objects, an int array for index lists and aggregates."""
+        import torch
+        rows, cols, nnz = self.query(what, level, sub)
+        dev = torch.device("cuda")
+        if what in (X_F, X_C, X_AMG_AGG):
+            col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+            _check(lib().mgr_export(self.h, what, level, sub, None, _ptr(col), None,
+                                    _stream(stream)))
+            return col[:nnz].cpu().numpy()
+        rp = torch.empty(rows + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+        _check(lib().mgr_export(self.h, what, level, sub, _ptr(rp), _ptr(col), _ptr(val),
+                                _stream(stream)))
+        return (rp.cpu().numpy(), col[:nnz].cpu().numpy().astype(np.int64),
+                val[:nnz].cpu().numpy(), (rows, cols))
+
+    def amg_levels(self, level):
+        return self.query(X_AMG_NLEV, level, 0)[0]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mgr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def estimate_footprint(n, nnz, opts: Options) -> int:
+    b = C.c_size_t()
+    o = opts.to_c()
+    _check(lib().mgr_estimate_footprint(int(n), int(nnz), C.byref(o), C.byref(b)))
+    return int(b.value)
+
+
+class Workspace:
+    """Caller-owned FGMRES workspace (torch allocation, reused across solves)."""
+
+    def __init__(self, n, restart, device="cuda"):
+        import torch
+        nbytes = int(lib().fgmres_workspace_bytes(int(n), int(restart)))
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+        self.n, self.restart = n, restart
+
+
+def fgmres(A: Matrix, b, x=None, M: Preconditioner | None = None, restart=30, rtol=1e-6,
+           maxit=1000, work: Workspace | None = None, history=False, stream=None,
+           raise_on_fail=True):
+    """Solve A x = b with FGMRES(restart) preconditioned by M (None = identity)."""
+    import torch
+    if x is None:
+        x = torch.zeros_like(b)
+    o = fgmres_opts(int(restart), int(maxit), float(rtol))
+    r = fgmres_result()
+    hist = None
+    if history:
+        cap = maxit + maxit // max(restart, 1) + 8
+        hist = (C.c_double * cap)()
+        r.history = C.cast(hist, C.POINTER(C.c_double))
+        r.history_cap = cap
+    wp, wb = (C.c_void_p(work.buf.data_ptr()), work.nbytes) if work is not None else (None, 0)
+    st = lib().fgmres_solve(C.byref(A.c), M.h if M is not None else None, _ptr(b), _ptr(x),
+                            C.byref(o), wp, C.c_size_t(wb), C.byref(r), _stream(stream))
+    info = dict(iters=r.iters, restarts=r.restarts, converged=bool(r.converged),
+                true_relres=r.true_relres, est_relres=r.est_relres, status=st)
+    if history:
+        info["history"] = [hist[i] for i in range(r.history_len)]
+    if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
+        raise MgrError(st, lib().mgr_last_error().decode())
+    return x, info
+
+
+def stream_copy(src, dst, stream=None):
+    _check(lib().mgr_stream_copy(_ptr(src), _ptr(dst), int(src.numel()), _stream(stream)))
+
+
+def profile_enable(family: int, on: bool = True):
+    _check(lib().mgr_profile_enable(family, int(on)))
+
+
+def profile_read(family: int):
+    n = C.c_int64()
+    ms = C.c_double()
+    by = C.c_double()
+    _check(lib().mgr_profile_read(family, C.byref(n), C.byref(ms), C.byref(by)))
+    return int(n.value), float(ms.value), float(by.value)

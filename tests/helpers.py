@@ -1,0 +1,53 @@
+"""Shared test helpers: translate one solver description into the oracle's plan and the
+library's options, move workloads to the device, compare CSR objects."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import amg as oamg
+from oracle import mgr as omgr
+from oracle.sparse import CSR
+
+
+def oracle_plan(opts) -> omgr.Plan:
+    """The oracle plan equivalent to a paper_1904_05960_amd.mgr355.Options."""
+    levels = []
+    for L in opts.levels:
+        levels.append(omgr.LevelPlan(
+            f_labels=tuple(L.f_labels), interp=L.interp, nmax=L.nmax,
+            frelax={"jacobi": "jacobi", "amg": "amg", "dense": "exact"}[L.frelax],
+            frelax_sweeps=L.frelax_sweeps, frelax_omega=L.frelax_omega,
+            frelax_block=L.frelax_block, global_smoother=L.global_smoother,
+            global_sweeps=L.global_sweeps, global_omega=L.global_omega))
+    a, c = opts.amg_frelax, opts.amg_coarse
+    return omgr.Plan(levels=levels, coarse=opts.coarse,
+                     amg_frelax=oamg.AMGOptions(a.theta0, a.max_levels, a.coarse_size, 3),
+                     amg_coarse=oamg.AMGOptions(c.theta0, c.max_levels, c.coarse_size, 1))
+
+
+def oracle_csr(w) -> CSR:
+    return CSR(w.indptr, w.indices, w.data, (w.n, w.n))
+
+
+def device_workload(w):
+    import torch
+    from paper_1904_05960_amd import mgr355
+    A = mgr355.Matrix.from_host(w.indptr, w.indices, w.data)
+    labels = torch.as_tensor(w.labels).cuda()
+    b = torch.as_tensor(w.b).cuda()
+    return A, labels, b
+
+
+def assert_csr_equal(got, exp: CSR, what=""):
+    """Bit-exact equality of a CSR export (indptr, indices, data, shape) and an oracle CSR."""
+    rp, ci, v, shape = got
+    assert tuple(shape) == exp.shape, (what, shape, exp.shape)
+    assert np.array_equal(rp, exp.indptr), f"{what}: row pointers differ"
+    assert np.array_equal(ci, exp.indices), f"{what}: column indices differ"
+    same = (v == exp.data) | (np.isnan(v) & np.isnan(exp.data))
+    if not np.all(same):
+        i = int(np.flatnonzero(~same)[0])
+        raise AssertionError(f"{what}: {int((~same).sum())} values differ, first at {i}: "
+                             f"{v[i]!r} vs {exp.data[i]!r}")
+    # +0.0 and -0.0 compare equal above; check the sign bits too
+    assert np.array_equal(np.signbit(v), np.signbit(exp.data)), f"{what}: signs of zeros differ"

@@ -1,0 +1,263 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Bars (from the method and its arithmetic):
+  * integer/index work (C/F split, aggregates, every sparsity pattern) - bit-exact;
+  * setup values (W_p, A_cor, G, coarse operators, AMG P and Galerkin products) - bit-exact:
+    both sides take every product and sum in the same order with separate roundings;
+  * preconditioner application in FP64 - relative 2-norm difference <= 1e-12 (different
+    summation orders in SpMV and a dense inverse in place of LU at the coarsest grids);
+  * FGMRES - iteration count within +-1 of the oracle (CGS2 on the GPU, MGS in the oracle),
+    true FP64 relative residual <= rtol.
+"""
+import numpy as np
+import pytest
+
+from oracle import amg as oamg
+from oracle import krylov as okry
+from oracle import mgr as omgr
+from oracle.sparse import CSR
+from tests.helpers import assert_csr_equal, device_workload, oracle_csr, oracle_plan
+from workloads import poromech as pm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+m = pytest.importorskip("paper_1904_05960_amd.mgr355")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def small_amg(opts, coarse_size=48):
+    opts.amg_frelax = m.AMG(coarse_size=coarse_size)
+    opts.amg_coarse = m.AMG(coarse_size=coarse_size)
+    return opts
+
+
+CASES = [
+    ("biot_8x8x8_paper_dense", lambda: pm.biot_single_phase(8, 8, 8, 0),
+     lambda: small_amg(m.paper_plan("biot1", coarse="dense"))),
+    ("biot_8x8x8_paper_amg", lambda: pm.biot_single_phase(8, 8, 8, 0),
+     lambda: small_amg(m.paper_plan("biot1", coarse="amg"))),
+    ("two_9x7x6_paper", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(m.paper_plan("two"))),
+    ("two_9x7x6_satfirst", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(m.saturation_first_plan("two"))),
+    ("three_6x5x4_paper", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(m.paper_plan("three"))),
+]
+
+
+def compare_amg(P, level, H: oamg.AMGHierarchy, tag):
+    nlev = P.amg_levels(level)
+    assert nlev == len(H.levels), (tag, nlev, len(H.levels))
+    for k, L in enumerate(H.levels):
+        assert_csr_equal(P.export(m.X_AMG_A, level, k), L.A, f"{tag} AMG A[{k}]")
+        if k + 1 < nlev:
+            agg = P.export(m.X_AMG_AGG, level, k)
+            assert np.array_equal(agg, L.agg), f"{tag} aggregates[{k}]"
+            assert_csr_equal(P.export(m.X_AMG_P, level, k), L.P, f"{tag} AMG P[{k}]")
+
+
+def compare_hierarchy(P, H: omgr.Hierarchy, tag):
+    for l, L in enumerate(H.levels):
+        log(f"  {tag}: level {l} n={L.A.shape[0]} nF={len(L.F)} nC={len(L.C)}")
+        assert np.array_equal(P.export(m.X_F, l), L.F), f"{tag} F[{l}]"
+        assert np.array_equal(P.export(m.X_C, l), L.C), f"{tag} C[{l}]"
+        assert_csr_equal(P.export(m.X_LEVEL_A, l), L.A, f"{tag} A[{l}]")
+        assert_csr_equal(P.export(m.X_WP, l), L.Wp, f"{tag} W_p[{l}]")
+        assert_csr_equal(P.export(m.X_ACOR, l), L.Acor, f"{tag} A_cor[{l}]")
+        assert_csr_equal(P.export(m.X_G, l), L.G, f"{tag} G[{l}]")
+        if L.amg is not None:
+            compare_amg(P, l, L.amg, f"{tag} F-AMG[{l}]")
+    nl = len(H.levels)
+    assert_csr_equal(P.export(m.X_LEVEL_A, nl), H.coarse_A, f"{tag} coarse A")
+    if H.coarse_amg is not None:
+        compare_amg(P, nl, H.coarse_amg, f"{tag} coarse AMG")
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    tag, make_w, make_o = request.param
+    log(f"[case] {tag}")
+    w = make_w()
+    opts = make_o()
+    opts.keep_setup = True
+    A, labels, b = device_workload(w)
+    P = m.Preconditioner(A, labels, opts)
+    H = omgr.setup(oracle_csr(w), w.labels, oracle_plan(opts))
+    yield tag, w, opts, A, labels, b, P, H
+    P.close()
+
+
+def test_setup_bit_exact(case):
+    tag, w, opts, A, labels, b, P, H = case
+    compare_hierarchy(P, H, tag)
+
+
+def test_apply_fp64_matches_oracle(case):
+    tag, w, opts, A, labels, b, P, H = case
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        v = rng.standard_normal(w.n) * np.where(w.labels == 0, 1e7, 1e-3)
+        z_ref = omgr.apply(H, v)
+        z = P.apply(torch.as_tensor(v).cuda()).cpu().numpy()
+        err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+        log(f"  {tag}: apply rel err {err:.3e}")
+        assert err <= 1e-12
+
+
+def test_fgmres_matches_oracle(case):
+    tag, w, opts, A, labels, b, P, H = case
+    rtol = 1e-8
+    Ao = oracle_csr(w)
+    ref = okry.fgmres(Ao.matvec, lambda v: omgr.apply(H, v), w.b, restart=30, rtol=rtol,
+                      maxit=400)
+    x, info = m.fgmres(A, b, M=P, restart=30, rtol=rtol, maxit=400)
+    xs = x.cpu().numpy()
+    true = np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b)
+    log(f"  {tag}: iters gpu {info['iters']} oracle {ref.iters}; true relres {true:.2e}")
+    assert ref.converged and info["converged"]
+    assert abs(info["iters"] - ref.iters) <= 1
+    assert true <= rtol * 1.0000001
+    assert info["true_relres"] == pytest.approx(true, rel=1e-6, abs=1e-14)
+    errx = np.linalg.norm(xs - ref.x) / np.linalg.norm(ref.x)
+    assert errx <= 1e-5
+
+
+def test_graph_replays_match_eager(case):
+    tag, w, opts, A, labels, b, P, H = case
+    import copy
+    o2 = copy.deepcopy(opts)
+    o2.use_graph = False
+    P2 = m.Preconditioner(A, labels, o2)
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        v = torch.as_tensor(rng.standard_normal(w.n)).cuda()
+        z1 = P.apply(v)
+        torch.cuda.synchronize()
+        z2 = P2.apply(v)
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z2)
+    P2.close()
+
+
+def random_system(rng, labels, density, diag_ff):
+    n = len(labels)
+    D = rng.standard_normal((n, n)) * (rng.random((n, n)) < density)
+    if diag_ff:
+        f = np.flatnonzero(labels == 0)
+        D[np.ix_(f, f)] = 0.0
+    D[np.arange(n), np.arange(n)] = 3.0 * (np.abs(D).sum(axis=1) + 1.0)
+    return D
+
+
+def test_exactness_pin_one_iteration():
+    """A_FF diagonal + one Jacobi sweep (omega = 1) + no dropping + exact coarse solve gives
+    M^{-1} = A^{-1}: FGMRES converges in one iteration on the GPU."""
+    rng = np.random.default_rng(7)
+    labels = np.sort(rng.integers(0, 2, size=300)).astype(np.int8)[::-1].copy()
+    labels = rng.permutation(labels).astype(np.int8)
+    D = random_system(rng, labels, 0.03, True)
+    Ao = CSR.from_dense(D)
+    A = m.Matrix.from_host(Ao.indptr, Ao.indices, Ao.data)
+    lab = torch.as_tensor(labels).cuda()
+    opts = m.Options(levels=[m.Level((0,), nmax=-1, frelax="jacobi")], coarse="dense")
+    P = m.Preconditioner(A, lab, opts)
+    bb = torch.as_tensor(rng.standard_normal(300)).cuda()
+    x, info = m.fgmres(A, bb, M=P, restart=30, rtol=1e-10)
+    assert info["iters"] == 1
+    v = rng.standard_normal(300)
+    z = P.apply(torch.as_tensor(v).cuda()).cpu().numpy()
+    assert np.linalg.norm(D @ z - v) / np.linalg.norm(v) <= 1e-12
+    P.close()
+
+
+def test_fp32_hierarchy_iterations_within_one():
+    w = pm.two_phase(12, 11, 10, 4)
+    A, labels, b = device_workload(w)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        P = m.Preconditioner(A, labels, small_amg(m.paper_plan("two", precision=prec)))
+        x, info = m.fgmres(A, b, M=P, restart=30, rtol=1e-6, maxit=400)
+        xs = x.cpu().numpy()
+        true = np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b)
+        res[prec] = (info["iters"], true)
+        log(f"  {prec}: iters {info['iters']} true relres {true:.2e}")
+        assert true <= 1e-6 * 1.0000001
+        P.close()
+    assert abs(res["fp64"][0] - res["fp32"][0]) <= 1
+
+
+def test_spmv_ragged_matches_scipy():
+    import scipy.sparse as sp
+    rng = np.random.default_rng(8)
+    for n, dens in ((1, 1.0), (37, 0.2), (1000, 0.01), (4099, 0.003)):
+        S = sp.random(n, n, density=dens, random_state=rng, format="csr")
+        S.sort_indices()
+        A = m.Matrix.from_host(S.indptr, S.indices, S.data)
+        x = rng.standard_normal(n)
+        y = A.spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+        ref = S @ x
+        assert np.allclose(y, ref, rtol=1e-13, atol=1e-13 * (np.abs(ref).max() + 1e-300))
+
+
+def test_error_paths():
+    w = pm.biot_single_phase(3, 3, 3, 0)
+    A, labels, b = device_workload(w)
+    bad = labels.clone()
+    bad[5] = 9
+    with pytest.raises(m.MgrError) as e:
+        m.Preconditioner(A, bad, m.paper_plan("biot1"))
+    assert e.value.status == m.MGR_ERR_ARG
+    # a zero on the diagonal of A_FF
+    data = w.data.copy()
+    r = 4
+    for q in range(w.indptr[r], w.indptr[r + 1]):
+        if w.indices[q] == r:
+            data[q] = 0.0
+    Az = m.Matrix.from_host(w.indptr, w.indices, data)
+    with pytest.raises(m.MgrError) as e:
+        m.Preconditioner(Az, labels, m.Options(levels=[m.Level((0,))], coarse="dense"))
+    assert e.value.status == m.MGR_ERR_ZERO_PIVOT
+    # an empty C set
+    with pytest.raises(m.MgrError) as e:
+        m.Preconditioner(A, labels, m.Options(levels=[m.Level((0, 2))], coarse="dense"))
+    assert e.value.status == m.MGR_ERR_ARG
+    # maxit reached: NOT_CONVERGED with the last iterate
+    x, info = m.fgmres(A, b, M=None, restart=5, rtol=1e-14, maxit=3, raise_on_fail=False)
+    assert info["status"] == m.MGR_ERR_NOT_CONVERGED and info["iters"] == 3
+
+
+def test_setup_numeric_same_pattern_equals_fresh_setup():
+    w1 = pm.two_phase(7, 6, 5, 11)
+    w2 = pm.two_phase(7, 6, 5, 12)     # same pattern, other values
+    A1, labels, b1 = device_workload(w1)
+    A2, _, b2 = device_workload(w2)
+    opts = small_amg(m.paper_plan("two"))
+    P = m.Preconditioner(A1, labels, opts)
+    P.setup_numeric(A2)
+    Pf = m.Preconditioner(A2, labels, opts)
+    v = torch.as_tensor(np.random.default_rng(1).standard_normal(w1.n)).cuda()
+    assert torch.equal(P.apply(v), Pf.apply(v))
+    w3 = pm.two_phase(7, 6, 6, 11)
+    A3, l3, _ = device_workload(w3)
+    with pytest.raises(m.MgrError) as e:
+        P.setup_numeric(A3)
+    assert e.value.status == m.MGR_ERR_PATTERN
+    P.close()
+    Pf.close()
+
+
+def test_setup_is_deterministic():
+    w = pm.two_phase(8, 8, 8, 2)
+    A, labels, b = device_workload(w)
+    opts = small_amg(m.paper_plan("two", precision="fp32"))
+    v = torch.as_tensor(np.random.default_rng(2).standard_normal(w.n)).cuda()
+    outs = []
+    for _ in range(2):
+        P = m.Preconditioner(A, labels, opts)
+        outs.append(P.apply(v))
+        P.close()
+    assert torch.equal(outs[0], outs[1])
