@@ -233,6 +233,34 @@ mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t 
 /* y = A x with the FP64 CSR kernel used by fgmres_solve.  Asynchronous. */
 mgr_status mgr_spmv(const mgr_csr *A, const double *x, double *y, void *stream);
 
+/* Setup building blocks on caller matrices, each the same kernel the setup uses.  Results
+ * are owned by an mgr_owned_csr (sizes[3] = rows, cols, entries), copied out with
+ * mgr_owned_export into caller arrays of those sizes, and freed with mgr_owned_free.
+ * All synchronise `stream`. */
+typedef struct mgr_owned_csr mgr_owned_csr;
+/* C = A B with the pinned summation order of the coarse-grid correction (Sec. 5.2):
+ * c_ij = sum over ascending k of a_ik * b_kj, separate roundings, from +0.0; the pattern
+ * keeps entries that cancel.  Errors: ARG, UNSUPPORTED (a row beyond 2^21 entries). */
+mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int64_t sizes[3],
+                      void *stream);
+/* T = A^T (rows sorted by column). */
+mgr_status mgr_transpose(const mgr_csr *A, mgr_owned_csr **T, int64_t sizes[3], void *stream);
+/* S = A - diag(w) G(B) on the union pattern (eq. drop_operator with w = NULL; the AMG
+ * prolongator P = T - diag(omega / a_ii) (A T) with w given).  nmax < 0 keeps all of B;
+ * otherwise per row of B the entries whose coarse points have equal rank within their
+ * label (labels_c, one per row/column of B) plus the nmax largest |b| (ties: smaller
+ * column).  Errors: ARG, UNSUPPORTED (a row of B beyond 2048 entries). */
+mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, int32_t nmax,
+                          const int8_t *labels_c, mgr_owned_csr **S, int64_t sizes[3],
+                          void *stream);
+/* Strength graph (bs = 1 scalar, 3 nodal), SplitMix64 priorities of AMG level `level`,
+ * MIS(2) and aggregation; agg receives nrows/bs aggregate ids (-1 = none). */
+mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,
+                         int32_t *agg, int64_t *nagg, void *stream);
+mgr_status mgr_owned_export(const mgr_owned_csr *C, int64_t *row_ptr, int32_t *col,
+                            double *val, void *stream);
+void mgr_owned_free(mgr_owned_csr *C);
+
 /* dst = src for n doubles with a plain streaming kernel (HBM counter calibration). */
 mgr_status mgr_stream_copy(const double *src, double *dst, int64_t n, void *stream);
 

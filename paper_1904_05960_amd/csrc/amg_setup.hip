@@ -229,7 +229,7 @@ void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t
     DArr<int> nrp, nci_unused;
     DArr<double> bv_unused;
     int64_t nn, mn, nnzb;
-    csr_to_bsr3(A, nrp, nci_unused, bv_unused, nn, mn, nnzb, s, dflag);
+    csr_to_bsr3(A, nrp, nci_unused, bv_unused, nn, mn, nnzb, s, dflag, "strength A");
     nci_unused.reset();
     bv_unused.reset();
     DArr<int> nci(nnzb, s);

@@ -184,7 +184,11 @@ void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s);
 
 // BSR3 conversion: scalar CSR with full 3x3 blocks -> block CSR
 void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, int64_t &nb,
-                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag);
+                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag, const char *what);
+// setup trace on stderr when MGR355_TRACE is set
+void trace(const std::string &msg);
+// message returned by mgr_last_error() on this thread
+void set_last_error(const std::string &msg);
 // block-Jacobi inverses over consecutive nb x nb diagonal blocks (nb = 2 or 3)
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag);
 

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 #include <mutex>
 
@@ -45,6 +47,11 @@ void dfree(void *p, hipStream_t s) {
   if (!p) return;
   if (g_free) g_free(p, s, g_ctx);
   else (void)hipFreeAsync(p, s);
+}
+
+void trace(const std::string &msg) {
+  static const bool on = std::getenv("MGR355_TRACE") != nullptr;
+  if (on) std::fprintf(stderr, "[mgr355] %s\n", msg.c_str());
 }
 
 // ===================================================================================
@@ -151,8 +158,10 @@ struct mgr_handle {
 
 namespace mgr {
 namespace {
-
 thread_local std::string t_err;
+}
+void set_last_error(const std::string &msg) { t_err = msg; }
+namespace {
 
 size_t esz(const mgr_opts &o) { return o.precision == MGR_PREC_FP32 ? 4 : 8; }
 
@@ -202,12 +211,15 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     AmgLevel &L = *H.lv.back();
     const int64_t n = L.A.n;
     if (n <= o.coarse_size || k + 1 >= o.max_levels) break;
+    trace("amg level " + std::to_string(k) + " n=" + std::to_string(n) + " nnz=" +
+          std::to_string(L.A.nnz) + " bs=" + std::to_string(bs));
     AmgGraph G;
     strength_graph(L.A, bs, o.theta0 * std::ldexp(1.0, -k), G, s, dflag);
     int64_t nagg = 0;
     DArr<int> agg;
     mis2_aggregate(G, k, agg, nagg, s);
     const int64_t nc = nagg * bs;
+    trace("  aggregates " + std::to_string(nagg) + ", strong edges " + std::to_string(G.ci.n));
     if (nc == 0 || (double)nc > 0.8 * (double)n) break;
     Csr T;
     tentative(agg, n / bs, bs, nagg, T, s);
@@ -247,12 +259,12 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     cast_values(L.dinv.p, L.tdinv, L.A.n, sz, s);
     if (bs == 3) {
       DArr<double> bv;
-      csr_to_bsr3(L.A, L.Ab_rp, L.Ab_ci, bv, L.nb, L.ncb, L.Ab_nnzb, s, dflag);
+      csr_to_bsr3(L.A, L.Ab_rp, L.Ab_ci, bv, L.nb, L.ncb, L.Ab_nnzb, s, dflag, "AMG A");
       to_planes(bv, L.Ab_nnzb, L.tA, sz, s);
       int64_t a, b;
-      csr_to_bsr3(L.P, L.Pb_rp, L.Pb_ci, bv, a, b, L.Pb_nnzb, s, dflag);
+      csr_to_bsr3(L.P, L.Pb_rp, L.Pb_ci, bv, a, b, L.Pb_nnzb, s, dflag, "AMG P");
       to_planes(bv, L.Pb_nnzb, L.tP, sz, s);
-      csr_to_bsr3(L.R, L.Rb_rp, L.Rb_ci, bv, a, b, L.Rb_nnzb, s, dflag);
+      csr_to_bsr3(L.R, L.Rb_rp, L.Rb_ci, bv, a, b, L.Rb_nnzb, s, dflag, "AMG R");
       to_planes(bv, L.Rb_nnzb, L.tR, sz, s);
     } else {
       cast_values(L.A.v.p, L.tA, L.A.nnz, sz, s);
@@ -500,6 +512,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   if (cur.n) HIPCHK(hipMemcpyAsync(lab.p, labels_in, cur.n, hipMemcpyDeviceToDevice, s));
   for (int l = 0; l < o.nlevels; ++l) {
     const mgr_level_opts &lo = o.level[l];
+    trace("mgr level " + std::to_string(l) + " n=" + std::to_string(cur.n) + " nnz=" +
+          std::to_string(cur.nnz));
     auto L = std::make_unique<MgrLevel>();
     L->A = std::move(cur);
     L->labels = std::move(lab);

@@ -158,6 +158,7 @@ __global__ void k_merge_drop(int64_t n, const int *__restrict__ arp, const int *
   __shared__ double bvals[MB_MAX];
   __shared__ int kpre[MB_MAX + 1];
   __shared__ unsigned char keep[MB_MAX];
+  __shared__ unsigned char bonly[MB_MAX];
   __shared__ int s_carry;
   const int row = blockIdx.x;
   const int lane = threadIdx.x;
@@ -188,11 +189,24 @@ __global__ void k_merge_drop(int64_t n, const int *__restrict__ arp, const int *
     }
     keep[t] = k;
   }
+  __syncthreads();
+  // kept entries of B whose column A lacks: they take their own slots in the union
+  for (int t = lane; t < mb; t += 64) {
+    bool only = keep[t];
+    if (only && la > 0) {
+      const int c = bc[t];
+      int lo = 0, hi = la;
+      while (lo < hi) { int mid = (lo + hi) >> 1; if (aci[as + mid] < c) lo = mid + 1; else hi = mid; }
+      only = !(lo < la && aci[as + lo] == c);
+    }
+    bonly[t] = only;
+  }
   if (lane == 0) s_carry = 0;
   __syncthreads();
+  // kpre[t] = number of B-only entries before t
   for (int c0 = 0; c0 < mb; c0 += 64) {
     const int t = c0 + lane;
-    const int kv = (t < mb) ? keep[t] : 0;
+    const int kv = (t < mb) ? bonly[t] : 0;
     int inc = kv;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -208,41 +222,34 @@ __global__ void k_merge_drop(int64_t n, const int *__restrict__ arp, const int *
   const int K = s_carry;
   if (lane == 0) kpre[mb] = K;
   __syncthreads();
-  // entries of A: position p + (# kept B entries with a smaller column)
-  int dup = 0;
-  const int so = (MODE == 1) ? srp[row] : 0;
+  if (MODE == 0) {
+    if (lane == 0) cnt[row] = la + K;
+    return;
+  }
+  // entries of A: position p + (# B-only entries with a smaller column)
+  const int so = srp[row];
   for (int p = lane; p < la; p += 64) {
     const int c = aci[as + p];
     int lo = 0, hi = mb;
     while (lo < hi) { int mid = (lo + hi) >> 1; if (bc[mid] < c) lo = mid + 1; else hi = mid; }
     const bool found = lo < mb && bc[lo] == c && keep[lo];
-    if (MODE == 0) { dup += found; }
-    else {
-      const int pos = p + kpre[lo];
-      sci[so + pos] = c;
-      if (sv) {
-        double a = av[as + p];
-        if (found) {
-          const double b = w ? __dmul_rn(w[row], bvals[lo]) : bvals[lo];
-          a = __dsub_rn(a, b);
-        }
-        sv[so + pos] = a;
+    const int pos = p + kpre[lo];
+    sci[so + pos] = c;
+    if (sv) {
+      double a = av[as + p];
+      if (found) {
+        const double b = w ? __dmul_rn(w[row], bvals[lo]) : bvals[lo];
+        a = __dsub_rn(a, b);
       }
+      sv[so + pos] = a;
     }
   }
-  if (MODE == 0) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dup += __shfl_xor(dup, o, 64);
-    if (lane == 0) cnt[row] = la + K - dup;
-    return;
-  }
-  // kept entries of B that A lacks: position (# A entries below) + (# kept B below)
+  // B-only entries: position (# A entries below) + (# B-only entries below)
   for (int t = lane; t < mb; t += 64) {
-    if (!keep[t]) continue;
+    if (!bonly[t]) continue;
     const int c = bc[t];
     int lo = 0, hi = la;
     while (lo < hi) { int mid = (lo + hi) >> 1; if (aci[as + mid] < c) lo = mid + 1; else hi = mid; }
-    if (lo < la && aci[as + lo] == c) continue;
     const int pos = lo + kpre[t];
     sci[so + pos] = c;
     if (sv) {
@@ -327,7 +334,7 @@ __global__ void k_omega_over(const double *__restrict__ d, double omega, double 
 // ---------------------------------------------------------------------------------
 // scalar CSR with full 3x3 blocks -> BSR3
 __global__ void k_bsr3_count(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
-                             int *__restrict__ cnt, int *flag) {
+                             int *__restrict__ cnt, int *flag, int *first_bad) {
   int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (I >= nb) return;
   const int s0 = rp[3 * I], L = rp[3 * I + 1] - s0;
@@ -341,7 +348,10 @@ __global__ void k_bsr3_count(int64_t nb, const int *__restrict__ rp, const int *
       }
     }
   }
-  if (!ok) atomicOr(flag, FLAG_NOT_BLOCKED);
+  if (!ok) {
+    atomicOr(flag, FLAG_NOT_BLOCKED);
+    atomicMin(first_bad, (int)I);
+  }
   cnt[I] = ok ? L / 3 : 0;
 }
 __global__ void k_bsr3_fill(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -617,17 +627,29 @@ uint64_t pattern_hash(const Csr &A, hipStream_t s) {
 }
 
 void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, int64_t &nb,
-                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag) {
+                 int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag, const char *what) {
   require(A.n % 3 == 0 && A.m % 3 == 0, MGR_ERR_UNSUPPORTED, "BSR3 needs sizes divisible by 3");
   nb = A.n / 3;
   mb = A.m / 3;
-  DArr<int> cnt(nb + 1, s);
-  k_bsr3_count<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, cnt.p, dflag);
+  DArr<int> cnt(nb + 1, s), bad(1, s);
+  fill<int>(bad.p, 0x7fffffff, 1, s);
+  k_bsr3_count<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, cnt.p, dflag, bad.p);
   KCHK();
   rp.alloc(nb + 1, s);
   nnzb = exclusive_scan_i32(cnt.p, rp.p, nb, s);
-  require(read_flag(dflag, s) == 0, MGR_ERR_UNSUPPORTED,
-          "nodal AMG level without full 3x3 block structure");
+  const int f = read_flag(dflag, s);
+  if (f & FLAG_NOT_BLOCKED) {
+    const int I = read_flag(bad.p, s);
+    int r[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(r, A.rp.p + 3 * (int64_t)I, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    throw Error(MGR_ERR_UNSUPPORTED,
+                std::string("nodal level without full 3x3 blocks (") + what + " " +
+                    std::to_string(A.n) + "x" + std::to_string(A.m) + ", node " +
+                    std::to_string(I) + ", row lengths " + std::to_string(r[1] - r[0]) + "/" +
+                    std::to_string(r[2] - r[1]) + "/" + std::to_string(r[3] - r[2]) + ")");
+  }
+  require(f == 0, MGR_ERR_HIP, "unexpected device flag before block conversion");
   ci.alloc(nnzb, s);
   v.alloc(nnzb * 9, s);
   k_bsr3_fill<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, A.v.p, rp.p, ci.p, v.p);

@@ -103,6 +103,15 @@ def lib():
         "mgr_profile_enable": (st, [C.c_int32, C.c_int32]),
         "mgr_profile_read": (st, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),
+        "mgr_spgemm": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), C.POINTER(vp),
+                            C.POINTER(C.c_int64), vp]),
+        "mgr_transpose": (st, [C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(C.c_int64), vp]),
+        "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
+                                C.POINTER(vp), C.POINTER(C.c_int64), vp]),
+        "mgr_aggregate": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_double, C.c_int32, vp,
+                               C.POINTER(C.c_int64), vp]),
+        "mgr_owned_export": (st, [vp, vp, vp, vp, vp]),
+        "mgr_owned_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -359,6 +368,52 @@ def fgmres(A: Matrix, b, x=None, M: Preconditioner | None = None, restart=30, rt
     if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
         raise MgrError(st, lib().mgr_last_error().decode())
     return x, info
+
+
+def _owned_to_host(h, sizes, stream=None):
+    import torch
+    rows, cols, nnz = (int(x) for x in sizes)
+    rp = torch.empty(rows + 1, dtype=torch.int64, device="cuda")
+    ci = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    v = torch.empty(max(nnz, 1), dtype=torch.float64, device="cuda")
+    try:
+        _check(lib().mgr_owned_export(h, _ptr(rp), _ptr(ci), _ptr(v), _stream(stream)))
+    finally:
+        lib().mgr_owned_free(h)
+    return (rp.cpu().numpy(), ci[:nnz].cpu().numpy().astype(np.int64), v[:nnz].cpu().numpy(),
+            (rows, cols))
+
+
+def spgemm(A: Matrix, B: Matrix, stream=None):
+    """C = A B with the pinned summation order; returns host (indptr, indices, data, shape)."""
+    h = C.c_void_p()
+    sz = (C.c_int64 * 3)()
+    _check(lib().mgr_spgemm(C.byref(A.c), C.byref(B.c), C.byref(h), sz, _stream(stream)))
+    return _owned_to_host(h, sz, stream)
+
+
+def transpose(A: Matrix, stream=None):
+    h = C.c_void_p()
+    sz = (C.c_int64 * 3)()
+    _check(lib().mgr_transpose(C.byref(A.c), C.byref(h), sz, _stream(stream)))
+    return _owned_to_host(h, sz, stream)
+
+
+def merge_drop(A: Matrix, B: Matrix, w=None, nmax=-1, labels_c=None, stream=None):
+    h = C.c_void_p()
+    sz = (C.c_int64 * 3)()
+    _check(lib().mgr_merge_drop(C.byref(A.c), C.byref(B.c), _ptr(w), int(nmax), _ptr(labels_c),
+                                C.byref(h), sz, _stream(stream)))
+    return _owned_to_host(h, sz, stream)
+
+
+def aggregate(A: Matrix, bs: int, theta: float, level: int, stream=None):
+    import torch
+    agg = torch.empty(max(A.nrows // bs, 1), dtype=torch.int32, device="cuda")
+    na = C.c_int64()
+    _check(lib().mgr_aggregate(C.byref(A.c), int(bs), float(theta), int(level), _ptr(agg),
+                               C.byref(na), _stream(stream)))
+    return agg[:A.nrows // bs].cpu().numpy().astype(np.int64), int(na.value)
 
 
 def stream_copy(src, dst, stream=None):

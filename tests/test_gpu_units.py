@@ -1,0 +1,99 @@
+"""GPU parity of the setup building blocks against the oracle, each through the C ABI:
+the pinned-order sparse product, transpose, drop/merge, and strength + MIS(2) aggregation.
+Bar: bit-exact (patterns, values, aggregate ids)."""
+import numpy as np
+import pytest
+
+from oracle import amg as oamg
+from oracle import mgr as omgr
+from oracle.sparse import CSR, merge_sub, spgemm, transpose
+from tests.helpers import assert_csr_equal
+from workloads import poromech as pm
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+m = pytest.importorskip("paper_1904_05960_amd.mgr355")
+
+
+def dev(M: CSR):
+    return m.Matrix.from_host(M.indptr, M.indices, M.data, ncols=M.shape[1])
+
+
+def rand_csr(rng, n, k, dens, ints=False):
+    D = rng.standard_normal((n, k)) * (rng.random((n, k)) < dens)
+    if ints:
+        D = np.round(D * 3)
+    mask = (D != 0) | (rng.random((n, k)) < dens * 0.2)
+    return CSR.from_dense(D, mask)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 9, 23), (300, 200, 250), (700, 900, 50)])
+def test_spgemm_random(shape):
+    rng = np.random.default_rng(sum(shape))
+    n, k, p = shape
+    A = rand_csr(rng, n, k, min(1.0, 6.0 / k))
+    B = rand_csr(rng, k, p, min(1.0, 8.0 / p))
+    assert_csr_equal(m.spgemm(dev(A), dev(B)), spgemm(A, B), f"spgemm {shape}")
+
+
+def test_spgemm_pinned_order_cancellation():
+    A = CSR([0, 3], [0, 1, 2], [1.0, 1.0, 1.0], (1, 3))
+    B = CSR([0, 1, 2, 3], [0, 0, 0], [1e16, 1.0, -1e16], (3, 1))
+    got = m.spgemm(dev(A), dev(B))
+    assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
+
+
+def test_spgemm_long_rows_global_fallback():
+    rng = np.random.default_rng(3)
+    A = rand_csr(rng, 40, 3000, 0.5)          # ~1500 products per row before B
+    B = rand_csr(rng, 3000, 6000, 0.002)
+    assert_csr_equal(m.spgemm(dev(A), dev(B)), spgemm(A, B), "spgemm long rows")
+
+
+def test_transpose_random():
+    rng = np.random.default_rng(4)
+    A = rand_csr(rng, 333, 129, 0.05)
+    assert_csr_equal(m.transpose(dev(A)), transpose(A), "transpose")
+
+
+@pytest.mark.parametrize("nmax", [-1, 0, 1, 4])
+def test_merge_drop_random(nmax):
+    rng = np.random.default_rng(10 + nmax)
+    n = 200
+    A = rand_csr(rng, n, n, 0.03)
+    B = rand_csr(rng, n, n, 0.06, ints=True)      # many ties in |b|
+    labels = np.tile(np.array([1, 2], dtype=np.int8), n // 2)
+    G = omgr.drop(B, labels, nmax)
+    exp = merge_sub(A, G)
+    got = m.merge_drop(dev(A), dev(B), None, nmax, torch.as_tensor(labels).cuda())
+    assert_csr_equal(got, exp, f"merge_drop nmax={nmax}")
+
+
+def test_merge_scaled_prolongator():
+    rng = np.random.default_rng(5)
+    n = 150
+    T = rand_csr(rng, n, 40, 0.02)
+    AT = rand_csr(rng, n, 40, 0.2)
+    w = rng.standard_normal(n)
+    exp = merge_sub(T, AT, w)
+    got = m.merge_drop(dev(T), dev(AT), torch.as_tensor(w).cuda(), -1, None)
+    assert_csr_equal(got, exp, "P = T - diag(w) AT")
+
+
+@pytest.mark.parametrize("bs,level", [(1, 0), (1, 2), (3, 0), (3, 1)])
+def test_aggregation_elasticity(bs, level):
+    w = pm.biot_single_phase(8, 8, 8, 0)
+    Nu = w.meta["Nu"]
+    A = CSR(w.indptr, w.indices, w.data, (w.n, w.n))
+    F = np.arange(Nu)
+    fmap = np.full(w.n, -1)
+    fmap[F] = F
+    from oracle.sparse import submatrix
+    Auu = submatrix(A, F, fmap, Nu)
+    theta = 0.08 * 0.5 ** level
+    g, gc = oamg.strength_graph(Auu, theta, bs)
+    prio = oamg.priorities(g.shape[0] - 1, level)
+    agg_o, nagg_o = oamg.aggregate(g, gc, oamg.mis2(g, gc, prio), prio)
+    agg, nagg = m.aggregate(dev(Auu), bs, theta, level)
+    assert nagg == nagg_o
+    assert np.array_equal(agg, agg_o)
