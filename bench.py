@@ -1,0 +1,217 @@
+"""Benchmark: MGR-preconditioned FGMRES time to a 1e-6 relative FP64 residual on one MI355X.
+
+One step = the whole hot path on one synthetic Jacobian already resident in HBM:
+mgr_setup (C/F splits, W_p, A_cor by pinned-order SpGEMM, G, coarse operators, both AMG
+hierarchies, FP32 cast, graph capture on first apply) + fgmres_solve to rtol = 1e-6 +
+mgr_destroy.  Default workload: two-phase poromechanics on a 64^3 cell grid (1,348,163
+unknowns, 92,914,761 nonzeros), paper reduction order (displacement, saturation,
+pressure), FP32 hierarchy inside FP64 FGMRES(30).
+
+    python bench.py [--steps K] [--warmup W] [--size 64] [--precision fp32|fp64]
+                    [--plan paper|satfirst] [--no-cpu-baseline]
+
+Prints one JSON line.  The dominant kernel's duration is measured live with HIP events
+recorded on its own stream around every launch inside the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(name, src):
+    """HBM bytes per launch from a committed counter summary, or None when absent or when
+    the kernel source changed since the counters were taken."""
+    p = os.path.join(PROFILES, name)
+    if not os.path.exists(p):
+        return None
+    text = open(p).read()
+    mh = re.search(r"source_sha256_16:\s*([0-9a-f]+)", text)
+    mt = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not mh or not mt or mh.group(1) != kernel_source_hash(src):
+        return None
+    return float(mt.group(1))
+
+
+def cpu_baseline(size_full_n):
+    """The oracle (FP64, NumPy/SciPy, untuned) on a bounded sample of the same workload
+    recipe: setup + FGMRES to 1e-6 on the 24^3 two-phase grid, scaled linearly by unknowns."""
+    from oracle import krylov as okry
+    from oracle import mgr as omgr
+    from oracle.sparse import CSR
+    from paper_1904_05960_amd import mgr355 as m
+    from tests.helpers import oracle_plan
+    from workloads import poromech as pm
+    w = pm.two_phase(24, 24, 24, 1)
+    A = CSR(w.indptr, w.indices, w.data, (w.n, w.n))
+    plan = oracle_plan(m.paper_plan("two"))
+    c0, t0 = os.times(), time.perf_counter()
+    H = omgr.setup(A, w.labels, plan)
+    t1 = time.perf_counter()
+    r = okry.fgmres(A.matvec, lambda v: omgr.apply(H, v), w.b, restart=30, rtol=1e-6, maxit=500)
+    t2, c1 = time.perf_counter(), os.times()
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    wall = t2 - t0
+    scale = size_full_n / w.n
+    return {
+        "value": round(wall * 1e3 * scale, 1), "unit": "ms",
+        "cores": max(1, round(cpu / wall)),
+        "kind": "oracle",
+        "sample": (f"oracle setup + FGMRES(30) to 1e-6 on the 24^3 two-phase grid of the same "
+                   f"recipe ({w.n} unknowns, {r.iters} iterations, setup {1e3*(t1-t0):.0f} ms, "
+                   f"solve {1e3*(t2-t1):.0f} ms), scaled by unknowns x{scale:.2f}"),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64-hierarchy step")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_05960_amd import mgr355 as m
+    from workloads import poromech as pm
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    w = pm.two_phase(a.size, a.size, a.size, 1)
+    print(f"[bench] generated {w.name}: n={w.n} nnz={w.nnz} in {time.perf_counter()-t:.1f}s",
+          file=sys.stderr, flush=True)
+    A = m.Matrix.from_host(w.indptr, w.indices, w.data)
+    labels = torch.as_tensor(w.labels).cuda()
+    b = torch.as_tensor(w.b).cuda()
+    x = torch.zeros_like(b)
+    work = m.Workspace(w.n, a.restart)
+    mk = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
+    stream = torch.cuda.current_stream()
+
+    def step(prec, record=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        P = m.Preconditioner(A, labels, mk("two", precision=prec))
+        ev[1].record(stream)
+        x.zero_()
+        _, info = m.fgmres(A, b, x=x, M=P, restart=a.restart, rtol=1e-6, maxit=1000, work=work)
+        ev[2].record(stream)
+        P.close()
+        if record is not None:
+            record.append((ev, info))
+        return info
+
+    for i in range(a.warmup):
+        step(a.precision)
+        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    m.profile_enable(1, True)            # HIP events around every outer SpMV launch
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(a.precision, rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, spmv_ms, spmv_bytes = m.profile_read(1)
+    m.profile_enable(1, False)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    setup_ms = [r[0][0].elapsed_time(r[0][1]) for r in rec]
+    solve_ms = [r[0][1].elapsed_time(r[0][2]) for r in rec]
+    info = rec[-1][1]
+    xs = x.cpu().numpy()
+    true = float(np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b))
+    err = float(np.linalg.norm(xs - w.x_true) / np.linalg.norm(w.x_true))
+    print(f"[bench] timed {a.steps} steps: {ms_step:.1f} ms/step, iters {info['iters']}",
+          file=sys.stderr, flush=True)
+
+    compare = None
+    if not a.no_compare:
+        other = "fp64" if a.precision == "fp32" else "fp32"
+        r2 = []
+        step(other, r2)
+        torch.cuda.synchronize()
+        compare = {"precision": other, "ms": round(r2[0][0][0].elapsed_time(r2[0][0][2]), 2),
+                   "iters": r2[0][1]["iters"], "true_relres": r2[0][1]["true_relres"]}
+
+    avg_launch_ms = spmv_ms / max(launches, 1)
+    bytes_per_launch = spmv_bytes / max(launches, 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile("spmv64_twophase_64.md",
+                                   os.path.join(ROOT, "paper_1904_05960_amd", "csrc", "krylov.hip"))
+    out = {
+        "metric": "MGR-FGMRES time-to-1e-6 relative FP64 residual (setup + solve)",
+        "value": round(ms_step, 2),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": ("f32 hierarchy + f64 Krylov" if a.precision == "fp32" else "f64"),
+        "data": "synthetic",
+        "config": {
+            "workload": f"two-phase poromechanics Jacobian, {a.size}^3 cells, log10 k ~ N(-13,1) "
+                        f"corr. 8 cells, Corey 2, s ~ U[0.2,0.8] (seed 1)",
+            "unknowns": w.n, "nnz": w.nnz,
+            "reduction": ("displacement -> saturation -> pressure AMG" if a.plan == "paper"
+                          else "saturation -> displacement -> pressure AMG"),
+            "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
+            "rtol": 1e-6, "parallelism": "single GPU",
+        },
+        "iterations": info["iters"],
+        "true_relres": true,
+        "solution_error_vs_x_true": err,
+        "setup_ms": round(float(np.median(setup_ms)), 2),
+        "solve_ms": round(float(np.median(solve_ms)), 2),
+        "compare_other_precision": compare,
+        "roofline": {
+            "kernel": "outer FP64 CSR SpMV (k_spmv64, 64 lanes per row)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": round(avg_launch_ms, 5),
+            "launches_timed": launches,
+        },
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w.n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
