@@ -202,6 +202,13 @@ void mgr_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
 /* Message of the last failing call on this thread ("" if none). [host] */
 const char *mgr_last_error(void);
 
+/* The default allocator keeps freed device blocks for reuse on the stream they were freed
+ * on (size-binned free lists); a failing allocation releases the cache and retries.
+ * mgr_release_cache synchronises the device and returns every cached block to HIP;
+ * mgr_cached_bytes reports the bytes held in the cache. [host] */
+mgr_status mgr_release_cache(void);
+size_t mgr_cached_bytes(void);
+
 /* ---------------------------------------------------------------------------------- */
 /* Inspection of a hierarchy (tests, diagnostics).  `what` selects an object:           */
 enum {

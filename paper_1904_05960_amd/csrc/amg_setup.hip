@@ -42,14 +42,16 @@ __global__ void k_strength_scalar(int64_t n, const int *__restrict__ rp, const i
 }
 
 // node blocks of a scalar CSR with full 3x3 blocks: squared Frobenius norm of every block,
-// summed row by row, left to right, from +0.0
+// summed row by row, left to right, from +0.0; G lanes per node, one block per lane
+template <int G>
 __global__ void k_node_norms(int64_t nn, const int *__restrict__ rp, const int *__restrict__ ci,
                              const double *__restrict__ v, const int *__restrict__ nrp,
                              int *__restrict__ nci, double *__restrict__ f) {
-  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (I >= nn) return;
   const int nb = nrp[I + 1] - nrp[I];
-  for (int q = 0; q < nb; ++q) {
+  for (int q = l; q < nb; q += G) {
     double acc = 0.0;
     for (int r = 0; r < 3; ++r) {
       const int s = rp[3 * I + r] + 3 * q;
@@ -234,7 +236,7 @@ void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t
     bv_unused.reset();
     DArr<int> nci(nnzb, s);
     DArr<double> f(nnzb, s), fd(nn, s);
-    k_node_norms<<<grid_for(nn, 256), 256, 0, s>>>(nn, A.rp.p, A.ci.p, A.v.p, nrp.p, nci.p, f.p);
+    k_node_norms<16><<<grid_for(nn * 16, 256), 256, 0, s>>>(nn, A.rp.p, A.ci.p, A.v.p, nrp.p, nci.p, f.p);
     KCHK();
     k_node_diag<<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp.p, nci.p, f.p, fd.p);
     KCHK();

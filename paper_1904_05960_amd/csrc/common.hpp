@@ -128,7 +128,10 @@ void rowptr64_to_32(const int64_t *in, int *out, int64_t n1, int *flag, hipStrea
 void rowptr32_to_64(const int *in, int64_t *out, int64_t n1, hipStream_t s);
 void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 int read_flag(const int *dflag, hipStream_t s);      // synchronises
+void *pinned_scratch();                               // 256 pinned host bytes per thread
 void clear_flag(int *dflag, hipStream_t s);
+// throws the error that the raised device flags describe (synchronises)
+void check_flags(const int *dflag, hipStream_t s, const char *where);
 
 // ------------------------------------------------------------------------------------
 // sparse setup kernels (spgemm.hip, setup.hip, amg_setup.hip)
@@ -149,7 +152,14 @@ struct CfSplit {
 };
 void cf_split(const int8_t *labels, int64_t n, uint32_t fmask, CfSplit &cf, hipStream_t s,
               int *dflag);
-void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s);
+// rank[x] = number of points before x with the label of x; `present` = mask of the labels
+// that occur (others are skipped)
+void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s,
+                uint32_t present = 0xffu);
+// mask of the labels that occur (ARG error for labels outside [0, 7]); synchronises
+uint32_t label_mask(const int8_t *labels, int64_t n, hipStream_t s);
+// true when labels[i] == labels[i % p] for all i; synchronises
+bool labels_periodic(const int8_t *labels, int64_t n, int p, hipStream_t s);
 void gather_labels(const int8_t *labels, const int *idx, int64_t n, int8_t *out,
                    hipStream_t s);
 // A_FF, A_FC, A_CF, A_CC of A under cf; dFF = diag(A_FF) (0 where missing).
@@ -174,6 +184,9 @@ void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
 void tentative(const DArr<int> &agg, int64_t nnode, int bs, int64_t nagg, Csr &T,
                hipStream_t s);
 double gershgorin_rho(const Csr &A, hipStream_t s, int *dflag);
+// d = diag(A), l1inv = 1 / (sum_j |a_ij|) in ascending order; returns
+// max_i sum_j |a_ij| / |a_ii| (ZERO_PIVOT on a zero diagonal); synchronises
+double row_stats(const Csr &A, double *d, double *l1inv, hipStream_t s, int *dflag);
 void diag_of(const Csr &A, double *d, hipStream_t s);
 void omega_over_diag(const double *d, double omega, double *w, int64_t n, hipStream_t s);
 void l1_inverse(const Csr &A, double *dinv, hipStream_t s);
@@ -251,6 +264,11 @@ void start_cycle_host_beta(const double *r, double beta, double *V0, double *g, 
                            int mp1, hipStream_t s);
 void spmv64_avg(const mgr_csr &A, const double *x, const double *b, double *y, double avg,
                 hipStream_t s);
+// CSR-stream SpMV (FP64, int64 row pointers): row blocks of about 2048 entries
+int64_t stream_blocks(int64_t nnz);
+void rowblocks64(const mgr_csr &A, int64_t nnz, int *rb, hipStream_t s);
+void spmv64_stream(const mgr_csr &A, int64_t nnz, const int *rb, const double *x, const double *b,
+                   double *y, hipStream_t s);
 
 // ------------------------------------------------------------------------------------
 // profiling hooks (abi.hip)

@@ -109,7 +109,7 @@ void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s) {
   DArr<double> colk(n, s);
   k_gauss_jordan<<<1, GJ_THREADS, 0, s>>>(Inv, n, piv.p, colk.p, dflag);
   KCHK();
-  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "singular coarsest-grid matrix");
+  check_flags(dflag, s, "dense inverse");
 }
 
 }  // namespace mgr

@@ -2,6 +2,8 @@
 // hierarchies, the V-cycle of Algorithm 2, flexible GMRES, and the C ABI of mgr355.h.
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -14,20 +16,47 @@ namespace mgr {
 
 // ===================================================================================
 // allocation
+// Default: a caching allocator.  Blocks are rounded up to size bins and kept, after free,
+// on a free list of the stream they were freed on; a later allocation on the same stream
+// reuses them in stream order (work queued on that stream before the free completes before
+// anything queued after the reuse).  Blocks are obtained with hipMalloc; when it fails the
+// cache is released (after a device synchronisation) and the allocation retried.
 static void *(*g_alloc)(size_t, void *, void *) = nullptr;
 static void (*g_free)(void *, void *, void *) = nullptr;
 static void *g_ctx = nullptr;
-static std::once_flag g_pool_once;
 
-static void init_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+namespace {
+struct CacheKey {
+  hipStream_t s;
+  size_t bin;
+  bool operator<(const CacheKey &o) const {
+    return s < o.s || (s == o.s && bin < o.bin);
   }
+};
+std::mutex g_cache_mu;
+std::map<CacheKey, std::vector<void *>> g_cache;  // free blocks
+std::map<void *, size_t> g_live;                  // block -> bin size
+size_t g_cached_bytes = 0;
+
+size_t bin_of(size_t bytes) {
+  if (bytes <= 512) return 512;
+  // powers of two up to 1 MiB, then multiples of 1/8 of the next power of two
+  size_t p = 1;
+  while (p < bytes) p <<= 1;
+  if (p <= ((size_t)1 << 20)) return p;
+  const size_t step = p / 8;
+  return (bytes + step - 1) / step * step;
 }
+
+void release_cache_locked() {
+  for (auto &kv : g_cache)
+    for (void *q : kv.second) {
+      (void)hipFree(q);
+    }
+  g_cache.clear();
+  g_cached_bytes = 0;
+}
+}  // namespace
 
 void *dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
@@ -36,22 +65,53 @@ void *dalloc(size_t bytes, hipStream_t s) {
     if (!p) throw Error(MGR_ERR_ALLOC, "allocator hook returned NULL");
     return p;
   }
-  std::call_once(g_pool_once, init_pool);
+  const size_t bin = bin_of(bytes);
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto it = g_cache.find(CacheKey{s, bin});
+  if (it != g_cache.end() && !it->second.empty()) {
+    void *p = it->second.back();
+    it->second.pop_back();
+    g_cached_bytes -= bin;
+    g_live[p] = bin;
+    return p;
+  }
   void *p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  hipError_t e = hipMalloc(&p, bin);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    release_cache_locked();
+    e = hipMalloc(&p, bin);
+  }
   if (e != hipSuccess || !p)
-    throw Error(MGR_ERR_ALLOC, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    throw Error(MGR_ERR_ALLOC, std::string("hipMalloc(") + std::to_string(bin) + "): " +
+                                   hipGetErrorString(e));
+  g_live[p] = bin;
   return p;
 }
+
 void dfree(void *p, hipStream_t s) {
   if (!p) return;
-  if (g_free) g_free(p, s, g_ctx);
-  else (void)hipFreeAsync(p, s);
+  if (g_free) {
+    g_free(p, s, g_ctx);
+    return;
+  }
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  const size_t bin = it->second;
+  g_live.erase(it);
+  g_cache[CacheKey{s, bin}].push_back(p);
+  g_cached_bytes += bin;
 }
 
 void trace(const std::string &msg) {
   static const bool on = std::getenv("MGR355_TRACE") != nullptr;
-  if (on) std::fprintf(stderr, "[mgr355] %s\n", msg.c_str());
+  if (!on) return;
+  static auto t0 = std::chrono::steady_clock::now();
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::fprintf(stderr, "[mgr355 %10.3f ms] %s\n", ms, msg.c_str());
 }
 
 // ===================================================================================
@@ -116,6 +176,7 @@ struct MgrLevel {
   DArr<int8_t> labels;
   CfSplit cf;
   bool f_prefix = false;     // F = 0..nF-1
+  bool needs_A = true;       // the V-cycle reads A_l
   DArr<double> dFF;
   Csr Acf, Wp, Acor, G;      // Acor / G only with keep_setup
   int nb_gs = 0;             // global smoother block size
@@ -215,6 +276,7 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
           std::to_string(L.A.nnz) + " bs=" + std::to_string(bs));
     AmgGraph G;
     strength_graph(L.A, bs, o.theta0 * std::ldexp(1.0, -k), G, s, dflag);
+    trace("  strength done");
     int64_t nagg = 0;
     DArr<int> agg;
     mis2_aggregate(G, k, agg, nagg, s);
@@ -223,25 +285,31 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     if (nc == 0 || (double)nc > 0.8 * (double)n) break;
     Csr T;
     tentative(agg, n / bs, bs, nagg, T, s);
-    const double rho = gershgorin_rho(L.A, s, dflag);
-    const double omega = (4.0 / 3.0) / rho;
     DArr<double> d(n, s), w(n, s);
-    diag_of(L.A, d.p, s);
+    L.dinv.alloc(n, s);
+    const double rho = row_stats(L.A, d.p, L.dinv.p, s, dflag);
+    const double omega = (4.0 / 3.0) / rho;
     omega_over_diag(d.p, omega, w.p, n, s);
     Csr AT;
+    trace("  T, rho done");
     spgemm(L.A, T, AT, s, dflag);
+    trace("  AT done");
     merge_drop(T, AT, w.p, -1, nullptr, L.P, true, s, dflag);
     transpose(L.P, L.R, true, s);
+    trace("  P, R done");
     Csr AP;
     spgemm(L.A, L.P, AP, s, dflag);
+    trace("  AP done");
     auto N = std::make_unique<AmgLevel>();
     spgemm(L.R, AP, N->A, s, dflag);
+    trace("  RAP done");
     L.agg = std::move(agg);
     L.nagg = nagg;
     L.omega = omega;
     H.lv.push_back(std::move(N));
   }
   // coarsest: dense inverse
+  trace("  levels done");
   AmgLevel &C = *H.lv.back();
   require(C.A.n <= 4096, MGR_ERR_UNSUPPORTED,
           "AMG coarsest level above 4096 unknowns (coarsening stalled)");
@@ -254,8 +322,6 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
   const size_t sz = esz(mo);
   for (size_t k = 0; k + 1 < H.lv.size(); ++k) {
     AmgLevel &L = *H.lv[k];
-    L.dinv.alloc(L.A.n, s);
-    l1_inverse(L.A, L.dinv.p, s);
     cast_values(L.dinv.p, L.tdinv, L.A.n, sz, s);
     if (bs == 3) {
       DArr<double> bv;
@@ -282,6 +348,7 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     Lc.b.alloc(std::max<int64_t>(Lc.A.n, 1) * sz, s);
   }
   cast_values(H.cinv64.p, H.tcinv, (int64_t)H.nc * H.nc, sz, s);
+  trace("  apply copies done");
   if (!mo.keep_setup) {
     // the V-cycle only needs the apply copies (scalar levels still share the CSR pattern)
     for (size_t k = 0; k < H.lv.size(); ++k) {
@@ -474,30 +541,6 @@ void destroy_graph(mgr_handle *h) {
   h->graph = nullptr;
 }
 
-std::vector<int8_t> host_labels(const int8_t *d, int64_t n, hipStream_t s) {
-  std::vector<int8_t> h(n);
-  if (n) HIPCHK(hipMemcpyAsync(h.data(), d, n, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return h;
-}
-
-// number of labels if the rows are interleaved cell by cell (labels periodic with distinct
-// labels inside one period), else 0
-int interleave_period(const std::vector<int8_t> &lab) {
-  if (lab.empty()) return 0;
-  int present[8] = {0};
-  for (int8_t t : lab) present[t & 7] = 1;
-  int nb = 0;
-  for (int t = 0; t < 8; ++t) nb += present[t];
-  if (nb < 1 || nb > 3 || lab.size() % nb) return 0;
-  for (int i = 0; i < nb; ++i)
-    for (int j = 0; j < i; ++j)
-      if (lab[i] == lab[j]) return 0;
-  for (size_t i = 0; i < lab.size(); ++i)
-    if (lab[i] != lab[i % nb]) return 0;
-  return nb;
-}
-
 void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   hipStream_t s = h->s;
   int *flag = h->dflag.p;
@@ -518,8 +561,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     L->A = std::move(cur);
     L->labels = std::move(lab);
     const int64_t n = L->A.n;
-    std::vector<int8_t> hl = host_labels(L->labels.p, n, s);
-    for (int8_t t : hl) require(t >= 0 && t <= 7, MGR_ERR_ARG, "labels must lie in [0, 7]");
+    const uint32_t present = label_mask(L->labels.p, n, s);
     cf_split(L->labels.p, n, lo.f_label_mask, L->cf, s, flag);
     L->nF = (int)L->cf.nF;
     {
@@ -532,13 +574,13 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     DArr<int8_t> labC(nC, s);
     gather_labels(L->labels.p, L->cf.C.p, nC, labC.p, s);
     DArr<int> lrankC;
-    if (lo.nmax_drop >= 0) label_rank(labC.p, nC, lrankC, s);
+    if (lo.nmax_drop >= 0) label_rank(labC.p, nC, lrankC, s, present & ~lo.f_label_mask);
     const bool need_ff = lo.frelax != MGR_FRELAX_JACOBI;
     Csr Aff, Afc, Acc;
     L->dFF.alloc(L->cf.nF, s);
     extract_blocks(L->A, L->cf, need_ff ? &Aff : nullptr, Afc, L->Acf, Acc, L->dFF.p, s);
     check_nonzero(L->dFF.p, L->cf.nF, flag, s);
-    require(read_flag(flag, s) == 0, MGR_ERR_ZERO_PIVOT, "zero or missing diagonal in A_FF");
+    check_flags(flag, s, "D_FF");
     // W_p = -D_FF^{-1} A_FC (eq. injective_rp); M = -W_p
     Csr M;
     if (lo.interp == MGR_INTERP_JACOBI) {
@@ -551,10 +593,13 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       M.rp.alloc(M.n + 1, s);
       fill<int>(M.rp.p, 0, M.n + 1, s);
     }
+    trace("  split/extract done");
     Csr Acor;
     spgemm(L->Acf, M, Acor, s, flag);
+    trace("  A_cor done");
     Csr S;
     merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag);
+    trace("  S done");
     if (o.keep_setup) {
       if (lo.nmax_drop >= 0) drop_only(Acor, lo.nmax_drop, lrankC.p, L->G, s, flag);
       else copy_csr(Acor, L->G, s);
@@ -576,8 +621,11 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     }
     // global smoother
     if (lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI) {
-      const int nb = interleave_period(hl);
-      require(nb >= 2, MGR_ERR_UNSUPPORTED,
+      // rows interleaved cell by cell: labels periodic with the present labels distinct
+      const int nb = __builtin_popcount(present);
+      const bool ok = nb >= 2 && nb <= 3 && n % nb == 0 && labels_periodic(L->labels.p, n, nb, s) &&
+                      (label_mask(L->labels.p, nb, s) == present);
+      require(ok, MGR_ERR_UNSUPPORTED,
               "block-Jacobi smoother needs rows interleaved cell by cell (2 or 3 unknowns)");
       L->nb_gs = nb;
       L->binv64.alloc(n * nb, s);
@@ -588,8 +636,12 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     DArr<double> dinvF(L->cf.nF, s);
     omega_over_diag(L->dFF.p, 1.0, dinvF.p, L->cf.nF, s);  // 1 / d_F
     cast_values(dinvF.p, L->tdinvF, L->cf.nF, sz, s);
+    // the level matrix itself is read by the V-cycle unless the F-relaxation is a solve that
+    // starts from z = 0 (then the residual uses A_CF only)
+    const bool needs_A = lo.global_smoother != MGR_GSMOOTH_NONE || lo.frelax == MGR_FRELAX_JACOBI;
+    L->needs_A = needs_A;
     if (sz == 4) {
-      cast_values(L->A.v.p, L->tA, L->A.nnz, sz, s);
+      if (needs_A) cast_values(L->A.v.p, L->tA, L->A.nnz, sz, s);
       cast_values(L->Acf.v.p, L->tAcf, L->Acf.nnz, sz, s);
       cast_values(L->Wp.v.p, L->tWp, L->Wp.nnz, sz, s);
     }
@@ -603,6 +655,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     h->lv.push_back(std::move(L));
   }
   // coarsest grid
+  trace("mgr levels done");
   const int64_t nc = cur.n;
   if (o.coarse == MGR_COARSE_DENSE) {
     require(nc <= 4096, MGR_ERR_UNSUPPORTED, "dense coarse solve limited to 4096 unknowns");
@@ -625,6 +678,11 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   // level 0 input / output are the handle vectors; release what apply does not need
   if (!o.keep_setup) {
     for (auto &L : h->lv) {
+      if (!L->needs_A) {
+        L->A.rp.reset();
+        L->A.ci.reset();
+        L->A.v.reset();
+      }
       if (sz == 4) {
         L->A.v.reset();
         L->Acf.v.reset();
@@ -637,7 +695,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (sz == 4) h->cdense64.reset();
   }
   HIPCHK(hipStreamSynchronize(s));
-  require(read_flag(flag, s) == 0, MGR_ERR_ZERO_PIVOT, "setup flagged an invalid pivot");
+  check_flags(flag, s, "setup");
+  trace("setup done");
 }
 
 void validate_opts(const mgr_opts &o) {
@@ -706,6 +765,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct FgWork {
   double *V, *Z, *w, *r, *partial, *H, *cs, *sn, *g, *h1, *h2, *hn2, *scal, *y, *red;
+  int *rb;  // SpMV row blocks
 };
 
 size_t fg_layout(int64_t n, int m, char *base, FgWork *w) {
@@ -731,16 +791,19 @@ size_t fg_layout(int64_t n, int m, char *base, FgWork *w) {
   take(&W->scal, 8);
   take(&W->y, m + 1);
   take(&W->red, 8);
+  // row blocks: at most n + 2 entries (one block per 2048 entries, never more than rows)
+  if (w) W->rb = reinterpret_cast<int *>(base + off);
+  off += align256((size_t)(n + 2) * sizeof(int));
   return off;
 }
 
 double host_norm(const double *r, int64_t n, FgWork &W, hipStream_t s) {
   norm2_partials(r, n, W.partial, s);
   reduce_partials(W.partial, 1, W.red, false, s);
-  double v = 0.0;
-  HIPCHK(hipMemcpyAsync(&v, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
+  double *v = static_cast<double *>(pinned_scratch());
+  HIPCHK(hipMemcpyAsync(v, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return std::sqrt(v);
+  return std::sqrt(*v);
 }
 
 mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
@@ -768,12 +831,17 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
     HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   }
+  // row blocks fit the workspace unless rows average more than 2048 entries; such
+  // matrices use the lanes-per-row kernel
+  const bool streamed = stream_blocks(nnz) + 1 <= n + 2;
+  if (streamed) rowblocks64(*A, nnz, W.rb, s);
   const double avg = n ? (double)nnz / (double)n : 0.0;
   const double spmv_bytes = (double)nnz * 12.0 + (double)n * (8.0 + 8.0 + 8.0);
   auto matvec = [&](const double *xx, const double *bb, double *yy) {
     const bool prof = Prof::on(1);
     if (prof) Prof::begin(1, s);
-    spmv64_avg(*A, xx, bb, yy, avg, s);
+    if (streamed) spmv64_stream(*A, nnz, W.rb, xx, bb, yy, s);
+    else spmv64_avg(*A, xx, bb, yy, avg, s);
     if (prof) Prof::end(1, s, spmv_bytes + (bb ? (double)n * 8.0 : 0.0));
   };
   const double bnorm = host_norm(b, n, W, s);
@@ -822,8 +890,8 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
       cgs_update_partials(W.V, n, j + 1, W.h2, W.w, W.partial, true, s);
       reduce_partials(W.partial, 1, W.hn2, false, s);
       givens_step(W.H, W.cs, W.sn, W.g, W.h1, W.h2, W.hn2, j, ldh, W.scal, nullptr, s);
-      double sc[3];
-      HIPCHK(hipMemcpyAsync(sc, W.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+      double *sc = static_cast<double *>(pinned_scratch());
+      HIPCHK(hipMemcpyAsync(sc, W.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       R.est_relres = sc[0] / bnorm;
       push(R.est_relres);
@@ -990,12 +1058,29 @@ mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts, 
 
 void mgr_set_allocator(void *(*alloc_fn)(size_t, void *, void *),
                        void (*free_fn)(void *, void *, void *), void *ctx) {
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    (void)hipDeviceSynchronize();
+    release_cache_locked();
+  }
   g_alloc = alloc_fn;
   g_free = free_fn;
   g_ctx = ctx;
 }
 
 const char *mgr_last_error(void) { return t_err.c_str(); }
+
+mgr_status mgr_release_cache(void) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  (void)hipDeviceSynchronize();
+  release_cache_locked();
+  return MGR_OK;
+}
+
+size_t mgr_cached_bytes(void) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  return g_cached_bytes;
+}
 
 mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t sub, int64_t out[3]) {
   t_err.clear();

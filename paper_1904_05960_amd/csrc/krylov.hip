@@ -43,6 +43,98 @@ void launch_spmv64(const mgr_csr &A, const double *x, const double *b, double *y
   KCHK();
 }
 
+// ---------------------------------------------------------------------------------
+// CSR-stream SpMV: block k owns rows [rb[k], rb[k+1]) whose entries start in
+// [k * SNNZ, (k+1) * SNNZ).  The block's products v[e] * x[ci[e]] are written to LDS with
+// coalesced loads, then every row is summed from LDS by 8 lanes.  A block whose rows hold
+// more than SCAP entries (a row longer than SCAP - SNNZ) sums each row directly.
+constexpr int SB = 256;
+constexpr int SNNZ = 2048;
+constexpr int SCAP = 4096;
+
+__global__ void k_rowblocks(int64_t n, const int64_t *__restrict__ rp, int64_t K,
+                            int *__restrict__ rb) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k > K) return;
+  if (k == K) { rb[k] = (int)n; return; }
+  const int64_t target = k * SNNZ;
+  int64_t lo = 0, hi = n;          // first row whose start is >= target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  rb[k] = (int)lo;
+}
+
+__global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
+                                                    const int64_t *__restrict__ rp,
+                                                    const int *__restrict__ ci,
+                                                    const double *__restrict__ v,
+                                                    const double *__restrict__ x,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ y) {
+  __shared__ double prod[SCAP];
+  const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int64_t base = rp[r0];
+  const int64_t cnt = rp[r1] - base;
+  const int t = threadIdx.x;
+  if (cnt <= SCAP) {
+    // all loads of a thread issued before any gather is consumed: PER independent chains
+    constexpr int PER = SNNZ / SB;
+    for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
+      int c[PER];
+      double vv[PER], xv[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        c[u] = 0;
+        vv[u] = 0.0;
+        if (e < cnt) {
+          c[u] = ci[base + e];
+          vv[u] = v[base + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        xv[u] = (e < cnt) ? x[c[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        if (e < cnt) prod[e] = vv[u] * xv[u];
+      }
+    }
+    __syncthreads();
+    constexpr int G = 8;
+    const int l = t & (G - 1);
+    for (int row = r0 + t / G; row < r1; row += SB / G) {
+      const int s = (int)(rp[row] - base), e1 = (int)(rp[row + 1] - base);
+      double acc = 0.0;
+      for (int e = s + l; e < e1; e += G) acc += prod[e];
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+      if (l == 0) y[row] = b ? b[row] - acc : acc;
+    }
+    return;
+  }
+  __shared__ double part[SB / 64];
+  for (int row = r0; row < r1; ++row) {
+    double acc = 0.0;
+    for (int64_t e = rp[row] + t; e < rp[row + 1]; e += SB) acc += v[e] * x[ci[e]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((t & 63) == 0) part[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      const double tot = (part[0] + part[1]) + (part[2] + part[3]);
+      y[row] = b ? b[row] - tot : tot;
+    }
+    __syncthreads();
+  }
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -98,7 +190,15 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double *__restrict__ V
   double nacc = 0.0;
   for (int64_t i = i0; i < n; i += stride) {
     double wi = w[i];
-    for (int k = 0; k < nv; ++k) wi -= sh_h[k] * V[(int64_t)k * n + i];
+    int k = 0;
+    for (; k + 8 <= nv; k += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = V[(int64_t)(k + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wi -= sh_h[k + u] * t[u];
+    }
+    for (; k < nv; ++k) wi -= sh_h[k] * V[(int64_t)k * n + i];
     w[i] = wi;
     nacc += wi * wi;
   }
@@ -225,7 +325,15 @@ __global__ void k_xupdate(const double *__restrict__ Z, int64_t n, int k,
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double s = x[i];
-    for (int c = 0; c < k; ++c) s += Z[(int64_t)c * n + i] * sy[c];
+    int c = 0;
+    for (; c + 8 <= k; c += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = Z[(int64_t)(c + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += t[u] * sy[c + u];
+    }
+    for (; c < k; ++c) s += Z[(int64_t)c * n + i] * sy[c];
     x[i] = s;
   }
 }
@@ -238,8 +346,34 @@ unsigned sgrid(int64_t n) {
 
 }  // namespace
 
+int64_t stream_blocks(int64_t nnz) { return (nnz + SNNZ - 1) / SNNZ; }
+
+void rowblocks64(const mgr_csr &A, int64_t nnz, int *rb, hipStream_t s) {
+  const int64_t K = stream_blocks(nnz);
+  k_rowblocks<<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
+  KCHK();
+}
+
+void spmv64_stream(const mgr_csr &A, int64_t nnz, const int *rb, const double *x, const double *b,
+                   double *y, hipStream_t s) {
+  const int64_t K = stream_blocks(nnz);
+  if (K == 0) {
+    if (A.nrows) launch_spmv64(A, x, b, y, s, 0.0);
+    return;
+  }
+  k_spmv_stream<<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
+  KCHK();
+}
+
 void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s) {
-  launch_spmv64(A, x, nullptr, y, s, A.nrows ? 1e9 : 0.0);
+  int64_t nnz = 0;
+  if (A.nrows) {
+    HIPCHK(hipMemcpyAsync(&nnz, A.row_ptr + A.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  DArr<int> rb(stream_blocks(nnz) + 1, s);
+  rowblocks64(A, nnz, rb.p, s);
+  spmv64_stream(A, nnz, rb.p, x, nullptr, y, s);
 }
 
 int krylov_partials_blocks() { return NB * KS; }

@@ -101,10 +101,10 @@ int64_t scan_generic(const T *in, T *out, int64_t n, hipStream_t s) {
   k_tile_scan<T><<<ntiles, SCAN_BLOCK, 0, s>>>(in, out, n, sums.p);
   KCHK();
   // the true total in 64 bits (the output type may be narrower)
-  int64_t tot = 0;
-  HIPCHK(hipMemcpyAsync(&tot, sums.p + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int64_t *h = static_cast<int64_t *>(pinned_scratch());
+  HIPCHK(hipMemcpyAsync(h, sums.p + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return tot;
+  return *h;
 }
 
 template <class T>
@@ -201,6 +201,7 @@ unsigned stride_grid(int64_t n) {
 }
 }  // namespace
 
+void *pinned_scratch();
 int64_t exclusive_scan_i32(const int *in, int *out, int64_t n, hipStream_t s) {
   int64_t t = scan_generic<int>(in, out, n, s);
   require(t <= 0x7fffffffLL, MGR_ERR_UNSUPPORTED, "prefix sum exceeds 2^31 (matrix too large)");
@@ -222,6 +223,8 @@ template void fill<double>(double *, double, int64_t, hipStream_t);
 template void fill<float>(float *, float, int64_t, hipStream_t);
 template void fill<int8_t>(int8_t *, int8_t, int64_t, hipStream_t);
 template void fill<uint64_t>(uint64_t *, uint64_t, int64_t, hipStream_t);
+template void fill<unsigned long long>(unsigned long long *, unsigned long long, int64_t, hipStream_t);
+template void fill<unsigned char>(unsigned char *, unsigned char, int64_t, hipStream_t);
 
 int64_t reduce_max_i64(const int64_t *p, int64_t n, hipStream_t s) {
   return reduce_generic<int64_t>(p, n, INT64_MIN, MaxOp(), s);
@@ -271,12 +274,32 @@ void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
     KCHK();
   }
 }
+// small pinned host buffer for scalar reads (one per thread)
+void *pinned_scratch() {
+  thread_local void *buf = nullptr;
+  if (!buf) HIPCHK(hipHostMalloc(&buf, 256, hipHostMallocDefault));
+  return buf;
+}
+
 int read_flag(const int *dflag, hipStream_t s) {
-  int h = 0;
-  HIPCHK(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  int *h = static_cast<int *>(pinned_scratch());
+  HIPCHK(hipMemcpyAsync(h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return h;
+  return *h;
 }
 void clear_flag(int *dflag, hipStream_t s) { fill<int>(dflag, 0, 1, s); }
+
+void check_flags(const int *dflag, hipStream_t s, const char *where) {
+  const int f = read_flag(dflag, s);
+  if (f == 0) return;
+  const std::string w = std::string(" (") + where + ")";
+  if (f & FLAG_BAD_LABEL) throw Error(MGR_ERR_ARG, "labels must lie in [0, 7]" + w);
+  if (f & FLAG_OVERFLOW) throw Error(MGR_ERR_ARG, "row pointers out of range" + w);
+  if (f & FLAG_ZERO_PIVOT)
+    throw Error(MGR_ERR_ZERO_PIVOT, "zero or missing pivot (D_FF, AMG diagonal, block or dense inverse)" + w);
+  if (f & FLAG_NOT_BLOCKED) throw Error(MGR_ERR_UNSUPPORTED, "nodal level without full 3x3 blocks" + w);
+  if (f & FLAG_ROW_TOO_LONG) throw Error(MGR_ERR_UNSUPPORTED, "a product row exceeds the supported length" + w);
+  throw Error(MGR_ERR_HIP, "internal consistency check failed (flag " + std::to_string(f) + ")" + w);
+}
 
 }  // namespace mgr

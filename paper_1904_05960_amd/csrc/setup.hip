@@ -44,6 +44,35 @@ __global__ void k_label_rank_set(const int8_t *__restrict__ lab, int64_t n, int 
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n && lab[i] == t) rank[i] = pos[i];
 }
+// bit t of *mask set when label t occurs; *bad set when a label lies outside [0, 7]
+__global__ void k_label_mask(const int8_t *__restrict__ lab, int64_t n, unsigned *__restrict__ mask,
+                             int *__restrict__ bad) {
+  unsigned m = 0;
+  int b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int t = lab[i];
+    if (t < 0 || t > 7) b = 1;
+    else m |= 1u << t;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    m |= __shfl_xor(m, o, 64);
+    b |= __shfl_xor(b, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (m) atomicOr(mask, m);
+    if (b) atomicOr(bad, 1);
+  }
+}
+// *bad set unless lab[i] == lab[i % p] for every i
+__global__ void k_label_period(const int8_t *__restrict__ lab, int64_t n, int p,
+                               int *__restrict__ bad) {
+  int b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (lab[i] != lab[i % p]) b = 1;
+  if (b) atomicOr(bad, 1);
+}
 __global__ void k_gather_i8(const int8_t *__restrict__ a, const int *__restrict__ idx, int64_t n,
                             int8_t *__restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -142,121 +171,79 @@ __global__ void k_check_nonzero(const double *__restrict__ d, int64_t n, int *fl
 }
 
 // ---------------------------------------------------------------------------------
-// merge with dropping: S = A - diag(w) keep(B).  One 64-lane workgroup per row; the row of
-// B is staged in LDS.
-constexpr int MB_MAX = 2048;
-
-template <int MODE>  // 0: count, 1: fill
-__global__ void k_merge_drop(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
-                             const double *__restrict__ av, const int *__restrict__ brp,
-                             const int *__restrict__ bci, const double *__restrict__ bv,
-                             const double *__restrict__ w, int nmax,
-                             const int *__restrict__ lrank, int *__restrict__ cnt,
-                             const int *__restrict__ srp, int *__restrict__ sci,
-                             double *__restrict__ sv, int *flag) {
-  __shared__ int bc[MB_MAX];
-  __shared__ double bvals[MB_MAX];
-  __shared__ int kpre[MB_MAX + 1];
-  __shared__ unsigned char keep[MB_MAX];
-  __shared__ unsigned char bonly[MB_MAX];
-  __shared__ int s_carry;
-  const int row = blockIdx.x;
-  const int lane = threadIdx.x;
+// merge with dropping: S = A - diag(w) keep(B).
+// keep flags (only when dropping): G lanes per row of B; an entry off the sub-block
+// diagonals is kept when fewer than nmax other off-diagonal entries beat it (larger |b|,
+// or equal |b| and a smaller column).
+template <int G>
+__global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *__restrict__ bci,
+                            const double *__restrict__ bv, int nmax,
+                            const int *__restrict__ lrank, unsigned char *__restrict__ keep) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (row >= n) return;
-  const int bs = brp[row], mb = brp[row + 1] - bs;
-  const int as = arp ? arp[row] : 0, la = arp ? arp[row + 1] - as : 0;
-  if (mb > MB_MAX) {
-    if (lane == 0) atomicOr(flag, FLAG_ROW_TOO_LONG);
-    return;
-  }
-  for (int t = lane; t < mb; t += 64) {
-    bc[t] = bci[bs + t];
-    bvals[t] = bv ? bv[bs + t] : 0.0;
-  }
-  __syncthreads();
-  const int myrank = (nmax >= 0) ? lrank[row] : 0;
-  for (int t = lane; t < mb; t += 64) {
+  const int bs = brp[row], be = brp[row + 1];
+  const int myrank = lrank[row];
+  for (int t = bs + l; t < be; t += G) {
+    const int ct = bci[t];
     bool k = true;
-    if (nmax >= 0 && lrank[bc[t]] != myrank) {
-      const double at = fabs(bvals[t]);
+    if (lrank[ct] != myrank) {
+      const double at = fabs(bv[t]);
       int rk = 0;
-      for (int u = 0; u < mb; ++u) {
-        if (lrank[bc[u]] == myrank) continue;
-        const double au = fabs(bvals[u]);
-        rk += (au > at) || (au == at && bc[u] < bc[t]);
+      for (int u = bs; u < be && rk < nmax; ++u) {
+        const int cu = bci[u];
+        if (lrank[cu] == myrank) continue;
+        const double au = fabs(bv[u]);
+        rk += (au > at) || (au == at && cu < ct);
       }
       k = rk < nmax;
     }
     keep[t] = k;
   }
-  __syncthreads();
-  // kept entries of B whose column A lacks: they take their own slots in the union
-  for (int t = lane; t < mb; t += 64) {
-    bool only = keep[t];
-    if (only && la > 0) {
-      const int c = bc[t];
-      int lo = 0, hi = la;
-      while (lo < hi) { int mid = (lo + hi) >> 1; if (aci[as + mid] < c) lo = mid + 1; else hi = mid; }
-      only = !(lo < la && aci[as + lo] == c);
-    }
-    bonly[t] = only;
-  }
-  if (lane == 0) s_carry = 0;
-  __syncthreads();
-  // kpre[t] = number of B-only entries before t
-  for (int c0 = 0; c0 < mb; c0 += 64) {
-    const int t = c0 + lane;
-    const int kv = (t < mb) ? bonly[t] : 0;
-    int inc = kv;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int x = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += x;
-    }
-    const int carry = s_carry;
-    if (t < mb) kpre[t] = carry + inc - kv;
-    __syncthreads();
-    if (lane == 63) s_carry = carry + inc;
-    __syncthreads();
-  }
-  const int K = s_carry;
-  if (lane == 0) kpre[mb] = K;
-  __syncthreads();
-  if (MODE == 0) {
-    if (lane == 0) cnt[row] = la + K;
-    return;
-  }
-  // entries of A: position p + (# B-only entries with a smaller column)
-  const int so = srp[row];
-  for (int p = lane; p < la; p += 64) {
-    const int c = aci[as + p];
-    int lo = 0, hi = mb;
-    while (lo < hi) { int mid = (lo + hi) >> 1; if (bc[mid] < c) lo = mid + 1; else hi = mid; }
-    const bool found = lo < mb && bc[lo] == c && keep[lo];
-    const int pos = p + kpre[lo];
-    sci[so + pos] = c;
-    if (sv) {
-      double a = av[as + p];
-      if (found) {
-        const double b = w ? __dmul_rn(w[row], bvals[lo]) : bvals[lo];
-        a = __dsub_rn(a, b);
+}
+
+// two-pointer merge of row `row` of A with the kept entries of row `row` of B; MODE 0
+// counts, MODE 1 writes columns (and values when sv != null)
+template <int MODE>
+__global__ void k_merge_rows(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
+                             const double *__restrict__ av, const int *__restrict__ brp,
+                             const int *__restrict__ bci, const double *__restrict__ bv,
+                             const unsigned char *__restrict__ keep, const double *__restrict__ w,
+                             int *__restrict__ cnt, const int *__restrict__ srp,
+                             int *__restrict__ sci, double *__restrict__ sv) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  int pa = arp ? arp[row] : 0;
+  const int ea = arp ? arp[row + 1] : 0;
+  int pb = brp[row];
+  const int eb = brp[row + 1];
+  const double wr = w ? w[row] : 1.0;
+  int o = MODE ? srp[row] : 0;
+  int c = 0;
+  for (;;) {
+    while (pb < eb && keep && !keep[pb]) ++pb;
+    const bool ha = pa < ea, hb = pb < eb;
+    if (!ha && !hb) break;
+    const int ca = ha ? aci[pa] : 0x7fffffff;
+    const int cb = hb ? bci[pb] : 0x7fffffff;
+    if (MODE) {
+      if (ca < cb) {
+        sci[o] = ca;
+        if (sv) sv[o] = av[pa];
+      } else {
+        const double b = w ? __dmul_rn(wr, bv[pb]) : bv[pb];
+        sci[o] = cb;
+        if (sv) sv[o] = (ca == cb) ? __dsub_rn(av[pa], b) : -b;
       }
-      sv[so + pos] = a;
+      ++o;
+    } else {
+      ++c;
     }
+    if (ca < cb) ++pa;
+    else if (cb < ca) ++pb;
+    else { ++pa; ++pb; }
   }
-  // B-only entries: position (# A entries below) + (# B-only entries below)
-  for (int t = lane; t < mb; t += 64) {
-    if (!bonly[t]) continue;
-    const int c = bc[t];
-    int lo = 0, hi = la;
-    while (lo < hi) { int mid = (lo + hi) >> 1; if (aci[as + mid] < c) lo = mid + 1; else hi = mid; }
-    const int pos = lo + kpre[t];
-    sci[so + pos] = c;
-    if (sv) {
-      const double b = w ? __dmul_rn(w[row], bvals[t]) : bvals[t];
-      sv[so + pos] = -b;
-    }
-  }
+  if (!MODE) cnt[row] = c;
 }
 
 // ---------------------------------------------------------------------------------
@@ -317,6 +304,28 @@ __global__ void k_gershgorin(int64_t n, const int *__restrict__ rp, const int *_
   if (d == 0.0) { atomicOr(flag, FLAG_ZERO_PIVOT); q[i] = 0.0; return; }
   q[i] = __ddiv_rn(rs, fabs(d));
 }
+// per row, one pass in ascending column order: the diagonal d_i, 1 / sum_j |a_ij| (the l1
+// smoother) and the Gershgorin ratio sum_j |a_ij| / |a_ii|
+__global__ void k_row_stats(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
+                            const double *__restrict__ v, double *__restrict__ d,
+                            double *__restrict__ q, double *__restrict__ l1inv, int *flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rs = 0.0, di = 0.0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const double x = v[e];
+    rs = __dadd_rn(rs, fabs(x));
+    if (ci[e] == i) di = x;
+  }
+  d[i] = di;
+  l1inv[i] = rs != 0.0 ? 1.0 / rs : 0.0;
+  if (di == 0.0) {
+    atomicOr(flag, FLAG_ZERO_PIVOT);
+    q[i] = 0.0;
+  } else {
+    q[i] = __ddiv_rn(rs, fabs(di));
+  }
+}
 __global__ void k_l1_inv(int64_t n, const int *__restrict__ rp, const double *__restrict__ v,
                          double *__restrict__ dinv) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -332,39 +341,52 @@ __global__ void k_omega_over(const double *__restrict__ d, double omega, double 
 }
 
 // ---------------------------------------------------------------------------------
-// scalar CSR with full 3x3 blocks -> BSR3
+// scalar CSR with full 3x3 blocks -> BSR3; G lanes per node, lanes over blocks
+template <int G>
 __global__ void k_bsr3_count(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
                              int *__restrict__ cnt, int *flag, int *first_bad) {
-  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (I >= nb) return;
-  const int s0 = rp[3 * I], L = rp[3 * I + 1] - s0;
-  bool ok = (L % 3 == 0) && (rp[3 * I + 2] - rp[3 * I + 1] == L) && (rp[3 * I + 3] - rp[3 * I + 2] == L);
+  const int s0 = rp[3 * I], s1 = rp[3 * I + 1], s2 = rp[3 * I + 2], s3 = rp[3 * I + 3];
+  const int L = s1 - s0;
+  bool ok = (L % 3 == 0) && (s2 - s1 == L) && (s3 - s2 == L);
   if (ok) {
-    for (int r = 0; r < 3 && ok; ++r) {
-      const int s = rp[3 * I + r];
-      for (int q = 0; q < L && ok; q += 3) {
-        const int c = ci[s + q];
-        ok = (c % 3 == 0) && ci[s + q + 1] == c + 1 && ci[s + q + 2] == c + 2 && ci[s0 + q] == c;
-      }
+    for (int q = 3 * l; q < L && ok; q += 3 * G) {
+      const int c = ci[s0 + q];
+      ok = (c % 3 == 0) && ci[s0 + q + 1] == c + 1 && ci[s0 + q + 2] == c + 2 &&
+           ci[s1 + q] == c && ci[s1 + q + 1] == c + 1 && ci[s1 + q + 2] == c + 2 &&
+           ci[s2 + q] == c && ci[s2 + q + 1] == c + 1 && ci[s2 + q + 2] == c + 2;
     }
   }
-  if (!ok) {
-    atomicOr(flag, FLAG_NOT_BLOCKED);
-    atomicMin(first_bad, (int)I);
+  // group AND
+  int bad = !ok;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, G);
+  if (l == 0) {
+    if (bad) {
+      atomicOr(flag, FLAG_NOT_BLOCKED);
+      atomicMin(first_bad, (int)I);
+    }
+    cnt[I] = bad ? 0 : L / 3;
   }
-  cnt[I] = ok ? L / 3 : 0;
 }
+template <int G>
 __global__ void k_bsr3_fill(int64_t nb, const int *__restrict__ rp, const int *__restrict__ ci,
                             const double *__restrict__ v, const int *__restrict__ brp,
                             int *__restrict__ bci, double *__restrict__ bv) {
-  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (I >= nb) return;
-  const int nbk = brp[I + 1] - brp[I];
-  for (int q = 0; q < nbk; ++q) {
-    const int blk = brp[I] + q;
-    bci[blk] = ci[rp[3 * I] + 3 * q] / 3;
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) bv[9 * (int64_t)blk + 3 * r + c] = v[rp[3 * I + r] + 3 * q + c];
+  const int b0 = brp[I], nbk = brp[I + 1] - b0;
+  const int r0 = rp[3 * I], r1 = rp[3 * I + 1], r2 = rp[3 * I + 2];
+  for (int q = l; q < nbk; q += G) {
+    const int blk = b0 + q;
+    bci[blk] = ci[r0 + 3 * q] / 3;
+    double *o = bv + 9 * (int64_t)blk;
+    o[0] = v[r0 + 3 * q]; o[1] = v[r0 + 3 * q + 1]; o[2] = v[r0 + 3 * q + 2];
+    o[3] = v[r1 + 3 * q]; o[4] = v[r1 + 3 * q + 1]; o[5] = v[r1 + 3 * q + 2];
+    o[6] = v[r2 + 3 * q]; o[7] = v[r2 + 3 * q + 1]; o[8] = v[r2 + 3 * q + 2];
   }
 }
 
@@ -427,7 +449,7 @@ void cf_split(const int8_t *labels, int64_t n, uint32_t fmask, CfSplit &cf, hipS
   KCHK();
   cf.nF = exclusive_scan_i32(isF.p, fpos.p, n, s);
   cf.nC = n - cf.nF;
-  require(read_flag(dflag, s) == 0, MGR_ERR_ARG, "labels must lie in [0, 7]");
+  check_flags(dflag, s, "C/F split");
   require(cf.nF > 0 && cf.nC > 0, MGR_ERR_ARG, "a reduction level has an empty F or C set");
   cf.F.alloc(cf.nF, s);
   cf.C.alloc(cf.nC, s);
@@ -436,10 +458,37 @@ void cf_split(const int8_t *labels, int64_t n, uint32_t fmask, CfSplit &cf, hipS
   KCHK();
 }
 
-void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s) {
+uint32_t label_mask(const int8_t *labels, int64_t n, hipStream_t s) {
+  DArr<int> buf(2, s);
+  fill<int>(buf.p, 0, 2, s);
+  if (n > 0) {
+    k_label_mask<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(
+        labels, n, reinterpret_cast<unsigned *>(buf.p), buf.p + 1);
+    KCHK();
+  }
+  int h[2];
+  HIPCHK(hipMemcpyAsync(h, buf.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  require(h[1] == 0, MGR_ERR_ARG, "labels must lie in [0, 7]");
+  return (uint32_t)h[0];
+}
+
+bool labels_periodic(const int8_t *labels, int64_t n, int p, hipStream_t s) {
+  DArr<int> bad(1, s);
+  fill<int>(bad.p, 0, 1, s);
+  if (n > 0) {
+    k_label_period<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(labels, n, p, bad.p);
+    KCHK();
+  }
+  return read_flag(bad.p, s) == 0;
+}
+
+void label_rank(const int8_t *labels, int64_t n, DArr<int> &rank, hipStream_t s,
+                uint32_t present) {
   rank.alloc(n, s);
   DArr<int> fl(n, s), pos(n + 1, s);
   for (int t = 0; t < 8; ++t) {
+    if (!((present >> t) & 1u)) continue;
     k_label_eq<<<grid_for(n, 256), 256, 0, s>>>(labels, n, t, fl.p);
     KCHK();
     if (exclusive_scan_i32(fl.p, pos.p, n, s) == 0) continue;
@@ -497,25 +546,38 @@ void check_nonzero(const double *d, int64_t n, int *dflag, hipStream_t s) {
 
 void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int *lrank, Csr &S,
                 bool values, hipStream_t s, int *dflag) {
+  (void)dflag;
   const int64_t n = B.n;
   S.n = n;
   S.m = B.m;
   S.rp.alloc(n + 1, s);
   DArr<int> cnt(n + 1, s);
+  DArr<unsigned char> keep;
+  if (nmax >= 0 && B.nnz > 0) {
+    require(lrank != nullptr, MGR_ERR_ARG, "dropping needs per-label ranks");
+    keep.alloc(B.nnz, s);
+    constexpr int G = 16;
+    k_drop_keep<G><<<grid_for(n * G, 256), 256, 0, s>>>(n, B.rp.p, B.ci.p, B.v.p, nmax, lrank,
+                                                        keep.p);
+    KCHK();
+  }
   const int *arp = A.n ? A.rp.p : nullptr;
-  k_merge_drop<0><<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
-      n, arp, A.ci.p, A.v.p, B.rp.p, B.ci.p, values ? B.v.p : nullptr, w, nmax, lrank, cnt.p,
-      nullptr, nullptr, nullptr, dflag);
-  KCHK();
+  const unsigned char *kp = keep.p;
+  if (n > 0) {
+    k_merge_rows<0><<<grid_for(n, 256), 256, 0, s>>>(n, arp, A.ci.p, nullptr, B.rp.p, B.ci.p,
+                                                     nullptr, kp, nullptr, cnt.p, nullptr,
+                                                     nullptr, nullptr);
+    KCHK();
+  }
   S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, n, s);
-  require(read_flag(dflag, s) == 0, MGR_ERR_UNSUPPORTED,
-          "merge/drop: a row of the correction term exceeds 2048 entries");
   S.ci.alloc(S.nnz, s);
   if (values) S.v.alloc(S.nnz, s);
-  k_merge_drop<1><<<(unsigned)std::max<int64_t>(n, 1), 64, 0, s>>>(
-      n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p, values ? B.v.p : nullptr, w,
-      nmax, lrank, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr, dflag);
-  KCHK();
+  if (n > 0) {
+    k_merge_rows<1><<<grid_for(n, 256), 256, 0, s>>>(
+        n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p, values ? B.v.p : nullptr, kp,
+        w, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr);
+    KCHK();
+  }
 }
 
 void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag) {
@@ -557,12 +619,24 @@ void diag_of(const Csr &A, double *d, hipStream_t s) {
   KCHK();
 }
 
+double row_stats(const Csr &A, double *d, double *l1inv, hipStream_t s, int *dflag) {
+  DArr<double> q(std::max<int64_t>(A.n, 1), s);
+  if (A.n > 0) {
+    k_row_stats<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d, q.p, l1inv,
+                                                   dflag);
+    KCHK();
+  }
+  const double r = reduce_max_f64(q.p, A.n, s);
+  check_flags(dflag, s, "AMG diagonal");
+  return r;
+}
+
 double gershgorin_rho(const Csr &A, hipStream_t s, int *dflag) {
   DArr<double> q(A.n, s);
   k_gershgorin<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, q.p, dflag);
   KCHK();
   double r = reduce_max_f64(q.p, A.n, s);
-  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "AMG level matrix has a zero diagonal");
+  check_flags(dflag, s, "AMG diagonal");
   return r;
 }
 
@@ -608,7 +682,7 @@ void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
     HIPCHK(hipMemcpyAsync(B.ci.p, A->col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(B.v.p, A->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  require(read_flag(dflag, s) == 0, MGR_ERR_ARG, "row pointers out of range");
+  check_flags(dflag, s, "matrix import");
 }
 
 uint64_t pattern_hash(const Csr &A, hipStream_t s) {
@@ -633,7 +707,7 @@ void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, in
   mb = A.m / 3;
   DArr<int> cnt(nb + 1, s), bad(1, s);
   fill<int>(bad.p, 0x7fffffff, 1, s);
-  k_bsr3_count<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, cnt.p, dflag, bad.p);
+  k_bsr3_count<16><<<grid_for(nb * 16, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, cnt.p, dflag, bad.p);
   KCHK();
   rp.alloc(nb + 1, s);
   nnzb = exclusive_scan_i32(cnt.p, rp.p, nb, s);
@@ -649,10 +723,10 @@ void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, in
                     std::to_string(I) + ", row lengths " + std::to_string(r[1] - r[0]) + "/" +
                     std::to_string(r[2] - r[1]) + "/" + std::to_string(r[3] - r[2]) + ")");
   }
-  require(f == 0, MGR_ERR_HIP, "unexpected device flag before block conversion");
+  check_flags(dflag, s, "block conversion");
   ci.alloc(nnzb, s);
   v.alloc(nnzb * 9, s);
-  k_bsr3_fill<<<grid_for(nb, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, A.v.p, rp.p, ci.p, v.p);
+  k_bsr3_fill<16><<<grid_for(nb * 16, 256), 256, 0, s>>>(nb, A.rp.p, A.ci.p, A.v.p, rp.p, ci.p, v.p);
   KCHK();
 }
 
@@ -661,7 +735,7 @@ void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *d
   const int64_t nblk = A.n / nb;
   k_block_inv<<<grid_for(nblk, 256), 256, 0, s>>>(nblk, nb, A.rp.p, A.ci.p, A.v.p, inv, dflag);
   KCHK();
-  require(read_flag(dflag, s) == 0, MGR_ERR_ZERO_PIVOT, "singular same-cell block");
+  check_flags(dflag, s, "same-cell blocks");
 }
 
 }  // namespace mgr

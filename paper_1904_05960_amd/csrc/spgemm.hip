@@ -21,10 +21,7 @@
 namespace mgr {
 namespace {
 
-constexpr int WG = 64;
-constexpr int SYM_HT = 4096;       // LDS symbolic table size (int keys)
-constexpr int NUM_HT_SMALL = 128;  // rows with <= 64 entries
-constexpr int NUM_HT_MID = 1024;   // rows with <= 512 entries
+constexpr int SYM_HT = 4096;       // second-pass LDS symbolic table size (int keys)
 
 __device__ __forceinline__ unsigned hslot(int key, unsigned mask) {
   return ((unsigned)key * 2654435761u) & mask;
@@ -36,16 +33,21 @@ __device__ __forceinline__ int next_pow2_dev(int64_t v) {
   return p;
 }
 
+// ub[i] = number of products of row i (sum of the lengths of the rows of B it selects)
 __global__ void k_upper_bound(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
                               const int *__restrict__ brp, int64_t *__restrict__ ub) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  constexpr int G = 16;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (i >= n) return;
   int64_t s = 0;
-  for (int e = arp[i]; e < arp[i + 1]; ++e) {
-    int k = aci[e];
+  for (int e = arp[i] + l; e < arp[i + 1]; e += G) {
+    const int k = aci[e];
     s += brp[k + 1] - brp[k];
   }
-  ub[i] = s;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (l == 0) ub[i] = s;
 }
 
 // Inserts `key` (>= 0) into the table; returns 1 if it was new, 0 if present, -1 if the
@@ -77,74 +79,101 @@ __device__ __forceinline__ unsigned table_find_or_insert(int *keys, unsigned mas
   return mask + 1;
 }
 
-// Symbolic count of one row with a table of `ht` slots; returns -1 if more than 3/4 of the
-// table would be needed.  All 64 lanes of the workgroup call it.
+// Symbolic count of one row by a group of G lanes with a table of `ht` slots; returns -1
+// if more than 3/4 of the table would be needed.  Products are taken flat (their order does
+// not matter here): the entries of the row of A are read G at a time and the lanes walk the
+// concatenated rows of B they select.
+template <int G>
 __device__ int sym_row(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                        const int *__restrict__ brp, const int *__restrict__ bci, int *keys,
                        int ht, int *s_count, int *s_excl, int *s_start) {
-  const int lane = threadIdx.x;
+  const int l = threadIdx.x & (G - 1);
   const unsigned mask = (unsigned)ht - 1;
-  for (int s = lane; s < ht; s += WG) keys[s] = -1;
-  if (lane == 0) *s_count = 0;
-  __syncthreads();
+  for (int s = l; s < ht; s += G) keys[s] = -1;
+  if (l == 0) *s_count = 0;
+  __builtin_amdgcn_wave_barrier();
   const int limit = (ht / 4) * 3;
   const int as = arp[row], ae = arp[row + 1];
-  bool over = false;
-  for (int c0 = as; c0 < ae; c0 += WG) {
-    // per chunk of 64 A entries: exclusive prefix of B row lengths
-    int e = c0 + lane;
+  int over = 0;
+  for (int c0 = as; c0 < ae; c0 += G) {
+    const int e = c0 + l;
     int len = 0, st = 0;
     if (e < ae) {
-      int k = aci[e];
+      const int k = aci[e];
       st = brp[k];
       len = brp[k + 1] - st;
     }
     int inc = len;
 #pragma unroll
-    for (int o = 1; o < WG; o <<= 1) {
-      int t = __shfl_up(inc, o, WG);
-      if (lane >= o) inc += t;
+    for (int o = 1; o < G; o <<= 1) {
+      const int t = __shfl_up(inc, o, G);
+      if (l >= o) inc += t;
     }
-    s_excl[lane] = inc - len;
-    s_start[lane] = st;
-    const int total = __shfl(inc, WG - 1, WG);
-    __syncthreads();
-    const int nent = min(WG, ae - c0);
-    for (int p = lane; p < total; p += WG) {
-      // entry t with s_excl[t] <= p < s_excl[t+1]
-      int lo = 0, hi = nent - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s_excl[mid] <= p) lo = mid; else hi = mid - 1;
+    s_excl[l] = inc - len;
+    s_start[l] = st;
+    const int total = __shfl(inc, G - 1, G);
+    __builtin_amdgcn_wave_barrier();
+    const int nent = min(G, ae - c0);
+    constexpr int PU = 4;
+    for (int p0 = 0; p0 < total; p0 += PU * G) {
+      int jj[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int p = p0 + u * G + l;
+        jj[u] = -1;
+        if (p < total) {
+          int lo = 0, hi = nent - 1;        // entry t with s_excl[t] <= p < s_excl[t+1]
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_excl[mid] <= p) lo = mid; else hi = mid - 1;
+          }
+          jj[u] = bci[s_start[lo] + (p - s_excl[lo])];
+        }
       }
-      int j = bci[s_start[lo] + (p - s_excl[lo])];
-      int r = table_insert(keys, mask, j);
-      if (r == 1) {
-        int c = atomicAdd(s_count, 1);
-        if (c >= limit) over = true;
-      } else if (r < 0) {
-        over = true;
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        if (jj[u] < 0) continue;
+        const int r = table_insert(keys, mask, jj[u]);
+        if (r == 1) {
+          if (atomicAdd(s_count, 1) >= limit) over = 1;
+        } else if (r < 0) {
+          over = 1;
+        }
       }
     }
-    __syncthreads();
-    if (__syncthreads_or(over)) return -1;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) over |= __shfl_xor(over, o, G);
+    if (over) return -1;
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
   return *s_count;
 }
 
-__global__ void k_sym_lds(int64_t n, const int64_t *__restrict__ ub, const int *__restrict__ arp,
-                          const int *__restrict__ aci, const int *__restrict__ brp,
-                          const int *__restrict__ bci, int *__restrict__ cnt,
-                          int *__restrict__ retry, int *__restrict__ nretry) {
-  __shared__ int keys[SYM_HT];
-  __shared__ int s_count, s_excl[WG], s_start[WG];
-  const int row = blockIdx.x;
-  if (row >= n) return;
+// rows of `rows` (or all rows when rows == nullptr), 64 / G per 64-lane workgroup, tables of
+// at most HT slots (smaller for rows with few products); overflowing rows go to `retry`
+template <int G, int HT>
+__global__ void __launch_bounds__(64) k_sym_lds(int64_t nrows, const int *__restrict__ rows,
+                                                const int64_t *__restrict__ ub,
+                                                const int *__restrict__ arp,
+                                                const int *__restrict__ aci,
+                                                const int *__restrict__ brp,
+                                                const int *__restrict__ bci,
+                                                int *__restrict__ cnt, int *__restrict__ retry,
+                                                int *__restrict__ nretry) {
+  constexpr int NR = 64 / G;
+  __shared__ int keys[NR][HT];
+  __shared__ int s_count[NR], s_excl[NR][G], s_start[NR][G];
+  const int g = threadIdx.x / G;
+  const int64_t idx = (int64_t)blockIdx.x * NR + g;
+  if (idx >= nrows) return;
+  const int row = rows ? rows[idx] : (int)idx;
   const int64_t u = ub[row];
-  const int ht = u > SYM_HT / 2 ? SYM_HT : next_pow2_dev(u < 32 ? 64 : 2 * u);
-  int c = sym_row(row, arp, aci, brp, bci, keys, ht, &s_count, s_excl, s_start);
-  if (threadIdx.x == 0) {
+  const int ht = u > HT / 2 ? HT : next_pow2_dev(u < 16 ? 32 : 2 * u);
+  const int c = sym_row<G>(row, arp, aci, brp, bci, keys[g], ht, &s_count[g], s_excl[g],
+                           s_start[g]);
+  if ((threadIdx.x & (G - 1)) == 0) {
     if (c < 0) {
       cnt[row] = 0;
       retry[atomicAdd(nretry, 1)] = row;
@@ -154,50 +183,89 @@ __global__ void k_sym_lds(int64_t n, const int64_t *__restrict__ ub, const int *
   }
 }
 
-__global__ void k_sym_global(int nrows, const int *__restrict__ rows, int ht,
-                             const int *__restrict__ arp, const int *__restrict__ aci,
-                             const int *__restrict__ brp, const int *__restrict__ bci,
-                             int *__restrict__ cnt, int *__restrict__ scratch,
-                             int *__restrict__ flag) {
-  __shared__ int s_count, s_excl[WG], s_start[WG];
+__global__ void __launch_bounds__(64) k_sym_global(int nrows, const int *__restrict__ rows, int ht,
+                                                   const int *__restrict__ arp,
+                                                   const int *__restrict__ aci,
+                                                   const int *__restrict__ brp,
+                                                   const int *__restrict__ bci,
+                                                   int *__restrict__ cnt,
+                                                   int *__restrict__ scratch,
+                                                   int *__restrict__ flag) {
+  __shared__ int s_count, s_excl[64], s_start[64];
   if ((int)blockIdx.x >= nrows) return;
   const int row = rows[blockIdx.x];
   int *keys = scratch + (int64_t)blockIdx.x * ht;
-  int c = sym_row(row, arp, aci, brp, bci, keys, ht, &s_count, s_excl, s_start);
+  const int c = sym_row<64>(row, arp, aci, brp, bci, keys, ht, &s_count, s_excl, s_start);
   if (threadIdx.x == 0) {
     if (c < 0) { atomicOr(flag, FLAG_ROW_TOO_LONG); cnt[row] = 0; }
     else cnt[row] = c;
   }
 }
 
-// Numeric phase for one row: keys/vals table of `ht` slots plus a compaction list of ht/2.
-__device__ void num_row(int row, const int *__restrict__ arp, const int *__restrict__ aci,
-                        const double *__restrict__ av, const int *__restrict__ brp,
-                        const int *__restrict__ bci, const double *__restrict__ bv,
-                        const int *__restrict__ crp, int *__restrict__ cci,
-                        double *__restrict__ cv, int *keys, double *vals, int *lk, double *lv,
-                        int ht, int *s_n, int *flag) {
-  const int lane = threadIdx.x;
+template <int G>
+__device__ void num_row_g(int row, const int *__restrict__ arp, const int *__restrict__ aci,
+                          const double *__restrict__ av, const int *__restrict__ brp,
+                          const int *__restrict__ bci, const double *__restrict__ bv,
+                          const int *__restrict__ crp, int *__restrict__ cci,
+                          double *__restrict__ cv, int *keys, double *vals, int *lk, double *lv,
+                          int ht, int *s_n, int *flag) {
+  const int l = threadIdx.x & (G - 1);
   const unsigned mask = (unsigned)ht - 1;
-  for (int s = lane; s < ht; s += WG) {
+  for (int s = l; s < ht; s += G) {
     keys[s] = -1;
     vals[s] = 0.0;
   }
-  if (lane == 0) *s_n = 0;
-  __syncthreads();
+  if (l == 0) *s_n = 0;
+  __builtin_amdgcn_wave_barrier();
   const int as = arp[row], ae = arp[row + 1];
-  for (int e = as; e < ae; ++e) {          // ascending k: the pinned order
-    const int k = aci[e];
-    const double a = av[e];
-    const int bs = brp[k], be = brp[k + 1];
-    for (int q = bs + lane; q < be; q += WG) {
-      const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
-      if (slot > mask) { atomicOr(flag, FLAG_PATTERN); continue; }
-      vals[slot] = __dadd_rn(vals[slot], __dmul_rn(a, bv[q]));
+  for (int c0 = as; c0 < ae; c0 += G) {
+    const int e = c0 + l;
+    int k = 0, b0 = 0, b1 = 0;
+    double a = 0.0;
+    if (e < ae) {
+      k = aci[e];
+      a = av[e];
+      b0 = brp[k];
+      b1 = brp[k + 1];
     }
-    __syncthreads();
+    const int cnt = min(G, ae - c0);
+    // PF steps at a time: the first G entries of each selected row of B are loaded into
+    // registers for all PF steps before they are applied, in ascending k
+    constexpr int PF = 8;
+    for (int t0 = 0; t0 < cnt; t0 += PF) {
+      int jj[PF], qa[PF], qb[PF];
+      double bb[PF], at[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int tt = (t0 + u < cnt) ? t0 + u : 0;
+        at[u] = __shfl(a, tt, G);
+        qa[u] = __shfl(b0, tt, G);
+        qb[u] = (t0 + u < cnt) ? __shfl(b1, tt, G) : qa[u];
+        const int q = qa[u] + l;
+        const bool ok = q < qb[u];
+        jj[u] = ok ? bci[q] : -1;
+        bb[u] = ok ? bv[q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (t0 + u < cnt) {
+          if (jj[u] >= 0) {
+            const unsigned slot = table_find_or_insert(keys, mask, jj[u]);
+            if (slot > mask) atomicOr(flag, FLAG_PATTERN);
+            else vals[slot] = __dadd_rn(vals[slot], __dmul_rn(at[u], bb[u]));
+          }
+          for (int q = qa[u] + G + l; q < qb[u]; q += G) {   // rows of B longer than G
+            const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
+            if (slot > mask) { atomicOr(flag, FLAG_PATTERN); continue; }
+            vals[slot] = __dadd_rn(vals[slot], __dmul_rn(at[u], bv[q]));
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
   }
-  for (int s = lane; s < ht; s += WG) {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int s = l; s < ht; s += G) {
     const int key = keys[s];
     if (key != -1) {
       const int t = atomicAdd(s_n, 1);
@@ -207,16 +275,15 @@ __device__ void num_row(int row, const int *__restrict__ arp, const int *__restr
       }
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
   const int m = *s_n;
-  if (m > ht / 2) {
-    if (lane == 0) atomicOr(flag, FLAG_PATTERN);
+  const int base = crp[row];
+  if (m > ht / 2 || m != crp[row + 1] - base) {
+    if (l == 0) atomicOr(flag, FLAG_PATTERN);
     return;
   }
-  const int base = crp[row];
-  if (lane == 0 && m != crp[row + 1] - base) atomicOr(flag, FLAG_PATTERN);
-  if (m != crp[row + 1] - base) return;
-  for (int t = lane; t < m; t += WG) {
+  for (int t = l; t < m; t += G) {
     const int key = lk[t];
     int rank = 0;
     for (int u = 0; u < m; ++u) rank += (lk[u] < key);
@@ -225,29 +292,40 @@ __device__ void num_row(int row, const int *__restrict__ arp, const int *__restr
   }
 }
 
-template <int HT>
-__global__ void k_num_lds(int nrows, const int *__restrict__ rows, const int *__restrict__ arp,
-                          const int *__restrict__ aci, const double *__restrict__ av,
-                          const int *__restrict__ brp, const int *__restrict__ bci,
-                          const double *__restrict__ bv, const int *__restrict__ crp,
-                          int *__restrict__ cci, double *__restrict__ cv, int *flag) {
-  __shared__ int keys[HT];
-  __shared__ double vals[HT];
-  __shared__ int lk[HT / 2];
-  __shared__ double lv[HT / 2];
-  __shared__ int s_n;
-  if ((int)blockIdx.x >= nrows) return;
-  const int row = rows[blockIdx.x];
-  num_row(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, HT, &s_n, flag);
+// one 64-lane workgroup = 64 / G rows, each with its own table of HT slots
+template <int G, int HT>
+__global__ void __launch_bounds__(64) k_num_lds(int nrows, const int *__restrict__ rows,
+                                                const int *__restrict__ arp,
+                                                const int *__restrict__ aci,
+                                                const double *__restrict__ av,
+                                                const int *__restrict__ brp,
+                                                const int *__restrict__ bci,
+                                                const double *__restrict__ bv,
+                                                const int *__restrict__ crp, int *__restrict__ cci,
+                                                double *__restrict__ cv, int *flag) {
+  constexpr int NR = 64 / G;
+  __shared__ int keys[NR][HT];
+  __shared__ double vals[NR][HT];
+  __shared__ int lk[NR][HT / 2];
+  __shared__ double lv[NR][HT / 2];
+  __shared__ int s_n[NR];
+  const int g = threadIdx.x / G;
+  const int idx = blockIdx.x * NR + g;
+  if (idx >= nrows) return;
+  num_row_g<G>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g], lk[g], lv[g],
+               HT, &s_n[g], flag);
 }
 
-__global__ void k_num_global(int nrows, const int *__restrict__ rows, int ht,
-                             const int *__restrict__ arp, const int *__restrict__ aci,
-                             const double *__restrict__ av, const int *__restrict__ brp,
-                             const int *__restrict__ bci, const double *__restrict__ bv,
-                             const int *__restrict__ crp, int *__restrict__ cci,
-                             double *__restrict__ cv, int *scratch_i, double *scratch_d,
-                             int *flag) {
+__global__ void __launch_bounds__(64) k_num_global(int nrows, const int *__restrict__ rows, int ht,
+                                                   const int *__restrict__ arp,
+                                                   const int *__restrict__ aci,
+                                                   const double *__restrict__ av,
+                                                   const int *__restrict__ brp,
+                                                   const int *__restrict__ bci,
+                                                   const double *__restrict__ bv,
+                                                   const int *__restrict__ crp,
+                                                   int *__restrict__ cci, double *__restrict__ cv,
+                                                   int *scratch_i, double *scratch_d, int *flag) {
   __shared__ int s_n;
   if ((int)blockIdx.x >= nrows) return;
   const int row = rows[blockIdx.x];
@@ -255,19 +333,30 @@ __global__ void k_num_global(int nrows, const int *__restrict__ rows, int ht,
   int *lk = keys + ht;
   double *vals = scratch_d + (int64_t)blockIdx.x * (ht + ht / 2);
   double *lv = vals + ht;
-  num_row(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
+  num_row_g<64>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
 }
 
-// rows by output length: bucket 0 (<= 64), 1 (<= 512), 2 (larger); empty rows skipped
+// rows by output length into NBUCKET buckets (table sizes 128 .. 1024, then global);
+// empty rows skipped.  Appends are aggregated per wavefront.
+constexpr int NBUCKET = 5;
 __global__ void k_bucket(int64_t n, const int *__restrict__ crp, int *__restrict__ lists,
                          int *__restrict__ counts, int64_t stride) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int len = crp[i + 1] - crp[i];
-  if (len == 0) return;
-  int b = len <= NUM_HT_SMALL / 2 ? 0 : (len <= NUM_HT_MID / 2 ? 1 : 2);
-  int pos = atomicAdd(&counts[b], 1);
-  lists[b * stride + pos] = (int)i;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int b = -1;
+  if (i < n) {
+    const int len = crp[i + 1] - crp[i];
+    if (len > 0) b = len <= 64 ? 0 : len <= 128 ? 1 : len <= 256 ? 2 : len <= 512 ? 3 : 4;
+  }
+  for (int k = 0; k < NBUCKET; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[k], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (b == k) lists[k * stride + base + __popcll(m & ((1ull << lane) - 1))] = (int)i;
+  }
 }
 
 __global__ void k_max_len(int nrows, const int *__restrict__ rows, const int *__restrict__ crp,
@@ -293,6 +382,39 @@ int64_t next_pow2(int64_t v) {
 
 }  // namespace
 
+namespace {
+template <int G, int HT>
+void launch_num(int nrows, const int *rows, const Csr &A, const Csr &B, Csr &C, int *dflag,
+                hipStream_t s) {
+  constexpr int NR = 64 / G;
+  k_num_lds<G, HT><<<(nrows + NR - 1) / NR, 64, 0, s>>>(nrows, rows, A.rp.p, A.ci.p, A.v.p, B.rp.p,
+                                                        B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p,
+                                                        dflag);
+  KCHK();
+}
+
+// table HT for rows of at most HT/2 outputs; G lanes per row, raised so that the tables of
+// one workgroup stay within 36 KB of LDS
+void dispatch_num(int bucket, int g0, int nrows, const int *rows, const Csr &A, const Csr &B,
+                  Csr &C, int *dflag, hipStream_t s) {
+  const int HT = 128 << bucket;
+  int G = std::max(g0, HT / 32);
+#define NUMCASE(GG, HH)                                          \
+  if (G == GG && HT == HH) {                                     \
+    launch_num<GG, HH>(nrows, rows, A, B, C, dflag, s);          \
+    return;                                                      \
+  }
+  NUMCASE(8, 128) NUMCASE(16, 128) NUMCASE(32, 128) NUMCASE(64, 128)
+  NUMCASE(8, 256) NUMCASE(16, 256) NUMCASE(32, 256) NUMCASE(64, 256)
+  NUMCASE(16, 512) NUMCASE(32, 512) NUMCASE(64, 512)
+  NUMCASE(32, 1024) NUMCASE(64, 1024)
+#undef NUMCASE
+  throw Error(MGR_ERR_HIP, "spgemm: no numeric kernel for this bucket");
+}
+
+int lanes_for(double mean) { return mean > 48 ? 64 : mean > 24 ? 32 : mean > 6 ? 16 : 8; }
+}  // namespace
+
 void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   require(A.m == B.n, MGR_ERR_ARG, "spgemm: inner dimensions differ");
   const int64_t n = A.n;
@@ -305,85 +427,97 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
     return;
   }
   DArr<int64_t> ub(n, s);
-  k_upper_bound<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, B.rp.p, ub.p);
+  k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, B.rp.p, ub.p);
   KCHK();
-  DArr<int> cnt(n + 1, s), retry(n, s), nretry(1, s);
-  fill<int>(nretry.p, 0, 1, s);
-  k_sym_lds<<<(unsigned)n, WG, 0, s>>>(n, ub.p, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt.p, retry.p,
-                                       nretry.p);
+  DArr<int> cnt(n + 1, s), retry(n, s), nretry(2, s);
+  fill<int>(nretry.p, 0, 2, s);
+  // symbolic pass 1: tables of <= 512 slots, 64 / G rows per workgroup
+  const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
+  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
+  const double prods = meanA * meanB;
+  if (prods > 256) {
+    k_sym_lds<64, 512><<<(unsigned)n, 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p, B.rp.p,
+                                                  B.ci.p, cnt.p, retry.p, nretry.p);
+  } else if (prods > 64) {
+    k_sym_lds<32, 512><<<(unsigned)((n + 1) / 2), 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p,
+                                                              B.rp.p, B.ci.p, cnt.p, retry.p,
+                                                              nretry.p);
+  } else {
+    k_sym_lds<16, 512><<<(unsigned)((n + 3) / 4), 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p,
+                                                              B.rp.p, B.ci.p, cnt.p, retry.p,
+                                                              nretry.p);
+  }
   KCHK();
-  int hretry = 0;
-  HIPCHK(hipMemcpyAsync(&hretry, nretry.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  int hretry = read_flag(nretry.p, s);
   if (hretry > 0) {
-    DArr<unsigned long long> mub(1, s);
-    HIPCHK(hipMemsetAsync(mub.p, 0, sizeof(unsigned long long), s));
-    k_max_ub<<<grid_for(hretry, 256), 256, 0, s>>>(hretry, retry.p, ub.p, mub.p);
+    // pass 2: 4096-slot tables, one row per workgroup
+    DArr<int> retry2(hretry, s);
+    k_sym_lds<64, SYM_HT><<<(unsigned)hretry, 64, 0, s>>>(hretry, retry.p, ub.p, A.rp.p, A.ci.p,
+                                                          B.rp.p, B.ci.p, cnt.p, retry2.p,
+                                                          nretry.p + 1);
     KCHK();
-    unsigned long long hm = 0;
-    HIPCHK(hipMemcpyAsync(&hm, mub.p, sizeof(hm), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int64_t cap = std::min<int64_t>((int64_t)hm, B.m);
-    int64_t ht = next_pow2(2 * std::max<int64_t>(cap, 32));
-    require(ht <= (int64_t)1 << 22, MGR_ERR_UNSUPPORTED,
-            "spgemm: a product row exceeds the supported length");
-    int64_t batch = std::max<int64_t>(1, ((int64_t)64 << 20) / (ht * 4));
-    DArr<int> scratch(std::min<int64_t>(batch, hretry) * ht, s);
-    for (int64_t b0 = 0; b0 < hretry; b0 += batch) {
-      int nb = (int)std::min<int64_t>(batch, hretry - b0);
-      k_sym_global<<<nb, WG, 0, s>>>(nb, retry.p + b0, (int)ht, A.rp.p, A.ci.p, B.rp.p, B.ci.p,
-                                     cnt.p, scratch.p, dflag);
+    const int hretry2 = read_flag(nretry.p + 1, s);
+    if (hretry2 > 0) {
+      // pass 3: tables in global memory sized by the largest row
+      DArr<unsigned long long> mub(1, s);
+      fill<unsigned long long>(mub.p, 0ull, 1, s);
+      k_max_ub<<<grid_for(hretry2, 256), 256, 0, s>>>(hretry2, retry2.p, ub.p, mub.p);
       KCHK();
+      unsigned long long hm = 0;
+      HIPCHK(hipMemcpyAsync(&hm, mub.p, sizeof(hm), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const int64_t cap = std::min<int64_t>((int64_t)hm, B.m);
+      const int64_t ht = next_pow2(2 * std::max<int64_t>(cap, 32));
+      require(ht <= (int64_t)1 << 22, MGR_ERR_UNSUPPORTED,
+              "spgemm: a product row exceeds the supported length");
+      const int64_t batch = std::max<int64_t>(1, ((int64_t)64 << 20) / (ht * 4));
+      DArr<int> scratch(std::min<int64_t>(batch, hretry2) * ht, s);
+      for (int64_t b0 = 0; b0 < hretry2; b0 += batch) {
+        const int nb = (int)std::min<int64_t>(batch, hretry2 - b0);
+        k_sym_global<<<nb, 64, 0, s>>>(nb, retry2.p + b0, (int)ht, A.rp.p, A.ci.p, B.rp.p,
+                                       B.ci.p, cnt.p, scratch.p, dflag);
+        KCHK();
+      }
     }
   }
   C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
-  require(read_flag(dflag, s) == 0, MGR_ERR_UNSUPPORTED, "spgemm: product row too long");
   C.ci.alloc(C.nnz, s);
   C.v.alloc(C.nnz, s);
   if (C.nnz == 0) return;
   // numeric phase by output row length
-  DArr<int> lists(3 * n, s), counts(3, s);
-  fill<int>(counts.p, 0, 3, s);
+  DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
+  fill<int>(counts.p, 0, NBUCKET, s);
   k_bucket<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
   KCHK();
-  int hc[3];
+  int hc[NBUCKET];
   HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (hc[0] > 0) {
-    k_num_lds<NUM_HT_SMALL><<<hc[0], WG, 0, s>>>(hc[0], lists.p, A.rp.p, A.ci.p, A.v.p, B.rp.p,
-                                                B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
-    KCHK();
-  }
-  if (hc[1] > 0) {
-    k_num_lds<NUM_HT_MID><<<hc[1], WG, 0, s>>>(hc[1], lists.p + n, A.rp.p, A.ci.p, A.v.p, B.rp.p,
-                                              B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
-    KCHK();
-  }
-  if (hc[2] > 0) {
+  const int g0 = lanes_for(meanB);
+  for (int b = 0; b < NBUCKET - 1; ++b)
+    if (hc[b] > 0) dispatch_num(b, g0, hc[b], lists.p + (size_t)b * n, A, B, C, dflag, s);
+  const int nbig = hc[NBUCKET - 1];
+  if (nbig > 0) {
+    const int *big = lists.p + (size_t)(NBUCKET - 1) * n;
     DArr<int> mx(1, s);
     fill<int>(mx.p, 0, 1, s);
-    k_max_len<<<grid_for(hc[2], 256), 256, 0, s>>>(hc[2], lists.p + 2 * n, C.rp.p, mx.p);
+    k_max_len<<<grid_for(nbig, 256), 256, 0, s>>>(nbig, big, C.rp.p, mx.p);
     KCHK();
-    int hm = 0;
-    HIPCHK(hipMemcpyAsync(&hm, mx.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int64_t ht = next_pow2(2 * (int64_t)hm);
+    const int hm = read_flag(mx.p, s);
+    const int64_t ht = next_pow2(2 * (int64_t)hm);
     require(ht <= (int64_t)1 << 22, MGR_ERR_UNSUPPORTED,
             "spgemm: a product row exceeds the supported length");
-    int64_t per = ht + ht / 2;
-    int64_t batch = std::max<int64_t>(1, ((int64_t)128 << 20) / (per * 12));
-    int64_t nb0 = std::min<int64_t>(batch, hc[2]);
+    const int64_t per = ht + ht / 2;
+    const int64_t batch = std::max<int64_t>(1, ((int64_t)128 << 20) / (per * 12));
+    const int64_t nb0 = std::min<int64_t>(batch, nbig);
     DArr<int> si(nb0 * per, s);
     DArr<double> sd(nb0 * per, s);
-    for (int64_t b0 = 0; b0 < hc[2]; b0 += batch) {
-      int nb = (int)std::min<int64_t>(batch, hc[2] - b0);
-      k_num_global<<<nb, WG, 0, s>>>(nb, lists.p + 2 * n + b0, (int)ht, A.rp.p, A.ci.p, A.v.p,
-                                     B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p, si.p, sd.p,
-                                     dflag);
+    for (int64_t b0 = 0; b0 < nbig; b0 += batch) {
+      const int nb = (int)std::min<int64_t>(batch, nbig - b0);
+      k_num_global<<<nb, 64, 0, s>>>(nb, big + b0, (int)ht, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
+                                     B.v.p, C.rp.p, C.ci.p, C.v.p, si.p, sd.p, dflag);
       KCHK();
     }
   }
-  require(read_flag(dflag, s) == 0, MGR_ERR_HIP, "spgemm: numeric pattern mismatch");
 }
 
 }  // namespace mgr

@@ -41,7 +41,7 @@ mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int
     auto out = std::make_unique<mgr_owned_csr>();
     out->s = s;
     spgemm(a, b, out->M, s, flag.p);
-    HIPCHK(hipStreamSynchronize(s));
+    check_flags(flag.p, s, "spgemm");
     sizes_of(out->M, sizes);
     *C = out.release();
   } catch (const Error &e) {
@@ -89,7 +89,7 @@ mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, i
     auto out = std::make_unique<mgr_owned_csr>();
     out->s = s;
     merge_drop(a, b, w, nmax, rank.p, out->M, true, s, flag.p);
-    HIPCHK(hipStreamSynchronize(s));
+    check_flags(flag.p, s, "merge/drop");
     sizes_of(out->M, sizes);
     *S = out.release();
   } catch (const Error &e) {

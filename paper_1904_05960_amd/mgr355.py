@@ -112,6 +112,8 @@ def lib():
                                C.POINTER(C.c_int64), vp]),
         "mgr_owned_export": (st, [vp, vp, vp, vp, vp]),
         "mgr_owned_free": (None, [vp]),
+        "mgr_release_cache": (st, []),
+        "mgr_cached_bytes": (C.c_size_t, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

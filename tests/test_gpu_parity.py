@@ -203,6 +203,30 @@ def test_spmv_ragged_matches_scipy():
         assert np.allclose(y, ref, rtol=1e-13, atol=1e-13 * (np.abs(ref).max() + 1e-300))
 
 
+def test_spmv_long_and_empty_rows():
+    """Rows longer than a streamed block, empty rows, and a single row."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(9)
+    n = 3000
+    lens = rng.integers(0, 40, size=n)
+    lens[[5, 6, 2000]] = [2900, 5000 if n > 5000 else 2999, 2500]
+    lens[100:110] = 0
+    rows, cols = [], []
+    for i, L in enumerate(lens):
+        c = np.sort(rng.choice(n, size=min(L, n), replace=False))
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    S = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(n, n))
+    S.sort_indices()
+    A = m.Matrix.from_host(S.indptr, S.indices, S.data)
+    x = rng.standard_normal(n)
+    y = A.spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+    assert np.allclose(y, S @ x, rtol=1e-12, atol=1e-12)
+    bb = torch.as_tensor(S @ x).cuda()
+    xs, info = m.fgmres(A, bb, restart=5, rtol=1e-30, maxit=2, raise_on_fail=False)
+    assert info["iters"] == 2
+
+
 def test_error_paths():
     w = pm.biot_single_phase(3, 3, 3, 0)
     A, labels, b = device_workload(w)
