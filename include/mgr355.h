@@ -208,6 +208,68 @@ const char *mgr_last_error(void);
  * mgr_cached_bytes reports the bytes held in the cache. [host] */
 mgr_status mgr_release_cache(void);
 size_t mgr_cached_bytes(void);
+/* Bytes currently handed out by the default allocator and the peak since the last reset
+ * (reset_peak != 0 sets the peak to the current value). [host] */
+void mgr_alloc_stats(size_t *live, size_t *peak, int32_t reset_peak);
+
+/* ---------------------------------------------------------------------------------- */
+/* Serving: a request loop over mgr_setup / mgr_setup_numeric / fgmres_solve with HBM
+ * admission, a setup cache across requests of one key, and concurrent HIP streams.
+ * `slots` worker threads each own a stream; an admitted request runs on a free slot while
+ * others run on theirs, so solves of different requests overlap on the device.  Admission
+ * is first-in first-out by the request's peak footprint (mgr_estimate_footprint for a
+ * fresh setup, plus the FGMRES workspace) against budget_bytes; idle cached setups are
+ * evicted least recently used first.  A request larger than the whole budget completes
+ * with MGR_ERR_ALLOC.  Requests that share `key` run one at a time in submission order and
+ * share the cached setup when the matrix has the same size (e.g. the Newton steps of one
+ * realization): reused as is (refresh_setup = 0, a lagged preconditioner) or recomputed
+ * with mgr_setup_numeric (refresh_setup = 1). */
+typedef struct mgr_server mgr_server;
+typedef struct {
+  size_t budget_bytes;        /* HBM admission budget (default 64 GiB)                 */
+  int32_t slots;              /* concurrent requests on the device, 1..64 (default 4) */
+  mgr_opts opts;              /* MGR options of every request                           */
+  fgmres_opts fopts;          /* FGMRES options (default restart 30, rtol 1e-6)         */
+  int32_t cache_setups;       /* keep setups between requests of a key (default 1)     */
+} mgr_server_config;
+typedef struct {
+  const mgr_csr *A;           /* [host struct, device arrays] valid until completion   */
+  int64_t nnz;                /* [host] A->row_ptr[A->nrows]                            */
+  const int8_t *labels;       /* n labels                                              */
+  const double *b;            /* right-hand side                                       */
+  double *x;                  /* initial guess in, solution out                        */
+  uint64_t key;               /* setup-cache key                                       */
+  int32_t refresh_setup;      /* 1: mgr_setup_numeric on a cached setup; 0: reuse it  */
+  int32_t last_use;           /* 1: drop the key's cached setup after this request     */
+} mgr_request;
+typedef struct {
+  int32_t status;             /* mgr_status of the request                             */
+  int32_t iters;              /* FGMRES iterations                                     */
+  int32_t setup_reused;       /* 1 if a cached setup served it                         */
+  int32_t slot;               /* worker slot that ran it                               */
+  double true_relres;         /* FP64 relative residual recomputed at the end          */
+  double t_submit_ms, t_admit_ms, t_start_ms, t_end_ms;  /* since server creation      */
+  double setup_ms, solve_ms;
+  size_t footprint;           /* bytes of the setup that served it                     */
+} mgr_result;
+typedef struct {
+  int64_t completed, queued, cache_hits, cache_misses, evictions, cached_setups;
+  size_t reserved_bytes, peak_reserved_bytes;
+} mgr_server_stats_t;
+
+void mgr_server_default_config(mgr_server_config *c);                       /* [host] */
+/* Start the worker threads.  Errors: ARG. */
+mgr_status mgr_server_create(const mgr_server_config *cfg, mgr_server **out);
+/* Queue a request (non-blocking); *ticket identifies it.  Errors: ARG. */
+mgr_status mgr_server_submit(mgr_server *s, const mgr_request *r, uint64_t *ticket);
+/* Block until the request completes; returns its status and fills *res (may be NULL).
+ * A ticket can be waited on once. */
+mgr_status mgr_server_wait(mgr_server *s, uint64_t ticket, mgr_result *res);
+/* 1 if done, 0 if pending, -1 if unknown. */
+int32_t mgr_server_poll(mgr_server *s, uint64_t ticket);
+mgr_status mgr_server_stats(mgr_server *s, mgr_server_stats_t *out);
+/* Finish every queued request, stop the workers and free the cached setups. */
+void mgr_server_destroy(mgr_server *s);
 
 /* ---------------------------------------------------------------------------------- */
 /* Inspection of a hierarchy (tests, diagnostics).  `what` selects an object:           */

@@ -37,6 +37,7 @@ std::mutex g_cache_mu;
 std::map<CacheKey, std::vector<void *>> g_cache;  // free blocks
 std::map<void *, size_t> g_live;                  // block -> bin size
 size_t g_cached_bytes = 0;
+size_t g_live_bytes = 0, g_peak_bytes = 0;        // bytes handed out (hook-less path)
 
 size_t bin_of(size_t bytes) {
   if (bytes <= 512) return 512;
@@ -73,6 +74,8 @@ void *dalloc(size_t bytes, hipStream_t s) {
     it->second.pop_back();
     g_cached_bytes -= bin;
     g_live[p] = bin;
+    g_live_bytes += bin;
+    g_peak_bytes = std::max(g_peak_bytes, g_live_bytes);
     return p;
   }
   void *p = nullptr;
@@ -87,6 +90,8 @@ void *dalloc(size_t bytes, hipStream_t s) {
     throw Error(MGR_ERR_ALLOC, std::string("hipMalloc(") + std::to_string(bin) + "): " +
                                    hipGetErrorString(e));
   g_live[p] = bin;
+  g_live_bytes += bin;
+  g_peak_bytes = std::max(g_peak_bytes, g_live_bytes);
   return p;
 }
 
@@ -101,6 +106,7 @@ void dfree(void *p, hipStream_t s) {
   if (it == g_live.end()) return;
   const size_t bin = it->second;
   g_live.erase(it);
+  g_live_bytes -= bin;
   g_cache[CacheKey{s, bin}].push_back(p);
   g_cached_bytes += bin;
 }
@@ -1048,10 +1054,13 @@ mgr_status mgr_footprint(const mgr_handle *h, size_t *bytes) {
 
 mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts, size_t *bytes) {
   if (!opts || !bytes || n < 0 || nnz < 0) { t_err = "bad argument"; return MGR_ERR_ARG; }
-  // level matrices, products and AMG hierarchies stay below three copies of A in FP64 CSR
-  // plus the setup temporaries of one sparse product of the same size, and 48 vectors.
+  // peak of setup: the imported copy of A, the level blocks and products, the AMG
+  // hierarchies and their sparse-product temporaries stay below four FP64 CSR copies of A,
+  // plus 64 level vectors and the dense coarsest inverses (size-binned by the allocator)
   const double a = (double)nnz * 12.0 + (double)(n + 1) * 4.0;
-  double est = 4.0 * a + 48.0 * 8.0 * (double)n + (double)(4096.0 * 4096.0 * 8.0 * 2);
+  const double cs = std::max(opts->amg_frelax.coarse_size, opts->amg_coarse.coarse_size);
+  const double dense = (opts->coarse == MGR_COARSE_DENSE ? 4096.0 * 4096.0 : 0.0) + cs * cs;
+  double est = 4.0 * a + 64.0 * 8.0 * (double)n + 4.0 * 8.0 * dense + (double)(16 << 20);
   *bytes = (size_t)est;
   return MGR_OK;
 }
@@ -1080,6 +1089,13 @@ mgr_status mgr_release_cache(void) {
 size_t mgr_cached_bytes(void) {
   std::lock_guard<std::mutex> g(g_cache_mu);
   return g_cached_bytes;
+}
+
+void mgr_alloc_stats(size_t *live, size_t *peak, int32_t reset_peak) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  if (live) *live = g_live_bytes;
+  if (peak) *peak = g_peak_bytes;
+  if (reset_peak) g_peak_bytes = g_live_bytes;
 }
 
 mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t sub, int64_t out[3]) {

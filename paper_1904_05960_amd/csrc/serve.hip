@@ -1,0 +1,364 @@
+// Serving engine: a device-resident request loop over the MGR/FGMRES entry points.
+//
+// Requests (a Jacobian already in HBM, its labels, b, x) arrive at any time through
+// mgr_server_submit.  `slots` worker threads, each with its own HIP stream, take admitted
+// requests concurrently, so the kernels of several solves overlap on the device
+// (continuous batching: a request is admitted as soon as a slot and enough of the HBM
+// budget are free).  Admission is FIFO by estimated peak footprint
+// (mgr_estimate_footprint for a fresh setup, plus the FGMRES workspace) against the budget;
+// idle cached setups are evicted, least recently used first, to make room.  Setups are
+// cached by a caller key (e.g. one realization across its Newton steps, whose Jacobians
+// share a sparsity pattern): a request whose key has a cached setup with the same pattern
+// reuses it, either as is (lagged preconditioner) or after mgr_setup_numeric.  Requests of
+// one key run one at a time, in submission order.  Every request records its queueing,
+// admission, start and completion times for latency percentiles.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+
+using Clock = std::chrono::steady_clock;
+
+struct mgr_server {
+  mgr_server_config cfg;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  Clock::time_point t0 = Clock::now();
+
+  struct Req {
+    uint64_t ticket;
+    mgr_request r;
+    mgr_csr A;
+    mgr_result res;
+    size_t reserve = 0;
+    bool done = false;
+  };
+  struct Entry {
+    mgr_handle *h = nullptr;
+    size_t bytes = 0;
+    int64_t n = 0, nnz = 0;
+    uint64_t last_use = 0;
+    bool busy = false;
+  };
+  std::deque<uint64_t> queue;                 // tickets waiting for admission
+  std::map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::map<uint64_t, Entry> cache;            // key -> setup
+  std::map<uint64_t, int> key_busy;           // keys with a request in flight
+  size_t used = 0;                            // reserved bytes (in flight + cached setups)
+  uint64_t next_ticket = 1, use_clock = 0;
+  int64_t completed = 0, hits = 0, misses = 0, evictions = 0;
+  size_t peak_used = 0;
+  std::vector<std::thread> workers;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+size_t fresh_setup_bytes(const mgr_server *S, const mgr_csr &A, int64_t nnz) {
+  size_t b = 0;
+  mgr_estimate_footprint(A.nrows, nnz, &S->cfg.opts, &b);
+  return b;
+}
+
+// evict idle cached setups (LRU) until `need` fits; called with the lock held
+bool make_room(mgr_server *S, size_t need) {
+  while (S->used + need > S->cfg.budget_bytes) {
+    uint64_t victim = 0;
+    uint64_t best = UINT64_MAX;
+    bool found = false;
+    for (auto &kv : S->cache)
+      if (!kv.second.busy && kv.second.last_use < best) {
+        best = kv.second.last_use;
+        victim = kv.first;
+        found = true;
+      }
+    if (!found) return false;
+    mgr_destroy(S->cache[victim].h);
+    S->used -= S->cache[victim].bytes;
+    S->cache.erase(victim);
+    ++S->evictions;
+  }
+  return true;
+}
+
+void worker(mgr_server *S, int slot) {
+  hipStream_t st = nullptr;
+  (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  void *work = nullptr;
+  size_t work_bytes = 0;
+  for (;;) {
+    mgr_server::Req *R = nullptr;
+    bool hit = false;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (;;) {
+        if (S->stop && S->queue.empty()) break;
+        // first admissible request in FIFO order; requests of a key that is in flight
+        // wait (and so do the later requests of that key); a request that can never fit
+        // the budget is rejected and the scan restarts
+        bool rescan = true;
+        while (rescan && !R) {
+          rescan = false;
+          std::map<uint64_t, bool> blocked;
+          for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+            mgr_server::Req *q = S->reqs[*it].get();
+            const uint64_t key = q->r.key;
+            if (S->key_busy[key] || blocked[key]) { blocked[key] = true; continue; }
+            const int64_t nnz = q->r.nnz;
+            auto c = S->cache.find(key);
+            if (c != S->cache.end() && !c->second.busy &&
+                (c->second.n != q->A.nrows || c->second.nnz != nnz)) {
+              // the key now names a matrix of another size: drop the stale setup
+              mgr_destroy(c->second.h);
+              S->used -= c->second.bytes;
+              S->cache.erase(c);
+              c = S->cache.end();
+            }
+            const bool cached = c != S->cache.end() && !c->second.busy;
+            size_t need = fgmres_workspace_bytes(q->A.nrows, S->cfg.fopts.restart);
+            if (!cached) need += fresh_setup_bytes(S, q->A, nnz);
+            if (need > S->cfg.budget_bytes) {
+              q->res.status = MGR_ERR_ALLOC;
+              q->res.t_admit_ms = q->res.t_start_ms = q->res.t_end_ms = S->now_ms();
+              q->done = true;
+              S->queue.erase(it);
+              S->cv_done.notify_all();
+              rescan = true;
+              break;
+            }
+            if (S->used + need > S->cfg.budget_bytes && !make_room(S, need)) {
+              break;  // strict FIFO for memory: the head blocks the requests behind it
+            }
+            R = q;
+            hit = cached;
+            R->reserve = need;
+            S->used += need;
+            S->peak_used = std::max(S->peak_used, S->used);
+            S->key_busy[key] = 1;
+            if (cached) c->second.busy = true;
+            S->queue.erase(it);
+            break;
+          }
+        }
+        if (R) break;
+        S->cv_work.wait(lk);
+      }
+      if (!R) break;
+      R->res.t_admit_ms = S->now_ms();
+    }
+    // ---- run the request on this slot's stream (no lock held) ----
+    mgr_result &res = R->res;
+    res.slot = slot;
+    mgr_status st_code = MGR_OK;
+    mgr_handle *h = nullptr;
+    const uint64_t key = R->r.key;
+    const double t_start = S->now_ms();
+    res.t_start_ms = t_start;
+    if (hit) {
+      std::lock_guard<std::mutex> g(S->mu);
+      h = S->cache[key].h;
+    }
+    if (hit && R->r.refresh_setup) {
+      st_code = mgr_setup_numeric(h, &R->A, st);
+      if (st_code == MGR_ERR_PATTERN) hit = false;  // a new pattern under the same key
+    }
+    mgr_handle *old = nullptr;
+    if (!hit) {
+      if (h) old = h;
+      h = nullptr;
+      st_code = mgr_setup(&R->A, R->r.labels, &S->cfg.opts, st, &h);
+    }
+    res.setup_reused = hit ? 1 : 0;
+    const double t_setup = S->now_ms();
+    const size_t need_ws = fgmres_workspace_bytes(R->A.nrows, S->cfg.fopts.restart);
+    if (st_code == MGR_OK && need_ws > work_bytes) {
+      if (work) mgr::dfree(work, st);
+      try {
+        work = mgr::dalloc(need_ws, st);
+        work_bytes = need_ws;
+      } catch (const mgr::Error &) {
+        work = nullptr;
+        work_bytes = 0;
+        st_code = MGR_ERR_ALLOC;
+      }
+    }
+    fgmres_result fr{};
+    if (st_code == MGR_OK) {
+      st_code = fgmres_solve(&R->A, h, R->r.b, R->r.x, &S->cfg.fopts, work, work_bytes, &fr, st);
+      (void)hipStreamSynchronize(st);
+    }
+    const double t_end = S->now_ms();
+    res.status = st_code;
+    res.iters = fr.iters;
+    res.true_relres = fr.true_relres;
+    res.setup_ms = t_setup - t_start;
+    res.solve_ms = t_end - t_setup;
+    res.t_end_ms = t_end;
+    size_t fp = 0;
+    if (h) mgr_footprint(h, &fp);
+    res.footprint = fp;
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->used -= R->reserve;
+      if (old) {
+        auto c = S->cache.find(key);
+        if (c != S->cache.end() && c->second.h == old) {
+          S->used -= c->second.bytes;
+          S->cache.erase(c);
+        }
+        mgr_destroy(old);
+      }
+      if (h) {
+        const bool keep = S->cfg.cache_setups && !R->r.last_use && st_code != MGR_ERR_ARG;
+        auto c = S->cache.find(key);
+        if (keep) {
+          if (c == S->cache.end()) {
+            mgr_server::Entry e;
+            e.h = h;
+            e.bytes = fp;
+            e.n = R->A.nrows;
+            e.nnz = R->r.nnz;
+            S->cache[key] = e;
+            S->used += fp;
+            S->peak_used = std::max(S->peak_used, S->used);
+            c = S->cache.find(key);
+          }
+          c->second.busy = false;
+          c->second.last_use = ++S->use_clock;
+        } else {
+          if (c != S->cache.end() && c->second.h == h) {
+            S->used -= c->second.bytes;
+            S->cache.erase(c);
+          }
+          mgr_destroy(h);
+        }
+      }
+      if (hit) ++S->hits; else ++S->misses;
+      S->key_busy[key] = 0;
+      R->done = true;
+      ++S->completed;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  if (work) mgr::dfree(work, st);
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+void mgr_server_default_config(mgr_server_config *c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->budget_bytes = (size_t)64 << 30;
+  c->slots = 4;
+  mgr_default_opts(&c->opts);
+  c->fopts.restart = 30;
+  c->fopts.maxit = 1000;
+  c->fopts.rtol = 1e-6;
+  c->cache_setups = 1;
+}
+
+mgr_status mgr_server_create(const mgr_server_config *cfg, mgr_server **out) {
+  if (!cfg || !out || cfg->slots < 1 || cfg->slots > 64) {
+    mgr::set_last_error("bad server configuration");
+    return MGR_ERR_ARG;
+  }
+  auto *S = new mgr_server();
+  S->cfg = *cfg;
+  for (int i = 0; i < cfg->slots; ++i) S->workers.emplace_back(worker, S, i);
+  *out = S;
+  return MGR_OK;
+}
+
+mgr_status mgr_server_submit(mgr_server *S, const mgr_request *r, uint64_t *ticket) {
+  if (!S || !r || !r->A || !r->labels || !r->b || !r->x || !ticket) {
+    mgr::set_last_error("null argument");
+    return MGR_ERR_ARG;
+  }
+  auto q = std::make_unique<mgr_server::Req>();
+  q->r = *r;
+  q->A = *r->A;
+  q->r.A = &q->A;
+  std::memset(&q->res, 0, sizeof(q->res));
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->stop) {
+      mgr::set_last_error("server is stopping");
+      return MGR_ERR_ARG;
+    }
+    q->ticket = S->next_ticket++;
+    q->res.t_submit_ms = S->now_ms();
+    *ticket = q->ticket;
+    S->queue.push_back(q->ticket);
+    S->reqs[q->ticket] = std::move(q);
+  }
+  S->cv_work.notify_all();
+  return MGR_OK;
+}
+
+mgr_status mgr_server_wait(mgr_server *S, uint64_t ticket, mgr_result *res) {
+  if (!S) return MGR_ERR_ARG;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) {
+    mgr::set_last_error("unknown ticket");
+    return MGR_ERR_ARG;
+  }
+  S->cv_done.wait(lk, [&] { return it->second->done; });
+  if (res) *res = it->second->res;
+  const mgr_status st = (mgr_status)it->second->res.status;
+  S->reqs.erase(it);
+  return st;
+}
+
+int32_t mgr_server_poll(mgr_server *S, uint64_t ticket) {
+  if (!S) return -1;
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return -1;
+  return it->second->done ? 1 : 0;
+}
+
+mgr_status mgr_server_stats(mgr_server *S, mgr_server_stats_t *out) {
+  if (!S || !out) return MGR_ERR_ARG;
+  std::lock_guard<std::mutex> g(S->mu);
+  out->completed = S->completed;
+  out->queued = (int64_t)S->queue.size();
+  out->cache_hits = S->hits;
+  out->cache_misses = S->misses;
+  out->evictions = S->evictions;
+  out->cached_setups = (int64_t)S->cache.size();
+  out->reserved_bytes = S->used;
+  out->peak_reserved_bytes = S->peak_used;
+  return MGR_OK;
+}
+
+void mgr_server_destroy(mgr_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  for (auto &t : S->workers) t.join();
+  for (auto &kv : S->cache) mgr_destroy(kv.second.h);
+  delete S;
+}
+
+}  // extern "C"

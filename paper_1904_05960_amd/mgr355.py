@@ -69,6 +69,31 @@ class fgmres_result(C.Structure):
                 ("history_len", C.c_int32)]
 
 
+class mgr_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_size_t), ("slots", C.c_int32), ("opts", mgr_opts),
+                ("fopts", fgmres_opts), ("cache_setups", C.c_int32)]
+
+
+class mgr_request(C.Structure):
+    _fields_ = [("A", C.POINTER(mgr_csr)), ("nnz", C.c_int64), ("labels", C.c_void_p),
+                ("b", C.c_void_p), ("x", C.c_void_p), ("key", C.c_uint64),
+                ("refresh_setup", C.c_int32), ("last_use", C.c_int32)]
+
+
+class mgr_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("setup_reused", C.c_int32),
+                ("slot", C.c_int32), ("true_relres", C.c_double), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_start_ms", C.c_double), ("t_end_ms", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("footprint", C.c_size_t)]
+
+
+class mgr_server_stats_t(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("queued", C.c_int64), ("cache_hits", C.c_int64),
+                ("cache_misses", C.c_int64), ("evictions", C.c_int64),
+                ("cached_setups", C.c_int64), ("reserved_bytes", C.c_size_t),
+                ("peak_reserved_bytes", C.c_size_t)]
+
+
 _lib = None
 
 
@@ -114,6 +139,14 @@ def lib():
         "mgr_owned_free": (None, [vp]),
         "mgr_release_cache": (st, []),
         "mgr_cached_bytes": (C.c_size_t, []),
+        "mgr_alloc_stats": (None, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.c_int32]),
+        "mgr_server_default_config": (None, [C.POINTER(mgr_server_config)]),
+        "mgr_server_create": (st, [C.POINTER(mgr_server_config), C.POINTER(vp)]),
+        "mgr_server_submit": (st, [vp, C.POINTER(mgr_request), C.POINTER(C.c_uint64)]),
+        "mgr_server_wait": (st, [vp, C.c_uint64, C.POINTER(mgr_result)]),
+        "mgr_server_poll": (C.c_int32, [vp, C.c_uint64]),
+        "mgr_server_stats": (st, [vp, C.POINTER(mgr_server_stats_t)]),
+        "mgr_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -420,6 +453,17 @@ def aggregate(A: Matrix, bs: int, theta: float, level: int, stream=None):
 
 def stream_copy(src, dst, stream=None):
     _check(lib().mgr_stream_copy(_ptr(src), _ptr(dst), int(src.numel()), _stream(stream)))
+
+
+def alloc_stats(reset_peak=False):
+    """(bytes handed out by the library allocator, peak since the last reset)."""
+    live, peak = C.c_size_t(), C.c_size_t()
+    lib().mgr_alloc_stats(C.byref(live), C.byref(peak), int(reset_peak))
+    return int(live.value), int(peak.value)
+
+
+def release_cache():
+    _check(lib().mgr_release_cache())
 
 
 def profile_enable(family: int, on: bool = True):

@@ -1,0 +1,225 @@
+"""Serving: Python wrapper of the library's request loop and a replay driver.
+
+`Server` wraps mgr_server_* (include/mgr355.h): worker slots with their own HIP streams,
+HBM admission by footprint, a setup cache keyed by realization.  `run_stream` replays an
+ensemble of Jacobians (realizations of different mesh sizes, several Newton steps each with
+the same sparsity pattern) with Poisson arrivals and reports solves/s and p50/p99 latency.
+
+    python -m paper_1904_05960_amd.serve [--realizations 16] [--newton 8] [--nmin 16]
+        [--nmax 64] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import mgr355 as m
+
+
+class Server:
+    def __init__(self, opts: m.Options, budget_bytes: int = 64 << 30, slots: int = 4,
+                 restart: int = 30, rtol: float = 1e-6, maxit: int = 1000, cache: bool = True):
+        L = m.lib()
+        cfg = m.mgr_server_config()
+        L.mgr_server_default_config(C.byref(cfg))
+        cfg.budget_bytes = int(budget_bytes)
+        cfg.slots = int(slots)
+        cfg.opts = opts.to_c()
+        cfg.fopts = m.fgmres_opts(int(restart), int(maxit), float(rtol))
+        cfg.cache_setups = int(cache)
+        self._cfg = cfg
+        h = C.c_void_p()
+        m._check(L.mgr_server_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, A: m.Matrix, labels, b, x, key: int, refresh: bool = False,
+               last_use: bool = False) -> int:
+        r = m.mgr_request()
+        r.A = C.pointer(A.c)
+        r.nnz = A.nnz
+        r.labels = labels.data_ptr()
+        r.b = b.data_ptr()
+        r.x = x.data_ptr()
+        r.key = int(key)
+        r.refresh_setup = int(refresh)
+        r.last_use = int(last_use)
+        t = C.c_uint64()
+        m._check(m.lib().mgr_server_submit(self.h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (A, labels, b, x)     # device arrays live until completion
+        return int(t.value)
+
+    def wait(self, ticket: int) -> dict:
+        res = m.mgr_result()
+        st = m.lib().mgr_server_wait(self.h, C.c_uint64(ticket), C.byref(res))
+        self._keep.pop(ticket, None)
+        return dict(status=st, iters=res.iters, setup_reused=bool(res.setup_reused),
+                    slot=res.slot, true_relres=res.true_relres, t_submit_ms=res.t_submit_ms,
+                    t_admit_ms=res.t_admit_ms, t_start_ms=res.t_start_ms,
+                    t_end_ms=res.t_end_ms, setup_ms=res.setup_ms, solve_ms=res.solve_ms,
+                    footprint=int(res.footprint))
+
+    def poll(self, ticket: int) -> int:
+        return int(m.lib().mgr_server_poll(self.h, C.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        s = m.mgr_server_stats_t()
+        m._check(m.lib().mgr_server_stats(self.h, C.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in s._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            m.lib().mgr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------------------
+# ensemble of requests
+class Realization:
+    """One permeability realization on the device, with its Newton-step variants."""
+
+    def __init__(self, idx: int, n: int, seed: int):
+        import torch
+        from workloads import poromech as pm
+        w = pm.two_phase(n, n, n, seed)
+        self.idx, self.n_cells, self.n = idx, n, w.n
+        self.A0 = m.Matrix.from_host(w.indptr, w.indices, w.data)
+        self.labels = torch.as_tensor(w.labels).cuda()
+        self.x_true = torch.as_tensor(w.x_true).cuda()
+        counts = np.diff(w.indptr)
+        self.row_of_entry = torch.as_tensor(np.repeat(np.arange(w.n), counts)).cuda()
+        self.flow_row = (self.labels != 0)
+
+    def step(self, k: int, seed: int):
+        """Newton step k: the flow rows of the base Jacobian scaled by exp(0.1 z_i), z iid
+        N(0, 1) seeded by (realization, k) (k = 0: the base matrix); same pattern; b = A x_true."""
+        import torch
+        if k == 0:
+            val = self.A0.val
+        else:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(seed)
+            z = torch.randn(self.n, generator=g, device="cuda", dtype=torch.float64)
+            scale = torch.where(self.flow_row, torch.exp(0.1 * z), torch.ones_like(z))
+            val = self.A0.val * scale[self.row_of_entry]
+        A = m.Matrix(self.A0.row_ptr, self.A0.col, val.contiguous())
+        b = A.spmv(self.x_true)
+        return A, b
+
+
+def build_ensemble(realizations: int, nmin: int, nmax: int, seed: int, log=print):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, size=realizations)
+    ens = []
+    for i, n in enumerate(sizes):
+        t = time.perf_counter()
+        ens.append(Realization(i, int(n), seed * 1000 + i))
+        log(f"[serve] realization {i}: {n}^3 cells, {ens[-1].n} unknowns "
+            f"({time.perf_counter() - t:.1f}s)")
+    return ens
+
+
+def request_order(realizations: int, newton: int, seed: int):
+    """A uniformly random interleaving of the realizations' step sequences, each
+    realization's steps in order."""
+    rng = np.random.default_rng(seed + 1)
+    seq = np.repeat(np.arange(realizations), newton)
+    rng.shuffle(seq)
+    nxt = np.zeros(realizations, dtype=int)
+    out = []
+    for r in seq:
+        out.append((int(r), int(nxt[r])))
+        nxt[r] += 1
+    return out
+
+
+def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
+               refresh: bool = False, log=print):
+    """Open-loop replay: request i arrives at the i-th event of a Poisson process of the
+    given rate; returns per-request records."""
+    import torch
+    rng = np.random.default_rng(seed + 2)
+    gaps = rng.exponential(1.0 / rate, size=len(order)) if rate > 0 else np.zeros(len(order))
+    arrivals = np.cumsum(gaps)
+    inputs = []
+    for (r, k) in order:       # prepare every request's matrix and rhs up front
+        A, b = ens[r].step(k, seed * 7919 + r * 101 + k)
+        inputs.append((A, b, torch.zeros_like(b)))
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for i, ((r, k), (A, b, x)) in enumerate(zip(order, inputs)):
+        delay = arrivals[i] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(server.submit(A, ens[r].labels, b, x, key=r, refresh=refresh,
+                                     last_use=(k == newton - 1)))
+    recs = []
+    for i, t in enumerate(tickets):
+        res = server.wait(t)
+        res["realization"], res["newton_step"] = order[i]
+        res["n"] = ens[order[i][0]].n
+        res["latency_ms"] = res["t_end_ms"] - res["t_submit_ms"]
+        recs.append(res)
+    wall = time.perf_counter() - t0
+    return recs, wall, [inp[2] for inp in inputs]
+
+
+def summarize(recs, wall):
+    lat = np.array([r["latency_ms"] for r in recs])
+    ok = sum(1 for r in recs if r["status"] == 0)
+    return dict(requests=len(recs), ok=ok, solves_per_s=len(recs) / wall,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                mean_iters=float(np.mean([r["iters"] for r in recs])),
+                max_relres=float(max(r["true_relres"] for r in recs)),
+                setup_reuse=float(np.mean([r["setup_reused"] for r in recs])), wall_s=wall)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--realizations", type=int, default=16)
+    ap.add_argument("--newton", type=int, default=8)
+    ap.add_argument("--nmin", type=int, default=16)
+    ap.add_argument("--nmax", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--refresh", action="store_true", help="recompute setups each step")
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--compare-fp64-serial", action="store_true")
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    ens = build_ensemble(a.realizations, a.nmin, a.nmax, a.seed, log)
+    order = request_order(a.realizations, a.newton, a.seed)
+    srv = Server(m.paper_plan("two", precision=a.precision), int(a.budget_gb * (1 << 30)),
+                 a.slots)
+    recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log)
+    out = {"metric": "served MGR-FGMRES solves (1e-6), p50/p99 latency", "mode": "served",
+           "precision": a.precision, "slots": a.slots, "rate_per_s": a.rate,
+           **summarize(recs, wall), "server": srv.stats()}
+    srv.close()
+    if a.compare_fp64_serial:
+        srv = Server(m.paper_plan("two", precision="fp64"), int(a.budget_gb * (1 << 30)), 1,
+                     cache=False)
+        recs2, wall2, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, False, log)
+        out["fp64_one_at_a_time"] = summarize(recs2, wall2)
+        srv.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

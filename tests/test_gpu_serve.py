@@ -1,0 +1,105 @@
+"""Serving: every result is the same alone and in the mix (bitwise: each request runs the
+same kernels in the same order on its own stream), admission never exceeds the budget,
+cached setups are reused and evicted, oversize requests are rejected, and the footprint
+estimate bounds the measured peak."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+m = pytest.importorskip("paper_1904_05960_amd.mgr355")
+from paper_1904_05960_amd import serve  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ens():
+    return serve.build_ensemble(5, 6, 13, seed=11, log=log)
+
+
+def opts():
+    o = m.paper_plan("two", precision="fp32")
+    o.amg_frelax = m.AMG(coarse_size=48)
+    o.amg_coarse = m.AMG(coarse_size=48)
+    return o
+
+
+def test_alone_equals_mix(ens):
+    order = serve.request_order(len(ens), 3, seed=11)
+    mix = serve.Server(opts(), 8 << 30, slots=4)
+    recs_mix, _, xs_mix = serve.run_stream(mix, ens, order, rate=0.0, seed=11, newton=3, log=log)
+    st = mix.stats()
+    mix.close()
+    alone = serve.Server(opts(), 8 << 30, slots=1)
+    recs_alone, _, xs_alone = serve.run_stream(alone, ens, order, rate=0.0, seed=11, newton=3,
+                                               log=log)
+    alone.close()
+    assert all(r["status"] == 0 for r in recs_mix + recs_alone)
+    assert all(r["true_relres"] <= 1e-6 for r in recs_mix)
+    assert len({r["slot"] for r in recs_mix}) > 1          # work really overlapped
+    for a, b in zip(xs_mix, xs_alone):
+        assert torch.equal(a, b)
+    assert st["cache_hits"] == len(order) - len(ens)        # steps 1.. reuse the setup
+    assert [r["iters"] for r in recs_mix] == [r["iters"] for r in recs_alone]
+
+
+def test_refresh_equals_fresh_setup(ens):
+    R = ens[1]
+    srv = serve.Server(opts(), 8 << 30, slots=2)
+    outs = []
+    for k in range(3):
+        A, b = R.step(k, 100 + k)
+        x = torch.zeros_like(b)
+        t = srv.submit(A, R.labels, b, x, key=7, refresh=True)
+        res = srv.wait(t)
+        assert res["status"] == 0 and res["setup_reused"] == (k > 0)
+        P = m.Preconditioner(A, R.labels, opts())
+        x2, info = m.fgmres(A, b, M=P, restart=30, rtol=1e-6)
+        P.close()
+        assert torch.equal(x, x2)
+        outs.append(res)
+    srv.close()
+
+
+def test_budget_evictions_and_rejection(ens):
+    # a budget that holds about two setups: evictions happen, the budget is never exceeded
+    sizes = []
+    for R in ens:
+        b = m.estimate_footprint(R.n, R.A0.nnz, opts()) + m.lib().fgmres_workspace_bytes(R.n, 30)
+        sizes.append(b)
+    budget = int(2.2 * max(sizes))
+    srv = serve.Server(opts(), budget, slots=3)
+    order = [(r, 0) for r in range(len(ens))] + [(r, 1) for r in range(len(ens))]
+    recs, _, _ = serve.run_stream(srv, ens, order, rate=0.0, seed=3, newton=2, log=log)
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in recs)
+    assert st["peak_reserved_bytes"] <= budget
+    assert st["evictions"] > 0
+    # a request larger than the whole budget completes with ALLOC
+    tiny = serve.Server(opts(), 1 << 20, slots=1)
+    R = ens[0]
+    A, b = R.step(0, 1)
+    x = torch.zeros_like(b)
+    res = tiny.wait(tiny.submit(A, R.labels, b, x, key=1))
+    tiny.close()
+    assert res["status"] == m.MGR_ERR_ALLOC
+
+
+def test_estimate_bounds_measured_peak(ens):
+    R = max(ens, key=lambda r: r.n)
+    A, b = R.step(0, 5)
+    torch.cuda.synchronize()
+    m.release_cache()
+    live0, _ = m.alloc_stats(reset_peak=True)
+    P = m.Preconditioner(A, R.labels, opts())
+    x, info = m.fgmres(A, b, M=P, restart=30, rtol=1e-6)
+    torch.cuda.synchronize()
+    live1, peak = m.alloc_stats()
+    P.close()
+    est = m.estimate_footprint(R.n, A.nnz, opts()) + m.lib().fgmres_workspace_bytes(R.n, 30)
+    log(f"  peak {peak - live0} estimate {est}")
+    assert peak - live0 <= est
