@@ -1,0 +1,195 @@
+"""Full-size parity: the 64^3 two-phase Jacobian the benchmark times (1.35M unknowns), the
+128x128x64 channelized two-phase one (5.3M) and the 96^3 three-phase one (5.4M), with the
+library in the benchmark's configuration (FP32 hierarchy, captured V-cycle, streamed FP64
+SpMV; the setup is kept only where it is exported).
+
+At these sizes the whole oracle setup takes minutes, so the checks are:
+  * every MGR level: the C/F lists whole, and sampled rows of W_p and A_{l+1} bit-exact,
+    computed by the oracle's own steps on row-restricted matrices (tests/sampled.py);
+  * the elasticity AMG (64^3): the first level's aggregates and prolongator whole and
+    bit-exact against the oracle run on the whole displacement block, sampled rows of the
+    Galerkin product R (A P) bit-exact;
+  * every level of every AMG: x^T A_{k+1} y = (P x)^T A_k (P y) for random x, y (a property
+    of the Galerkin product that holds at any size);
+  * the outer SpMV: the whole vector against the oracle's matvec;
+  * FGMRES(30) to 1e-6: the true FP64 residual recomputed on the host from the returned x,
+    and the FP32-hierarchy iteration count within +-1 of the FP64-hierarchy one.
+"""
+import gc
+import time
+
+import numpy as np
+import pytest
+
+from oracle import amg as oamg
+from oracle import mgr as omgr
+from oracle.sparse import CSR, transpose, spgemm
+from tests.helpers import oracle_plan
+from tests.sampled import assert_rows_equal, level_chain, restrict_rows, sample_rows
+from workloads import poromech as pm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+m = pytest.importorskip("paper_1904_05960_amd.mgr355")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+CASES = {
+    "two_64x64x64": (lambda: pm.two_phase(64, 64, 64, 1), "two"),
+    "channels_128x128x64": (lambda: pm.two_phase_channels(128, 128, 64, 2), "two"),
+    "three_96x96x96": (lambda: pm.three_phase(96, 96, 96, 3), "three"),
+}
+
+
+class Case:
+    def __init__(self, name):
+        make, self.model = CASES[name]
+        self.name = name
+        t = time.perf_counter()
+        self.w = make()
+        log(f"[fullsize] {name}: n={self.w.n} nnz={self.w.nnz} "
+            f"generated in {time.perf_counter() - t:.1f}s")
+        self.A = CSR(self.w.indptr, self.w.indices, self.w.data, (self.w.n, self.w.n))
+        self.dA = m.Matrix.from_host(self.w.indptr, self.w.indices, self.w.data)
+        self.labels = torch.as_tensor(self.w.labels).cuda()
+        self.b = torch.as_tensor(self.w.b).cuda()
+        self._kept = None
+
+    def opts(self, precision="fp32", keep_setup=False):
+        return m.paper_plan(self.model, precision=precision, keep_setup=keep_setup)
+
+    def kept(self):
+        """A handle of the benchmark's configuration with its setup kept for export."""
+        if self._kept is None:
+            t = time.perf_counter()
+            self._kept = m.Preconditioner(self.dA, self.labels, self.opts(keep_setup=True))
+            torch.cuda.synchronize()
+            log(f"[fullsize] {self.name}: setup (kept) {time.perf_counter() - t:.2f}s")
+        return self._kept
+
+    def close(self):
+        if self._kept is not None:
+            self._kept.close()
+        self._kept = None
+        self.dA = self.labels = self.b = None
+        gc.collect()
+        torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    c = Case(request.param)
+    yield c
+    c.close()
+
+
+def test_mgr_levels_sampled_rows(case):
+    P = case.kept()
+    plan = oracle_plan(case.opts())
+    chain = level_chain(case.A, case.w.labels, plan)
+    for lvl, R in enumerate(chain):
+        assert np.array_equal(P.export(m.X_F, lvl), R.F), f"F list of level {lvl}"
+        assert np.array_equal(P.export(m.X_C, lvl), R.C), f"C list of level {lvl}"
+        rows = sample_rows(R.C.shape[0], 48, seed=17 + lvl)
+        t = time.perf_counter()
+        S_rows, Wp_rows, ks = R.coarse_rows(rows)
+        log(f"[fullsize] {case.name} level {lvl}: {rows.size} rows of A_{lvl + 1}, "
+            f"{ks.size} rows of W_p ({time.perf_counter() - t:.1f}s)")
+        assert_rows_equal(P.export(m.X_COARSE, lvl), S_rows, rows, f"A_{lvl + 1}")
+        assert_rows_equal(P.export(m.X_WP, lvl), Wp_rows, ks, f"W_p of level {lvl}")
+
+
+def test_elasticity_amg_first_level(case):
+    if case.name != "two_64x64x64":
+        pytest.skip("the whole-block oracle AMG level runs on the 64^3 case only")
+    P = case.kept()
+    plan = oracle_plan(case.opts())
+    lp = plan.levels[0]
+    assert lp.frelax == "amg" and lp.frelax_block == 3
+    F, C = omgr.cf_split(case.w.labels, lp.f_labels)
+    A_FF = omgr.blocks_of(case.A, F, C)[0]
+    o = plan.amg_frelax
+    t = time.perf_counter()
+    g, c = oamg.strength_graph(A_FF, oamg.theta_at(o.theta0, 0), 3)
+    prio = oamg.priorities(g.shape[0] - 1, 0)
+    agg, nagg = oamg.aggregate(g, c, oamg.mis2(g, c, prio), prio)
+    T = oamg.tentative(agg, nagg, 3)
+    Po, _ = oamg.smoothed_prolongator(A_FF, T)
+    log(f"[fullsize] oracle AMG level 0: {nagg} aggregates ({time.perf_counter() - t:.1f}s)")
+    assert np.array_equal(P.export(m.X_AMG_AGG, 0, 0), agg), "aggregates"
+    Pe = P.export(m.X_AMG_P, 0, 0)
+    assert_rows_equal(Pe, Po, np.arange(Po.shape[0]), "AMG P[0]")
+    R = transpose(Po)
+    rows = sample_rows(R.shape[0], 24, seed=5)
+    Rr = restrict_rows(R, rows)
+    Ac_rows = spgemm(Rr, spgemm(restrict_rows(A_FF, np.unique(Rr.indices)), Po))
+    assert_rows_equal(P.export(m.X_AMG_A, 0, 1), Ac_rows, rows, "AMG A[1]")
+
+
+def _galerkin_gap(Ak, Pk, Ak1, rng):
+    """(|x^T A_{k+1} y - (P x)^T A_k (P y)|, the same sum over absolute values)."""
+    import scipy.sparse as sp
+    def mat(e):
+        rp, ci, v, shape = e
+        return sp.csr_matrix((v, ci, rp), shape=shape)
+    A0, Pm, A1 = mat(Ak), mat(Pk), mat(Ak1)
+    x = rng.standard_normal(A1.shape[0])
+    y = rng.standard_normal(A1.shape[0])
+    Px, Py = Pm @ x, Pm @ y
+    lhs = x @ (A1 @ y)
+    rhs = Px @ (A0 @ Py)
+    scale = np.abs(Px) @ (abs(A0) @ np.abs(Py))
+    return abs(lhs - rhs), scale
+
+
+def test_galerkin_identity_every_amg_level(case):
+    P = case.kept()
+    nmgr = len(case.opts().levels)
+    rng = np.random.default_rng(3)
+    owners = [lv for lv in range(nmgr) if case.opts().levels[lv].frelax == "amg"] + [nmgr]
+    for lvl in owners:
+        nk = P.amg_levels(lvl)
+        assert nk >= 2, (lvl, nk)
+        for k in range(nk - 1):
+            gap, scale = _galerkin_gap(P.export(m.X_AMG_A, lvl, k), P.export(m.X_AMG_P, lvl, k),
+                                       P.export(m.X_AMG_A, lvl, k + 1), rng)
+            log(f"[fullsize] {case.name} AMG of level {lvl}, {k}->{k + 1}: "
+                f"gap {gap:.3e} scale {scale:.3e}")
+            assert gap <= 1e-11 * scale
+
+
+def test_outer_spmv_whole_vector(case):
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(case.w.n)
+    y = case.dA.spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+    ref = case.A.matvec(x)
+    bound = abs(case.A.scipy()) @ np.abs(x)
+    err = np.abs(y - ref)
+    assert np.all(err <= 1e-13 * bound + 1e-300), float(np.max(err / np.maximum(bound, 1e-300)))
+
+
+def test_fgmres_fp32_hierarchy_vs_fp64(case):
+    res = {}
+    bn = float(np.linalg.norm(case.w.b))
+    for prec in ("fp64", "fp32"):
+        t = time.perf_counter()
+        Pc = m.Preconditioner(case.dA, case.labels, case.opts(precision=prec))
+        x, info = m.fgmres(case.dA, case.b, M=Pc, restart=30, rtol=1e-6, maxit=600,
+                           raise_on_fail=False)
+        torch.cuda.synchronize()
+        Pc.close()
+        xh = x.cpu().numpy()
+        relres = float(np.linalg.norm(case.w.b - case.A.matvec(xh)) / bn)
+        err = float(np.linalg.norm(xh - case.w.x_true) / np.linalg.norm(case.w.x_true))
+        log(f"[fullsize] {case.name} {prec}: {info['iters']} iterations, host relres "
+            f"{relres:.3e}, device {info['true_relres']:.3e}, error {err:.3e} "
+            f"({time.perf_counter() - t:.2f}s)")
+        assert info["converged"]
+        assert relres <= 1e-6 * (1 + 1e-9)
+        assert abs(relres - info["true_relres"]) <= 1e-4 * relres
+        res[prec] = info["iters"]
+    assert abs(res["fp32"] - res["fp64"]) <= 1, res
