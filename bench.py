@@ -5,7 +5,7 @@ mgr_setup (C/F splits, W_p, A_cor by pinned-order SpGEMM, G, coarse operators, b
 hierarchies, FP32 cast, graph capture on first apply) + fgmres_solve to rtol = 1e-6 +
 mgr_destroy.  Default workload: two-phase poromechanics on a 64^3 cell grid (1,348,163
 unknowns, 92,914,761 nonzeros), paper reduction order (displacement, saturation,
-pressure), FP32 hierarchy inside FP64 FGMRES(30).
+pressure), FP32 hierarchy inside FP64 FGMRES(64).
 
     python bench.py [--steps K] [--warmup W] [--size 64] [--precision fp32|fp64]
                     [--plan paper|satfirst] [--no-cpu-baseline]
@@ -49,7 +49,7 @@ def traffic_from_profile(name, src):
     return float(mt.group(1))
 
 
-def cpu_baseline(size_full_n):
+def cpu_baseline(size_full_n, restart):
     """The oracle (FP64, NumPy/SciPy, untuned) on a bounded sample of the same workload
     recipe: setup + FGMRES to 1e-6 on the 24^3 two-phase grid, scaled linearly by unknowns."""
     from oracle import krylov as okry
@@ -64,7 +64,8 @@ def cpu_baseline(size_full_n):
     c0, t0 = os.times(), time.perf_counter()
     H = omgr.setup(A, w.labels, plan)
     t1 = time.perf_counter()
-    r = okry.fgmres(A.matvec, lambda v: omgr.apply(H, v), w.b, restart=30, rtol=1e-6, maxit=500)
+    r = okry.fgmres(A.matvec, lambda v: omgr.apply(H, v), w.b, restart=restart, rtol=1e-6,
+                    maxit=500)
     t2, c1 = time.perf_counter(), os.times()
     cpu = (c1.user - c0.user) + (c1.system - c0.system)
     wall = t2 - t0
@@ -73,7 +74,7 @@ def cpu_baseline(size_full_n):
         "value": round(wall * 1e3 * scale, 1), "unit": "ms",
         "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
-        "sample": (f"oracle setup + FGMRES(30) to 1e-6 on the 24^3 two-phase grid of the same "
+        "sample": (f"oracle setup + FGMRES({restart}) to 1e-6 on the 24^3 two-phase grid of the same "
                    f"recipe ({w.n} unknowns, {r.iters} iterations, setup {1e3*(t1-t0):.0f} ms, "
                    f"solve {1e3*(t2-t1):.0f} ms), scaled by unknowns x{scale:.2f}"),
         "host_cpus": os.cpu_count(),
@@ -105,7 +106,7 @@ def main():
     ap.add_argument("--size", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-hierarchy step")
     a = ap.parse_args()
@@ -228,7 +229,7 @@ def main():
         },
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.n)
+        out["cpu_baseline"] = cpu_baseline(w.n, a.restart)
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,7 @@ enum { MGR_INTERP_JACOBI = 0, MGR_INTERP_ZERO = 1 };
 enum { MGR_FRELAX_JACOBI = 0, MGR_FRELAX_AMG = 1, MGR_FRELAX_DENSE = 2 };
 enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1 };
 enum { MGR_COARSE_AMG = 0, MGR_COARSE_DENSE = 1 };
+enum { MGR_COUPLING_FULL = 0, MGR_COUPLING_QUASI_IMPES = 1 };
 enum { MGR_PREC_FP64 = 0, MGR_PREC_FP32 = 1 };
 
 /* One reduction level (Sec. 5.2, Algorithm 2). */
@@ -91,6 +92,12 @@ typedef struct {
                                   rows of equal rank within their label; the level's rows
                                   must be interleaved cell by cell                       */
   int32_t global_sweeps;       /* default 1                                              */
+  int32_t coupling;            /* A_CF in the coarse product A_CF D_FF^{-1} A_FC:
+                                  MGR_COUPLING_FULL (eq. coarse_grid_pressure, default) or
+                                  MGR_COUPLING_QUASI_IMPES: only its entries between points
+                                  of the same entity (equal rank within their labels), the
+                                  diagonal that the quasi-IMPES reduction described with
+                                  that equation uses; W_p and residuals keep all of A_CF  */
   double global_omega;         /* weight of sweeps after the first (default 1.0)         */
 } mgr_level_opts;
 

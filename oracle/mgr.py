@@ -24,7 +24,9 @@ Readings where the paper is silent (each also listed in the design notes):
   * the residual in the F-relaxation step of Algorithm 2 uses the level's own matrix A_l;
   * the global smoother is block Jacobi over the same-cell blocks (a stand-in for the
     ILU/Gauss-Seidel smoothers of Sec. 5.3): first sweep z = D_B^{-1} v, later sweeps
-    z += omega D_B^{-1} (v - A z).
+    z += omega D_B^{-1} (v - A z);
+  * the quasi-IMPES option keeps, of A_CF, only the same-entity entries in the coarse
+    product ("its diagonal" under the field-ordered view of Sec. 5.3).
 """
 from __future__ import annotations
 
@@ -53,6 +55,7 @@ class LevelPlan:
     global_smoother: str = "none"    # 'none' | 'block_jacobi'
     global_sweeps: int = 1
     global_omega: float = 1.0
+    coupling: str = "full"           # 'full' | 'quasi_impes' (A_CF of the coarse product)
 
 
 @dataclass
@@ -128,6 +131,26 @@ def jacobi_interpolation(A_FC: CSR, dFF: np.ndarray) -> tuple:
     return M, Wp
 
 
+def coupling_block(A_CF: CSR, labels: np.ndarray, F, C, coupling: str) -> CSR:
+    """The C-F block that enters the coarse product A_CF D_FF^{-1} A_FC.
+
+    'full' keeps A_CF (eq. coarse_grid_pressure).  'quasi_impes' replaces it by its diagonal,
+    as the quasi-IMPES reduction described beside that equation does: only the entries
+    (i, k) whose C-point C[i] and F-point F[k] are the same entity, i.e. have the same rank
+    among the points of their own label (the same cell under cell-wise ordering).  W_p and
+    the residual still use the whole block."""
+    if coupling == "full":
+        return A_CF
+    if coupling != "quasi_impes":
+        raise ValueError(coupling)
+    rank = label_rank(np.asarray(labels))
+    r = A_CF.row_ids()
+    keep = rank[np.asarray(C)[r]] == rank[np.asarray(F)[A_CF.indices]]
+    indptr = np.zeros(A_CF.shape[0] + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r[keep], minlength=A_CF.shape[0]), out=indptr[1:])
+    return CSR(indptr, A_CF.indices[keep], A_CF.data[keep], A_CF.shape)
+
+
 def drop(Acor: CSR, labels_c: np.ndarray, nmax: int) -> CSR:
     """The dropping operator G of eq. drop_operator: per row, keep the entries on the
     diagonals of the sub-blocks (same per-label rank) and the nmax largest |values| among
@@ -200,7 +223,7 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
             Wp = CSR(M.indptr, M.indices, -M.data, M.shape)
         else:
             raise ValueError(lp.interp)
-        Acor = spgemm(A_CF, M)
+        Acor = spgemm(coupling_block(A_CF, lab, F, C, lp.coupling), M)
         G = drop(Acor, lab[C], lp.nmax)
         S = merge_sub(A_CC, G)
         L = Level(A=cur, labels=lab, F=F, C=C, dFF=d, A_FF=A_FF, A_FC=A_FC, A_CF=A_CF,

@@ -163,6 +163,9 @@ bool labels_periodic(const int8_t *labels, int64_t n, int p, hipStream_t s);
 void gather_labels(const int8_t *labels, const int *idx, int64_t n, int8_t *out,
                    hipStream_t s);
 // A_FF, A_FC, A_CF, A_CC of A under cf; dFF = diag(A_FF) (0 where missing).
+// Entries (i, k) of A_CF with rank[C[i]] == rank[F[k]] (same entity), order kept.
+void same_entity_filter(const Csr &Acf, const int *C, const int *F, const int *rank, Csr &out,
+                        hipStream_t s);
 void extract_blocks(const Csr &A, const CfSplit &cf, Csr *Aff, Csr &Afc, Csr &Acf, Csr &Acc,
                     double *dFF, hipStream_t s);
 // M = D^{-1} A_FC (values a/d), in place on a copy.

@@ -600,8 +600,15 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       fill<int>(M.rp.p, 0, M.n + 1, s);
     }
     trace("  split/extract done");
+    // the C-F block of the coarse product: all of A_CF, or its same-entity entries
+    Csr AcfQ;
+    if (lo.coupling == MGR_COUPLING_QUASI_IMPES) {
+      DArr<int> rankL;
+      label_rank(L->labels.p, n, rankL, s, present);
+      same_entity_filter(L->Acf, L->cf.C.p, L->cf.F.p, rankL.p, AcfQ, s);
+    }
     Csr Acor;
-    spgemm(L->Acf, M, Acor, s, flag);
+    spgemm(lo.coupling == MGR_COUPLING_QUASI_IMPES ? AcfQ : L->Acf, M, Acor, s, flag);
     trace("  A_cor done");
     Csr S;
     merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag);
@@ -717,6 +724,8 @@ void validate_opts(const mgr_opts &o) {
     require(lo.frelax_sweeps >= 1 && lo.frelax_sweeps <= 100, MGR_ERR_ARG, "frelax_sweeps");
     require(lo.global_smoother == 0 || lo.global_smoother == 1, MGR_ERR_ARG, "global_smoother");
     require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
+    require(lo.coupling == MGR_COUPLING_FULL || lo.coupling == MGR_COUPLING_QUASI_IMPES, MGR_ERR_ARG,
+            "coupling");
   }
 }
 
@@ -953,6 +962,7 @@ void mgr_default_opts(mgr_opts *o) {
     L.global_smoother = MGR_GSMOOTH_NONE;
     L.global_sweeps = 1;
     L.global_omega = 1.0;
+    L.coupling = MGR_COUPLING_FULL;
   }
 }
 

@@ -532,6 +532,58 @@ void extract_blocks(const Csr &A, const CfSplit &cf, Csr *Aff, Csr &Afc, Csr &Ac
   KCHK();
 }
 
+// ---- same-entity filter of A_CF (quasi-IMPES coupling) ----------------------------
+namespace {
+__global__ void k_same_entity_count(int64_t n, const int *__restrict__ rp,
+                                    const int *__restrict__ ci, const int *__restrict__ C,
+                                    const int *__restrict__ F, const int *__restrict__ rank,
+                                    int *__restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ri = rank[C[i]];
+  int c = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) c += rank[F[ci[e]]] == ri;
+  cnt[i] = c;
+}
+__global__ void k_same_entity_fill(int64_t n, const int *__restrict__ rp,
+                                   const int *__restrict__ ci, const double *__restrict__ v,
+                                   const int *__restrict__ C, const int *__restrict__ F,
+                                   const int *__restrict__ rank, const int *__restrict__ orp,
+                                   int *__restrict__ oci, double *__restrict__ ov) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ri = rank[C[i]];
+  int o = orp[i];
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    if (rank[F[ci[e]]] != ri) continue;
+    oci[o] = ci[e];
+    ov[o] = v[e];
+    ++o;
+  }
+}
+}  // namespace
+
+void same_entity_filter(const Csr &Acf, const int *C, const int *F, const int *rank, Csr &out,
+                        hipStream_t s) {
+  out.n = Acf.n;
+  out.m = Acf.m;
+  out.rp.alloc(Acf.n + 1, s);
+  DArr<int> cnt(std::max<int64_t>(Acf.n, 1), s);
+  if (Acf.n) {
+    k_same_entity_count<<<grid_for(Acf.n, 256), 256, 0, s>>>(Acf.n, Acf.rp.p, Acf.ci.p, C, F,
+                                                              rank, cnt.p);
+    KCHK();
+  }
+  out.nnz = exclusive_scan_i32(cnt.p, out.rp.p, Acf.n, s);
+  out.ci.alloc(std::max<int64_t>(out.nnz, 1), s);
+  out.v.alloc(std::max<int64_t>(out.nnz, 1), s);
+  if (Acf.n) {
+    k_same_entity_fill<<<grid_for(Acf.n, 256), 256, 0, s>>>(Acf.n, Acf.rp.p, Acf.ci.p, Acf.v.p, C,
+                                                             F, rank, out.rp.p, out.ci.p, out.v.p);
+    KCHK();
+  }
+}
+
 void scale_rows_div(Csr &M, const double *d, hipStream_t s) {
   if (M.n == 0) return;
   k_scale_rows_div<<<grid_for(M.n, 256), 256, 0, s>>>(M.n, M.rp.p, M.v.p, d);

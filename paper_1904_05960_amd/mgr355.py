@@ -25,6 +25,7 @@ FRELAX = {"jacobi": 0, "amg": 1, "dense": 2}
 GSMOOTH = {"none": 0, "block_jacobi": 1}
 COARSE = {"amg": 0, "dense": 1}
 PREC = {"fp64": 0, "fp32": 1}
+COUPLING = {"full": 0, "quasi_impes": 1}
 
 X_LEVEL_A, X_F, X_C, X_WP, X_ACOR, X_G, X_COARSE, X_AMG_A, X_AMG_P, X_AMG_AGG, X_AMG_NLEV = range(11)
 MAX_LEVELS = 8
@@ -49,7 +50,8 @@ class mgr_level_opts(C.Structure):
     _fields_ = [("f_label_mask", C.c_uint32), ("interp", C.c_int32), ("nmax_drop", C.c_int32),
                 ("frelax", C.c_int32), ("frelax_sweeps", C.c_int32), ("frelax_omega", C.c_double),
                 ("frelax_block", C.c_int32), ("global_smoother", C.c_int32),
-                ("global_sweeps", C.c_int32), ("global_omega", C.c_double)]
+                ("global_sweeps", C.c_int32), ("coupling", C.c_int32),
+                ("global_omega", C.c_double)]
 
 
 class mgr_opts(C.Structure):
@@ -216,6 +218,7 @@ class Level:
     global_smoother: str = "none"
     global_sweeps: int = 1
     global_omega: float = 1.0
+    coupling: str = "full"          # 'full' | 'quasi_impes'
 
 
 @dataclass
@@ -253,6 +256,7 @@ class Options:
             c.global_smoother = GSMOOTH[L.global_smoother]
             c.global_sweeps = int(L.global_sweeps)
             c.global_omega = float(L.global_omega)
+            c.coupling = COUPLING[L.coupling]
         o.coarse = COARSE[self.coarse]
         for dst, src in ((o.amg_frelax, self.amg_frelax), (o.amg_coarse, self.amg_coarse)):
             dst.theta0, dst.max_levels, dst.coarse_size = src.theta0, src.max_levels, src.coarse_size
@@ -262,19 +266,23 @@ class Options:
         return o
 
 
-def paper_plan(model: str, **kw) -> Options:
+def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 3,
+               **kw) -> Options:
     """Reduction order of Sec. 5.3: displacement first (one nodal AMG V-cycle, N_max = 4),
-    then the saturations (Jacobi, Galerkin, with the global block smoother on the level that
-    holds only cell unknowns), pressure last (AMG)."""
+    then the saturations (Jacobi, Galerkin, with the global block smoother on the levels that
+    hold only cell unknowns), pressure last (AMG).  `quasi_impes` uses the quasi-IMPES
+    coupling on the saturation levels; `global_sweeps` sets the block smoother's sweeps
+    (three: the block-Jacobi sweeps stand in for the single, stronger ILU(1) step of
+    Sec. 6)."""
+    sat = dict(nmax=-1, frelax="jacobi", global_smoother="block_jacobi",
+               global_sweeps=global_sweeps, coupling="quasi_impes" if quasi_impes else "full")
     if model == "biot1":
         levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3)]
     elif model == "two":
-        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3),
-                  Level((1,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi")]
+        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3), Level((1,), **sat)]
     elif model == "three":
-        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3),
-                  Level((3,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi"),
-                  Level((1,), nmax=-1, frelax="jacobi", global_smoother="block_jacobi")]
+        levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3), Level((3,), **sat),
+                  Level((1,), **sat)]
     else:
         raise ValueError(model)
     return Options(levels=levels, **kw)

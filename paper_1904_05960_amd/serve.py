@@ -7,6 +7,7 @@ the same sparsity pattern) with Poisson arrivals and reports solves/s and p50/p9
 
     python -m paper_1904_05960_amd.serve [--realizations 16] [--newton 8] [--nmin 16]
         [--nmax 64] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
+        [--restart 64]
 """
 from __future__ import annotations
 
@@ -196,6 +197,7 @@ def main(argv=None):
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--refresh", action="store_true", help="recompute setups each step")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--compare-fp64-serial", action="store_true")
@@ -206,15 +208,16 @@ def main(argv=None):
     ens = build_ensemble(a.realizations, a.nmin, a.nmax, a.seed, log)
     order = request_order(a.realizations, a.newton, a.seed)
     srv = Server(m.paper_plan("two", precision=a.precision), int(a.budget_gb * (1 << 30)),
-                 a.slots)
+                 a.slots, restart=a.restart)
     recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log)
     out = {"metric": "served MGR-FGMRES solves (1e-6), p50/p99 latency", "mode": "served",
            "precision": a.precision, "slots": a.slots, "rate_per_s": a.rate,
+           "restart": a.restart,
            **summarize(recs, wall), "server": srv.stats()}
     srv.close()
     if a.compare_fp64_serial:
         srv = Server(m.paper_plan("two", precision="fp64"), int(a.budget_gb * (1 << 30)), 1,
-                     cache=False)
+                     restart=a.restart, cache=False)
         recs2, wall2, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, False, log)
         out["fp64_one_at_a_time"] = summarize(recs2, wall2)
         srv.close()

@@ -74,7 +74,8 @@ class LevelRows:
         A_FF, A_FC, A_CF, A_CC = omgr.blocks_of(Ar, self.F, self.C)
         d = diagonal(A_FF)      # NaN on emptied rows; their rows of A_FC are empty too
         M, Wp = omgr.jacobi_interpolation(A_FC, d)
-        Acor = spgemm(A_CF, M)
+        Acor = spgemm(omgr.coupling_block(A_CF, self.labels, self.F, self.C,
+                                          self.lp.coupling), M)
         G = omgr.drop(Acor, self.labels[self.C], self.lp.nmax)
         S = merge_sub(A_CC, G)
         return restrict_rows(S, rows_c), restrict_rows(Wp, self.fpos[ks]), self.fpos[ks]

@@ -42,10 +42,18 @@ CASES = [
      lambda: small_amg(m.paper_plan("biot1", coarse="amg"))),
     ("two_9x7x6_paper", lambda: pm.two_phase(9, 7, 6, 1),
      lambda: small_amg(m.paper_plan("two"))),
+    ("two_9x7x6_paper_one_sweep", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(m.paper_plan("two", global_sweeps=1))),
     ("two_9x7x6_satfirst", lambda: pm.two_phase(9, 7, 6, 1),
      lambda: small_amg(m.saturation_first_plan("two"))),
     ("three_6x5x4_paper", lambda: pm.three_phase(6, 5, 4, 3),
      lambda: small_amg(m.paper_plan("three"))),
+    ("two_9x7x6_quasi_impes", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
+    ("channels_12x10x6_quasi_impes", lambda: pm.two_phase_channels(12, 10, 6, 2),
+     lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
+    ("three_6x5x4_quasi_impes", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(m.paper_plan("three", quasi_impes=True, global_sweeps=2))),
 ]
 
 
@@ -108,9 +116,13 @@ def test_apply_fp64_matches_oracle(case):
         assert err <= 1e-12
 
 
+# the channelized case stalls above 1e-8 (in the oracle too); it is compared at 1e-6
+FGMRES_RTOL = {"channels_12x10x6_quasi_impes": 1e-6}
+
+
 def test_fgmres_matches_oracle(case):
     tag, w, opts, A, labels, b, P, H = case
-    rtol = 1e-8
+    rtol = FGMRES_RTOL.get(tag, 1e-8)
     Ao = oracle_csr(w)
     ref = okry.fgmres(Ao.matvec, lambda v: omgr.apply(H, v), w.b, restart=30, rtol=rtol,
                       maxit=400)

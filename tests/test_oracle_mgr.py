@@ -290,3 +290,34 @@ def test_zero_pivot_detected():
     A = CSR.from_dense(D, np.ones((2, 2), dtype=bool))
     with pytest.raises(mgr.ZeroPivot):
         mgr.setup(A, np.array([0, 1], dtype=np.int8), mgr.Plan(levels=[mgr.LevelPlan(f_labels=(0,))]))
+
+
+def test_quasi_impes_closed_form():
+    """Quasi-IMPES coupling (the alternative described beside eq. coarse_grid_pressure):
+    in field order the coarse grid is A_pp - D_ps D_ss^{-1} A_sp with D_ps = diag(A_ps),
+    D_ss = diag(A_ss).  Rows are interleaved cell by cell (s, p, s, p, ...), so "diag"
+    pairs the s and p unknowns of one cell.  The full coupling gives A_pp - A_ps D_ss^{-1}
+    A_sp instead, which must differ."""
+    rng = np.random.default_rng(7)
+    ncell = 7
+    labels = np.tile(np.array([1, 2], dtype=np.int8), ncell)
+    D = random_system(rng, labels, density=0.5)
+    A = csr_from_dense(D)
+    s_idx, p_idx = np.arange(0, 2 * ncell, 2), np.arange(1, 2 * ncell, 2)
+    Ass, Asp = D[np.ix_(s_idx, s_idx)], D[np.ix_(s_idx, p_idx)]
+    Aps, App = D[np.ix_(p_idx, s_idx)], D[np.ix_(p_idx, p_idx)]
+    dss, dps = np.diag(Ass), np.diag(Aps)
+    want_qi = App - (dps / dss)[:, None] * Asp
+    want_full = App - Aps @ (Asp / dss[:, None])
+    got = {}
+    for coupling in ("quasi_impes", "full"):
+        plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(1,), coupling=coupling)], coarse="dense")
+        got[coupling] = mgr.setup(A, labels, plan).coarse_A.to_dense()
+    scale = np.abs(App).max() + np.abs(Asp).max()
+    assert np.allclose(got["quasi_impes"], want_qi, rtol=0, atol=1e-13 * scale)
+    assert np.allclose(got["full"], want_full, rtol=0, atol=1e-13 * scale)
+    assert not np.allclose(got["quasi_impes"], got["full"], rtol=0, atol=1e-6 * scale)
+    # W_p is the same under both couplings (only the coarse product changes)
+    plan = mgr.Plan(levels=[mgr.LevelPlan(f_labels=(1,), coupling="quasi_impes")], coarse="dense")
+    Wp = mgr.setup(A, labels, plan).levels[0].Wp.to_dense()
+    assert np.allclose(Wp, -Asp / dss[:, None], rtol=0, atol=1e-15 * np.abs(Asp).max())
