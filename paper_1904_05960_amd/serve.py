@@ -5,9 +5,9 @@ HBM admission by footprint, a setup cache keyed by realization.  `run_stream` re
 ensemble of Jacobians (realizations of different mesh sizes, several Newton steps each with
 the same sparsity pattern) with Poisson arrivals and reports solves/s and p50/p99 latency.
 
-    python -m paper_1904_05960_amd.serve [--realizations 16] [--newton 8] [--nmin 16]
-        [--nmax 64] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
-        [--restart 64]
+    python -m paper_1904_05960_amd.serve [--realizations 64] [--newton 8] [--nmin 16]
+        [--nmax 80] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
+        [--restart 64] [--input-pool-gb 32] [--compare-fp64-serial]
 """
 from __future__ import annotations
 
@@ -98,9 +98,13 @@ class Realization:
         self.A0 = m.Matrix.from_host(w.indptr, w.indices, w.data)
         self.labels = torch.as_tensor(w.labels).cuda()
         self.x_true = torch.as_tensor(w.x_true).cuda()
-        counts = np.diff(w.indptr)
-        self.row_of_entry = torch.as_tensor(np.repeat(np.arange(w.n), counts)).cuda()
+        self.row_len = torch.as_tensor(np.diff(w.indptr)).cuda()
         self.flow_row = (self.labels != 0)
+        self.nnz = int(w.nnz)
+
+    def input_bytes(self) -> int:
+        """Device bytes of one materialized request (values, b, x)."""
+        return 8 * self.nnz + 16 * self.n
 
     def step(self, k: int, seed: int):
         """Newton step k: the flow rows of the base Jacobian scaled by exp(0.1 z_i), z iid
@@ -113,7 +117,7 @@ class Realization:
             g.manual_seed(seed)
             z = torch.randn(self.n, generator=g, device="cuda", dtype=torch.float64)
             scale = torch.where(self.flow_row, torch.exp(0.1 * z), torch.ones_like(z))
-            val = self.A0.val * scale[self.row_of_entry]
+            val = self.A0.val * torch.repeat_interleave(scale, self.row_len)
         A = m.Matrix(self.A0.row_ptr, self.A0.col, val.contiguous())
         b = A.spmv(self.x_true)
         return A, b
@@ -146,35 +150,57 @@ def request_order(realizations: int, newton: int, seed: int):
 
 
 def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
-               refresh: bool = False, log=print):
+               refresh: bool = False, log=print, input_pool_bytes: int = 32 << 30,
+               keep_x: bool = True):
     """Open-loop replay: request i arrives at the i-th event of a Poisson process of the
-    given rate; returns per-request records."""
+    given rate.  Its matrix values and right-hand side are materialized on the device when
+    it arrives; at most `input_pool_bytes` of materialized inputs are held by requests in
+    flight (past that, the replay first waits for the oldest one to finish).  Latency runs
+    from the arrival time to completion, so such waits count.  Returns per-request
+    records, the wall time and the solutions (if keep_x)."""
+    import collections
     import torch
     rng = np.random.default_rng(seed + 2)
     gaps = rng.exponential(1.0 / rate, size=len(order)) if rate > 0 else np.zeros(len(order))
     arrivals = np.cumsum(gaps)
-    inputs = []
-    for (r, k) in order:       # prepare every request's matrix and rhs up front
-        A, b = ens[r].step(k, seed * 7919 + r * 101 + k)
-        inputs.append((A, b, torch.zeros_like(b)))
-    torch.cuda.synchronize()
-    tickets = []
+    inflight = collections.deque()          # (ticket, index, bytes)
+    held = 0
+    recs = [None] * len(order)
+    xs = [None] * len(order)
+    late = np.zeros(len(order))             # seconds from arrival to submission
+
+    def finish_oldest():
+        nonlocal held
+        t, j, nb = inflight.popleft()
+        res = server.wait(t)
+        res["realization"], res["newton_step"] = order[j]
+        res["n"] = ens[order[j][0]].n
+        res["latency_ms"] = res["t_end_ms"] - res["t_submit_ms"] + 1e3 * late[j]
+        recs[j] = res
+        held -= nb
+
     t0 = time.perf_counter()
-    for i, ((r, k), (A, b, x)) in enumerate(zip(order, inputs)):
+    for i, (r, k) in enumerate(order):
         delay = arrivals[i] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        tickets.append(server.submit(A, ens[r].labels, b, x, key=r, refresh=refresh,
-                                     last_use=(k == newton - 1)))
-    recs = []
-    for i, t in enumerate(tickets):
-        res = server.wait(t)
-        res["realization"], res["newton_step"] = order[i]
-        res["n"] = ens[order[i][0]].n
-        res["latency_ms"] = res["t_end_ms"] - res["t_submit_ms"]
-        recs.append(res)
+        need = ens[r].input_bytes()
+        while inflight and held + need > input_pool_bytes:
+            finish_oldest()
+        A, b = ens[r].step(k, seed * 7919 + r * 101 + k)
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()              # inputs complete before the server reads them
+        late[i] = max(0.0, time.perf_counter() - t0 - arrivals[i])
+        t = server.submit(A, ens[r].labels, b, x, key=r, refresh=refresh,
+                          last_use=(k == newton - 1))
+        inflight.append((t, i, need))
+        held += need
+        if keep_x:
+            xs[i] = x
+    while inflight:
+        finish_oldest()
     wall = time.perf_counter() - t0
-    return recs, wall, [inp[2] for inp in inputs]
+    return recs, wall, xs
 
 
 def summarize(recs, wall):
@@ -189,10 +215,10 @@ def summarize(recs, wall):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--realizations", type=int, default=16)
+    ap.add_argument("--realizations", type=int, default=64)
     ap.add_argument("--newton", type=int, default=8)
     ap.add_argument("--nmin", type=int, default=16)
-    ap.add_argument("--nmax", type=int, default=64)
+    ap.add_argument("--nmax", type=int, default=80)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=200.0)
@@ -201,6 +227,7 @@ def main(argv=None):
     ap.add_argument("--refresh", action="store_true", help="recompute setups each step")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--compare-fp64-serial", action="store_true")
+    ap.add_argument("--input-pool-gb", type=float, default=32.0)
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -209,7 +236,9 @@ def main(argv=None):
     order = request_order(a.realizations, a.newton, a.seed)
     srv = Server(m.paper_plan("two", precision=a.precision), int(a.budget_gb * (1 << 30)),
                  a.slots, restart=a.restart)
-    recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log)
+    pool = int(a.input_pool_gb * (1 << 30))
+    recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log,
+                               pool, keep_x=False)
     out = {"metric": "served MGR-FGMRES solves (1e-6), p50/p99 latency", "mode": "served",
            "precision": a.precision, "slots": a.slots, "rate_per_s": a.rate,
            "restart": a.restart,
@@ -218,7 +247,8 @@ def main(argv=None):
     if a.compare_fp64_serial:
         srv = Server(m.paper_plan("two", precision="fp64"), int(a.budget_gb * (1 << 30)), 1,
                      restart=a.restart, cache=False)
-        recs2, wall2, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, False, log)
+        recs2, wall2, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, False, log,
+                                     pool, keep_x=False)
         out["fp64_one_at_a_time"] = summarize(recs2, wall2)
         srv.close()
     print(json.dumps(out), flush=True)
