@@ -89,6 +89,14 @@ struct Csr {
   size_t bytes() const { return rp.bytes() + ci.bytes() + v.bytes(); }
 };
 
+// 3x3 block CSR with row-major blocks (9 doubles per block, entry (r, s) at 3r + s), used
+// by the nodal AMG setup products.
+struct Bsr3 {
+  int64_t nb = 0, mb = 0, nnzb = 0;
+  DArr<int> rp, ci;
+  DArr<double> v;
+};
+
 // Read-only views used by apply kernels (T = float or double).
 template <class T>
 struct CsrV {
@@ -199,6 +207,20 @@ void csr_to_dense(const Csr &A, double *D, hipStream_t s);
 void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s);
 
 // BSR3 conversion: scalar CSR with full 3x3 blocks -> block CSR
+// Symbolic sparse product: crp (n + 1, caller-allocated) gets the row pointers of the
+// pattern of A B (A: n rows; B: bn x bm), cnnz its size.
+void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
+                     const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
+                     int64_t &cnnz, hipStream_t s, int *dflag);
+// C = A B on 3x3 block matrices: the scalar product of their expansions, bit for bit (B's
+// blocks diagonal when diagb).
+void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s, int *dflag);
+void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what);
+void bsr3_to_csr(const Bsr3 &B, Csr &C, hipStream_t s);
+// R = P^T (block pattern transposed, each block transposed)
+void bsr3_transpose(const Bsr3 &P, Bsr3 &R, hipStream_t s);
+// tentative prolongator of a nodal aggregation: block (node, agg(node)) = I3
+void tentative_b3(const DArr<int> &agg, int64_t nnode, int64_t nagg, Bsr3 &T, hipStream_t s);
 void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, int64_t &nb,
                  int64_t &mb, int64_t &nnzb, hipStream_t s, int *dflag, const char *what);
 // setup trace on stderr when MGR355_TRACE is set

@@ -160,6 +160,8 @@ struct AmgLevel {
   int64_t nagg = 0;
   double omega = 0.0;
   DArr<double> dinv;         // l1 row sums inverted
+  // nodal (3x3 block) forms: FP64 row-major blocks during the setup products
+  std::unique_ptr<Bsr3> Ab64, Pb64, Rb64;
   // nodal (3x3 block) copies for the V-cycle
   DArr<int> Ab_rp, Ab_ci, Pb_rp, Pb_ci, Rb_rp, Rb_ci;
   int64_t nb = 0, ncb = 0, Ab_nnzb = 0, Pb_nnzb = 0, Rb_nnzb = 0;
@@ -298,17 +300,43 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     omega_over_diag(d.p, omega, w.p, n, s);
     Csr AT;
     trace("  T, rho done");
-    spgemm(L.A, T, AT, s, dflag);
-    trace("  AT done");
-    merge_drop(T, AT, w.p, -1, nullptr, L.P, true, s, dflag);
-    transpose(L.P, L.R, true, s);
-    trace("  P, R done");
-    Csr AP;
-    spgemm(L.A, L.P, AP, s, dflag);
-    trace("  AP done");
     auto N = std::make_unique<AmgLevel>();
-    spgemm(L.R, AP, N->A, s, dflag);
-    trace("  RAP done");
+    if (bs == 3) {
+      // the products on 3x3 blocks (same values as the scalar products, bit for bit)
+      if (!L.Ab64) {
+        L.Ab64 = std::make_unique<Bsr3>();
+        csr_to_bsr3(L.A, *L.Ab64, s, dflag, "AMG A");
+      }
+      Bsr3 Tb, ATb;
+      tentative_b3(agg, n / 3, nagg, Tb, s);
+      spgemm_b3(*L.Ab64, Tb, true, ATb, s, dflag);
+      bsr3_to_csr(ATb, AT, s);
+      trace("  AT done");
+      merge_drop(T, AT, w.p, -1, nullptr, L.P, true, s, dflag);
+      L.Pb64 = std::make_unique<Bsr3>();
+      csr_to_bsr3(L.P, *L.Pb64, s, dflag, "AMG P");
+      L.Rb64 = std::make_unique<Bsr3>();
+      bsr3_transpose(*L.Pb64, *L.Rb64, s);
+      trace("  P, R done");
+      Bsr3 APb;
+      spgemm_b3(*L.Ab64, *L.Pb64, false, APb, s, dflag);
+      trace("  AP done");
+      N->Ab64 = std::make_unique<Bsr3>();
+      spgemm_b3(*L.Rb64, APb, false, *N->Ab64, s, dflag);
+      bsr3_to_csr(*N->Ab64, N->A, s);
+      trace("  RAP done");
+    } else {
+      spgemm(L.A, T, AT, s, dflag);
+      trace("  AT done");
+      merge_drop(T, AT, w.p, -1, nullptr, L.P, true, s, dflag);
+      transpose(L.P, L.R, true, s);
+      trace("  P, R done");
+      Csr AP;
+      spgemm(L.A, L.P, AP, s, dflag);
+      trace("  AP done");
+      spgemm(L.R, AP, N->A, s, dflag);
+      trace("  RAP done");
+    }
     L.agg = std::move(agg);
     L.nagg = nagg;
     L.omega = omega;
@@ -330,14 +358,28 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     AmgLevel &L = *H.lv[k];
     cast_values(L.dinv.p, L.tdinv, L.A.n, sz, s);
     if (bs == 3) {
-      DArr<double> bv;
-      csr_to_bsr3(L.A, L.Ab_rp, L.Ab_ci, bv, L.nb, L.ncb, L.Ab_nnzb, s, dflag, "AMG A");
-      to_planes(bv, L.Ab_nnzb, L.tA, sz, s);
-      int64_t a, b;
-      csr_to_bsr3(L.P, L.Pb_rp, L.Pb_ci, bv, a, b, L.Pb_nnzb, s, dflag, "AMG P");
-      to_planes(bv, L.Pb_nnzb, L.tP, sz, s);
-      csr_to_bsr3(L.R, L.Rb_rp, L.Rb_ci, bv, a, b, L.Rb_nnzb, s, dflag, "AMG R");
-      to_planes(bv, L.Rb_nnzb, L.tR, sz, s);
+      // block forms from the setup products; the block index arrays move to the V-cycle
+      if (!L.Ab64) {
+        L.Ab64 = std::make_unique<Bsr3>();
+        csr_to_bsr3(L.A, *L.Ab64, s, dflag, "AMG A");
+      }
+      L.nb = L.Ab64->nb;
+      L.ncb = L.Ab64->mb;
+      L.Ab_nnzb = L.Ab64->nnzb;
+      L.Pb_nnzb = L.Pb64->nnzb;
+      L.Rb_nnzb = L.Rb64->nnzb;
+      to_planes(L.Ab64->v, L.Ab_nnzb, L.tA, sz, s);
+      to_planes(L.Pb64->v, L.Pb_nnzb, L.tP, sz, s);
+      to_planes(L.Rb64->v, L.Rb_nnzb, L.tR, sz, s);
+      L.Ab_rp = std::move(L.Ab64->rp);
+      L.Ab_ci = std::move(L.Ab64->ci);
+      L.Pb_rp = std::move(L.Pb64->rp);
+      L.Pb_ci = std::move(L.Pb64->ci);
+      L.Rb_rp = std::move(L.Rb64->rp);
+      L.Rb_ci = std::move(L.Rb64->ci);
+      L.Ab64.reset();
+      L.Pb64.reset();
+      L.Rb64.reset();
     } else {
       cast_values(L.A.v.p, L.tA, L.A.nnz, sz, s);
       cast_values(L.P.v.p, L.tP, L.P.nnz, sz, s);
@@ -350,6 +392,7 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
   }
   {
     AmgLevel &Lc = *H.lv.back();
+    Lc.Ab64.reset();      // the coarsest level is solved densely
     Lc.y.alloc(std::max<int64_t>(Lc.A.n, 1) * sz, s);
     Lc.b.alloc(std::max<int64_t>(Lc.A.n, 1) * sz, s);
   }

@@ -782,6 +782,132 @@ void csr_to_bsr3(const Csr &A, DArr<int> &rp, DArr<int> &ci, DArr<double> &v, in
   KCHK();
 }
 
+void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what) {
+  csr_to_bsr3(A, B.rp, B.ci, B.v, B.nb, B.mb, B.nnzb, s, dflag, what);
+}
+
+namespace {
+__global__ void k_b3_rowptr(int64_t nb, const int *__restrict__ brp, int *__restrict__ rp) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // scalar row
+  if (t > 3 * nb) return;
+  if (t == 3 * nb) {
+    rp[t] = 9 * brp[nb];
+    return;
+  }
+  const int64_t I = t / 3, r = t % 3;
+  rp[t] = 9 * brp[I] + 3 * (int)r * (brp[I + 1] - brp[I]);
+}
+__global__ void k_b3_expand(int64_t nb, const int *__restrict__ brp, const int *__restrict__ bci,
+                            const double *__restrict__ bv, const int *__restrict__ rp,
+                            int *__restrict__ ci, double *__restrict__ v) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // (scalar row, block)
+  if (t >= 3 * (int64_t)brp[nb]) return;
+  const int64_t e = t / 3;
+  const int r = (int)(t % 3);
+  // block row of entry e: binary search in brp
+  int64_t lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (brp[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  const int64_t I = lo;
+  const int64_t pos = rp[3 * I + r] + 3 * (e - brp[I]);
+  const int J = bci[e];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ci[pos + c] = 3 * J + c;
+    v[pos + c] = bv[9 * e + 3 * r + c];
+  }
+}
+__global__ void k_iota_f64(int64_t n, double *__restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (double)i;
+}
+__global__ void k_b3_gather_t(int64_t nnzb, const double *__restrict__ idx,
+                              const double *__restrict__ pv, double *__restrict__ rv) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nnzb) return;
+  const int64_t q = (int64_t)idx[e];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rv[9 * e + 3 * r + c] = pv[9 * q + 3 * c + r];
+}
+__global__ void k_tent_b3(int64_t nnode, const int *__restrict__ agg, const int *__restrict__ rp,
+                          int *__restrict__ ci, double *__restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nnode || agg[i] < 0) return;
+  const int e = rp[i];
+  ci[e] = agg[i];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) v[9 * (int64_t)e + q] = (q % 4 == 0) ? 1.0 : 0.0;
+}
+__global__ void k_tent_b3_count(int64_t nnode, const int *__restrict__ agg, int *__restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nnode) cnt[i] = agg[i] >= 0 ? 1 : 0;
+}
+}  // namespace
+
+void bsr3_to_csr(const Bsr3 &B, Csr &C, hipStream_t s) {
+  C.n = 3 * B.nb;
+  C.m = 3 * B.mb;
+  require(9 * B.nnzb < ((int64_t)1 << 31), MGR_ERR_UNSUPPORTED, "matrix too large");
+  C.nnz = 9 * B.nnzb;
+  C.rp.alloc(C.n + 1, s);
+  C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
+  C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
+  k_b3_rowptr<<<grid_for(C.n + 1, 256), 256, 0, s>>>(B.nb, B.rp.p, C.rp.p);
+  KCHK();
+  if (B.nnzb == 0) return;
+  k_b3_expand<<<grid_for(3 * B.nnzb, 256), 256, 0, s>>>(B.nb, B.rp.p, B.ci.p, B.v.p, C.rp.p,
+                                                        C.ci.p, C.v.p);
+  KCHK();
+}
+
+void bsr3_transpose(const Bsr3 &P, Bsr3 &R, hipStream_t s) {
+  // transpose the block pattern carrying each block's index, then gather transposed blocks
+  Csr Pp;
+  Pp.n = P.nb;
+  Pp.m = P.mb;
+  Pp.nnz = P.nnzb;
+  Pp.rp.alloc(P.nb + 1, s);
+  HIPCHK(hipMemcpyAsync(Pp.rp.p, P.rp.p, (P.nb + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+  Pp.ci.alloc(std::max<int64_t>(P.nnzb, 1), s);
+  if (P.nnzb)
+    HIPCHK(hipMemcpyAsync(Pp.ci.p, P.ci.p, P.nnzb * sizeof(int), hipMemcpyDeviceToDevice, s));
+  Pp.v.alloc(std::max<int64_t>(P.nnzb, 1), s);
+  if (P.nnzb) {
+    k_iota_f64<<<grid_for(P.nnzb, 256), 256, 0, s>>>(P.nnzb, Pp.v.p);
+    KCHK();
+  }
+  Csr Rp;
+  transpose(Pp, Rp, true, s);
+  R.nb = P.mb;
+  R.mb = P.nb;
+  R.nnzb = P.nnzb;
+  R.rp = std::move(Rp.rp);
+  R.ci = std::move(Rp.ci);
+  R.v.alloc(std::max<int64_t>(9 * P.nnzb, 1), s);
+  if (P.nnzb) {
+    k_b3_gather_t<<<grid_for(P.nnzb, 256), 256, 0, s>>>(P.nnzb, Rp.v.p, P.v.p, R.v.p);
+    KCHK();
+  }
+}
+
+void tentative_b3(const DArr<int> &agg, int64_t nnode, int64_t nagg, Bsr3 &T, hipStream_t s) {
+  T.nb = nnode;
+  T.mb = nagg;
+  T.rp.alloc(nnode + 1, s);
+  DArr<int> cnt(nnode + 1, s);
+  k_tent_b3_count<<<grid_for(nnode, 256), 256, 0, s>>>(nnode, agg.p, cnt.p);
+  KCHK();
+  T.nnzb = exclusive_scan_i32(cnt.p, T.rp.p, nnode, s);
+  T.ci.alloc(std::max<int64_t>(T.nnzb, 1), s);
+  T.v.alloc(std::max<int64_t>(9 * T.nnzb, 1), s);
+  k_tent_b3<<<grid_for(nnode, 256), 256, 0, s>>>(nnode, agg.p, T.rp.p, T.ci.p, T.v.p);
+  KCHK();
+}
+
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag) {
   require(A.n % nb == 0, MGR_ERR_UNSUPPORTED, "block smoother: size not divisible by block");
   const int64_t nblk = A.n / nb;

@@ -415,46 +415,35 @@ void dispatch_num(int bucket, int g0, int nrows, const int *rows, const Csr &A, 
 int lanes_for(double mean) { return mean > 48 ? 64 : mean > 24 ? 32 : mean > 6 ? 16 : 8; }
 }  // namespace
 
-void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
-  require(A.m == B.n, MGR_ERR_ARG, "spgemm: inner dimensions differ");
-  const int64_t n = A.n;
-  C.n = n;
-  C.m = B.m;
-  C.rp.alloc(n + 1, s);
-  if (n == 0) {
-    fill<int>(C.rp.p, 0, 1, s);
-    C.nnz = 0;
-    return;
-  }
+void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
+                     const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
+                     int64_t &cnnz, hipStream_t s, int *dflag) {
   DArr<int64_t> ub(n, s);
-  k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, B.rp.p, ub.p);
+  k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, arp, aci, brp, ub.p);
   KCHK();
   DArr<int> cnt(n + 1, s), retry(n, s), nretry(2, s);
   fill<int>(nretry.p, 0, 2, s);
   // symbolic pass 1: tables of <= 512 slots, 64 / G rows per workgroup
-  const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
-  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
+  const double meanA = (double)annz / (double)std::max<int64_t>(n, 1);
+  const double meanB = (double)bnnz / (double)std::max<int64_t>(bn, 1);
   const double prods = meanA * meanB;
   if (prods > 256) {
-    k_sym_lds<64, 512><<<(unsigned)n, 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p, B.rp.p,
-                                                  B.ci.p, cnt.p, retry.p, nretry.p);
+    k_sym_lds<64, 512><<<(unsigned)n, 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp, bci, cnt.p,
+                                                  retry.p, nretry.p);
   } else if (prods > 64) {
-    k_sym_lds<32, 512><<<(unsigned)((n + 1) / 2), 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p,
-                                                              B.rp.p, B.ci.p, cnt.p, retry.p,
-                                                              nretry.p);
+    k_sym_lds<32, 512><<<(unsigned)((n + 1) / 2), 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp,
+                                                              bci, cnt.p, retry.p, nretry.p);
   } else {
-    k_sym_lds<16, 512><<<(unsigned)((n + 3) / 4), 64, 0, s>>>(n, nullptr, ub.p, A.rp.p, A.ci.p,
-                                                              B.rp.p, B.ci.p, cnt.p, retry.p,
-                                                              nretry.p);
+    k_sym_lds<16, 512><<<(unsigned)((n + 3) / 4), 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp,
+                                                              bci, cnt.p, retry.p, nretry.p);
   }
   KCHK();
   int hretry = read_flag(nretry.p, s);
   if (hretry > 0) {
     // pass 2: 4096-slot tables, one row per workgroup
     DArr<int> retry2(hretry, s);
-    k_sym_lds<64, SYM_HT><<<(unsigned)hretry, 64, 0, s>>>(hretry, retry.p, ub.p, A.rp.p, A.ci.p,
-                                                          B.rp.p, B.ci.p, cnt.p, retry2.p,
-                                                          nretry.p + 1);
+    k_sym_lds<64, SYM_HT><<<(unsigned)hretry, 64, 0, s>>>(hretry, retry.p, ub.p, arp, aci, brp,
+                                                          bci, cnt.p, retry2.p, nretry.p + 1);
     KCHK();
     const int hretry2 = read_flag(nretry.p + 1, s);
     if (hretry2 > 0) {
@@ -466,7 +455,7 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
       unsigned long long hm = 0;
       HIPCHK(hipMemcpyAsync(&hm, mub.p, sizeof(hm), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      const int64_t cap = std::min<int64_t>((int64_t)hm, B.m);
+      const int64_t cap = std::min<int64_t>((int64_t)hm, bm);
       const int64_t ht = next_pow2(2 * std::max<int64_t>(cap, 32));
       require(ht <= (int64_t)1 << 22, MGR_ERR_UNSUPPORTED,
               "spgemm: a product row exceeds the supported length");
@@ -474,13 +463,29 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
       DArr<int> scratch(std::min<int64_t>(batch, hretry2) * ht, s);
       for (int64_t b0 = 0; b0 < hretry2; b0 += batch) {
         const int nb = (int)std::min<int64_t>(batch, hretry2 - b0);
-        k_sym_global<<<nb, 64, 0, s>>>(nb, retry2.p + b0, (int)ht, A.rp.p, A.ci.p, B.rp.p,
-                                       B.ci.p, cnt.p, scratch.p, dflag);
+        k_sym_global<<<nb, 64, 0, s>>>(nb, retry2.p + b0, (int)ht, arp, aci, brp, bci, cnt.p,
+                                       scratch.p, dflag);
         KCHK();
       }
     }
   }
-  C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
+  cnnz = exclusive_scan_i32(cnt.p, crp, n, s);
+}
+
+void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
+  require(A.m == B.n, MGR_ERR_ARG, "spgemm: inner dimensions differ");
+  const int64_t n = A.n;
+  C.n = n;
+  C.m = B.m;
+  C.rp.alloc(n + 1, s);
+  if (n == 0) {
+    fill<int>(C.rp.p, 0, 1, s);
+    C.nnz = 0;
+    return;
+  }
+  spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnz, B.rp.p, B.ci.p, B.n, B.m, B.nnz, C.rp.p, C.nnz, s,
+                  dflag);
+  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
   C.ci.alloc(C.nnz, s);
   C.v.alloc(C.nnz, s);
   if (C.nnz == 0) return;
@@ -515,6 +520,214 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
       const int nb = (int)std::min<int64_t>(batch, nbig - b0);
       k_num_global<<<nb, 64, 0, s>>>(nb, big + b0, (int)ht, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
                                      B.v.p, C.rp.p, C.ci.p, C.v.p, si.p, sd.p, dflag);
+      KCHK();
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------------------
+// 3x3 block products for the nodal AMG (A T, A P and R (A P) of matrices whose patterns
+// consist of full 3x3 blocks).  Scalar entry (3I+r, 3J+s) of C = A B is the sum over the
+// scalar columns k = 3K+c of row 3I+r, in ascending k; walking the blocks K of block row I
+// in ascending order and c = 0, 1, 2 inside each block visits the same k in the same order,
+// so every entry gets the same products, rounded the same way, added in the same order as
+// in the scalar product above: the values agree bit for bit, with 1/9 of the index work.
+// With `diagb` the blocks of B are diagonal (the tentative prolongator): only c = s
+// contributes, exactly the products the scalar form takes.
+namespace {
+
+template <int G, bool DIAGB>
+__device__ void num_row_b3(int row, const int *__restrict__ arp, const int *__restrict__ aci,
+                           const double *__restrict__ av, const int *__restrict__ brp,
+                           const int *__restrict__ bci, const double *__restrict__ bv,
+                           const int *__restrict__ crp, int *__restrict__ cci,
+                           double *__restrict__ cv, int *keys, double *vals, int *lk, int *ls,
+                           int ht, int *s_n, int *flag) {
+  const int l = threadIdx.x & (G - 1);
+  const unsigned mask = (unsigned)ht - 1;
+  for (int q = l; q < ht; q += G) keys[q] = -1;
+  for (int q = l; q < 9 * ht; q += G) vals[q] = 0.0;
+  if (l == 0) *s_n = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  const int as = arp[row], ae = arp[row + 1];
+  for (int e = as; e < ae; ++e) {            // blocks K of the row in ascending order
+    const int k = aci[e];
+    double a[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) a[t] = av[9 * (int64_t)e + t];
+    const int b0 = brp[k], b1 = brp[k + 1];
+    for (int q = b0 + l; q < b1; q += G) {   // distinct output blocks per lane
+      const int j = bci[q];
+      double b[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) b[t] = bv[9 * (int64_t)q + t];
+      const unsigned slot = table_find_or_insert(keys, mask, j);
+      if (slot > mask) {
+        atomicOr(flag, FLAG_PATTERN);
+        continue;
+      }
+      double *c = vals + 9 * slot;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          double x = c[3 * r + t];
+          if (DIAGB) {
+            x = __dadd_rn(x, __dmul_rn(a[3 * r + t], b[4 * t]));
+          } else {
+            x = __dadd_rn(x, __dmul_rn(a[3 * r + 0], b[0 + t]));
+            x = __dadd_rn(x, __dmul_rn(a[3 * r + 1], b[3 + t]));
+            x = __dadd_rn(x, __dmul_rn(a[3 * r + 2], b[6 + t]));
+          }
+          c[3 * r + t] = x;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int q = l; q < ht; q += G) {
+    const int key = keys[q];
+    if (key != -1) {
+      const int t = atomicAdd(s_n, 1);
+      if (t < ht / 2) {
+        lk[t] = key;
+        ls[t] = q;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  const int m = *s_n;
+  const int base = crp[row];
+  if (m > ht / 2 || m != crp[row + 1] - base) {
+    if (l == 0) atomicOr(flag, FLAG_PATTERN);
+    return;
+  }
+  for (int t = l; t < m; t += G) {
+    const int key = lk[t];
+    int rank = 0;
+    for (int u = 0; u < m; ++u) rank += (lk[u] < key);
+    cci[base + rank] = key;
+    const double *c = vals + 9 * ls[t];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) cv[9 * (int64_t)(base + rank) + q] = c[q];
+  }
+}
+
+template <int G, int HT, bool DIAGB>
+__global__ void __launch_bounds__(64) k_num_b3(int nrows, const int *__restrict__ rows,
+                                               const int *__restrict__ arp,
+                                               const int *__restrict__ aci,
+                                               const double *__restrict__ av,
+                                               const int *__restrict__ brp,
+                                               const int *__restrict__ bci,
+                                               const double *__restrict__ bv,
+                                               const int *__restrict__ crp, int *__restrict__ cci,
+                                               double *__restrict__ cv, int *flag) {
+  constexpr int NR = 64 / G;
+  __shared__ int keys[NR][HT];
+  __shared__ double vals[NR][9 * HT];
+  __shared__ int lk[NR][HT / 2], ls[NR][HT / 2];
+  __shared__ int s_n[NR];
+  const int g = threadIdx.x / G;
+  const int idx = blockIdx.x * NR + g;
+  if (idx >= nrows) return;
+  num_row_b3<G, DIAGB>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g],
+                       lk[g], ls[g], HT, &s_n[g], flag);
+}
+
+template <bool DIAGB>
+__global__ void __launch_bounds__(64) k_num_b3_global(
+    int nrows, const int *__restrict__ rows, int ht, const int *__restrict__ arp,
+    const int *__restrict__ aci, const double *__restrict__ av, const int *__restrict__ brp,
+    const int *__restrict__ bci, const double *__restrict__ bv, const int *__restrict__ crp,
+    int *__restrict__ cci, double *__restrict__ cv, int *scratch_i, double *scratch_d,
+    int *flag) {
+  __shared__ int s_n;
+  if ((int)blockIdx.x >= nrows) return;
+  const int row = rows[blockIdx.x];
+  int *keys = scratch_i + (int64_t)blockIdx.x * 2 * ht;
+  int *lk = keys + ht;
+  int *ls = lk + ht / 2;
+  double *vals = scratch_d + (int64_t)blockIdx.x * 9 * ht;
+  num_row_b3<64, DIAGB>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, ls, ht,
+                        &s_n, flag);
+}
+
+template <int G, int HT>
+void launch_num_b3(bool diagb, int nrows, const int *rows, const Bsr3 &A, const Bsr3 &B,
+                   Bsr3 &C, int *dflag, hipStream_t s) {
+  constexpr int NR = 64 / G;
+  const unsigned grid = (unsigned)((nrows + NR - 1) / NR);
+  if (diagb)
+    k_num_b3<G, HT, true><<<grid, 64, 0, s>>>(nrows, rows, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
+                                              B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
+  else
+    k_num_b3<G, HT, false><<<grid, 64, 0, s>>>(nrows, rows, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
+                                               B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
+  KCHK();
+}
+
+}  // namespace
+
+void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s, int *dflag) {
+  require(A.mb == B.nb, MGR_ERR_ARG, "block spgemm: inner dimensions differ");
+  const int64_t n = A.nb;
+  C.nb = n;
+  C.mb = B.mb;
+  C.rp.alloc(n + 1, s);
+  if (n == 0) {
+    fill<int>(C.rp.p, 0, 1, s);
+    C.nnzb = 0;
+    return;
+  }
+  spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnzb, B.rp.p, B.ci.p, B.nb, B.mb, B.nnzb, C.rp.p, C.nnzb,
+                  s, dflag);
+  C.ci.alloc(std::max<int64_t>(C.nnzb, 1), s);
+  C.v.alloc(std::max<int64_t>(9 * C.nnzb, 1), s);
+  if (C.nnzb == 0) return;
+  // rows by output block count: <= 64 (LDS table 128), <= 128 (256), <= 256 (512), longer
+  // rows with tables in global memory
+  DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
+  fill<int>(counts.p, 0, NBUCKET, s);
+  k_bucket<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
+  KCHK();
+  int hc[NBUCKET];
+  HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hc[0] > 0) launch_num_b3<16, 128>(diagb, hc[0], lists.p, A, B, C, dflag, s);
+  if (hc[1] > 0) launch_num_b3<32, 256>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
+  if (hc[2] > 0) launch_num_b3<64, 512>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
+  for (int b = 3; b < NBUCKET; ++b) {
+    const int nbig = hc[b];
+    if (nbig == 0) continue;
+    const int *big = lists.p + (size_t)b * n;
+    DArr<int> mx(1, s);
+    fill<int>(mx.p, 0, 1, s);
+    k_max_len<<<grid_for(nbig, 256), 256, 0, s>>>(nbig, big, C.rp.p, mx.p);
+    KCHK();
+    const int hm = read_flag(mx.p, s);
+    const int64_t ht = next_pow2(2 * (int64_t)hm);
+    require(ht <= (int64_t)1 << 20, MGR_ERR_UNSUPPORTED,
+            "block spgemm: a product row exceeds the supported length");
+    const int64_t per = 2 * ht * 4 + 9 * ht * 8;
+    const int64_t batch = std::max<int64_t>(1, ((int64_t)256 << 20) / per);
+    const int64_t nb0 = std::min<int64_t>(batch, nbig);
+    DArr<int> si(nb0 * 2 * ht, s);
+    DArr<double> sd(nb0 * 9 * ht, s);
+    for (int64_t b0 = 0; b0 < nbig; b0 += batch) {
+      const int nb = (int)std::min<int64_t>(batch, nbig - b0);
+      if (diagb)
+        k_num_b3_global<true><<<nb, 64, 0, s>>>(nb, big + b0, (int)ht, A.rp.p, A.ci.p, A.v.p,
+                                                B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p,
+                                                si.p, sd.p, dflag);
+      else
+        k_num_b3_global<false><<<nb, 64, 0, s>>>(nb, big + b0, (int)ht, A.rp.p, A.ci.p, A.v.p,
+                                                 B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p,
+                                                 si.p, sd.p, dflag);
       KCHK();
     }
   }
