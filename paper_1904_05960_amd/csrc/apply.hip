@@ -59,6 +59,153 @@ __global__ void __launch_bounds__(256) k_csr(int64_t nw, const int *__restrict__
   }
 }
 
+// CSR-stream variant (matrices with row blocks): block k owns rows [rb[k], rb[k+1]) whose
+// entries start in the k-th window of SNNZ entries.  The window's products are formed with
+// coalesced loads, PER independent loads in flight per thread, staged in LDS, and each row
+// is summed from LDS by 8 lanes; a block whose rows hold more than SCAP entries sums each
+// row directly.  Row t of the matrix is work item t; `bidx` indexes b (RESID) and `oidx`
+// the output (INTERP: z[oidx[t]] (+)= [eF[t]] + acc).
+constexpr int SB = 256;
+constexpr int SNNZ = 2048;
+constexpr int SCAP = 4096;
+enum { M_INTERP = 5 };
+
+template <class T, int MODE>
+__device__ __forceinline__ void csr_epilogue(int row, T acc, const int *__restrict__ bidx,
+                                             const int *__restrict__ oidx,
+                                             const T *__restrict__ x, const T *__restrict__ b,
+                                             const T *__restrict__ dinv, T *__restrict__ out,
+                                             T *__restrict__ out2, int accumulate) {
+  if (MODE == M_RESID) {
+    out[row] = b[bidx ? bidx[row] : row] - acc;
+  } else if (MODE == M_SPMV) {
+    out[row] = acc;
+  } else if (MODE == M_SPMV_ADD) {
+    out[row] += acc;
+  } else if (MODE == M_L1PRE) {
+    const T bi = b[row];
+    out2[row] = dinv[row] * bi;
+    out[row] = bi - acc;
+  } else if (MODE == M_L1POST) {
+    out[row] = x[row] + dinv[row] * (b[row] - acc);
+  } else {  // M_INTERP: x = eF (may be null), out = z
+    const int i = oidx[row];
+    const T base = accumulate ? out[i] : (x ? x[row] : (T)0);
+    out[i] = base + acc;
+  }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
+                                                   const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const T *__restrict__ v,
+                                                   const T *__restrict__ xin,
+                                                   const T *__restrict__ x,
+                                                   const T *__restrict__ b,
+                                                   const T *__restrict__ dinv,
+                                                   const int *__restrict__ bidx,
+                                                   const int *__restrict__ oidx,
+                                                   T *__restrict__ out, T *__restrict__ out2,
+                                                   int accumulate) {
+  // xin: the vector the products gather (x, or for L1PRE b scaled by dinv on the fly)
+  __shared__ T prod[SCAP];
+  const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int base = rp[r0];
+  const int cnt = rp[r1] - base;
+  const int t = threadIdx.x;
+  if (cnt <= SCAP) {
+    constexpr int PER = SNNZ / SB;
+    for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
+      int c[PER];
+      T vv[PER], xv[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        c[u] = 0;
+        vv[u] = 0;
+        if (e < cnt) {
+          c[u] = ci[base + e];
+          vv[u] = v[base + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        if (MODE == M_L1PRE) xv[u] = (e < cnt) ? dinv[c[u]] * b[c[u]] : (T)0;
+        else xv[u] = (e < cnt) ? xin[c[u]] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * SB + t;
+        if (e < cnt) prod[e] = vv[u] * xv[u];
+      }
+    }
+    __syncthreads();
+    constexpr int G = 8;
+    const int l = t & (G - 1);
+    for (int row = r0 + t / G; row < r1; row += SB / G) {
+      const int s0 = rp[row] - base, e1 = rp[row + 1] - base;
+      T acc = 0;
+      for (int e = s0 + l; e < e1; e += G) acc += prod[e];
+      acc = group_sum<T, G>(acc);
+      if (l == 0) csr_epilogue<T, MODE>(row, acc, bidx, oidx, x, b, dinv, out, out2, accumulate);
+    }
+    return;
+  }
+  __shared__ T part[SB / 64];
+  for (int row = r0; row < r1; ++row) {
+    T acc = 0;
+    for (int e = rp[row] + t; e < rp[row + 1]; e += SB) {
+      const int c = ci[e];
+      acc += v[e] * (MODE == M_L1PRE ? dinv[c] * b[c] : xin[c]);
+    }
+    acc = group_sum<T, 64>(acc);
+    if ((t & 63) == 0) part[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      const T tot = (part[0] + part[1]) + (part[2] + part[3]);
+      csr_epilogue<T, MODE>(row, tot, bidx, oidx, x, b, dinv, out, out2, accumulate);
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int MODE>
+void launch_csr_stream(const CsrV<T> &A, const T *xin, const T *x, const T *b, const T *dinv,
+                       const int *bidx, const int *oidx, T *out, T *out2, int accumulate,
+                       hipStream_t s) {
+  if (A.nblk <= 0) return;
+  k_csr_stream<T, MODE><<<(unsigned)A.nblk, SB, 0, s>>>(A.rb, A.rp, A.ci, A.v, xin, x, b, dinv,
+                                                        bidx, oidx, out, out2, accumulate);
+  KCHK();
+}
+
+// z_C (+)= e_C
+template <class T>
+__global__ void k_scatter_c(const int *__restrict__ C, int64_t nC, const T *__restrict__ eC,
+                            T *__restrict__ z, int accumulate) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nC) return;
+  const int i = C[k];
+  z[i] = accumulate ? z[i] + eC[k] : eC[k];
+}
+
+__global__ void k_rowblocks32(int64_t n, const int *__restrict__ rp, int64_t K,
+                              int *__restrict__ rb) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k > K) return;
+  if (k == K) { rb[k] = (int)n; return; }
+  const int64_t target = k * SNNZ;
+  int64_t lo = 0, hi = n;          // first row whose start is >= target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  rb[k] = (int)lo;
+}
+
 template <class T, int MODE>
 void launch_csr(const CsrV<T> &A, int64_t nw, const int *rows, const int *bidx, const T *x,
                 const T *b, const T *dinv, T *out, T *out2, hipStream_t s) {
@@ -238,12 +385,37 @@ __global__ void k_cast(const A *__restrict__ a, B *__restrict__ b, int64_t n) {
 template <class T>
 void VecOps<T>::resid(const CsrV<T> &A, int64_t nw, const int *rows, const int *bidx, const T *x,
                       const T *b, T *out, hipStream_t s) {
-  launch_csr<T, M_RESID>(A, nw, rows, bidx, x, b, nullptr, out, nullptr, s);
+  if (!rows && A.rb && nw == A.n)
+    launch_csr_stream<T, M_RESID>(A, x, x, b, nullptr, bidx, nullptr, out, nullptr, 0, s);
+  else
+    launch_csr<T, M_RESID>(A, nw, rows, bidx, x, b, nullptr, out, nullptr, s);
 }
 template <class T>
 void VecOps<T>::spmv(const CsrV<T> &A, const T *x, T *y, bool accumulate, hipStream_t s) {
+  if (A.rb) {
+    if (accumulate)
+      launch_csr_stream<T, M_SPMV_ADD>(A, x, x, nullptr, nullptr, nullptr, nullptr, y, nullptr, 0, s);
+    else
+      launch_csr_stream<T, M_SPMV>(A, x, x, nullptr, nullptr, nullptr, nullptr, y, nullptr, 0, s);
+    return;
+  }
   if (accumulate) launch_csr<T, M_SPMV_ADD>(A, A.n, nullptr, nullptr, x, nullptr, nullptr, y, nullptr, s);
   else launch_csr<T, M_SPMV>(A, A.n, nullptr, nullptr, x, nullptr, nullptr, y, nullptr, s);
+}
+template <class T>
+void VecOps<T>::interp_fc(int64_t n, const int *map, const int *F, int64_t nF, const int *C,
+                          int64_t nC, const CsrV<T> &Wp, const T *eC, const T *eF, T *z,
+                          bool accumulate, hipStream_t s) {
+  if (!Wp.rb) {
+    interp(n, map, Wp, eC, eF, z, accumulate, s);
+    return;
+  }
+  launch_csr_stream<T, M_INTERP>(Wp, eC, eF, nullptr, nullptr, nullptr, F, z, nullptr,
+                                 accumulate ? 1 : 0, s);
+  if (nC > 0) {
+    k_scatter_c<T><<<grid_for(nC, 256), 256, 0, s>>>(C, nC, eC, z, accumulate ? 1 : 0);
+    KCHK();
+  }
 }
 template <class T>
 void VecOps<T>::interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC, const T *eF,
@@ -255,12 +427,18 @@ void VecOps<T>::interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC
 }
 template <class T>
 void VecOps<T>::l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r, hipStream_t s) {
-  launch_csr<T, M_L1PRE>(A, A.n, nullptr, nullptr, nullptr, b, dinv, r, x, s);
+  if (A.rb)
+    launch_csr_stream<T, M_L1PRE>(A, nullptr, nullptr, b, dinv, nullptr, nullptr, r, x, 0, s);
+  else
+    launch_csr<T, M_L1PRE>(A, A.n, nullptr, nullptr, nullptr, b, dinv, r, x, s);
 }
 template <class T>
 void VecOps<T>::l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,
                         hipStream_t s) {
-  launch_csr<T, M_L1POST>(A, A.n, nullptr, nullptr, x, b, dinv, y, nullptr, s);
+  if (A.rb)
+    launch_csr_stream<T, M_L1POST>(A, x, x, b, dinv, nullptr, nullptr, y, nullptr, 0, s);
+  else
+    launch_csr<T, M_L1POST>(A, A.n, nullptr, nullptr, x, b, dinv, y, nullptr, s);
 }
 template <class T>
 void VecOps<T>::b_spmv(const Bsr3V<T> &A, const T *x, T *y, bool accumulate, hipStream_t s) {
@@ -343,6 +521,15 @@ void cast_from(const float *in, double *out, int64_t n, hipStream_t s) {
 void cast_from(const double *in, double *out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_cast<double, double><<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+  KCHK();
+}
+
+void make_rowblocks(Csr &M, hipStream_t s) {
+  // at least one block when there are rows, so that every row gets its epilogue
+  const int64_t K = std::max<int64_t>((M.nnz + SNNZ - 1) / SNNZ, M.n > 0 ? 1 : 0);
+  M.nblk = K;
+  M.rb.alloc(K + 1, s);
+  k_rowblocks32<<<grid_for(K + 1, 256), 256, 0, s>>>(M.n, M.rp.p, K, M.rb.p);
   KCHK();
 }
 

@@ -86,7 +86,9 @@ struct Csr {
   int64_t n = 0, m = 0, nnz = 0;
   DArr<int> rp, ci;
   DArr<double> v;
-  size_t bytes() const { return rp.bytes() + ci.bytes() + v.bytes(); }
+  DArr<int> rb;              // CSR-stream row blocks of apply matrices (nblk + 1), or empty
+  int64_t nblk = 0;
+  size_t bytes() const { return rp.bytes() + ci.bytes() + v.bytes() + rb.bytes(); }
 };
 
 // 3x3 block CSR with row-major blocks (9 doubles per block, entry (r, s) at 3r + s), used
@@ -103,6 +105,8 @@ struct CsrV {
   int64_t n = 0, m = 0, nnz = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;
+  const int *rb = nullptr;   // CSR-stream row blocks (nblk + 1) when set
+  int64_t nblk = 0;
 };
 // 3x3 block CSR: n, m in block rows/cols, values row-major per block (9 per block).
 template <class T>
@@ -215,6 +219,11 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
 // C = A B on 3x3 block matrices: the scalar product of their expansions, bit for bit (B's
 // blocks diagonal when diagb).
 void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s, int *dflag);
+// CSR-stream row blocks of M (block k owns the rows whose entries start in the k-th window
+// of the stream kernels); kept with the matrix for the apply kernels.
+void make_rowblocks(Csr &M, hipStream_t s);
+// rows `rows` (ascending, nr of them) of A as a CSR matrix of its own (columns unchanged)
+void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_t s);
 void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what);
 void bsr3_to_csr(const Bsr3 &B, Csr &C, hipStream_t s);
 // R = P^T (block pattern transposed, each block transposed)
@@ -239,6 +248,10 @@ struct VecOps {
   static void spmv(const CsrV<T> &A, const T *x, T *y, bool accumulate, hipStream_t s);
   static void interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC,
                      const T *eF, T *z, bool accumulate, hipStream_t s);
+  // the same with the F and C lists: z_F (+)= [eF] + W_p e_C, z_C (+)= e_C
+  static void interp_fc(int64_t n, const int *map, const int *F, int64_t nF, const int *C,
+                        int64_t nC, const CsrV<T> &Wp, const T *eC, const T *eF, T *z,
+                        bool accumulate, hipStream_t s);
   static void l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r,
                      hipStream_t s);
   static void l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,

@@ -187,13 +187,14 @@ struct MgrLevel {
   bool needs_A = true;       // the V-cycle reads A_l
   DArr<double> dFF;
   Csr Acf, Wp, Acor, G;      // Acor / G only with keep_setup
+  Csr AF, AC;                // rows F and rows C of A_l (residuals of uncompacted levels)
   int nb_gs = 0;             // global smoother block size
   DArr<double> binv64;
   Amg amg;                   // F-relaxation AMG
   DArr<double> ffinv64;      // dense F-relaxation inverse
   int nF = 0;
   // apply-precision copies
-  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv;
+  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv, tAF, tAC;
   // work vectors
   DArr<char> v, z, rF, eF, rfull;
 };
@@ -381,6 +382,9 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
       L.Pb64.reset();
       L.Rb64.reset();
     } else {
+      make_rowblocks(L.A, s);
+      make_rowblocks(L.P, s);
+      make_rowblocks(L.R, s);
       cast_values(L.A.v.p, L.tA, L.A.nnz, sz, s);
       cast_values(L.P.v.p, L.tP, L.P.nnz, sz, s);
       cast_values(L.R.v.p, L.tR, L.R.nnz, sz, s);
@@ -423,6 +427,8 @@ CsrV<T> view(const Csr &M, const DArr<char> &tv) {
   v.n = M.n; v.m = M.m; v.nnz = M.nnz;
   v.rp = M.rp.p; v.ci = M.ci.p;
   v.v = reinterpret_cast<const T *>(tv.p);
+  v.rb = M.nblk ? M.rb.p : nullptr;
+  v.nblk = M.nblk;
   return v;
 }
 template <class T>
@@ -431,6 +437,8 @@ CsrV<T> view64(const Csr &M) {
   v.n = M.n; v.m = M.m; v.nnz = M.nnz;
   v.rp = M.rp.p; v.ci = M.ci.p;
   v.v = reinterpret_cast<const T *>(M.v.p);
+  v.rb = M.nblk ? M.rb.p : nullptr;
+  v.nblk = M.nblk;
   return v;
 }
 template <class T>
@@ -503,6 +511,9 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
   CsrV<T> A = fp64 ? view64<T>(L.A) : view<T>(L.A, L.tA);
   CsrV<T> Acf = fp64 ? view64<T>(L.Acf) : view<T>(L.Acf, L.tAcf);
   CsrV<T> Wp = fp64 ? view64<T>(L.Wp) : view<T>(L.Wp, L.tWp);
+  CsrV<T> AF = fp64 ? view64<T>(L.AF) : view<T>(L.AF, L.tAF);
+  CsrV<T> AC = fp64 ? view64<T>(L.AC) : view<T>(L.AC, L.tAC);
+  const bool sub = L.AF.n == nF && L.AC.n == nC && (nF + nC) > 0 && L.AF.rp.p && L.AC.rp.p;
   T *rF = Ptr<T>::of(L.rF), *eF = Ptr<T>::of(L.eF);
   // the next level's input/output vectors (the coarsest grid uses this level's buffer)
   T *rC = N ? Ptr<T>::of(N->v) : Ptr<T>::of(L.rfull);
@@ -529,7 +540,8 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
       zero_z = false;
     }
     for (int sw = sw0; sw < o.frelax_sweeps; ++sw) {
-      V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      if (sub) V::resid(AF, nF, nullptr, L.cf.F.p, z, v, rF, s);
+      else V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
       V::jacobi_update(L.cf.F.p, nF, dinvF, (T)o.frelax_omega, rF, z, s);
     }
   } else {
@@ -538,7 +550,8 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
       if (L.f_prefix) rin = v;
       else { V::gather(L.cf.F.p, nF, v, rF, s); rin = rF; }
     } else {
-      V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      if (sub) V::resid(AF, nF, nullptr, L.cf.F.p, z, v, rF, s);
+      else V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
       rin = rF;
     }
     if (o.frelax == MGR_FRELAX_AMG) vcycle<T>(L.amg, 0, rin, eF, s);
@@ -548,10 +561,12 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
   }
   // restrict the residual by injection
   if (compactF) V::resid(Acf, nC, nullptr, L.cf.C.p, eF, v, rC, s);
+  else if (sub) V::resid(AC, nC, nullptr, L.cf.C.p, z, v, rC, s);
   else V::resid(A, nC, L.cf.C.p, L.cf.C.p, z, v, rC, s);
   apply_level<T>(h, l + 1, rC, eC, s);
   // interpolate and correct
-  V::interp(n, L.cf.map.p, Wp, eC, compactF ? eF : nullptr, z, !compactF, s);
+  V::interp_fc(n, L.cf.map.p, L.cf.F.p, nF, L.cf.C.p, nC, Wp, eC, compactF ? eF : nullptr, z,
+               !compactF, s);
 }
 
 namespace {
@@ -696,10 +711,25 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     // starts from z = 0 (then the residual uses A_CF only)
     const bool needs_A = lo.global_smoother != MGR_GSMOOTH_NONE || lo.frelax == MGR_FRELAX_JACOBI;
     L->needs_A = needs_A;
+    // rows F and rows C of A_l for the residuals of levels that are not compacted
+    const bool need_sub = lo.frelax == MGR_FRELAX_JACOBI || lo.global_smoother != MGR_GSMOOTH_NONE;
+    if (need_sub) {
+      gather_rows(L->A, L->cf.F.p, L->cf.nF, L->AF, s);
+      gather_rows(L->A, L->cf.C.p, nC, L->AC, s);
+      make_rowblocks(L->AF, s);
+      make_rowblocks(L->AC, s);
+    }
+    if (needs_A) make_rowblocks(L->A, s);
+    make_rowblocks(L->Acf, s);
+    make_rowblocks(L->Wp, s);
     if (sz == 4) {
       if (needs_A) cast_values(L->A.v.p, L->tA, L->A.nnz, sz, s);
       cast_values(L->Acf.v.p, L->tAcf, L->Acf.nnz, sz, s);
       cast_values(L->Wp.v.p, L->tWp, L->Wp.nnz, sz, s);
+      if (need_sub) {
+        cast_values(L->AF.v.p, L->tAF, L->AF.nnz, sz, s);
+        cast_values(L->AC.v.p, L->tAC, L->AC.nnz, sz, s);
+      }
     }
     L->rF.alloc(std::max<int64_t>(L->cf.nF, 1) * sz, s);
     L->eF.alloc(std::max<int64_t>(L->cf.nF, 1) * sz, s);
@@ -743,6 +773,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->A.v.reset();
         L->Acf.v.reset();
         L->Wp.v.reset();
+        L->AF.v.reset();
+        L->AC.v.reset();
         L->binv64.reset();
         L->ffinv64.reset();
       }
@@ -786,10 +818,11 @@ size_t handle_bytes(const mgr_handle *h) {
     b += H.cinv64.bytes() + H.tcinv.bytes();
   };
   for (auto &L : h->lv) {
-    csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G);
+    csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G); csr(L->AF); csr(L->AC);
     b += L->labels.bytes() + L->cf.F.bytes() + L->cf.C.bytes() + L->cf.map.bytes() +
          L->dFF.bytes() + L->binv64.bytes() + L->ffinv64.bytes() + L->tA.bytes() +
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
+         L->tAF.bytes() + L->tAC.bytes() +
          L->tffinv.bytes() + L->v.bytes() + L->z.bytes() + L->rF.bytes() + L->eF.bytes() +
          L->rfull.bytes();
     amg(L->amg);
@@ -1108,12 +1141,13 @@ mgr_status mgr_footprint(const mgr_handle *h, size_t *bytes) {
 mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts, size_t *bytes) {
   if (!opts || !bytes || n < 0 || nnz < 0) { t_err = "bad argument"; return MGR_ERR_ARG; }
   // peak of setup: the imported copy of A, the level blocks and products, the AMG
-  // hierarchies and their sparse-product temporaries stay below four FP64 CSR copies of A,
+  // hierarchies, their sparse-product temporaries and the row-split copies of levels that
+  // are not compacted stay below five FP64 CSR copies of A,
   // plus 64 level vectors and the dense coarsest inverses (size-binned by the allocator)
   const double a = (double)nnz * 12.0 + (double)(n + 1) * 4.0;
   const double cs = std::max(opts->amg_frelax.coarse_size, opts->amg_coarse.coarse_size);
   const double dense = (opts->coarse == MGR_COARSE_DENSE ? 4096.0 * 4096.0 : 0.0) + cs * cs;
-  double est = 4.0 * a + 64.0 * 8.0 * (double)n + 4.0 * 8.0 * dense + (double)(16 << 20);
+  double est = 5.0 * a + 64.0 * 8.0 * (double)n + 4.0 * 8.0 * dense + (double)(16 << 20);
   *bytes = (size_t)est;
   return MGR_OK;
 }

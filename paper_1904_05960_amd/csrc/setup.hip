@@ -306,17 +306,34 @@ __global__ void k_gershgorin(int64_t n, const int *__restrict__ rp, const int *_
 }
 // per row, one pass in ascending column order: the diagonal d_i, 1 / sum_j |a_ij| (the l1
 // smoother) and the Gershgorin ratio sum_j |a_ij| / |a_ii|
+// G lanes per row load the row coalesced; every lane then adds the values in ascending
+// column order (the order of the sum is the row's, not the lanes')
+template <int G>
 __global__ void k_row_stats(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
                             const double *__restrict__ v, double *__restrict__ d,
                             double *__restrict__ q, double *__restrict__ l1inv, int *flag) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (i >= n) return;
   double rs = 0.0, di = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const double x = v[e];
-    rs = __dadd_rn(rs, fabs(x));
-    if (ci[e] == i) di = x;
+  const int e0 = rp[i], e1 = rp[i + 1];
+  for (int c0 = e0; c0 < e1; c0 += G) {
+    const int e = c0 + l;
+    double x = 0.0;
+    int col = -1;
+    if (e < e1) {
+      x = v[e];
+      col = ci[e];
+    }
+    const int cnt = min(G, e1 - c0);
+    for (int t = 0; t < cnt; ++t) {
+      const double y = __shfl(x, t, G);
+      const int cy = __shfl(col, t, G);
+      rs = __dadd_rn(rs, fabs(y));
+      if (cy == (int)i) di = y;
+    }
   }
+  if (l != 0) return;
   d[i] = di;
   l1inv[i] = rs != 0.0 ? 1.0 / rs : 0.0;
   if (di == 0.0) {
@@ -674,8 +691,8 @@ void diag_of(const Csr &A, double *d, hipStream_t s) {
 double row_stats(const Csr &A, double *d, double *l1inv, hipStream_t s, int *dflag) {
   DArr<double> q(std::max<int64_t>(A.n, 1), s);
   if (A.n > 0) {
-    k_row_stats<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d, q.p, l1inv,
-                                                   dflag);
+    k_row_stats<16><<<grid_for(A.n * 16, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d, q.p,
+                                                           l1inv, dflag);
     KCHK();
   }
   const double r = reduce_max_f64(q.p, A.n, s);
@@ -906,6 +923,47 @@ void tentative_b3(const DArr<int> &agg, int64_t nnode, int64_t nagg, Bsr3 &T, hi
   T.v.alloc(std::max<int64_t>(9 * T.nnzb, 1), s);
   k_tent_b3<<<grid_for(nnode, 256), 256, 0, s>>>(nnode, agg.p, T.rp.p, T.ci.p, T.v.p);
   KCHK();
+}
+
+namespace {
+__global__ void k_rows_count(int64_t nr, const int *__restrict__ rows, const int *__restrict__ rp,
+                             int *__restrict__ cnt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < nr) cnt[t] = rp[rows[t] + 1] - rp[rows[t]];
+}
+template <int G>
+__global__ void k_rows_copy(int64_t nr, const int *__restrict__ rows, const int *__restrict__ rp,
+                            const int *__restrict__ ci, const double *__restrict__ v,
+                            const int *__restrict__ orp, int *__restrict__ oci,
+                            double *__restrict__ ov) {
+  const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (t >= nr) return;
+  const int r = rows[t], s0 = rp[r], len = rp[r + 1] - s0, o = orp[t];
+  for (int e = l; e < len; e += G) {
+    oci[o + e] = ci[s0 + e];
+    ov[o + e] = v[s0 + e];
+  }
+}
+}  // namespace
+
+void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_t s) {
+  out.n = nr;
+  out.m = A.m;
+  out.rp.alloc(nr + 1, s);
+  DArr<int> cnt(std::max<int64_t>(nr, 1), s);
+  if (nr > 0) {
+    k_rows_count<<<grid_for(nr, 256), 256, 0, s>>>(nr, rows, A.rp.p, cnt.p);
+    KCHK();
+  }
+  out.nnz = exclusive_scan_i32(cnt.p, out.rp.p, nr, s);
+  out.ci.alloc(std::max<int64_t>(out.nnz, 1), s);
+  out.v.alloc(std::max<int64_t>(out.nnz, 1), s);
+  if (nr > 0 && out.nnz > 0) {
+    k_rows_copy<16><<<grid_for(nr * 16, 256), 256, 0, s>>>(nr, rows, A.rp.p, A.ci.p, A.v.p,
+                                                          out.rp.p, out.ci.p, out.v.p);
+    KCHK();
+  }
 }
 
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag) {

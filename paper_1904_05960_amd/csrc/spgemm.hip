@@ -554,34 +554,45 @@ __device__ void num_row_b3(int row, const int *__restrict__ arp, const int *__re
   const int as = arp[row], ae = arp[row + 1];
   for (int e = as; e < ae; ++e) {            // blocks K of the row in ascending order
     const int k = aci[e];
-    double a[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) a[t] = av[9 * (int64_t)e + t];
     const int b0 = brp[k], b1 = brp[k + 1];
-    for (int q = b0 + l; q < b1; q += G) {   // distinct output blocks per lane
-      const int j = bci[q];
-      double b[9];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) b[t] = bv[9 * (int64_t)q + t];
-      const unsigned slot = table_find_or_insert(keys, mask, j);
-      if (slot > mask) {
-        atomicOr(flag, FLAG_PATTERN);
-        continue;
+    if (DIAGB) {
+      // lane t < 9 owns entry t = 3r + s of the output block; products a_rs * b_ss
+      const double a = l < 9 ? av[9 * (int64_t)e + l] : 0.0;
+      for (int q = b0; q < b1; ++q) {
+        const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
+        if (slot > mask) {
+          atomicOr(flag, FLAG_PATTERN);
+          continue;
+        }
+        if (l < 9) {
+          double *c = vals + 9 * slot + l;
+          *c = __dadd_rn(*c, __dmul_rn(a, bv[9 * (int64_t)q + 4 * (l % 3)]));
+        }
       }
-      double *c = vals + 9 * slot;
+    } else {
+      // lane item = (block of row k of B, output row r): three entries of one block row
+      const int items = 3 * (b1 - b0);
+      for (int it = l; it < items; it += G) {
+        const int q = b0 + it / 3;
+        const int r = it - 3 * (it / 3);
+        const double a0 = av[9 * (int64_t)e + 3 * r], a1 = av[9 * (int64_t)e + 3 * r + 1],
+                     a2 = av[9 * (int64_t)e + 3 * r + 2];
+        double b[9];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
+        for (int t = 0; t < 9; ++t) b[t] = bv[9 * (int64_t)q + t];
+        const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
+        if (slot > mask) {
+          atomicOr(flag, FLAG_PATTERN);
+          continue;
+        }
+        double *c = vals + 9 * slot + 3 * r;
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-          double x = c[3 * r + t];
-          if (DIAGB) {
-            x = __dadd_rn(x, __dmul_rn(a[3 * r + t], b[4 * t]));
-          } else {
-            x = __dadd_rn(x, __dmul_rn(a[3 * r + 0], b[0 + t]));
-            x = __dadd_rn(x, __dmul_rn(a[3 * r + 1], b[3 + t]));
-            x = __dadd_rn(x, __dmul_rn(a[3 * r + 2], b[6 + t]));
-          }
-          c[3 * r + t] = x;
+          double x = c[t];
+          x = __dadd_rn(x, __dmul_rn(a0, b[0 + t]));
+          x = __dadd_rn(x, __dmul_rn(a1, b[3 + t]));
+          x = __dadd_rn(x, __dmul_rn(a2, b[6 + t]));
+          c[t] = x;
         }
       }
     }
@@ -657,6 +668,27 @@ __global__ void __launch_bounds__(64) k_num_b3_global(
                         &s_n, flag);
 }
 
+// block rows by output block count: <= 32, <= 64, <= 128, <= 256, longer
+__global__ void k_bucket_b3(int64_t n, const int *__restrict__ crp, int *__restrict__ lists,
+                            int *__restrict__ counts, int64_t stride) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int b = -1;
+  if (i < n) {
+    const int len = crp[i + 1] - crp[i];
+    if (len > 0) b = len <= 32 ? 0 : len <= 64 ? 1 : len <= 128 ? 2 : len <= 256 ? 3 : 4;
+  }
+  for (int k = 0; k < NBUCKET; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[k], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (b == k) lists[k * stride + base + __popcll(m & ((1ull << lane) - 1))] = (int)i;
+  }
+}
+
 template <int G, int HT>
 void launch_num_b3(bool diagb, int nrows, const int *rows, const Bsr3 &A, const Bsr3 &B,
                    Bsr3 &C, int *dflag, hipStream_t s) {
@@ -689,22 +721,22 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
   C.ci.alloc(std::max<int64_t>(C.nnzb, 1), s);
   C.v.alloc(std::max<int64_t>(9 * C.nnzb, 1), s);
   if (C.nnzb == 0) return;
-  // rows by output block count: <= 64 (LDS table 128), <= 128 (256), <= 256 (512), longer
-  // rows with tables in global memory
+  // rows by output block count; LDS tables of twice that (<= 21 KB per 64-lane workgroup,
+  // so that several workgroups share a CU), rows beyond 256 blocks in global memory
   DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
   fill<int>(counts.p, 0, NBUCKET, s);
-  k_bucket<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
+  k_bucket_b3<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
   KCHK();
   int hc[NBUCKET];
   HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (hc[0] > 0) launch_num_b3<16, 128>(diagb, hc[0], lists.p, A, B, C, dflag, s);
-  if (hc[1] > 0) launch_num_b3<32, 256>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
-  if (hc[2] > 0) launch_num_b3<64, 512>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
-  for (int b = 3; b < NBUCKET; ++b) {
-    const int nbig = hc[b];
-    if (nbig == 0) continue;
-    const int *big = lists.p + (size_t)b * n;
+  if (hc[0] > 0) launch_num_b3<16, 64>(diagb, hc[0], lists.p, A, B, C, dflag, s);
+  if (hc[1] > 0) launch_num_b3<32, 128>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
+  if (hc[2] > 0) launch_num_b3<64, 256>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
+  if (hc[3] > 0) launch_num_b3<64, 512>(diagb, hc[3], lists.p + (size_t)3 * n, A, B, C, dflag, s);
+  if (hc[NBUCKET - 1] > 0) {
+    const int nbig = hc[NBUCKET - 1];
+    const int *big = lists.p + (size_t)(NBUCKET - 1) * n;
     DArr<int> mx(1, s);
     fill<int>(mx.p, 0, 1, s);
     k_max_len<<<grid_for(nbig, 256), 256, 0, s>>>(nbig, big, C.rp.p, mx.p);
