@@ -95,7 +95,7 @@ __device__ __forceinline__ void csr_epilogue(int row, T acc, const int *__restri
   }
 }
 
-template <class T, int MODE>
+template <class T, int MODE, int G>
 __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
                                                    const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
@@ -143,13 +143,14 @@ __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
       }
     }
     __syncthreads();
-    constexpr int G = 8;
+    // G lanes per row (G ~ mean row length / 8, so that the block's rows take about one
+    // pass of its 256 threads)
     const int l = t & (G - 1);
     for (int row = r0 + t / G; row < r1; row += SB / G) {
       const int s0 = rp[row] - base, e1 = rp[row + 1] - base;
       T acc = 0;
       for (int e = s0 + l; e < e1; e += G) acc += prod[e];
-      acc = group_sum<T, G>(acc);
+      if (G > 1) acc = group_sum<T, G>(acc);
       if (l == 0) csr_epilogue<T, MODE>(row, acc, bidx, oidx, x, b, dinv, out, out2, accumulate);
     }
     return;
@@ -177,8 +178,16 @@ void launch_csr_stream(const CsrV<T> &A, const T *xin, const T *x, const T *b, c
                        const int *bidx, const int *oidx, T *out, T *out2, int accumulate,
                        hipStream_t s) {
   if (A.nblk <= 0) return;
-  k_csr_stream<T, MODE><<<(unsigned)A.nblk, SB, 0, s>>>(A.rb, A.rp, A.ci, A.v, xin, x, b, dinv,
-                                                        bidx, oidx, out, out2, accumulate);
+  const double avg = A.n ? (double)A.nnz / (double)A.n : 0.0;
+#define LST(GG)                                                                            \
+  k_csr_stream<T, MODE, GG><<<(unsigned)A.nblk, SB, 0, s>>>(A.rb, A.rp, A.ci, A.v, xin, x, b, \
+                                                            dinv, bidx, oidx, out, out2,      \
+                                                            accumulate)
+  if (avg < 12) LST(1);
+  else if (avg < 24) LST(2);
+  else if (avg < 48) LST(4);
+  else LST(8);
+#undef LST
   KCHK();
 }
 
