@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <memory>
 #include <mutex>
+#include <thread>
 
 #include "common.hpp"
 
@@ -221,6 +222,7 @@ struct mgr_handle {
   uint64_t pattern = 0;
   mgr::DArr<char> v0, z0;    // apply-precision level-0 vectors
   hipStream_t cap = nullptr; // private capture stream
+  hipStream_t s2 = nullptr;  // setup stream of the F-relaxation AMG (built concurrently)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   ~mgr_handle();
@@ -402,6 +404,8 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
   }
   cast_values(H.cinv64.p, H.tcinv, (int64_t)H.nc * H.nc, sz, s);
   trace("  apply copies done");
+  // buffers released below may have been allocated on another stream (the level matrix)
+  HIPCHK(hipStreamSynchronize(s));
   if (!mo.keep_setup) {
     // the V-cycle only needs the apply copies (scalar levels still share the CSR pattern)
     for (size_t k = 0; k < H.lv.size(); ++k) {
@@ -605,8 +609,32 @@ void destroy_graph(mgr_handle *h) {
   h->graph = nullptr;
 }
 
+struct AsyncAmg {
+  std::thread th;
+  std::exception_ptr err;
+};
+// joins every setup thread on scope exit (also when the building thread throws)
+struct Jobs {
+  std::vector<std::unique_ptr<AsyncAmg>> v;
+  void join() {
+    for (auto &j : v)
+      if (j->th.joinable()) j->th.join();
+  }
+  void rethrow() {
+    for (auto &j : v)
+      if (j->err) std::rethrow_exception(j->err);
+  }
+  ~Jobs() { join(); }
+};
+
 void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   hipStream_t s = h->s;
+  Jobs jobs;
+  std::vector<hipEvent_t> events;
+  struct EventGuard {
+    std::vector<hipEvent_t> &e;
+    ~EventGuard() { for (auto x : e) (void)hipEventDestroy(x); }
+  } event_guard{events};
   int *flag = h->dflag.p;
   const mgr_opts &o = h->opts;
   const size_t sz = esz(o);
@@ -681,7 +709,33 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     // F-relaxation solvers
     if (lo.frelax == MGR_FRELAX_AMG) {
       require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
-      amg_setup(std::move(Aff), lo.frelax_block, o.amg_frelax, L->amg, o, s, flag);
+      // built on a second stream by a second host thread while this thread goes on with the
+      // coarser levels (both are bound by sparse products and host synchronisation)
+      if (!h->s2) HIPCHK(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev, s));
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      auto job = std::make_unique<AsyncAmg>();
+      AsyncAmg *J = job.get();
+      MgrLevel *Lp = L.get();
+      const int bs = lo.frelax_block;
+      hipStream_t s2 = h->s2;
+      job->th = std::thread([J, Lp, bs, dev, ev, s2, o, A = std::move(Aff)]() mutable {
+        try {
+          HIPCHK(hipSetDevice(dev));
+          HIPCHK(hipStreamWaitEvent(s2, ev, 0));
+          DArr<int> f2(1, s2);
+          clear_flag(f2.p, s2);
+          amg_setup(std::move(A), bs, o.amg_frelax, Lp->amg, o, s2, f2.p);
+          HIPCHK(hipStreamSynchronize(s2));
+        } catch (...) {
+          J->err = std::current_exception();
+        }
+      });
+      jobs.v.push_back(std::move(job));
+      events.push_back(ev);
     } else if (lo.frelax == MGR_FRELAX_DENSE) {
       require(L->cf.nF <= 4096, MGR_ERR_UNSUPPORTED, "dense F-relaxation limited to 4096 rows");
       DArr<double> D(L->cf.nF * L->cf.nF, s);
@@ -759,6 +813,9 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (o.keep_setup) h->coarseA = std::move(keep);
   }
   h->coarse_labels = std::move(lab);
+  jobs.join();
+  jobs.rethrow();
+  trace("  F-relaxation AMG joined");
   h->v0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
   h->z0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
   // level 0 input / output are the handle vectors; release what apply does not need
@@ -844,8 +901,13 @@ mgr_status fail(const Error &e) {
 
 mgr_handle::~mgr_handle() {
   if (s) (void)hipStreamSynchronize(s);
+  if (s2) (void)hipStreamSynchronize(s2);
   mgr::destroy_graph(this);
   if (cap) (void)hipStreamDestroy(cap);
+  // the hierarchy's buffers are released before the stream that allocated some of them
+  lv.clear();
+  coarse_amg.lv.clear();
+  if (s2) (void)hipStreamDestroy(s2);
 }
 
 // ===================================================================================
