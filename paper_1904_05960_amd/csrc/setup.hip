@@ -174,8 +174,10 @@ __global__ void k_check_nonzero(const double *__restrict__ d, int64_t n, int *fl
 // merge with dropping: S = A - diag(w) keep(B).
 // keep flags (only when dropping): G lanes per row of B; an entry off the sub-block
 // diagonals is kept when fewer than nmax other off-diagonal entries beat it (larger |b|,
-// or equal |b| and a smaller column).
-template <int G>
+// or equal |b| and a smaller column).  Rows of up to G * MAXCH entries are held in the
+// lanes' registers (chunk c of lane l = entry c * G + l) and compared through shuffles;
+// longer rows compare against global memory.
+template <int G, int MAXCH>
 __global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *__restrict__ bci,
                             const double *__restrict__ bv, int nmax,
                             const int *__restrict__ lrank, unsigned char *__restrict__ keep) {
@@ -183,7 +185,42 @@ __global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *_
   const int l = threadIdx.x & (G - 1);
   if (row >= n) return;
   const int bs = brp[row], be = brp[row + 1];
+  const int len = be - bs;
   const int myrank = lrank[row];
+  if (len <= G * MAXCH) {
+    const int nch = (len + G - 1) / G;
+    double av[MAXCH];
+    int cc[MAXCH], rk[MAXCH];
+    bool el[MAXCH];
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+      const int t = bs + c * G + l;
+      const bool in = c < nch && t < be;
+      cc[c] = in ? bci[t] : 0x7fffffff;
+      av[c] = in ? fabs(bv[t]) : 0.0;
+      el[c] = in && lrank[cc[c]] != myrank;
+      rk[c] = 0;
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < MAXCH; ++c2) {
+      if (c2 >= nch) break;
+      for (int j = 0; j < G; ++j) {
+        const double au = __shfl(av[c2], j, G);
+        const int cu = __shfl(cc[c2], j, G);
+        const bool eu = __shfl((int)el[c2], j, G) != 0;
+        if (!eu) continue;
+#pragma unroll
+        for (int c1 = 0; c1 < MAXCH; ++c1)
+          rk[c1] += (au > av[c1]) || (au == av[c1] && cu < cc[c1]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+      const int t = bs + c * G + l;
+      if (c < nch && t < be) keep[t] = !el[c] || rk[c] < nmax;
+    }
+    return;
+  }
   for (int t = bs + l; t < be; t += G) {
     const int ct = bci[t];
     bool k = true;
@@ -626,8 +663,8 @@ void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int
     require(lrank != nullptr, MGR_ERR_ARG, "dropping needs per-label ranks");
     keep.alloc(B.nnz, s);
     constexpr int G = 16;
-    k_drop_keep<G><<<grid_for(n * G, 256), 256, 0, s>>>(n, B.rp.p, B.ci.p, B.v.p, nmax, lrank,
-                                                        keep.p);
+    k_drop_keep<G, 8><<<grid_for(n * G, 256), 256, 0, s>>>(n, B.rp.p, B.ci.p, B.v.p, nmax, lrank,
+                                                           keep.p);
     KCHK();
   }
   const int *arp = A.n ? A.rp.p : nullptr;
