@@ -609,9 +609,13 @@ void destroy_graph(mgr_handle *h) {
   h->graph = nullptr;
 }
 
+// the hierarchy is built into the job (not into the level, which an exception on the
+// building thread may destroy first) and moved into the level after the join
 struct AsyncAmg {
   std::thread th;
   std::exception_ptr err;
+  Amg amg;
+  MgrLevel *level = nullptr;
 };
 // joins every setup thread on scope exit (also when the building thread throws)
 struct Jobs {
@@ -629,12 +633,12 @@ struct Jobs {
 
 void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   hipStream_t s = h->s;
-  Jobs jobs;
   std::vector<hipEvent_t> events;
   struct EventGuard {
     std::vector<hipEvent_t> &e;
     ~EventGuard() { for (auto x : e) (void)hipEventDestroy(x); }
   } event_guard{events};
+  Jobs jobs;                 // declared last: joined before the events are destroyed
   int *flag = h->dflag.p;
   const mgr_opts &o = h->opts;
   const size_t sz = esz(o);
@@ -673,6 +677,37 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     extract_blocks(L->A, L->cf, need_ff ? &Aff : nullptr, Afc, L->Acf, Acc, L->dFF.p, s);
     check_nonzero(L->dFF.p, L->cf.nF, flag, s);
     check_flags(flag, s, "D_FF");
+    // F-relaxation AMG: A_FF is ready
+    if (lo.frelax == MGR_FRELAX_AMG) {
+      require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
+      // built on a second stream by a second host thread while this thread goes on with the
+      // coarser levels (both are bound by sparse products and host synchronisation)
+      if (!h->s2) HIPCHK(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev, s));
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      auto job = std::make_unique<AsyncAmg>();
+      AsyncAmg *J = job.get();
+      J->level = L.get();
+      const int bs = lo.frelax_block;
+      hipStream_t s2 = h->s2;
+      job->th = std::thread([J, bs, dev, ev, s2, o, A = std::move(Aff)]() mutable {
+        try {
+          HIPCHK(hipSetDevice(dev));
+          HIPCHK(hipStreamWaitEvent(s2, ev, 0));
+          DArr<int> f2(1, s2);
+          clear_flag(f2.p, s2);
+          amg_setup(std::move(A), bs, o.amg_frelax, J->amg, o, s2, f2.p);
+          HIPCHK(hipStreamSynchronize(s2));
+        } catch (...) {
+          J->err = std::current_exception();
+        }
+      });
+      jobs.v.push_back(std::move(job));
+      events.push_back(ev);
+    }
     // W_p = -D_FF^{-1} A_FC (eq. injective_rp); M = -W_p
     Csr M;
     if (lo.interp == MGR_INTERP_JACOBI) {
@@ -706,37 +741,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     }
     negate_f64(M.v.p, M.nnz, s);
     L->Wp = std::move(M);
-    // F-relaxation solvers
-    if (lo.frelax == MGR_FRELAX_AMG) {
-      require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
-      // built on a second stream by a second host thread while this thread goes on with the
-      // coarser levels (both are bound by sparse products and host synchronisation)
-      if (!h->s2) HIPCHK(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
-      hipEvent_t ev;
-      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      HIPCHK(hipEventRecord(ev, s));
-      int dev = 0;
-      HIPCHK(hipGetDevice(&dev));
-      auto job = std::make_unique<AsyncAmg>();
-      AsyncAmg *J = job.get();
-      MgrLevel *Lp = L.get();
-      const int bs = lo.frelax_block;
-      hipStream_t s2 = h->s2;
-      job->th = std::thread([J, Lp, bs, dev, ev, s2, o, A = std::move(Aff)]() mutable {
-        try {
-          HIPCHK(hipSetDevice(dev));
-          HIPCHK(hipStreamWaitEvent(s2, ev, 0));
-          DArr<int> f2(1, s2);
-          clear_flag(f2.p, s2);
-          amg_setup(std::move(A), bs, o.amg_frelax, Lp->amg, o, s2, f2.p);
-          HIPCHK(hipStreamSynchronize(s2));
-        } catch (...) {
-          J->err = std::current_exception();
-        }
-      });
-      jobs.v.push_back(std::move(job));
-      events.push_back(ev);
-    } else if (lo.frelax == MGR_FRELAX_DENSE) {
+    // F-relaxation solvers (the AMG one is already under way)
+    if (lo.frelax == MGR_FRELAX_DENSE) {
       require(L->cf.nF <= 4096, MGR_ERR_UNSUPPORTED, "dense F-relaxation limited to 4096 rows");
       DArr<double> D(L->cf.nF * L->cf.nF, s);
       L->ffinv64.alloc(L->cf.nF * L->cf.nF, s);
@@ -815,6 +821,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   h->coarse_labels = std::move(lab);
   jobs.join();
   jobs.rethrow();
+  for (auto &j : jobs.v) j->level->amg = std::move(j->amg);
   trace("  F-relaxation AMG joined");
   h->v0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
   h->z0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
