@@ -374,6 +374,83 @@ __global__ void k_max_ub(int nrows, const int *__restrict__ rows, const int64_t 
   atomicMax(out, (unsigned long long)ub[rows[t]]);
 }
 
+// Products with few output columns (coarse AMG levels, m <= DMAX): the row is accumulated
+// in a dense LDS array indexed by column instead of a hash table; one 64-lane workgroup per
+// row, lanes over the entries of the selected row of B, a barrier between consecutive k
+// (the same pinned order), then the flagged columns are written in ascending order.
+constexpr int DMAX = 4096;
+
+__global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *__restrict__ arp,
+                                                  const int *__restrict__ aci,
+                                                  const int *__restrict__ brp,
+                                                  const int *__restrict__ bci,
+                                                  int *__restrict__ cnt) {
+  __shared__ int flag[DMAX];
+  const int64_t row = blockIdx.x;
+  if (row >= n) return;
+  const int l = threadIdx.x;
+  for (int j = l; j < m; j += 64) flag[j] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  int c = 0;
+  for (int e = arp[row]; e < arp[row + 1]; ++e) {
+    const int k = aci[e];
+    for (int q = brp[k] + l; q < brp[k + 1]; q += 64) c += atomicExch(&flag[bci[q]], 1) == 0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (l == 0) cnt[row] = c;
+}
+
+__global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *__restrict__ arp,
+                                                  const int *__restrict__ aci,
+                                                  const double *__restrict__ av,
+                                                  const int *__restrict__ brp,
+                                                  const int *__restrict__ bci,
+                                                  const double *__restrict__ bv,
+                                                  const int *__restrict__ crp,
+                                                  int *__restrict__ cci, double *__restrict__ cv,
+                                                  int *flagp) {
+  __shared__ double acc[DMAX];
+  __shared__ int flag[DMAX];
+  const int64_t row = blockIdx.x;
+  if (row >= n) return;
+  const int l = threadIdx.x;
+  for (int j = l; j < m; j += 64) {
+    acc[j] = 0.0;
+    flag[j] = 0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = arp[row]; e < arp[row + 1]; ++e) {      // ascending k
+    const int k = aci[e];
+    const double a = av[e];
+    for (int q = brp[k] + l; q < brp[k + 1]; q += 64) {  // distinct columns per step
+      const int j = bci[q];
+      acc[j] = __dadd_rn(acc[j], __dmul_rn(a, bv[q]));
+      flag[j] = 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+  int o = crp[row];
+  const int end = crp[row + 1];
+  for (int j0 = 0; j0 < m; j0 += 64) {
+    const int j = j0 + l;
+    const bool f = j < m && flag[j];
+    const uint64_t mask = __ballot(f);
+    if (f) {
+      const int pos = o + __popcll(mask & ((1ull << l) - 1));
+      if (pos < end) {
+        cci[pos] = j;
+        cv[pos] = acc[j];
+      }
+    }
+    o += __popcll(mask);
+  }
+  if (l == 0 && o != end) atomicOr(flagp, FLAG_PATTERN);
+}
+
 int64_t next_pow2(int64_t v) {
   int64_t p = 1;
   while (p < v) p <<= 1;
@@ -483,9 +560,25 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
     C.nnz = 0;
     return;
   }
+  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
+  const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
+  if (B.m <= DMAX && meanA * meanB >= 64.0 && (double)B.m <= 64.0 * meanA * meanB) {
+    // few output columns and many products per row: dense accumulation
+    DArr<int> cnt(n + 1, s);
+    k_sym_dense<<<(unsigned)n, 64, 0, s>>>(n, (int)B.m, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt.p);
+    KCHK();
+    C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
+    C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
+    C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
+    if (C.nnz > 0) {
+      k_num_dense<<<(unsigned)n, 64, 0, s>>>(n, (int)B.m, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
+                                             B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
+      KCHK();
+    }
+    return;
+  }
   spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnz, B.rp.p, B.ci.p, B.n, B.m, B.nnz, C.rp.p, C.nnz, s,
                   dflag);
-  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
   C.ci.alloc(C.nnz, s);
   C.v.alloc(C.nnz, s);
   if (C.nnz == 0) return;
