@@ -225,6 +225,44 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double *__restrict__ V
   }
 }
 
+// First correction of CGS2 in one pass: w -= sum_k h[k] V_k and, with the same V_k(i)
+// values still in registers, the partial dots of the new w with every V_k (the second
+// projection).  NVB >= nv basis vectors per thread; the arithmetic and its order are those
+// of k_cgs_update, which re-reads V for the dots.
+template <int NVB>
+__global__ void __launch_bounds__(256) k_cgs_fused(const double *__restrict__ V, int64_t n, int nv,
+                                                   const double *__restrict__ h,
+                                                   double *__restrict__ w,
+                                                   double *__restrict__ partial) {
+  __shared__ double sh_h[KS];
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) sh_h[k] = h[k];
+  __syncthreads();
+  double acc[NVB];
+#pragma unroll
+  for (int k = 0; k < NVB; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double t[NVB];
+#pragma unroll
+    for (int k = 0; k < NVB; ++k) t[k] = k < nv ? V[(int64_t)k * n + i] : 0.0;
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NVB; ++k)
+      if (k < nv) wi -= sh_h[k] * t[k];
+    w[i] = wi;
+#pragma unroll
+    for (int k = 0; k < NVB; ++k) acc[k] += t[k] * wi;
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < NVB; k0 += KC) {
+    if (k0 >= nv) break;
+    double a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) a[k] = acc[k0 + k];
+    block_store(a, min(KC, nv - k0), k0, partial);
+  }
+}
+
 __global__ void k_norm_partials(const double *__restrict__ r, int64_t n, double *__restrict__ partial) {
   double acc[KC];
 #pragma unroll
@@ -385,6 +423,15 @@ void multidot_partials(const double *V, int64_t n, int nv, const double *w, doub
 }
 void cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
                          double *partial, bool norm_only, hipStream_t s) {
+  // the fused pass holds nv basis values per thread; beyond 48 they would not fit the
+  // register file, and the two-pass form is used
+  if (!norm_only && nv <= 48) {
+    if (nv <= 16) k_cgs_fused<16><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
+    else if (nv <= 32) k_cgs_fused<32><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
+    else k_cgs_fused<48><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
+    KCHK();
+    return;
+  }
   k_cgs_update<<<NB, 256, 0, s>>>(V, n, nv, h, w, partial, norm_only ? 1 : 0);
   KCHK();
 }
