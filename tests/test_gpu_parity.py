@@ -261,6 +261,16 @@ def test_error_paths():
     with pytest.raises(m.MgrError) as e:
         m.Preconditioner(A, labels, m.Options(levels=[m.Level((0, 2))], coarse="dense"))
     assert e.value.status == m.MGR_ERR_ARG
+    # an F block without full 3x3 node blocks: the nodal AMG, built on a second host thread
+    # and stream, fails there and the error reaches the caller
+    odd = labels.clone()
+    odd[1] = 2
+    with pytest.raises(m.MgrError) as e:
+        m.Preconditioner(A, odd, m.paper_plan("biot1"))
+    assert e.value.status == m.MGR_ERR_UNSUPPORTED
+    # the library stays usable afterwards
+    P = m.Preconditioner(A, labels, m.paper_plan("biot1", coarse="dense"))
+    P.close()
     # maxit reached: NOT_CONVERGED with the last iterate
     x, info = m.fgmres(A, b, M=None, restart=5, rtol=1e-14, maxit=3, raise_on_fail=False)
     assert info["status"] == m.MGR_ERR_NOT_CONVERGED and info["iters"] == 3
