@@ -1020,6 +1020,18 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   const int ldh = m + 1;
   int its = 0;
   bool first = true;
+  // per-step residual estimates land in two pinned slots, each with its completion event
+  double *slot[2] = {static_cast<double *>(pinned_scratch()) + 8,
+                     static_cast<double *>(pinned_scratch()) + 16};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
+  for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
   for (;;) {
     matvec(x, b, W.r);  // r = b - A x
     const double beta = host_norm(W.r, n, W, s);
@@ -1030,8 +1042,12 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
     if (!first) ++R.restarts;
     first = false;
     start_cycle_host_beta(W.r, beta, W.V, W.g, n, m + 1, s);
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
+    // Arnoldi steps are software-pipelined by one: step j+1 (whose basis vector comes from
+    // step j's device-side scalars) is enqueued before the host waits for step j's
+    // residual estimate, so the GPU never idles on the host's convergence check.  When
+    // step j ends the cycle, step j+1 has only written column j+1 of H, g[j+1..j+2] and
+    // Z[j+1], none of which the update with k = j+1 reads.
+    auto step = [&](int j) {
       double *vj = W.V + (int64_t)j * n;
       double *zj = W.Z + (int64_t)j * n;
       if (M) {
@@ -1041,7 +1057,6 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
         HIPCHK(hipMemcpyAsync(zj, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
       matvec(zj, nullptr, W.w);
-      ++its;
       // classical Gram-Schmidt, twice
       multidot_partials(W.V, n, j + 1, W.w, W.partial, s);
       reduce_partials(W.partial, j + 1, W.h1, false, s);
@@ -1050,14 +1065,24 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
       cgs_update_partials(W.V, n, j + 1, W.h2, W.w, W.partial, true, s);
       reduce_partials(W.partial, 1, W.hn2, false, s);
       givens_step(W.H, W.cs, W.sn, W.g, W.h1, W.h2, W.hn2, j, ldh, W.scal, nullptr, s);
-      double *sc = static_cast<double *>(pinned_scratch());
-      HIPCHK(hipMemcpyAsync(sc, W.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipMemcpyAsync(slot[j & 1], W.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(ev[j & 1], s));
+    };
+    int k = 0;
+    step(0);
+    for (int j = 0; j < m; ++j) {
+      const bool ahead = j + 1 < m && its + 1 < o->maxit;
+      if (ahead) {
+        scale_vec(W.w, W.scal + 2, W.V + (int64_t)(j + 1) * n, n, s);
+        step(j + 1);
+      }
+      HIPCHK(hipEventSynchronize(ev[j & 1]));
+      ++its;
+      const double *sc = slot[j & 1];
       R.est_relres = sc[0] / bnorm;
       push(R.est_relres);
       k = j + 1;
       if (sc[0] <= tol || sc[1] == 0.0 || its >= o->maxit || !std::isfinite(sc[0])) break;
-      scale_vec(W.w, W.scal + 2, W.V + (int64_t)(j + 1) * n, n, s);
     }
     tri_solve_and_update(W.H, W.g, k, ldh, W.Z, n, x, W.y, s);
   }

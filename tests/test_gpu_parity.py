@@ -266,7 +266,7 @@ def test_error_paths():
     odd = labels.clone()
     odd[1] = 2
     with pytest.raises(m.MgrError) as e:
-        m.Preconditioner(A, odd, m.paper_plan("biot1"))
+        m.Preconditioner(A, odd, small_amg(m.paper_plan("biot1"), coarse_size=24))
     assert e.value.status == m.MGR_ERR_UNSUPPORTED
     # the library stays usable afterwards
     P = m.Preconditioner(A, labels, m.paper_plan("biot1", coarse="dense"))
