@@ -49,18 +49,41 @@ def traffic_from_profile(name, src):
     return float(mt.group(1))
 
 
-def cpu_baseline(size_full_n, restart):
+def _two(n):
+    from workloads import poromech as pm
+    return pm.two_phase(n, n, n, 1)
+
+
+def _three(n):
+    from workloads import poromech as pm
+    return pm.three_phase(n, n, n, 3)
+
+
+# name: (generator by cells per side, CPU-baseline sample size, model, reduction, description)
+WORKLOADS = {
+    "two": (_two, 24, "two", "displacement -> saturation -> pressure AMG",
+            "two-phase poromechanics Jacobian, {n}^3 cells, log10 k ~ N(-13,1) corr. 8 cells, "
+            "Corey 2, s ~ U[0.2,0.8] (seed 1)"),
+    "three": (_three, 20, "three",
+              "displacement -> gas saturation -> water saturation -> pressure AMG",
+              "three-phase poromechanics Jacobian, {n}^3 cells, ln k ~ N(ln 1e-13, 1.5^2) corr. "
+              "12 cells, s_w ~ U[0.2,0.5], s_g ~ U[0.05,0.3] (seed 3)"),
+}
+
+
+def cpu_baseline(size_full_n, restart, workload="two"):
     """The oracle (FP64, NumPy/SciPy, untuned) on a bounded sample of the same workload
-    recipe: setup + FGMRES to 1e-6 on the 24^3 two-phase grid, scaled linearly by unknowns."""
+    recipe (24^3 two-phase, 20^3 three-phase): setup + FGMRES to 1e-6, scaled linearly by
+    unknowns."""
     from oracle import krylov as okry
     from oracle import mgr as omgr
     from oracle.sparse import CSR
     from paper_1904_05960_amd import mgr355 as m
     from tests.helpers import oracle_plan
-    from workloads import poromech as pm
-    w = pm.two_phase(24, 24, 24, 1)
+    gen, ns = WORKLOADS[workload][0], WORKLOADS[workload][1]
+    w = gen(ns)
     A = CSR(w.indptr, w.indices, w.data, (w.n, w.n))
-    plan = oracle_plan(m.paper_plan("two"))
+    plan = oracle_plan(m.paper_plan(WORKLOADS[workload][2]))
     c0, t0 = os.times(), time.perf_counter()
     H = omgr.setup(A, w.labels, plan)
     t1 = time.perf_counter()
@@ -74,7 +97,7 @@ def cpu_baseline(size_full_n, restart):
         "value": round(wall * 1e3 * scale, 1), "unit": "ms",
         "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
-        "sample": (f"oracle setup + FGMRES({restart}) to 1e-6 on the 24^3 two-phase grid of the same "
+        "sample": (f"oracle setup + FGMRES({restart}) to 1e-6 on the {w.name} grid of the same "
                    f"recipe ({w.n} unknowns, {r.iters} iterations, setup {1e3*(t1-t0):.0f} ms, "
                    f"solve {1e3*(t2-t1):.0f} ms), scaled by unknowns x{scale:.2f}"),
         "host_cpus": os.cpu_count(),
@@ -103,7 +126,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--size", type=int, default=64)
+    ap.add_argument("--workload", default="two", choices=sorted(WORKLOADS))
+    ap.add_argument("--size", type=int, default=None, help="cells per side (64 two, 96 three)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
     ap.add_argument("--restart", type=int, default=64)
@@ -111,19 +135,20 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-hierarchy step")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
     from paper_1904_05960_amd import mgr355 as m
-    from workloads import poromech as pm
 
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    w = pm.two_phase(a.size, a.size, a.size, 1)
+    if a.size is None:
+        a.size = 64 if a.workload == "two" else 96
+    w = WORKLOADS[a.workload][0](a.size)
     print(f"[bench] generated {w.name}: n={w.n} nnz={w.nnz} in {time.perf_counter()-t:.1f}s",
           file=sys.stderr, flush=True)
     A = m.Matrix.from_host(w.indptr, w.indices, w.data)
@@ -137,7 +162,7 @@ def main():
     def step(prec, record=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record(stream)
-        P = m.Preconditioner(A, labels, mk("two", precision=prec))
+        P = m.Preconditioner(A, labels, mk(WORKLOADS[a.workload][2], precision=prec))
         ev[1].record(stream)
         x.zero_()
         _, info = m.fgmres(A, b, x=x, M=P, restart=a.restart, rtol=1e-6, maxit=1000, work=work)
@@ -184,8 +209,11 @@ def main():
     avg_launch_ms = spmv_ms / max(launches, 1)
     bytes_per_launch = spmv_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile("spmv64_twophase_64.md",
-                                   os.path.join(ROOT, "paper_1904_05960_amd", "csrc", "krylov.hip"))
+    # counter traffic is recorded for the default workload only
+    traffic = None
+    if a.workload == "two" and a.size == 64:
+        traffic = traffic_from_profile(
+            "spmv64_twophase_64.md", os.path.join(ROOT, "paper_1904_05960_amd", "csrc", "krylov.hip"))
     out = {
         "metric": "MGR-FGMRES time-to-1e-6 relative FP64 residual (setup + solve)",
         "value": round(ms_step, 2),
@@ -200,11 +228,10 @@ def main():
         "dtype": ("f32 hierarchy + f64 Krylov" if a.precision == "fp32" else "f64"),
         "data": "synthetic",
         "config": {
-            "workload": f"two-phase poromechanics Jacobian, {a.size}^3 cells, log10 k ~ N(-13,1) "
-                        f"corr. 8 cells, Corey 2, s ~ U[0.2,0.8] (seed 1)",
+            "workload": WORKLOADS[a.workload][4].format(n=a.size),
             "unknowns": w.n, "nnz": w.nnz,
-            "reduction": ("displacement -> saturation -> pressure AMG" if a.plan == "paper"
-                          else "saturation -> displacement -> pressure AMG"),
+            "reduction": (WORKLOADS[a.workload][3] if a.plan == "paper"
+                          else "saturations -> displacement -> pressure AMG"),
             "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
             "rtol": 1e-6, "parallelism": "single GPU",
         },
@@ -229,7 +256,7 @@ def main():
         },
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.n, a.restart)
+        out["cpu_baseline"] = cpu_baseline(w.n, a.restart, a.workload)
     print(json.dumps(out), flush=True)
 
 

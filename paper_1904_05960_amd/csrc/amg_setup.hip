@@ -17,28 +17,38 @@ __device__ __forceinline__ unsigned long long splitmix64_first(unsigned long lon
   return z ^ (z >> 31);
 }
 
-// scalar strength: count pass (MODE 0) and fill pass (MODE 1), one thread per row
-template <int MODE>
+// scalar strength: count pass (MODE 0) and fill pass (MODE 1); G lanes per row take the
+// row G entries at a time, and the strong ones of a chunk are placed in column order by
+// their rank among the group's ballot bits
+template <int G, int MODE>
 __global__ void k_strength_scalar(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
                                   const double *__restrict__ v, const double *__restrict__ d,
                                   double th2, int *__restrict__ cnt, const int *__restrict__ srp,
                                   int *__restrict__ sci) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  const int gbase = (threadIdx.x & 63) & ~(G - 1);     // first lane of the group in the wave
   if (i >= n) return;
   const double di = d[i];
   int c = 0;
   const int o = MODE ? srp[i] : 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const int j = ci[e];
-    if (j == i) continue;
-    const double a = v[e];
-    const bool strong = a != 0.0 && __dmul_rn(a, a) >= __dmul_rn(th2, fabs(__dmul_rn(di, d[j])));
-    if (strong) {
-      if (MODE) sci[o + c] = j;
-      ++c;
+  const int e1 = rp[i + 1];
+  for (int e0 = rp[i]; e0 < e1; e0 += G) {
+    const int e = e0 + l;
+    bool strong = false;
+    int j = 0;
+    if (e < e1) {
+      j = ci[e];
+      const double a = v[e];
+      strong = j != (int)i && a != 0.0 &&
+               __dmul_rn(a, a) >= __dmul_rn(th2, fabs(__dmul_rn(di, d[j])));
     }
+    const uint64_t wave = __ballot(strong);
+    const uint64_t grp = (wave >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1));
+    if (MODE && strong) sci[o + c + __popcll(grp & ((1ull << l) - 1))] = j;
+    c += __popcll(grp);
   }
-  if (!MODE) cnt[i] = c;
+  if (!MODE && l == 0) cnt[i] = c;
 }
 
 // node blocks of a scalar CSR with full 3x3 blocks: squared Frobenius norm of every block,
@@ -216,15 +226,15 @@ void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t
     DArr<double> d(n, s);
     diag_of(A, d.p, s);
     DArr<int> cnt(n + 1, s);
-    k_strength_scalar<0><<<grid_for(n, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, A.v.p, d.p, th2,
-                                                          cnt.p, nullptr, nullptr);
+    k_strength_scalar<16, 0><<<grid_for(n * 16, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, A.v.p, d.p,
+                                                                   th2, cnt.p, nullptr, nullptr);
     KCHK();
     S.n = S.m = n;
     S.rp.alloc(n + 1, s);
     S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, n, s);
     S.ci.alloc(S.nnz, s);
-    k_strength_scalar<1><<<grid_for(n, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, A.v.p, d.p, th2,
-                                                          nullptr, S.rp.p, S.ci.p);
+    k_strength_scalar<16, 1><<<grid_for(n * 16, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, A.v.p, d.p,
+                                                                   th2, nullptr, S.rp.p, S.ci.p);
     KCHK();
   } else {
     require(bs == 3, MGR_ERR_ARG, "AMG block size must be 1 or 3");

@@ -336,28 +336,7 @@ __global__ void __launch_bounds__(64) k_num_global(int nrows, const int *__restr
   num_row_g<64>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
 }
 
-// rows by output length into NBUCKET buckets (table sizes 128 .. 1024, then global);
-// empty rows skipped.  Appends are aggregated per wavefront.
-constexpr int NBUCKET = 5;
-__global__ void k_bucket(int64_t n, const int *__restrict__ crp, int *__restrict__ lists,
-                         int *__restrict__ counts, int64_t stride) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  int b = -1;
-  if (i < n) {
-    const int len = crp[i + 1] - crp[i];
-    if (len > 0) b = len <= 64 ? 0 : len <= 128 ? 1 : len <= 256 ? 2 : len <= 512 ? 3 : 4;
-  }
-  for (int k = 0; k < NBUCKET; ++k) {
-    const uint64_t m = __ballot(b == k);
-    if (m == 0) continue;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counts[k], __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (b == k) lists[k * stride + base + __popcll(m & ((1ull << lane) - 1))] = (int)i;
-  }
-}
+constexpr int NBUCKET = 5;   // block-product row buckets
 
 __global__ void k_max_len(int nrows, const int *__restrict__ rows, const int *__restrict__ crp,
                           int *__restrict__ out) {
@@ -378,14 +357,15 @@ __global__ void k_max_ub(int nrows, const int *__restrict__ rows, const int64_t 
 // in a dense LDS array indexed by column instead of a hash table; one 64-lane workgroup per
 // row, lanes over the entries of the selected row of B, a barrier between consecutive k
 // (the same pinned order), then the flagged columns are written in ascending order.
-constexpr int DMAX = 4096;
+constexpr int DMAX = 8192;   // largest dense row: 96 KB of LDS per workgroup
 
+template <int DM>
 __global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *__restrict__ arp,
                                                   const int *__restrict__ aci,
                                                   const int *__restrict__ brp,
                                                   const int *__restrict__ bci,
                                                   int *__restrict__ cnt) {
-  __shared__ int flag[DMAX];
+  __shared__ int flag[DM];
   const int64_t row = blockIdx.x;
   if (row >= n) return;
   const int l = threadIdx.x;
@@ -402,6 +382,7 @@ __global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *_
   if (l == 0) cnt[row] = c;
 }
 
+template <int DM>
 __global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *__restrict__ arp,
                                                   const int *__restrict__ aci,
                                                   const double *__restrict__ av,
@@ -411,8 +392,8 @@ __global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *_
                                                   const int *__restrict__ crp,
                                                   int *__restrict__ cci, double *__restrict__ cv,
                                                   int *flagp) {
-  __shared__ double acc[DMAX];
-  __shared__ int flag[DMAX];
+  __shared__ double acc[DM];
+  __shared__ int flag[DM];
   const int64_t row = blockIdx.x;
   if (row >= n) return;
   const int l = threadIdx.x;
@@ -451,6 +432,31 @@ __global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *_
   if (l == 0 && o != end) atomicOr(flagp, FLAG_PATTERN);
 }
 
+// scalar numeric pass: rows by output length, tables of 128 .. 4096 slots in LDS (up to
+// 72 KB per workgroup on gfx950), longer rows in global memory
+constexpr int NBS = 7;
+__global__ void k_bucket_s(int64_t n, const int *__restrict__ crp, int *__restrict__ lists,
+                           int *__restrict__ counts, int64_t stride) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int b = -1;
+  if (i < n) {
+    const int len = crp[i + 1] - crp[i];
+    if (len > 0)
+      b = len <= 64 ? 0 : len <= 128 ? 1 : len <= 256 ? 2 : len <= 512 ? 3 : len <= 1024 ? 4
+        : len <= 2048 ? 5 : 6;
+  }
+  for (int k = 0; k < NBS; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (m == 0) continue;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[k], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (b == k) lists[k * stride + base + __popcll(m & ((1ull << lane) - 1))] = (int)i;
+  }
+}
+
 int64_t next_pow2(int64_t v) {
   int64_t p = 1;
   while (p < v) p <<= 1;
@@ -475,7 +481,7 @@ void launch_num(int nrows, const int *rows, const Csr &A, const Csr &B, Csr &C, 
 void dispatch_num(int bucket, int g0, int nrows, const int *rows, const Csr &A, const Csr &B,
                   Csr &C, int *dflag, hipStream_t s) {
   const int HT = 128 << bucket;
-  int G = std::max(g0, HT / 32);
+  int G = std::min(64, std::max(g0, HT / 32));
 #define NUMCASE(GG, HH)                                          \
   if (G == GG && HT == HH) {                                     \
     launch_num<GG, HH>(nrows, rows, A, B, C, dflag, s);          \
@@ -484,7 +490,7 @@ void dispatch_num(int bucket, int g0, int nrows, const int *rows, const Csr &A, 
   NUMCASE(8, 128) NUMCASE(16, 128) NUMCASE(32, 128) NUMCASE(64, 128)
   NUMCASE(8, 256) NUMCASE(16, 256) NUMCASE(32, 256) NUMCASE(64, 256)
   NUMCASE(16, 512) NUMCASE(32, 512) NUMCASE(64, 512)
-  NUMCASE(32, 1024) NUMCASE(64, 1024)
+  NUMCASE(32, 1024) NUMCASE(64, 1024) NUMCASE(64, 2048) NUMCASE(64, 4096)
 #undef NUMCASE
   throw Error(MGR_ERR_HIP, "spgemm: no numeric kernel for this bucket");
 }
@@ -564,15 +570,26 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
   if (B.m <= DMAX && meanA * meanB >= 64.0 && (double)B.m <= 64.0 * meanA * meanB) {
     // few output columns and many products per row: dense accumulation
+    // tables sized to the column count: small ones leave room for several workgroups per CU
     DArr<int> cnt(n + 1, s);
-    k_sym_dense<<<(unsigned)n, 64, 0, s>>>(n, (int)B.m, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt.p);
+    const int mm = (int)B.m;
+#define DSYM(DM) k_sym_dense<DM><<<(unsigned)n, 64, 0, s>>>(n, mm, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt.p)
+    if (mm <= 2048) DSYM(2048);
+    else if (mm <= 4096) DSYM(4096);
+    else DSYM(DMAX);
+#undef DSYM
     KCHK();
     C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
     C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
     C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
     if (C.nnz > 0) {
-      k_num_dense<<<(unsigned)n, 64, 0, s>>>(n, (int)B.m, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,
-                                             B.v.p, C.rp.p, C.ci.p, C.v.p, dflag);
+#define DNUM(DM)                                                                           \
+  k_num_dense<DM><<<(unsigned)n, 64, 0, s>>>(n, mm, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, \
+                                             B.v.p, C.rp.p, C.ci.p, C.v.p, dflag)
+      if (mm <= 2048) DNUM(2048);
+      else if (mm <= 4096) DNUM(4096);
+      else DNUM(DMAX);
+#undef DNUM
       KCHK();
     }
     return;
@@ -583,19 +600,19 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   C.v.alloc(C.nnz, s);
   if (C.nnz == 0) return;
   // numeric phase by output row length
-  DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
-  fill<int>(counts.p, 0, NBUCKET, s);
-  k_bucket<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
+  DArr<int> lists((size_t)NBS * n, s), counts(NBS, s);
+  fill<int>(counts.p, 0, NBS, s);
+  k_bucket_s<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
   KCHK();
-  int hc[NBUCKET];
+  int hc[NBS];
   HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const int g0 = lanes_for(meanB);
-  for (int b = 0; b < NBUCKET - 1; ++b)
+  for (int b = 0; b < NBS - 1; ++b)
     if (hc[b] > 0) dispatch_num(b, g0, hc[b], lists.p + (size_t)b * n, A, B, C, dflag, s);
-  const int nbig = hc[NBUCKET - 1];
+  const int nbig = hc[NBS - 1];
   if (nbig > 0) {
-    const int *big = lists.p + (size_t)(NBUCKET - 1) * n;
+    const int *big = lists.p + (size_t)(NBS - 1) * n;
     DArr<int> mx(1, s);
     fill<int>(mx.p, 0, 1, s);
     k_max_len<<<grid_for(nbig, 256), 256, 0, s>>>(nbig, big, C.rp.p, mx.p);
