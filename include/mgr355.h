@@ -325,7 +325,7 @@ mgr_status mgr_transpose(const mgr_csr *A, mgr_owned_csr **T, int64_t sizes[3], 
  * prolongator P = T - diag(omega / a_ii) (A T) with w given).  nmax < 0 keeps all of B;
  * otherwise per row of B the entries whose coarse points have equal rank within their
  * label (labels_c, one per row/column of B) plus the nmax largest |b| (ties: smaller
- * column).  Errors: ARG, UNSUPPORTED (a row of B beyond 2048 entries). */
+ * column).  Errors: ARG. */
 mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, int32_t nmax,
                           const int8_t *labels_c, mgr_owned_csr **S, int64_t sizes[3],
                           void *stream);

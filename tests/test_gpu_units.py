@@ -27,6 +27,15 @@ def rand_csr(rng, n, k, dens, ints=False):
     return CSR.from_dense(D, mask)
 
 
+def rows_csr(rng, lens, ncols):
+    """CSR with the given row lengths, distinct random columns, N(0,1) values."""
+    indptr = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    cols = np.concatenate([np.sort(rng.choice(ncols, size=c, replace=False)) for c in lens])
+    return CSR(indptr, cols.astype(np.int64), rng.standard_normal(indptr[-1]),
+               (len(lens), ncols))
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 9, 23), (300, 200, 250), (700, 900, 50)])
 def test_spgemm_random(shape):
     rng = np.random.default_rng(sum(shape))
@@ -43,11 +52,25 @@ def test_spgemm_pinned_order_cancellation():
     assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
 
 
-def test_spgemm_long_rows_global_fallback():
-    rng = np.random.default_rng(3)
-    A = rand_csr(rng, 40, 3000, 0.5)          # ~1500 products per row before B
-    B = rand_csr(rng, 3000, 6000, 0.002)
-    assert_csr_equal(m.spgemm(dev(A), dev(B)), spgemm(A, B), "spgemm long rows")
+@pytest.mark.parametrize("case", [
+    # (rows, inner, cols, density of A, density of B): which accumulation the product takes
+    ("dense accumulator, 2048-column table", 200, 500, 0.08, 300, 0.03),
+    ("dense accumulator, 8192-column table", 40, 3000, 0.5, 6000, 0.002),
+    ("LDS hash tables of 2048 and 4096 slots", 64, 2000, None, 30000, None),
+    ("symbolic and numeric tables in global memory", 12, 4000, 0.8, 50000, 0.00025),
+])
+def test_spgemm_row_length_paths(case):
+    what, n, k, da, p, db = case
+    rng = np.random.default_rng(n + k)
+    if da is None:
+        # rows of A with 40..160 entries times rows of B with 12: 480..1920 products, output
+        # rows between 512 and 2048 columns
+        A = rows_csr(rng, [40 + 40 * (i % 4) for i in range(n)], k)
+        B = rows_csr(rng, [12] * k, p)
+    else:
+        A = rand_csr(rng, n, k, da)
+        B = rand_csr(rng, k, p, db)
+    assert_csr_equal(m.spgemm(dev(A), dev(B)), spgemm(A, B), f"spgemm: {what}")
 
 
 def test_transpose_random():
