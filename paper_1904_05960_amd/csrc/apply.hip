@@ -62,12 +62,14 @@ __global__ void __launch_bounds__(256) k_csr(int64_t nw, const int *__restrict__
 // CSR-stream variant (matrices with row blocks): block k owns rows [rb[k], rb[k+1]) whose
 // entries start in the k-th window of SNNZ entries.  The window's products are formed with
 // coalesced loads, PER independent loads in flight per thread, staged in LDS, and each row
-// is summed from LDS by 8 lanes; a block whose rows hold more than SCAP entries sums each
-// row directly.  Row t of the matrix is work item t; `bidx` indexes b (RESID) and `oidx`
+// is summed from LDS by 8 lanes; a block whose rows hold more than scap<T> entries sums
+// each row directly.  The FP64 window keeps 256 entries of slack (18 KB of LDS, 8 blocks per
+// CU); the FP32 one 2048 (16 KB).  Row t of the matrix is work item t; `bidx` indexes b (RESID) and `oidx`
 // the output (INTERP: z[oidx[t]] (+)= [eF[t]] + acc).
 constexpr int SB = 256;
 constexpr int SNNZ = 2048;
-constexpr int SCAP = 4096;
+template <class T>
+constexpr int scap = sizeof(T) == 4 ? 2 * SNNZ : SNNZ + 256;
 enum { M_INTERP = 5 };
 
 template <class T, int MODE>
@@ -109,13 +111,13 @@ __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
                                                    T *__restrict__ out, T *__restrict__ out2,
                                                    int accumulate) {
   // xin: the vector the products gather (x, or for L1PRE b scaled by dinv on the fly)
-  __shared__ T prod[SCAP];
+  __shared__ T prod[scap<T>];
   const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
   if (r0 >= r1) return;
   const int base = rp[r0];
   const int cnt = rp[r1] - base;
   const int t = threadIdx.x;
-  if (cnt <= SCAP) {
+  if (cnt <= scap<T>) {
     constexpr int PER = SNNZ / SB;
     for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
       int c[PER];

@@ -47,10 +47,12 @@ void launch_spmv64(const mgr_csr &A, const double *x, const double *b, double *y
 // CSR-stream SpMV: block k owns rows [rb[k], rb[k+1]) whose entries start in
 // [k * SNNZ, (k+1) * SNNZ).  The block's products v[e] * x[ci[e]] are written to LDS with
 // coalesced loads, then every row is summed from LDS by 8 lanes.  A block whose rows hold
-// more than SCAP entries (a row longer than SCAP - SNNZ) sums each row directly.
+// more than SCAP entries (only possible with a row longer than SCAP - SNNZ = 256) sums each
+// row directly.  SCAP is kept just above SNNZ: 18 KB of LDS per block lets 8 blocks (32
+// waves) share a CU, where a 32 KB window held 5.
 constexpr int SB = 256;
 constexpr int SNNZ = 2048;
-constexpr int SCAP = 4096;
+constexpr int SCAP = SNNZ + 256;
 
 __global__ void k_rowblocks(int64_t n, const int64_t *__restrict__ rp, int64_t K,
                             int *__restrict__ rb) {
@@ -119,6 +121,7 @@ __global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
     }
     return;
   }
+  static_assert(SB == 256, "the fallback sums four wave partials");
   __shared__ double part[SB / 64];
   for (int row = r0; row < r1; ++row) {
     double acc = 0.0;

@@ -216,12 +216,14 @@ def test_spmv_ragged_matches_scipy():
 
 
 def test_spmv_long_and_empty_rows():
-    """Rows longer than a streamed block, empty rows, and a single row."""
+    """Rows longer than a streamed block, rows just over the staged-window slack (257 and
+    300 entries), empty rows, and a single row."""
     import scipy.sparse as sp
     rng = np.random.default_rng(9)
     n = 3000
     lens = rng.integers(0, 40, size=n)
     lens[[5, 6, 2000]] = [2900, 5000 if n > 5000 else 2999, 2500]
+    lens[[700, 1500, 2600]] = [257, 300, 256]
     lens[100:110] = 0
     rows, cols = [], []
     for i, L in enumerate(lens):
