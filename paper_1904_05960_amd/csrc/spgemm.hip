@@ -84,7 +84,7 @@ __device__ __forceinline__ unsigned table_find_or_insert(int *keys, unsigned mas
 // not matter here): the entries of the row of A are read G at a time and the lanes walk the
 // concatenated rows of B they select.
 template <int G>
-__device__ int sym_row(int row, const int *__restrict__ arp, const int *__restrict__ aci,
+__device__ __forceinline__ int sym_row(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                        const int *__restrict__ brp, const int *__restrict__ bci, int *keys,
                        int ht, int *s_count, int *s_excl, int *s_start) {
   const int l = threadIdx.x & (G - 1);
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(64) k_sym_global(int nrows, const int *__restr
 }
 
 template <int G>
-__device__ void num_row_g(int row, const int *__restrict__ arp, const int *__restrict__ aci,
+__device__ __forceinline__ void num_row_g(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                           const double *__restrict__ av, const int *__restrict__ brp,
                           const int *__restrict__ bci, const double *__restrict__ bv,
                           const int *__restrict__ crp, int *__restrict__ cci,
@@ -648,7 +648,7 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
 namespace {
 
 template <int G, bool DIAGB>
-__device__ void num_row_b3(int row, const int *__restrict__ arp, const int *__restrict__ aci,
+__device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                            const double *__restrict__ av, const int *__restrict__ brp,
                            const int *__restrict__ bci, const double *__restrict__ bv,
                            const int *__restrict__ crp, int *__restrict__ cci,
