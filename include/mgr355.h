@@ -319,6 +319,17 @@ typedef struct mgr_owned_csr mgr_owned_csr;
  * keeps entries that cancel.  Errors: ARG, UNSUPPORTED (a row beyond 2^21 entries). */
 mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int64_t sizes[3],
                       void *stream);
+/* C = A B for matrices made of full 3x3 blocks (nodal elasticity levels of the AMG that
+ * relaxes the displacement block, Sec. 5.3), computed on the block patterns with the same
+ * per-entry products, roundings and order as mgr_spgemm on the scalar matrices, so the
+ * result equals mgr_spgemm's bit for bit.  A and B are scalar CSR whose dimensions are
+ * multiples of 3 and whose every 3x3 block is either absent or has all nine entries stored
+ * (zeros included).  With diag_b != 0 only the diagonal of each block of B is used (the
+ * tentative prolongator's form): the result is mgr_spgemm(A, B') where B' keeps the
+ * diagonal entries of B's blocks.  C is returned with full 3x3 blocks.  Errors: ARG,
+ * UNSUPPORTED (sizes not multiples of 3, a block not fully stored). */
+mgr_status mgr_spgemm_b3(const mgr_csr *A, const mgr_csr *B, int32_t diag_b, mgr_owned_csr **C,
+                         int64_t sizes[3], void *stream);
 /* T = A^T (rows sorted by column). */
 mgr_status mgr_transpose(const mgr_csr *A, mgr_owned_csr **T, int64_t sizes[3], void *stream);
 /* S = A - diag(w) G(B) on the union pattern (eq. drop_operator with w = NULL; the AMG

@@ -212,10 +212,11 @@ void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s);
 
 // BSR3 conversion: scalar CSR with full 3x3 blocks -> block CSR
 // Symbolic sparse product: crp (n + 1, caller-allocated) gets the row pointers of the
-// pattern of A B (A: n rows; B: bn x bm), cnnz its size.
+// pattern of A B (A: n rows; B: bn x bm), cnnz its size; ub_out, when given, receives the
+// number of products of every row (sum of the lengths of the rows of B it selects).
 void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
                      const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
-                     int64_t &cnnz, hipStream_t s, int *dflag);
+                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out = nullptr);
 // C = A B on 3x3 block matrices: the scalar product of their expansions, bit for bit (B's
 // blocks diagonal when diagb).
 void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s, int *dflag);

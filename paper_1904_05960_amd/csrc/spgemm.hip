@@ -79,6 +79,17 @@ __device__ __forceinline__ unsigned table_find_or_insert(int *keys, unsigned mas
   return mask + 1;
 }
 
+// Orders the table updates of consecutive steps between the lanes of one wave.  A table in
+// LDS needs no wait: a wave's LDS operations execute in issue order, so a wavefront-scope
+// fence (a compiler barrier) suffices and loads already in flight for later steps stay in
+// flight.  A table in global memory takes a workgroup-scope fence.
+template <bool LDS_TABLE>
+__device__ __forceinline__ void table_step_fence() {
+  if (LDS_TABLE) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Symbolic count of one row by a group of G lanes with a table of `ht` slots; returns -1
 // if more than 3/4 of the table would be needed.  Products are taken flat (their order does
 // not matter here): the entries of the row of A are read G at a time and the lanes walk the
@@ -202,7 +213,7 @@ __global__ void __launch_bounds__(64) k_sym_global(int nrows, const int *__restr
   }
 }
 
-template <int G>
+template <int G, bool LDS_TABLE>
 __device__ __forceinline__ void num_row_g(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                           const double *__restrict__ av, const int *__restrict__ brp,
                           const int *__restrict__ bci, const double *__restrict__ bv,
@@ -260,7 +271,7 @@ __device__ __forceinline__ void num_row_g(int row, const int *__restrict__ arp, 
             vals[slot] = __dadd_rn(vals[slot], __dmul_rn(at[u], bv[q]));
           }
         }
-        __builtin_amdgcn_wave_barrier();
+        table_step_fence<LDS_TABLE>();
       }
     }
   }
@@ -312,7 +323,7 @@ __global__ void __launch_bounds__(64) k_num_lds(int nrows, const int *__restrict
   const int g = threadIdx.x / G;
   const int idx = blockIdx.x * NR + g;
   if (idx >= nrows) return;
-  num_row_g<G>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g], lk[g], lv[g],
+  num_row_g<G, true>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g], lk[g], lv[g],
                HT, &s_n[g], flag);
 }
 
@@ -333,10 +344,13 @@ __global__ void __launch_bounds__(64) k_num_global(int nrows, const int *__restr
   int *lk = keys + ht;
   double *vals = scratch_d + (int64_t)blockIdx.x * (ht + ht / 2);
   double *lv = vals + ht;
-  num_row_g<64>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
+  num_row_g<64, false>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
 }
 
-constexpr int NBUCKET = 5;   // block-product row buckets
+// block-product row buckets: output blocks <= 32, <= 64, <= 128, <= 256, longer (global
+// tables), then <= 32 and <= 64 for rows whose steps carry many items (wide)
+constexpr int NBUCKET = 7;
+constexpr int B_GLOBAL = 4;
 
 __global__ void k_max_len(int nrows, const int *__restrict__ rows, const int *__restrict__ crp,
                           int *__restrict__ out) {
@@ -500,7 +514,7 @@ int lanes_for(double mean) { return mean > 48 ? 64 : mean > 24 ? 32 : mean > 6 ?
 
 void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
                      const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
-                     int64_t &cnnz, hipStream_t s, int *dflag) {
+                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out) {
   DArr<int64_t> ub(n, s);
   k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, arp, aci, brp, ub.p);
   KCHK();
@@ -553,6 +567,7 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
     }
   }
   cnnz = exclusive_scan_i32(cnt.p, crp, n, s);
+  if (ub_out) *ub_out = std::move(ub);
 }
 
 void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
@@ -647,7 +662,7 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
 // contributes, exactly the products the scalar form takes.
 namespace {
 
-template <int G, bool DIAGB>
+template <int G, bool DIAGB, bool LDS_TABLE>
 __device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp, const int *__restrict__ aci,
                            const double *__restrict__ av, const int *__restrict__ brp,
                            const int *__restrict__ bci, const double *__restrict__ bv,
@@ -662,53 +677,126 @@ __device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp,
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
   const int as = arp[row], ae = arp[row + 1];
-  for (int e = as; e < ae; ++e) {            // blocks K of the row in ascending order
-    const int k = aci[e];
-    const int b0 = brp[k], b1 = brp[k + 1];
+  // The column and B-row bounds of G blocks of the row are loaded at once, one per lane, and
+  // handed to the steps by shuffles.  The work of a step is split into units of at most one
+  // item per lane; the loads of PB units are issued together, then the units update the
+  // table in order, so one memory latency is paid per PB units.  Updates of consecutive
+  // steps are ordered by a fence.
+  constexpr int PB = 8;
+  for (int c0 = as; c0 < ae; c0 += G) {
+    int kb0 = 0, kb1 = 0;
+    if (c0 + l < ae) {
+      const int kk = aci[c0 + l];
+      kb0 = brp[kk];
+      kb1 = brp[kk + 1];
+    }
+    const int cnt = min(G, ae - c0);
     if (DIAGB) {
-      // lane t < 9 owns entry t = 3r + s of the output block; products a_rs * b_ss
-      const double a = l < 9 ? av[9 * (int64_t)e + l] : 0.0;
-      for (int q = b0; q < b1; ++q) {
-        const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
-        if (slot > mask) {
-          atomicOr(flag, FLAG_PATTERN);
-          continue;
+      // unit = one step; lane t < 9 owns entry t = 3r + s of the output block and takes the
+      // products a_rs * b_ss; the first block of each step's row of B is prefetched
+      const int s3 = l % 3;
+      for (int st0 = 0; st0 < cnt; st0 += PB) {
+        double a[PB], bd[PB];
+        int key[PB], q0[PB], q1[PB];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+          const int st = st0 + j < cnt ? st0 + j : cnt - 1;
+          q0[j] = __shfl(kb0, st, G);
+          q1[j] = __shfl(kb1, st, G);
+          a[j] = 0.0;
+          bd[j] = 0.0;
+          key[j] = -1;
+          if (st0 + j < cnt) {
+            if (l < 9) a[j] = av[9 * (int64_t)(c0 + st) + l];
+            if (q0[j] < q1[j]) {
+              key[j] = bci[q0[j]];
+              if (l < 9) bd[j] = bv[9 * (int64_t)q0[j] + 4 * s3];
+            }
+          }
         }
-        if (l < 9) {
-          double *c = vals + 9 * slot + l;
-          *c = __dadd_rn(*c, __dmul_rn(a, bv[9 * (int64_t)q + 4 * (l % 3)]));
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+          if (st0 + j >= cnt) break;
+          for (int q = q0[j]; q < q1[j]; ++q) {
+            const int kq = q == q0[j] ? key[j] : bci[q];
+            const double bq = q == q0[j] ? bd[j] : (l < 9 ? bv[9 * (int64_t)q + 4 * s3] : 0.0);
+            const unsigned slot = table_find_or_insert(keys, mask, kq);
+            if (slot > mask) {
+              atomicOr(flag, FLAG_PATTERN);
+              continue;
+            }
+            if (l < 9) {
+              double *c = vals + 9 * slot + l;
+              *c = __dadd_rn(*c, __dmul_rn(a[j], bq));
+            }
+          }
+          table_step_fence<LDS_TABLE>();
         }
       }
     } else {
-      // lane item = (block of row k of B, output row r): three entries of one block row
-      const int items = 3 * (b1 - b0);
-      for (int it = l; it < items; it += G) {
-        const int q = b0 + it / 3;
-        const int r = it - 3 * (it / 3);
-        const double a0 = av[9 * (int64_t)e + 3 * r], a1 = av[9 * (int64_t)e + 3 * r + 1],
-                     a2 = av[9 * (int64_t)e + 3 * r + 2];
-        double b[9];
+      // unit = (step, items i0 .. i0 + G - 1); item it = 3 (q - b0) + r: the output block
+      // row r of the block product with block q of B, three entries of one block row
+      int st = 0, i0 = 0;
+      int b0 = __shfl(kb0, 0, G), b1 = __shfl(kb1, 0, G);
+      while (st < cnt) {
+        int key[PB], r[PB], ust[PB];
+        double a0[PB], a1[PB], a2[PB], b[PB][9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) b[t] = bv[9 * (int64_t)q + t];
-        const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
-        if (slot > mask) {
-          atomicOr(flag, FLAG_PATTERN);
-          continue;
-        }
-        double *c = vals + 9 * slot + 3 * r;
+        for (int j = 0; j < PB; ++j) {
+          key[j] = -1;
+          ust[j] = -1;
+          r[j] = 0;
+          if (st < cnt) {
+            ust[j] = st;
+            const int it = i0 + l;
+            if (it < 3 * (b1 - b0)) {
+              const int e = c0 + st;
+              const int q = b0 + it / 3;
+              r[j] = it - 3 * (it / 3);
+              a0[j] = av[9 * (int64_t)e + 3 * r[j]];
+              a1[j] = av[9 * (int64_t)e + 3 * r[j] + 1];
+              a2[j] = av[9 * (int64_t)e + 3 * r[j] + 2];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          double x = c[t];
-          x = __dadd_rn(x, __dmul_rn(a0, b[0 + t]));
-          x = __dadd_rn(x, __dmul_rn(a1, b[3 + t]));
-          x = __dadd_rn(x, __dmul_rn(a2, b[6 + t]));
-          c[t] = x;
+              for (int t = 0; t < 9; ++t) b[j][t] = bv[9 * (int64_t)q + t];
+              key[j] = bci[q];
+            }
+            i0 += G;
+            if (i0 >= 3 * (b1 - b0)) {
+              ++st;
+              i0 = 0;
+              const int ss = st < cnt ? st : cnt - 1;
+              b0 = __shfl(kb0, ss, G);
+              b1 = __shfl(kb1, ss, G);
+            }
+          }
         }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+          if (ust[j] < 0) break;
+          if (j > 0 && ust[j] != ust[j - 1]) table_step_fence<LDS_TABLE>();
+          if (key[j] >= 0) {
+            const unsigned slot = table_find_or_insert(keys, mask, key[j]);
+            if (slot > mask) {
+              atomicOr(flag, FLAG_PATTERN);
+            } else {
+              double *c = vals + 9 * slot + 3 * r[j];
+#pragma unroll
+              for (int t = 0; t < 3; ++t) {
+                double x = c[t];
+                x = __dadd_rn(x, __dmul_rn(a0[j], b[j][0 + t]));
+                x = __dadd_rn(x, __dmul_rn(a1[j], b[j][3 + t]));
+                x = __dadd_rn(x, __dmul_rn(a2[j], b[j][6 + t]));
+                c[t] = x;
+              }
+            }
+          }
+        }
+        table_step_fence<LDS_TABLE>();
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
   for (int q = l; q < ht; q += G) {
     const int key = keys[q];
     if (key != -1) {
@@ -756,7 +844,7 @@ __global__ void __launch_bounds__(64) k_num_b3(int nrows, const int *__restrict_
   const int g = threadIdx.x / G;
   const int idx = blockIdx.x * NR + g;
   if (idx >= nrows) return;
-  num_row_b3<G, DIAGB>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g],
+  num_row_b3<G, DIAGB, true>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g],
                        lk[g], ls[g], HT, &s_n[g], flag);
 }
 
@@ -774,19 +862,26 @@ __global__ void __launch_bounds__(64) k_num_b3_global(
   int *lk = keys + ht;
   int *ls = lk + ht / 2;
   double *vals = scratch_d + (int64_t)blockIdx.x * 9 * ht;
-  num_row_b3<64, DIAGB>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, ls, ht,
+  num_row_b3<64, DIAGB, false>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, ls, ht,
                         &s_n, flag);
 }
 
-// block rows by output block count: <= 32, <= 64, <= 128, <= 256, longer
-__global__ void k_bucket_b3(int64_t n, const int *__restrict__ crp, int *__restrict__ lists,
+// block rows by output block count: <= 32, <= 64, <= 128, <= 256, longer.  A row of the
+// first two classes whose steps average more items (3 per block of B) than two per lane of
+// its group goes to the wide class of the same table size, one 64-lane group per row.
+__global__ void k_bucket_b3(int64_t n, const int *__restrict__ crp, const int *__restrict__ arp,
+                            const int64_t *__restrict__ ub, int diagb, int *__restrict__ lists,
                             int *__restrict__ counts, int64_t stride) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   int b = -1;
   if (i < n) {
     const int len = crp[i + 1] - crp[i];
-    if (len > 0) b = len <= 32 ? 0 : len <= 64 ? 1 : len <= 128 ? 2 : len <= 256 ? 3 : 4;
+    if (len > 0) b = len <= 32 ? 0 : len <= 64 ? 1 : len <= 128 ? 2 : len <= 256 ? 3 : B_GLOBAL;
+    if (!diagb && b >= 0 && b <= 1) {
+      const int64_t items = 3 * ub[i], steps = arp[i + 1] - arp[i];
+      if (items > (b == 0 ? 32 : 64) * steps) b += 5;
+    }
   }
   for (int k = 0; k < NBUCKET; ++k) {
     const uint64_t m = __ballot(b == k);
@@ -826,8 +921,9 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
     C.nnzb = 0;
     return;
   }
+  DArr<int64_t> ub;
   spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnzb, B.rp.p, B.ci.p, B.nb, B.mb, B.nnzb, C.rp.p, C.nnzb,
-                  s, dflag);
+                  s, dflag, &ub);
   C.ci.alloc(std::max<int64_t>(C.nnzb, 1), s);
   C.v.alloc(std::max<int64_t>(9 * C.nnzb, 1), s);
   if (C.nnzb == 0) return;
@@ -835,7 +931,8 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
   // so that several workgroups share a CU), rows beyond 256 blocks in global memory
   DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
   fill<int>(counts.p, 0, NBUCKET, s);
-  k_bucket_b3<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
+  k_bucket_b3<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, A.rp.p, ub.p, diagb ? 1 : 0, lists.p,
+                                                counts.p, n);
   KCHK();
   int hc[NBUCKET];
   HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -844,9 +941,11 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
   if (hc[1] > 0) launch_num_b3<32, 128>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
   if (hc[2] > 0) launch_num_b3<64, 256>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
   if (hc[3] > 0) launch_num_b3<64, 512>(diagb, hc[3], lists.p + (size_t)3 * n, A, B, C, dflag, s);
-  if (hc[NBUCKET - 1] > 0) {
-    const int nbig = hc[NBUCKET - 1];
-    const int *big = lists.p + (size_t)(NBUCKET - 1) * n;
+  if (hc[5] > 0) launch_num_b3<64, 64>(diagb, hc[5], lists.p + (size_t)5 * n, A, B, C, dflag, s);
+  if (hc[6] > 0) launch_num_b3<64, 128>(diagb, hc[6], lists.p + (size_t)6 * n, A, B, C, dflag, s);
+  if (hc[B_GLOBAL] > 0) {
+    const int nbig = hc[B_GLOBAL];
+    const int *big = lists.p + (size_t)B_GLOBAL * n;
     DArr<int> mx(1, s);
     fill<int>(mx.p, 0, 1, s);
     k_max_len<<<grid_for(nbig, 256), 256, 0, s>>>(nbig, big, C.rp.p, mx.p);

@@ -50,6 +50,34 @@ mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int
   return MGR_OK;
 }
 
+mgr_status mgr_spgemm_b3(const mgr_csr *A, const mgr_csr *B, int32_t diag_b, mgr_owned_csr **C,
+                         int64_t sizes[3], void *stream) {
+  if (!A || !B || !C || !sizes) return MGR_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DArr<int> flag(1, s);
+    clear_flag(flag.p, s);
+    Csr a, b;
+    import_csr(A, a, s, flag.p);
+    import_csr(B, b, s, flag.p);
+    require(a.m == b.n, MGR_ERR_ARG, "inner dimensions differ");
+    Bsr3 ab, bb, cb;
+    csr_to_bsr3(a, ab, s, flag.p, "A");
+    csr_to_bsr3(b, bb, s, flag.p, "B");
+    spgemm_b3(ab, bb, diag_b != 0, cb, s, flag.p);
+    check_flags(flag.p, s, "block spgemm");
+    auto out = std::make_unique<mgr_owned_csr>();
+    out->s = s;
+    bsr3_to_csr(cb, out->M, s);
+    HIPCHK(hipStreamSynchronize(s));
+    sizes_of(out->M, sizes);
+    *C = out.release();
+  } catch (const Error &e) {
+    return ufail(e);
+  }
+  return MGR_OK;
+}
+
 mgr_status mgr_transpose(const mgr_csr *A, mgr_owned_csr **T, int64_t sizes[3], void *stream) {
   if (!A || !T || !sizes) return MGR_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -132,6 +132,8 @@ def lib():
                                   C.POINTER(C.c_double)]),
         "mgr_spgemm": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), C.POINTER(vp),
                             C.POINTER(C.c_int64), vp]),
+        "mgr_spgemm_b3": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), C.c_int32, C.POINTER(vp),
+                               C.POINTER(C.c_int64), vp]),
         "mgr_transpose": (st, [C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
                                 C.POINTER(vp), C.POINTER(C.c_int64), vp]),
@@ -438,6 +440,16 @@ def spgemm(A: Matrix, B: Matrix, stream=None):
     h = C.c_void_p()
     sz = (C.c_int64 * 3)()
     _check(lib().mgr_spgemm(C.byref(A.c), C.byref(B.c), C.byref(h), sz, _stream(stream)))
+    return _owned_to_host(h, sz, stream)
+
+
+def spgemm_b3(A: Matrix, B: Matrix, diag_b=False, stream=None):
+    """C = A B on full 3x3 blocks (with diag_b only the diagonals of B's blocks); returns
+    host (indptr, indices, data, shape)."""
+    h = C.c_void_p()
+    sz = (C.c_int64 * 3)()
+    _check(lib().mgr_spgemm_b3(C.byref(A.c), C.byref(B.c), int(bool(diag_b)), C.byref(h), sz,
+                               _stream(stream)))
     return _owned_to_host(h, sz, stream)
 
 

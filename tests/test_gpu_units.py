@@ -73,6 +73,67 @@ def test_spgemm_row_length_paths(case):
     assert_csr_equal(m.spgemm(dev(A), dev(B)), spgemm(A, B), f"spgemm: {what}")
 
 
+def block_csr(rng, lens, nbc, diag_only=False):
+    """Scalar CSR of 3x3 blocks: block row i holds lens[i] distinct random block columns out
+    of nbc, every block with all nine entries stored (about one in ten exactly zero, some
+    -0.0); with diag_only the same pattern keeps only the diagonal of each block."""
+    rows, cols, vals = [], [], []
+    for i, L in enumerate(lens):
+        J = np.sort(rng.choice(nbc, size=L, replace=False))
+        for r in range(3):
+            for j in J:
+                for c in range(3):
+                    if diag_only and c != r:
+                        continue
+                    v = rng.standard_normal()
+                    u = rng.random()
+                    v = 0.0 if u < 0.07 else (-0.0 if u < 0.1 else v)
+                    rows.append(3 * i + r)
+                    cols.append(3 * j + c)
+                    vals.append(v)
+    n = 3 * len(lens)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(indptr, np.asarray(rows, dtype=np.int64) + 1, 1)
+    np.cumsum(indptr, out=indptr)
+    return CSR(indptr, np.asarray(cols, dtype=np.int64), np.asarray(vals, dtype=np.float64),
+               (n, 3 * nbc))
+
+
+@pytest.mark.parametrize("case", [
+    # (block rows of A, blocks per row of A, inner block dim, blocks per row of B, block cols)
+    ("short rows", 40, (1, 12), 30, (0, 6), 25),
+    ("output rows of 33..256 blocks (larger LDS tables)", 24, (8, 40), 400, (4, 9), 3000),
+    ("output rows beyond 256 blocks (global tables)", 6, (40, 60), 800, (8, 12), 6000),
+    ("many items per step, outputs <= 32 blocks (wide groups)", 30, (5, 20), 50, (12, 20), 30),
+    ("many items per step, outputs 33..64 blocks (wide groups)", 30, (5, 20), 50, (22, 40), 60),
+])
+@pytest.mark.parametrize("diag_b", [False, True])
+def test_spgemm_b3_equals_scalar_product(case, diag_b):
+    """The 3x3-block product used by the nodal AMG setup gives mgr_spgemm's scalar result
+    bit for bit (patterns, values, signs of zeros), in every row-length class."""
+    what, na, (la0, la1), nk, (lb0, lb1), nc = case
+    rng = np.random.default_rng(na + nk + int(diag_b))
+    A = block_csr(rng, rng.integers(la0, la1 + 1, size=na), nk)
+    Bf = block_csr(rng, rng.integers(lb0, lb1 + 1, size=nk), nc)
+    if diag_b:
+        keep = (Bf.indices % 3) == (Bf.row_ids() % 3)
+        lens = np.bincount(Bf.row_ids()[keep], minlength=Bf.shape[0])
+        indptr = np.zeros(Bf.shape[0] + 1, dtype=np.int64)
+        np.cumsum(lens, out=indptr[1:])
+        B = CSR(indptr, Bf.indices[keep], Bf.data[keep], Bf.shape)
+    else:
+        B = Bf
+    assert_csr_equal(m.spgemm_b3(dev(A), dev(Bf), diag_b), spgemm(A, B),
+                     f"block spgemm: {what}, diag_b={diag_b}")
+
+
+def test_spgemm_b3_rejects_partial_blocks():
+    A = CSR.from_dense(np.eye(3))
+    B = CSR([0, 1, 1, 1], [0], [1.0], (3, 3))
+    with pytest.raises(m.MgrError):
+        m.spgemm_b3(dev(A), dev(B))
+
+
 def test_transpose_random():
     rng = np.random.default_rng(4)
     A = rand_csr(rng, 333, 129, 0.05)
