@@ -283,21 +283,24 @@ void cast_from(const double *in, double *out, int64_t n, hipStream_t s);
 void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s);
 void resid64(const mgr_csr &A, const double *x, const double *b, double *r, hipStream_t s);
 int krylov_partials_blocks();
-// partial[blk * 64 + k] = sum over rows of blk of V_k . w  (k < nv)
-void multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
-                       hipStream_t s);
+// The *_partials functions write one partial sum per block and return the number of
+// blocks; reduce_partials adds those in a fixed order.
+// partial[blk * KS + k] = sum over the rows of blk of V_k . w  (k < nv)
+int multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
+                      hipStream_t s);
 // w -= sum_k h[k] V_k ; partial dots of the updated w with V_k (k < nv) or its norm^2
-void cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
-                         double *partial, bool norm_only, hipStream_t s);
-void reduce_partials(const double *partial, int nv, double *out, bool add, hipStream_t s);
+int cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
+                        double *partial, bool norm_only, hipStream_t s);
+void reduce_partials(const double *partial, int nblk, int nv, double *out, bool add,
+                     hipStream_t s);
 void givens_step(double *H, double *cs, double *sn, double *g, const double *h1,
                  const double *h2, const double *hn2, int j, int ldh, double *scal,
                  double *unused, hipStream_t s);
 void scale_vec(const double *w, const double *scale, double *v, int64_t n, hipStream_t s);
 void tri_solve_and_update(const double *H, const double *g, int k, int ldh, const double *Z,
                           int64_t n, double *x, double *y, hipStream_t s);
-void norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s);
-void dot_partials(const double *a, const double *b, int64_t n, double *partial,
+int norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s);
+int dot_partials(const double *a, const double *b, int64_t n, double *partial,
                   hipStream_t s);
 void start_cycle_host_beta(const double *r, double beta, double *V0, double *g, int64_t n,
                            int mp1, hipStream_t s);

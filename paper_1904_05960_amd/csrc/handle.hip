@@ -958,8 +958,8 @@ size_t fg_layout(int64_t n, int m, char *base, FgWork *w) {
 }
 
 double host_norm(const double *r, int64_t n, FgWork &W, hipStream_t s) {
-  norm2_partials(r, n, W.partial, s);
-  reduce_partials(W.partial, 1, W.red, false, s);
+  const int nb = norm2_partials(r, n, W.partial, s);
+  reduce_partials(W.partial, nb, 1, W.red, false, s);
   double *v = static_cast<double *>(pinned_scratch());
   HIPCHK(hipMemcpyAsync(v, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1058,12 +1058,12 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
       }
       matvec(zj, nullptr, W.w);
       // classical Gram-Schmidt, twice
-      multidot_partials(W.V, n, j + 1, W.w, W.partial, s);
-      reduce_partials(W.partial, j + 1, W.h1, false, s);
-      cgs_update_partials(W.V, n, j + 1, W.h1, W.w, W.partial, false, s);
-      reduce_partials(W.partial, j + 1, W.h2, false, s);
-      cgs_update_partials(W.V, n, j + 1, W.h2, W.w, W.partial, true, s);
-      reduce_partials(W.partial, 1, W.hn2, false, s);
+      int nb = multidot_partials(W.V, n, j + 1, W.w, W.partial, s);
+      reduce_partials(W.partial, nb, j + 1, W.h1, false, s);
+      nb = cgs_update_partials(W.V, n, j + 1, W.h1, W.w, W.partial, false, s);
+      reduce_partials(W.partial, nb, j + 1, W.h2, false, s);
+      nb = cgs_update_partials(W.V, n, j + 1, W.h2, W.w, W.partial, true, s);
+      reduce_partials(W.partial, nb, 1, W.hn2, false, s);
       givens_step(W.H, W.cs, W.sn, W.g, W.h1, W.h2, W.hn2, j, ldh, W.scal, nullptr, s);
       HIPCHK(hipMemcpyAsync(slot[j & 1], W.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipEventRecord(ev[j & 1], s));

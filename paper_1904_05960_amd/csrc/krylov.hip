@@ -3,6 +3,9 @@
 // the Givens update of the Hessenberg least-squares problem, and x = x0 + Z y.
 // Reductions are two-stage with a fixed tree (per-block partials, then one block per
 // output), so results are identical from run to run.
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 
 namespace mgr {
@@ -181,6 +184,34 @@ __global__ void __launch_bounds__(256) k_multidot(const double *__restrict__ V, 
 }
 
 // w -= sum_k h[k] V_k; then partial dots of the new w with every V_k, or its norm^2
+// all nv <= NVB dot products of one pass in registers: V and w are read once, and each
+// block reduces its nv sums once
+template <int NVB>
+__global__ void __launch_bounds__(256) k_multidot_reg(const double *__restrict__ V, int64_t n,
+                                                      int nv, const double *__restrict__ w,
+                                                      double *__restrict__ partial) {
+  double acc[NVB];
+#pragma unroll
+  for (int k = 0; k < NVB; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+    double t[NVB];
+#pragma unroll
+    for (int k = 0; k < NVB; ++k) t[k] = k < nv ? V[(int64_t)k * n + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NVB; ++k) acc[k] += t[k] * wi;
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < NVB; k0 += KC) {
+    if (k0 >= nv) break;
+    double a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) a[k] = acc[k0 + k];
+    block_store(a, min(KC, nv - k0), k0, partial);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_cgs_update(const double *__restrict__ V, int64_t n, int nv,
                                                     const double *__restrict__ h,
                                                     double *__restrict__ w,
@@ -232,6 +263,9 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double *__restrict__ V
 // values still in registers, the partial dots of the new w with every V_k (the second
 // projection).  NVB >= nv basis vectors per thread; the arithmetic and its order are those
 // of k_cgs_update, which re-reads V for the dots.
+// The rows are walked from the last one down: the pass before (the first projection)
+// walked them upwards, so the rows it read last, still held by the memory-side cache, are
+// read first.
 template <int NVB>
 __global__ void __launch_bounds__(256) k_cgs_fused(const double *__restrict__ V, int64_t n, int nv,
                                                    const double *__restrict__ h,
@@ -243,8 +277,9 @@ __global__ void __launch_bounds__(256) k_cgs_fused(const double *__restrict__ V,
   double acc[NVB];
 #pragma unroll
   for (int k = 0; k < NVB; ++k) acc[k] = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = n - 1 - r;
     double t[NVB];
 #pragma unroll
     for (int k = 0; k < NVB; ++k) t[k] = k < nv ? V[(int64_t)k * n + i] : 0.0;
@@ -287,12 +322,12 @@ __global__ void k_dot_partials(const double *__restrict__ a, const double *__res
 }
 
 // out[k] (+)= sum over blocks of partial[blk * KS + k]; one block per k, fixed order
-__global__ void k_reduce_partials(const double *__restrict__ partial, double *__restrict__ out,
-                                  int add) {
+__global__ void k_reduce_partials(const double *__restrict__ partial, int nblk,
+                                  double *__restrict__ out, int add) {
   __shared__ double sh[256];
   const int k = blockIdx.x;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < NB; b += 256) acc += partial[b * KS + k];
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[b * KS + k];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -419,27 +454,66 @@ void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s) {
 
 int krylov_partials_blocks() { return NB * KS; }
 
-void multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
-                       hipStream_t s) {
+// Blocks of 256 threads of `kernel` that are resident on the device at once (at most NB):
+// a grid of that size runs in a single round, without a partly filled last one.
+static int resident_grid(const void *kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, int> cache;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({dev, kernel});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int g = std::max(1, std::min(NB, per_cu * cus));
+  cache[{dev, kernel}] = g;
+  return g;
+}
+
+int multidot_partials(const double *V, int64_t n, int nv, const double *w, double *partial,
+                      hipStream_t s) {
+#define MDR(NVB)                                                                       \
+  {                                                                                    \
+    const int g = resident_grid(reinterpret_cast<const void *>(&k_multidot_reg<NVB>)); \
+    k_multidot_reg<NVB><<<g, 256, 0, s>>>(V, n, nv, w, partial);                        \
+    KCHK();                                                                            \
+    return g;                                                                          \
+  }
+  if (nv <= 16) MDR(16)
+  if (nv <= 32) MDR(32)
+  if (nv <= 48) MDR(48)
+  if (nv <= 64) MDR(64)
+#undef MDR
   k_multidot<<<NB, 256, 0, s>>>(V, n, nv, w, partial);
   KCHK();
+  return NB;
 }
-void cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
-                         double *partial, bool norm_only, hipStream_t s) {
+int cgs_update_partials(const double *V, int64_t n, int nv, const double *h, double *w,
+                        double *partial, bool norm_only, hipStream_t s) {
   // the fused pass holds nv basis values per thread; beyond 48 they would not fit the
   // register file, and the two-pass form is used
   if (!norm_only && nv <= 48) {
-    if (nv <= 16) k_cgs_fused<16><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
-    else if (nv <= 32) k_cgs_fused<32><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
-    else k_cgs_fused<48><<<NB, 256, 0, s>>>(V, n, nv, h, w, partial);
-    KCHK();
-    return;
+#define CGF(NVB)                                                                    \
+  {                                                                                 \
+    const int g = resident_grid(reinterpret_cast<const void *>(&k_cgs_fused<NVB>)); \
+    k_cgs_fused<NVB><<<g, 256, 0, s>>>(V, n, nv, h, w, partial);                     \
+    KCHK();                                                                         \
+    return g;                                                                       \
+  }
+    if (nv <= 16) CGF(16)
+    if (nv <= 32) CGF(32)
+    CGF(48)
+#undef CGF
   }
   k_cgs_update<<<NB, 256, 0, s>>>(V, n, nv, h, w, partial, norm_only ? 1 : 0);
   KCHK();
+  return NB;
 }
-void reduce_partials(const double *partial, int nv, double *out, bool add, hipStream_t s) {
-  k_reduce_partials<<<nv, 256, 0, s>>>(partial, out, add ? 1 : 0);
+void reduce_partials(const double *partial, int nblk, int nv, double *out, bool add,
+                     hipStream_t s) {
+  k_reduce_partials<<<nv, 256, 0, s>>>(partial, nblk, out, add ? 1 : 0);
   KCHK();
 }
 void givens_step(double *H, double *cs, double *sn, double *g, const double *h1, const double *h2,
@@ -460,13 +534,15 @@ void tri_solve_and_update(const double *H, const double *g, int k, int ldh, cons
   k_xupdate<<<sgrid(n), 256, 0, s>>>(Z, n, k, y, x);
   KCHK();
 }
-void norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s) {
+int norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s) {
   k_norm_partials<<<NB, 256, 0, s>>>(r, n, partial);
   KCHK();
+  return NB;
 }
-void dot_partials(const double *a, const double *b, int64_t n, double *partial, hipStream_t s) {
+int dot_partials(const double *a, const double *b, int64_t n, double *partial, hipStream_t s) {
   k_dot_partials<<<NB, 256, 0, s>>>(a, b, n, partial);
   KCHK();
+  return NB;
 }
 void start_cycle_host_beta(const double *r, double beta, double *V0, double *g, int64_t n, int mp1,
                            hipStream_t s) {

@@ -257,14 +257,27 @@ __device__ __forceinline__ void num_row_g(int row, const int *__restrict__ arp, 
         jj[u] = ok ? bci[q] : -1;
         bb[u] = ok ? bv[q] : 0.0;
       }
+      // slots of the PF steps first, independent of each other: the home slots are read
+      // together and only keys not found there take the probing path
+      unsigned sl[PF];
+      int seen[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) sl[u] = hslot(jj[u] >= 0 ? jj[u] : 0, mask);
+#pragma unroll
+      for (int u = 0; u < PF; ++u) seen[u] = jj[u] >= 0 ? keys[sl[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (jj[u] >= 0 && seen[u] != jj[u]) {
+          sl[u] = table_find_or_insert(keys, mask, jj[u]);
+          if (sl[u] > mask) atomicOr(flag, FLAG_PATTERN);
+        }
+      }
+      // then the products, added in ascending k
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         if (t0 + u < cnt) {
-          if (jj[u] >= 0) {
-            const unsigned slot = table_find_or_insert(keys, mask, jj[u]);
-            if (slot > mask) atomicOr(flag, FLAG_PATTERN);
-            else vals[slot] = __dadd_rn(vals[slot], __dmul_rn(at[u], bb[u]));
-          }
+          if (jj[u] >= 0 && sl[u] <= mask)
+            vals[sl[u]] = __dadd_rn(vals[sl[u]], __dmul_rn(at[u], bb[u]));
           for (int q = qa[u] + G + l; q < qb[u]; q += G) {   // rows of B longer than G
             const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
             if (slot > mask) { atomicOr(flag, FLAG_PATTERN); continue; }
