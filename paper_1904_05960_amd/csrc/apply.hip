@@ -293,7 +293,11 @@ void launch_bsr3(const Bsr3V<T> &A, const T *x, const T *b, const T *dinv, T *ou
 #define LB(GG)                                                                         \
   k_bsr3<T, GG, MODE><<<grid_for(A.n * GG, 256), 256, 0, s>>>(A.n, A.rp, A.ci, A.nnzb, A.v, \
                                                                x, b, dinv, out, out2)
-  if (avg > 12) LB(16);
+  // lanes per block row ~ its mean length / 1.5, up to a wave (the restrictions of the
+  // coarse levels have rows of a hundred blocks and more)
+  if (avg > 96) LB(64);
+  else if (avg > 48) LB(32);
+  else if (avg > 12) LB(16);
   else if (avg > 6) LB(8);
   else LB(4);
 #undef LB

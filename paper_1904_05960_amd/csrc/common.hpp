@@ -297,6 +297,11 @@ void givens_step(double *H, double *cs, double *sn, double *g, const double *h1,
                  const double *h2, const double *hn2, int j, int ldh, double *scal,
                  double *unused, hipStream_t s);
 void scale_vec(const double *w, const double *scale, double *v, int64_t n, hipStream_t s);
+// v = w * scale[0], with a copy of v in float or double (the preconditioner's input)
+void scale_vec_copy(const double *w, const double *scale, double *v, float *vf, int64_t n,
+                    hipStream_t s);
+void scale_vec_copy(const double *w, const double *scale, double *v, double *vd, int64_t n,
+                    hipStream_t s);
 void tri_solve_and_update(const double *H, const double *g, int k, int ldh, const double *Z,
                           int64_t n, double *x, double *y, hipStream_t s);
 int norm2_partials(const double *r, int64_t n, double *partial, hipStream_t s);

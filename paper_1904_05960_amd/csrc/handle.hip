@@ -575,10 +575,12 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
 
 namespace {
 
+// z = M^{-1} v; with input_ready the caller has already written v, in T, to h->v0
 template <class T>
-void apply_typed(mgr_handle *h, const double *v, double *z, hipStream_t s) {
+void apply_typed(mgr_handle *h, const double *v, double *z, hipStream_t s,
+                 bool input_ready = false) {
   T *v0 = Ptr<T>::of(h->v0), *z0 = Ptr<T>::of(h->z0);
-  cast_to(v, v0, h->n, s);
+  if (!input_ready) cast_to(v, v0, h->n, s);
   const bool prof = Prof::on(0);
   if (h->opts.use_graph && !prof) {
     if (!h->gexec) {
@@ -1047,12 +1049,13 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
     // residual estimate, so the GPU never idles on the host's convergence check.  When
     // step j ends the cycle, step j+1 has only written column j+1 of H, g[j+1..j+2] and
     // Z[j+1], none of which the update with k = j+1 reads.
-    auto step = [&](int j) {
+    // step j of the cycle; `ready`: v_j was also written into the preconditioner's input
+    auto step = [&](int j, bool ready) {
       double *vj = W.V + (int64_t)j * n;
       double *zj = W.Z + (int64_t)j * n;
       if (M) {
-        if (M->opts.precision == MGR_PREC_FP32) apply_typed<float>(M, vj, zj, s);
-        else apply_typed<double>(M, vj, zj, s);
+        if (M->opts.precision == MGR_PREC_FP32) apply_typed<float>(M, vj, zj, s, ready);
+        else apply_typed<double>(M, vj, zj, s, ready);
       } else {
         HIPCHK(hipMemcpyAsync(zj, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
@@ -1069,12 +1072,17 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
       HIPCHK(hipEventRecord(ev[j & 1], s));
     };
     int k = 0;
-    step(0);
+    step(0, false);
     for (int j = 0; j < m; ++j) {
       const bool ahead = j + 1 < m && its + 1 < o->maxit;
       if (ahead) {
-        scale_vec(W.w, W.scal + 2, W.V + (int64_t)(j + 1) * n, n, s);
-        step(j + 1);
+        double *vn = W.V + (int64_t)(j + 1) * n;
+        if (!M) scale_vec(W.w, W.scal + 2, vn, n, s);
+        else if (M->opts.precision == MGR_PREC_FP32)
+          scale_vec_copy(W.w, W.scal + 2, vn, Ptr<float>::of(M->v0), n, s);
+        else
+          scale_vec_copy(W.w, W.scal + 2, vn, Ptr<double>::of(M->v0), n, s);
+        step(j + 1, M != nullptr);
       }
       HIPCHK(hipEventSynchronize(ev[j & 1]));
       ++its;

@@ -343,27 +343,40 @@ __global__ void k_givens(double *__restrict__ H, double *__restrict__ cs, double
                          double *__restrict__ g, const double *__restrict__ h1,
                          const double *__restrict__ h2, const double *__restrict__ hn2, int j,
                          int ldh, double *__restrict__ scal) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double *col = H + (int64_t)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double hn = sqrt(hn2[0]);
-  col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  // the column and the earlier rotations are gathered by the whole block; one lane then
+  // applies the rotations in order
+  __shared__ double col[KS + 1], c[KS], sv[KS];
+  const int t = threadIdx.x;
+  for (int i = t; i <= j; i += blockDim.x) col[i] = h1[i] + h2[i];
+  for (int i = t; i < j; i += blockDim.x) {
+    c[i] = cs[i];
+    sv[i] = sn[i];
   }
-  const double a = col[j], b = col[j + 1];
-  const double r = hypot(a, b);
-  cs[j] = r != 0.0 ? a / r : 1.0;
-  sn[j] = r != 0.0 ? b / r : 0.0;
-  col[j] = r;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  scal[0] = fabs(g[j + 1]);
-  scal[1] = hn;
-  scal[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  __syncthreads();
+  if (t == 0) {
+    const double hn = sqrt(hn2[0]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double u = c[i] * col[i] + sv[i] * col[i + 1];
+      col[i + 1] = -sv[i] * col[i] + c[i] * col[i + 1];
+      col[i] = u;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    cs[j] = r != 0.0 ? a / r : 1.0;
+    sn[j] = r != 0.0 ? b / r : 0.0;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sn[j] * gj;
+    g[j] = cs[j] * gj;
+    scal[0] = fabs(g[j + 1]);
+    scal[1] = hn;
+    scal[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+  }
+  __syncthreads();
+  double *out = H + (int64_t)j * ldh;
+  for (int i = t; i <= j + 1; i += blockDim.x) out[i] = col[i];
 }
 
 __global__ void k_scale(const double *__restrict__ w, const double *__restrict__ sc,
@@ -372,6 +385,18 @@ __global__ void k_scale(const double *__restrict__ w, const double *__restrict__
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     v[i] = w[i] * a;
+}
+// the same, also writing the new basis vector in the preconditioner's precision
+template <class T>
+__global__ void k_scale_copy(const double *__restrict__ w, const double *__restrict__ sc,
+                             double *__restrict__ v, T *__restrict__ vt, int64_t n) {
+  const double a = sc[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double u = w[i] * a;
+    v[i] = u;
+    vt[i] = static_cast<T>(u);
+  }
 }
 
 __global__ void k_start(const double *__restrict__ r, double inv_beta, double beta,
@@ -524,6 +549,16 @@ void givens_step(double *H, double *cs, double *sn, double *g, const double *h1,
 }
 void scale_vec(const double *w, const double *scale, double *v, int64_t n, hipStream_t s) {
   k_scale<<<sgrid(n), 256, 0, s>>>(w, scale, v, n);
+  KCHK();
+}
+void scale_vec_copy(const double *w, const double *scale, double *v, float *vf, int64_t n,
+                    hipStream_t s) {
+  k_scale_copy<float><<<sgrid(n), 256, 0, s>>>(w, scale, v, vf, n);
+  KCHK();
+}
+void scale_vec_copy(const double *w, const double *scale, double *v, double *vd, int64_t n,
+                    hipStream_t s) {
+  k_scale_copy<double><<<sgrid(n), 256, 0, s>>>(w, scale, v, vd, n);
   KCHK();
 }
 void tri_solve_and_update(const double *H, const double *g, int k, int ldh, const double *Z,
