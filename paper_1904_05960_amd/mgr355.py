@@ -117,6 +117,9 @@ def lib():
         "fgmres_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
         "fgmres_solve": (st, [C.POINTER(mgr_csr), vp, vp, vp, C.POINTER(fgmres_opts), vp,
                               C.c_size_t, C.POINTER(fgmres_result), vp]),
+        "mgr_batch_solve": (st, [C.c_int32, C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(vp),
+                                 C.POINTER(vp), C.POINTER(mgr_opts), C.POINTER(fgmres_opts),
+                                 C.POINTER(C.c_double), C.POINTER(fgmres_result), vp]),
         "mgr_destroy": (None, [vp]),
         "mgr_footprint": (st, [vp, C.POINTER(C.c_size_t)]),
         "mgr_estimate_footprint": (st, [C.c_int64, C.c_int64, C.POINTER(mgr_opts),
@@ -419,6 +422,31 @@ def fgmres(A: Matrix, b, x=None, M: Preconditioner | None = None, restart=30, rt
     if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
         raise MgrError(st, lib().mgr_last_error().decode())
     return x, info
+
+
+def batch_solve(As, labels, bs, opts: Options, xs=None, restart=30, rtol=1e-6, maxit=1000,
+                stream=None, raise_on_fail=True):
+    """Solve the independent systems As[i] x_i = bs[i] together (mgr_batch_solve): one
+    setup and one FGMRES over their block-diagonal union.  Returns (xs, relres, info)."""
+    import torch
+    k = len(As)
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    Ac = (mgr_csr * k)(*[A.c for A in As])
+    lp = (C.c_void_p * k)(*[_ptr(l) for l in labels])
+    bp = (C.c_void_p * k)(*[_ptr(b) for b in bs])
+    xp = (C.c_void_p * k)(*[_ptr(x) for x in xs])
+    rel = (C.c_double * k)()
+    copts = opts.to_c()
+    o = fgmres_opts(int(restart), int(maxit), float(rtol))
+    r = fgmres_result()
+    st = lib().mgr_batch_solve(k, Ac, lp, bp, xp, C.byref(copts), C.byref(o), rel, C.byref(r),
+                               _stream(stream))
+    info = dict(iters=r.iters, restarts=r.restarts, converged=bool(r.converged),
+                true_relres=r.true_relres, status=st)
+    if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
+        raise MgrError(st, lib().mgr_last_error().decode())
+    return xs, [rel[i] for i in range(k)], info
 
 
 def _owned_to_host(h, sizes, stream=None):
