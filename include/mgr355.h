@@ -254,7 +254,11 @@ void mgr_alloc_stats(size_t *live, size_t *peak, int32_t reset_peak);
  * with MGR_ERR_ALLOC.  Requests that share `key` run one at a time in submission order and
  * share the cached setup when the matrix has the same size (e.g. the Newton steps of one
  * realization): reused as is (refresh_setup = 0, a lagged preconditioner) or recomputed
- * with mgr_setup_numeric (refresh_setup = 1). */
+ * with mgr_setup_numeric (refresh_setup = 1).
+ * Small requests can be batched (batch_rows > 0): a request of at most batch_rows rows
+ * whose key has no cached setup is solved together with the other such requests admissible
+ * at that moment (up to batch_max of them, keys not in flight) by mgr_batch_solve, on one
+ * slot; batched requests leave no cached setup. */
 typedef struct mgr_server mgr_server;
 typedef struct {
   size_t budget_bytes;        /* HBM admission budget (default 64 GiB)                 */
@@ -262,6 +266,9 @@ typedef struct {
   mgr_opts opts;              /* MGR options of every request                           */
   fgmres_opts fopts;          /* FGMRES options (default restart 30, rtol 1e-6)         */
   int32_t cache_setups;       /* keep setups between requests of a key (default 1)     */
+  int32_t batch_rows;         /* batch requests of at most this many rows (default 0:
+                                 no batching)                                          */
+  int32_t batch_max;          /* requests per batch, 1..65535 (default 16)             */
 } mgr_server_config;
 typedef struct {
   const mgr_csr *A;           /* [host struct, device arrays] valid until completion   */
@@ -282,6 +289,9 @@ typedef struct {
   double t_submit_ms, t_admit_ms, t_start_ms, t_end_ms;  /* since server creation      */
   double setup_ms, solve_ms;
   size_t footprint;           /* bytes of the setup that served it                     */
+  int32_t batch;              /* requests solved together with it (1: alone); for a
+                                 batch, setup_ms is 0 and solve_ms covers the batched
+                                 setup and solve                                        */
 } mgr_result;
 typedef struct {
   int64_t completed, queued, cache_hits, cache_misses, evictions, cached_setups;

@@ -93,11 +93,101 @@ bool make_room(mgr_server *S, size_t need) {
   return true;
 }
 
+// bytes a batched request adds for its share of the union (matrix copy and vectors)
+size_t union_bytes(const mgr_server::Req *q) {
+  return (size_t)q->r.nnz * 12 + (size_t)q->A.nrows * 40;
+}
+
+// With R admitted (no cached setup, small): take further admissible small requests
+// without a cached setup, keys not in flight and not behind an earlier request of their
+// key, up to batch_max in all.  Called with the lock held; R is batch[0].
+void gather_batch(mgr_server *S, mgr_server::Req *R, std::vector<mgr_server::Req *> &batch) {
+  batch.assign(1, R);
+  const int cap = std::max(1, std::min(S->cfg.batch_max, 65535));
+  std::map<uint64_t, bool> blocked;
+  for (auto it = S->queue.begin(); it != S->queue.end() && (int)batch.size() < cap;) {
+    mgr_server::Req *q = S->reqs[*it].get();
+    const uint64_t key = q->r.key;
+    bool take = !S->key_busy[key] && !blocked[key] && q->A.nrows <= S->cfg.batch_rows &&
+                S->cache.find(key) == S->cache.end();
+    size_t need = 0;
+    if (take) {
+      need = fgmres_workspace_bytes(q->A.nrows, S->cfg.fopts.restart) +
+             fresh_setup_bytes(S, q->A, q->r.nnz) + union_bytes(q);
+      take = S->used + need <= S->cfg.budget_bytes;
+    }
+    if (!take) {
+      blocked[key] = true;
+      ++it;
+      continue;
+    }
+    q->reserve = need;
+    S->used += need;
+    S->key_busy[key] = 1;
+    q->res.t_admit_ms = S->now_ms();
+    batch.push_back(q);
+    it = S->queue.erase(it);
+  }
+  if (batch.size() > 1) {
+    const size_t extra = union_bytes(R);
+    R->reserve += extra;
+    S->used += extra;
+  }
+  S->peak_used = std::max(S->peak_used, S->used);
+}
+
+// solve a gathered batch with mgr_batch_solve on this slot's stream
+void run_batch(mgr_server *S, int slot, hipStream_t st, std::vector<mgr_server::Req *> &batch) {
+  const int k = (int)batch.size();
+  std::vector<mgr_csr> A(k);
+  std::vector<const int8_t *> lab(k);
+  std::vector<const double *> b(k);
+  std::vector<double *> x(k);
+  std::vector<double> rel(k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    A[i] = batch[i]->A;
+    lab[i] = batch[i]->r.labels;
+    b[i] = batch[i]->r.b;
+    x[i] = batch[i]->r.x;
+  }
+  const double t_start = S->now_ms();
+  fgmres_result fr{};
+  const mgr_status code = mgr_batch_solve(k, A.data(), lab.data(), b.data(), x.data(),
+                                          &S->cfg.opts, &S->cfg.fopts, rel.data(), &fr, st);
+  (void)hipStreamSynchronize(st);
+  const double t_end = S->now_ms();
+  std::lock_guard<std::mutex> g(S->mu);
+  for (int i = 0; i < k; ++i) {
+    mgr_result &res = batch[i]->res;
+    res.slot = slot;
+    res.t_start_ms = t_start;
+    res.t_end_ms = t_end;
+    res.setup_ms = 0.0;
+    res.solve_ms = t_end - t_start;
+    res.iters = fr.iters;
+    res.true_relres = rel[i];
+    res.setup_reused = 0;
+    res.batch = k;
+    res.footprint = 0;
+    res.status = code == MGR_OK || code == MGR_ERR_NOT_CONVERGED
+                     ? (rel[i] <= S->cfg.fopts.rtol ? MGR_OK : MGR_ERR_NOT_CONVERGED)
+                     : code;
+    S->used -= batch[i]->reserve;
+    S->key_busy[batch[i]->r.key] = 0;
+    ++S->misses;
+    ++S->completed;
+    batch[i]->done = true;
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+}
+
 void worker(mgr_server *S, int slot) {
   hipStream_t st = nullptr;
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   void *work = nullptr;
   size_t work_bytes = 0;
+  std::vector<mgr_server::Req *> batch;
   for (;;) {
     mgr_server::Req *R = nullptr;
     bool hit = false;
@@ -157,7 +247,15 @@ void worker(mgr_server *S, int slot) {
       }
       if (!R) break;
       R->res.t_admit_ms = S->now_ms();
+      if (!hit && S->cfg.batch_rows > 0 && R->A.nrows <= S->cfg.batch_rows)
+        gather_batch(S, R, batch);
     }
+    if (batch.size() > 1) {
+      run_batch(S, slot, st, batch);
+      batch.clear();
+      continue;
+    }
+    batch.clear();
     // ---- run the request on this slot's stream (no lock held) ----
     mgr_result &res = R->res;
     res.slot = slot;
@@ -181,6 +279,7 @@ void worker(mgr_server *S, int slot) {
       st_code = mgr_setup(&R->A, R->r.labels, &S->cfg.opts, st, &h);
     }
     res.setup_reused = hit ? 1 : 0;
+    res.batch = 1;
     const double t_setup = S->now_ms();
     const size_t need_ws = fgmres_workspace_bytes(R->A.nrows, S->cfg.fopts.restart);
     if (st_code == MGR_OK && need_ws > work_bytes) {
@@ -272,10 +371,13 @@ void mgr_server_default_config(mgr_server_config *c) {
   c->fopts.maxit = 1000;
   c->fopts.rtol = 1e-6;
   c->cache_setups = 1;
+  c->batch_rows = 0;
+  c->batch_max = 16;
 }
 
 mgr_status mgr_server_create(const mgr_server_config *cfg, mgr_server **out) {
-  if (!cfg || !out || cfg->slots < 1 || cfg->slots > 64) {
+  if (!cfg || !out || cfg->slots < 1 || cfg->slots > 64 || cfg->batch_rows < 0 ||
+      (cfg->batch_rows > 0 && (cfg->batch_max < 1 || cfg->batch_max > 65535))) {
     mgr::set_last_error("bad server configuration");
     return MGR_ERR_ARG;
   }

@@ -73,7 +73,8 @@ class fgmres_result(C.Structure):
 
 class mgr_server_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_size_t), ("slots", C.c_int32), ("opts", mgr_opts),
-                ("fopts", fgmres_opts), ("cache_setups", C.c_int32)]
+                ("fopts", fgmres_opts), ("cache_setups", C.c_int32), ("batch_rows", C.c_int32),
+                ("batch_max", C.c_int32)]
 
 
 class mgr_request(C.Structure):
@@ -86,7 +87,8 @@ class mgr_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("setup_reused", C.c_int32),
                 ("slot", C.c_int32), ("true_relres", C.c_double), ("t_submit_ms", C.c_double),
                 ("t_admit_ms", C.c_double), ("t_start_ms", C.c_double), ("t_end_ms", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("footprint", C.c_size_t)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("footprint", C.c_size_t),
+                ("batch", C.c_int32)]
 
 
 class mgr_server_stats_t(C.Structure):

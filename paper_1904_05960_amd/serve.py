@@ -8,6 +8,8 @@ the same sparsity pattern) with Poisson arrivals and reports solves/s and p50/p9
     python -m paper_1904_05960_amd.serve [--realizations 64] [--newton 8] [--nmin 16]
         [--nmax 80] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
         [--restart 64] [--input-pool-gb 32] [--compare-fp64-serial]
+        [--batch-rows R] [--batch-max 16]
+    python -m paper_1904_05960_amd.serve --batch-compare K [--nmin 16]
 """
 from __future__ import annotations
 
@@ -24,7 +26,8 @@ from . import mgr355 as m
 
 class Server:
     def __init__(self, opts: m.Options, budget_bytes: int = 64 << 30, slots: int = 4,
-                 restart: int = 30, rtol: float = 1e-6, maxit: int = 1000, cache: bool = True):
+                 restart: int = 30, rtol: float = 1e-6, maxit: int = 1000, cache: bool = True,
+                 batch_rows: int = 0, batch_max: int = 16):
         L = m.lib()
         cfg = m.mgr_server_config()
         L.mgr_server_default_config(C.byref(cfg))
@@ -33,6 +36,8 @@ class Server:
         cfg.opts = opts.to_c()
         cfg.fopts = m.fgmres_opts(int(restart), int(maxit), float(rtol))
         cfg.cache_setups = int(cache)
+        cfg.batch_rows = int(batch_rows)
+        cfg.batch_max = int(batch_max)
         self._cfg = cfg
         h = C.c_void_p()
         m._check(L.mgr_server_create(C.byref(cfg), C.byref(h)))
@@ -63,7 +68,7 @@ class Server:
                     slot=res.slot, true_relres=res.true_relres, t_submit_ms=res.t_submit_ms,
                     t_admit_ms=res.t_admit_ms, t_start_ms=res.t_start_ms,
                     t_end_ms=res.t_end_ms, setup_ms=res.setup_ms, solve_ms=res.solve_ms,
-                    footprint=int(res.footprint))
+                    footprint=int(res.footprint), batch=int(res.batch))
 
     def poll(self, ticket: int) -> int:
         return int(m.lib().mgr_server_poll(self.h, C.c_uint64(ticket)))
@@ -213,6 +218,52 @@ def summarize(recs, wall):
                 setup_reuse=float(np.mean([r["setup_reused"] for r in recs])), wall_s=wall)
 
 
+def batch_compare(nside: int, k: int, restart: int, precision: str, seed: int, reps: int = 3):
+    """k two-phase systems of nside^3 cells (different seeds): setup + FGMRES to 1e-6 one
+    after another, against one mgr_batch_solve of all k.  Median of `reps` runs each."""
+    import torch
+    from workloads import poromech as pm
+    opts = m.paper_plan("two", precision=precision)
+    sys_ = []
+    for i in range(k):
+        w = pm.two_phase(nside, nside, nside, seed + i)
+        sys_.append((m.Matrix.from_host(w.indptr, w.indices, w.data),
+                     torch.as_tensor(w.labels).cuda(), torch.as_tensor(w.b).cuda()))
+
+    def one_by_one():
+        its = []
+        for A, lab, b in sys_:
+            P = m.Preconditioner(A, lab, opts)
+            _, info = m.fgmres(A, b, M=P, restart=restart, rtol=1e-6)
+            P.close()
+            its.append(info["iters"])
+        return its
+
+    def batched():
+        _, rel, info = m.batch_solve([s[0] for s in sys_], [s[1] for s in sys_],
+                                     [s[2] for s in sys_], opts, restart=restart, rtol=1e-6)
+        return info["iters"], max(rel)
+
+    one_by_one(), batched()          # warm up
+    t_one, t_bat = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = one_by_one()
+        torch.cuda.synchronize()
+        t_one.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        bits, worst = batched()
+        torch.cuda.synchronize()
+        t_bat.append(time.perf_counter() - t0)
+    n = sys_[0][0].c.nrows
+    return {"metric": "ms per small system (setup + FGMRES to 1e-6)", "systems": k,
+            "cells": f"{nside}^3", "unknowns_per_system": int(n), "precision": precision,
+            "one_by_one_ms_per_system": 1e3 * float(np.median(t_one)) / k,
+            "batched_ms_per_system": 1e3 * float(np.median(t_bat)) / k,
+            "iters_one_by_one": its, "iters_batched": bits, "batched_max_relres": worst}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--realizations", type=int, default=64)
@@ -228,20 +279,29 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--compare-fp64-serial", action="store_true")
     ap.add_argument("--input-pool-gb", type=float, default=32.0)
+    ap.add_argument("--batch-rows", type=int, default=0,
+                    help="batch requests of at most this many rows (0: off)")
+    ap.add_argument("--batch-max", type=int, default=16)
+    ap.add_argument("--batch-compare", type=int, default=0, metavar="K",
+                    help="only time K systems of --nmin^3 cells solved one by one and batched")
     a = ap.parse_args(argv)
+    if a.batch_compare:
+        print(json.dumps(batch_compare(a.nmin, a.batch_compare, a.restart, a.precision,
+                                       a.seed)), flush=True)
+        return
     import torch
     torch.cuda.set_device(0)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
     ens = build_ensemble(a.realizations, a.nmin, a.nmax, a.seed, log)
     order = request_order(a.realizations, a.newton, a.seed)
     srv = Server(m.paper_plan("two", precision=a.precision), int(a.budget_gb * (1 << 30)),
-                 a.slots, restart=a.restart)
+                 a.slots, restart=a.restart, batch_rows=a.batch_rows, batch_max=a.batch_max)
     pool = int(a.input_pool_gb * (1 << 30))
     recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log,
                                pool, keep_x=False)
     out = {"metric": "served MGR-FGMRES solves (1e-6), p50/p99 latency", "mode": "served",
            "precision": a.precision, "slots": a.slots, "rate_per_s": a.rate,
-           "restart": a.restart,
+           "restart": a.restart, "batch_rows": a.batch_rows, "batch_max": a.batch_max,
            **summarize(recs, wall), "server": srv.stats()}
     srv.close()
     if a.compare_fp64_serial:

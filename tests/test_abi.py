@@ -41,16 +41,21 @@ def test_struct_layouts_match_c(tmp_path):
     from paper_1904_05960_amd import mgr355 as m
     src = tmp_path / "sz.c"
     src.write_text('#include "%s"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu\\n", sizeof(mgr_opts),'
+                   'int main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu'
+                   ' %%zu\\n", sizeof(mgr_opts),'
                    'sizeof(mgr_level_opts), sizeof(mgr_amg_opts), sizeof(fgmres_opts),'
-                   'sizeof(fgmres_result), sizeof(mgr_csr), offsetof(mgr_opts, precision));}\n'
+                   'sizeof(fgmres_result), sizeof(mgr_csr), offsetof(mgr_opts, precision),'
+                   'sizeof(mgr_server_config), sizeof(mgr_request), sizeof(mgr_result),'
+                   'offsetof(mgr_result, batch));}\n'
                    % HEADER)
     exe = tmp_path / "sz"
     subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     exp = [ctypes.sizeof(m.mgr_opts), ctypes.sizeof(m.mgr_level_opts),
            ctypes.sizeof(m.mgr_amg_opts), ctypes.sizeof(m.fgmres_opts),
-           ctypes.sizeof(m.fgmres_result), ctypes.sizeof(m.mgr_csr), m.mgr_opts.precision.offset]
+           ctypes.sizeof(m.fgmres_result), ctypes.sizeof(m.mgr_csr), m.mgr_opts.precision.offset,
+           ctypes.sizeof(m.mgr_server_config), ctypes.sizeof(m.mgr_request),
+           ctypes.sizeof(m.mgr_result), m.mgr_result.batch.offset]
     assert got == exp
 
 

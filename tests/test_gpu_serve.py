@@ -103,3 +103,28 @@ def test_estimate_bounds_measured_peak(ens):
     est = m.estimate_footprint(R.n, A.nnz, opts()) + m.lib().fgmres_workspace_bytes(R.n, 30)
     log(f"  peak {peak - live0} estimate {est}")
     assert peak - live0 <= est
+
+
+def test_small_requests_are_batched(ens):
+    """With batching on, small requests queued together are solved by one block-diagonal
+    solve; every request still meets its own tolerance, its residual checks on the host,
+    and the budget holds."""
+    srv = serve.Server(opts(), 8 << 30, slots=1, batch_rows=1 << 30, batch_max=4)
+    order = [(r, 0) for r in range(len(ens))]
+    recs, _, xs = serve.run_stream(srv, ens, order, rate=0.0, seed=5, newton=1, log=log)
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in recs)
+    assert all(r["true_relres"] <= 1e-6 for r in recs)
+    assert max(r["batch"] for r in recs) > 1
+    assert all(1 <= r["batch"] <= 4 for r in recs)
+    assert st["peak_reserved_bytes"] <= 8 << 30
+    for (ri, k), r, x in zip(order, recs, xs):
+        R = ens[ri]
+        A, b = R.step(k, 5 * 7919 + ri * 101 + k)
+        rp, ci, v = (t.cpu().numpy() for t in (A.row_ptr, A.col, A.val))
+        import scipy.sparse as sp
+        M = sp.csr_matrix((v, ci, rp), shape=(R.n, R.n))
+        bb = b.cpu().numpy()
+        rel = np.linalg.norm(bb - M @ x.cpu().numpy()) / np.linalg.norm(bb)
+        assert rel <= 1e-6 * 1.001, (ri, rel, r)
