@@ -193,24 +193,27 @@ mgr_status fgmres_solve(const mgr_csr *A, mgr_handle *M, const double *b, double
  * placed on the diagonal of one block-diagonal matrix, which gets one MGR setup (Sec. 5:
  * every step of it is row-local and no AMG aggregate crosses two systems, so the
  * hierarchy is that of each system, up to the AMG's random priorities and its coarsest
- * dense level) and one FGMRES solve: every kernel launch serves all k systems.  Each b_i
- * is scaled to unit norm and the union is solved to the absolute residual rtol, which
- * bounds every system's relative residual by rtol; the solutions are scaled back.
+ * dense level) and one FGMRES(m) in which every system keeps its own Arnoldi process
+ * (basis coefficients, Hessenberg matrix, Givens rotations, restarts and the test
+ * ||b_i - A_i x_i|| <= rtol ||b_i||); the SpMV, the preconditioner and the Gram-Schmidt
+ * passes are shared launches over the union.  A converged system stops contributing.
  *   A       [host] array of k matrices (device arrays), square, row_ptr[0] = 0.
  *   labels, b, x   [host] arrays of k device pointers; x: initial guesses in, solutions
  *           out (x_i = 0 where b_i = 0).
  *   relres  [host] k entries out: ||b_i - A_i x_i|| / ||b_i|| (0 where b_i = 0).
- *   res     [host] optional: iterations and restarts of the shared solve; true_relres is
- *           the largest relres[i]; history as in fgmres_solve (of the union).
- * Allocates the union (matrix, vectors, hierarchy and FGMRES workspace) for the call and
- * frees it before returning; synchronises `stream`.
+ *   iters   [host] optional, k entries out: iterations of each system.
+ *   res     [host] optional: iters = steps of the shared loop (the largest iters[i]),
+ *           true_relres = the largest relres[i], converged; no history is recorded.
+ * Allocates the union (matrix, vectors, hierarchy and Krylov workspace) for the call and
+ * frees it before returning; synchronises `stream` once per step.
  * Errors: ARG (k outside 1..65535, null pointers, a non-square or empty system, a
- * non-finite b), UNSUPPORTED (the union has 2^31 rows or entries or more), NOT_CONVERGED
- * (some relres[i] > rtol; x and relres filled), and those of mgr_setup / fgmres_solve. */
+ * non-finite b, restart outside 1..64), UNSUPPORTED (the union has 2^31 rows or entries
+ * or more), NOT_CONVERGED (some relres[i] > rtol after maxit steps; x and relres filled),
+ * and those of mgr_setup. */
 mgr_status mgr_batch_solve(int32_t k, const mgr_csr *A, const int8_t *const *labels,
                            const double *const *b, double *const *x, const mgr_opts *opts,
-                           const fgmres_opts *o, double *relres, fgmres_result *res,
-                           void *stream);
+                           const fgmres_opts *o, double *relres, int32_t *iters,
+                           fgmres_result *res, void *stream);
 
 /* Free every device allocation of the handle.  NULL is ignored. */
 void mgr_destroy(mgr_handle *h);

@@ -144,6 +144,7 @@ void run_batch(mgr_server *S, int slot, hipStream_t st, std::vector<mgr_server::
   std::vector<const double *> b(k);
   std::vector<double *> x(k);
   std::vector<double> rel(k, 0.0);
+  std::vector<int32_t> its(k, 0);
   for (int i = 0; i < k; ++i) {
     A[i] = batch[i]->A;
     lab[i] = batch[i]->r.labels;
@@ -153,7 +154,8 @@ void run_batch(mgr_server *S, int slot, hipStream_t st, std::vector<mgr_server::
   const double t_start = S->now_ms();
   fgmres_result fr{};
   const mgr_status code = mgr_batch_solve(k, A.data(), lab.data(), b.data(), x.data(),
-                                          &S->cfg.opts, &S->cfg.fopts, rel.data(), &fr, st);
+                                          &S->cfg.opts, &S->cfg.fopts, rel.data(), its.data(),
+                                          &fr, st);
   (void)hipStreamSynchronize(st);
   const double t_end = S->now_ms();
   std::lock_guard<std::mutex> g(S->mu);
@@ -164,7 +166,7 @@ void run_batch(mgr_server *S, int slot, hipStream_t st, std::vector<mgr_server::
     res.t_end_ms = t_end;
     res.setup_ms = 0.0;
     res.solve_ms = t_end - t_start;
-    res.iters = fr.iters;
+    res.iters = its[i];
     res.true_relres = rel[i];
     res.setup_reused = 0;
     res.batch = k;

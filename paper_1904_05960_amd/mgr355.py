@@ -121,7 +121,8 @@ def lib():
                               C.c_size_t, C.POINTER(fgmres_result), vp]),
         "mgr_batch_solve": (st, [C.c_int32, C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(vp),
                                  C.POINTER(vp), C.POINTER(mgr_opts), C.POINTER(fgmres_opts),
-                                 C.POINTER(C.c_double), C.POINTER(fgmres_result), vp]),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                 C.POINTER(fgmres_result), vp]),
         "mgr_destroy": (None, [vp]),
         "mgr_footprint": (st, [vp, C.POINTER(C.c_size_t)]),
         "mgr_estimate_footprint": (st, [C.c_int64, C.c_int64, C.POINTER(mgr_opts),
@@ -439,13 +440,14 @@ def batch_solve(As, labels, bs, opts: Options, xs=None, restart=30, rtol=1e-6, m
     bp = (C.c_void_p * k)(*[_ptr(b) for b in bs])
     xp = (C.c_void_p * k)(*[_ptr(x) for x in xs])
     rel = (C.c_double * k)()
+    its = (C.c_int32 * k)()
     copts = opts.to_c()
     o = fgmres_opts(int(restart), int(maxit), float(rtol))
     r = fgmres_result()
-    st = lib().mgr_batch_solve(k, Ac, lp, bp, xp, C.byref(copts), C.byref(o), rel, C.byref(r),
-                               _stream(stream))
-    info = dict(iters=r.iters, restarts=r.restarts, converged=bool(r.converged),
-                true_relres=r.true_relres, status=st)
+    st = lib().mgr_batch_solve(k, Ac, lp, bp, xp, C.byref(copts), C.byref(o), rel, its,
+                               C.byref(r), _stream(stream))
+    info = dict(iters=r.iters, system_iters=[its[i] for i in range(k)],
+                converged=bool(r.converged), true_relres=r.true_relres, status=st)
     if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
         raise MgrError(st, lib().mgr_last_error().decode())
     return xs, [rel[i] for i in range(k)], info

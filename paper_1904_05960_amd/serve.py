@@ -242,7 +242,7 @@ def batch_compare(nside: int, k: int, restart: int, precision: str, seed: int, r
     def batched():
         _, rel, info = m.batch_solve([s[0] for s in sys_], [s[1] for s in sys_],
                                      [s[2] for s in sys_], opts, restart=restart, rtol=1e-6)
-        return info["iters"], max(rel)
+        return info["system_iters"], max(rel)
 
     one_by_one(), batched()          # warm up
     t_one, t_bat = [], []
