@@ -184,6 +184,9 @@ def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
         recs[j] = res
         held -= nb
 
+    # inputs are materialized on a stream of their own and only that stream is awaited: a
+    # device-wide synchronisation is refused while a worker thread captures a V-cycle graph
+    side = torch.cuda.Stream()
     t0 = time.perf_counter()
     for i, (r, k) in enumerate(order):
         delay = arrivals[i] - (time.perf_counter() - t0)
@@ -192,9 +195,10 @@ def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
         need = ens[r].input_bytes()
         while inflight and held + need > input_pool_bytes:
             finish_oldest()
-        A, b = ens[r].step(k, seed * 7919 + r * 101 + k)
-        x = torch.zeros_like(b)
-        torch.cuda.synchronize()              # inputs complete before the server reads them
+        with torch.cuda.stream(side):
+            A, b = ens[r].step(k, seed * 7919 + r * 101 + k)
+            x = torch.zeros_like(b)
+        side.synchronize()                    # inputs complete before the server reads them
         late[i] = max(0.0, time.perf_counter() - t0 - arrivals[i])
         t = server.submit(A, ens[r].labels, b, x, key=r, refresh=refresh,
                           last_use=(k == newton - 1))

@@ -53,6 +53,7 @@ def test_refresh_equals_fresh_setup(ens):
     for k in range(3):
         A, b = R.step(k, 100 + k)
         x = torch.zeros_like(b)
+        torch.cuda.current_stream().synchronize()   # inputs complete before the server reads
         t = srv.submit(A, R.labels, b, x, key=7, refresh=True)
         res = srv.wait(t)
         assert res["status"] == 0 and res["setup_reused"] == (k > 0)
@@ -78,7 +79,24 @@ def test_budget_evictions_and_rejection(ens):
     srv.close()
     assert all(r["status"] == 0 for r in recs)
     assert st["peak_reserved_bytes"] <= budget
-    assert st["evictions"] > 0
+    # deterministic eviction: one slot, one matrix under two keys, and a budget one byte
+    # short of a cached setup plus a fresh request: the second key's request must evict the
+    # first key's setup
+    R = ens[0]
+    need = m.estimate_footprint(R.n, R.A0.nnz, opts()) + m.lib().fgmres_workspace_bytes(R.n, 30)
+    P = m.Preconditioner(R.A0, R.labels, opts())
+    fp = P.footprint()
+    P.close()
+    srv = serve.Server(opts(), need + fp - 1, slots=1)
+    for key in (1, 2):
+        A, b = R.step(0, 9)
+        x = torch.zeros_like(b)
+        torch.cuda.current_stream().synchronize()
+        res = srv.wait(srv.submit(A, R.labels, b, x, key=key))
+        assert res["status"] == 0
+    st = srv.stats()
+    srv.close()
+    assert st["evictions"] == 1 and st["peak_reserved_bytes"] <= need + fp - 1
     # a request larger than the whole budget completes with ALLOC
     tiny = serve.Server(opts(), 1 << 20, slots=1)
     R = ens[0]
