@@ -56,6 +56,7 @@ class LevelPlan:
     global_sweeps: int = 1
     global_omega: float = 1.0
     coupling: str = "full"           # 'full' | 'quasi_impes' (A_CF of the coarse product)
+    drop_tol: float = -1.0           # >= 0: tolerance form of G instead of nmax
 
 
 @dataclass
@@ -151,10 +152,29 @@ def coupling_block(A_CF: CSR, labels: np.ndarray, F, C, coupling: str) -> CSR:
     return CSR(indptr, A_CF.indices[keep], A_CF.data[keep], A_CF.shape)
 
 
-def drop(Acor: CSR, labels_c: np.ndarray, nmax: int) -> CSR:
+def drop(Acor: CSR, labels_c: np.ndarray, nmax: int, tol: float = -1.0) -> CSR:
     """The dropping operator G of eq. drop_operator: per row, keep the entries on the
     diagonals of the sub-blocks (same per-label rank) and the nmax largest |values| among
-    the rest (ties to the smaller column).  nmax < 0 keeps everything."""
+    the rest (ties to the smaller column).  nmax < 0 keeps everything.
+
+    tol >= 0 selects the tolerance form the paper names beside it (Sec. 5.2) instead: an
+    entry off the sub-block diagonals is kept when it is nonzero and its |value| is at least
+    tol times the largest |value| of its row; the sub-block diagonals are always kept, so a
+    tolerance above 1 keeps exactly what nmax = 0 keeps."""
+    if tol >= 0:
+        rank = label_rank(labels_c)
+        r = Acor.row_ids()
+        c = Acor.indices
+        prot = rank[c] == rank[r]
+        absv = np.abs(Acor.data)
+        rowmax = np.zeros(Acor.shape[0])
+        np.maximum.at(rowmax, r, absv)
+        thr = tol * rowmax
+        keep = prot | ((absv > 0.0) & (absv >= thr[r]))
+        kr = r[keep]
+        indptr = np.zeros(Acor.shape[0] + 1, dtype=np.int64)
+        np.cumsum(np.bincount(kr, minlength=Acor.shape[0]), out=indptr[1:])
+        return CSR(indptr, c[keep], Acor.data[keep], Acor.shape)
     if nmax < 0:
         return Acor
     rank = label_rank(labels_c)
@@ -224,7 +244,7 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
         else:
             raise ValueError(lp.interp)
         Acor = spgemm(coupling_block(A_CF, lab, F, C, lp.coupling), M)
-        G = drop(Acor, lab[C], lp.nmax)
+        G = drop(Acor, lab[C], lp.nmax, lp.drop_tol)
         S = merge_sub(A_CC, G)
         L = Level(A=cur, labels=lab, F=F, C=C, dFF=d, A_FF=A_FF, A_FC=A_FC, A_CF=A_CF,
                   A_CC=A_CC, Wp=Wp, Acor=Acor, G=G, plan=lp)

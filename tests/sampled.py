@@ -76,7 +76,7 @@ class LevelRows:
         M, Wp = omgr.jacobi_interpolation(A_FC, d)
         Acor = spgemm(omgr.coupling_block(A_CF, self.labels, self.F, self.C,
                                           self.lp.coupling), M)
-        G = omgr.drop(Acor, self.labels[self.C], self.lp.nmax)
+        G = omgr.drop(Acor, self.labels[self.C], self.lp.nmax, self.lp.drop_tol)
         S = merge_sub(A_CC, G)
         return restrict_rows(S, rows_c), restrict_rows(Wp, self.fpos[ks]), self.fpos[ks]
 

@@ -207,6 +207,53 @@ def test_drop_extremes_block_diagonal():
     assert np.array_equal(mgr.drop(Acor, labels_c, 10 ** 6).to_dense(), D)
 
 
+def test_drop_tolerance_by_hand():
+    """Tolerance form of G (Sec. 5.2), worked by hand on one row of a two-label coarse grid:
+    the sub-block diagonal entries (columns of the same per-label rank as the row: its own
+    diagonal and the same-cell entry of the other label) are kept whatever their size, the
+    others when nonzero and at least tol times the row's largest |value| (2.0 here)."""
+    labels_c = np.array([1, 2, 1, 2, 1, 2], dtype=np.int8)   # ranks 0 0 1 1 2 2
+    # row 0 (label 1, rank 0): columns 0 and 1 have rank 0
+    D = np.array([[0.1, 0.01, -2.0, 0.5, 1.9, 0.0]] + [[0.0] * 6] * 5)
+    mask = np.zeros_like(D, dtype=bool)
+    mask[0, :] = True                                           # an explicit zero at (0, 5)
+    Acor = CSR.from_dense(D, mask)
+    row = lambda G: G.row(0)[0].tolist()                        # noqa: E731
+    assert row(mgr.drop(Acor, labels_c, -1, tol=0.5)) == [0, 1, 2, 4]       # >= 1.0
+    assert row(mgr.drop(Acor, labels_c, -1, tol=0.25)) == [0, 1, 2, 3, 4]   # >= 0.5
+    assert row(mgr.drop(Acor, labels_c, -1, tol=0.0)) == [0, 1, 2, 3, 4]    # nonzeros
+    assert row(mgr.drop(Acor, labels_c, -1, tol=0.95)) == [0, 1, 2, 4]      # >= 1.9: equal kept
+    assert row(mgr.drop(Acor, labels_c, -1, tol=1.0)) == [0, 1, 2]          # >= 2.0
+    assert row(mgr.drop(Acor, labels_c, -1, tol=1.5)) == [0, 1]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_drop_tolerance_limits_and_nesting(seed):
+    """A tolerance above 1 keeps exactly what N_max = 0 keeps (the paper's 'extremely large
+    tolerance'); tolerance 0 keeps what N_max = infinity keeps except explicit zeros; a
+    larger tolerance keeps a subset."""
+    rng = np.random.default_rng(40 + seed)
+    nC = 50
+    labels_c = np.tile(np.array([1, 2], dtype=np.int8), nC // 2)
+    D = rng.standard_normal((nC, nC)) * (rng.random((nC, nC)) < 0.3)
+    mask = (D != 0) | (rng.random((nC, nC)) < 0.05)
+    Acor = CSR.from_dense(D, mask)
+    for big in (1.0000001, 2.0, 1e300):
+        assert np.array_equal(mgr.drop(Acor, labels_c, -1, tol=big).to_dense(),
+                              mgr.drop(Acor, labels_c, 0).to_dense())
+    G0 = mgr.drop(Acor, labels_c, -1, tol=0.0)
+    prot = mgr.label_rank(labels_c)[Acor.indices] == mgr.label_rank(labels_c)[Acor.row_ids()]
+    assert G0.nnz == int(np.count_nonzero((Acor.data != 0) | prot))
+    assert np.array_equal(G0.to_dense(), D)
+    prev = None
+    for tol in (0.0, 0.1, 0.3, 0.6, 0.9):
+        G = mgr.drop(Acor, labels_c, -1, tol=tol)
+        kept = set(zip(G.row_ids().tolist(), G.indices.tolist()))
+        if prev is not None:
+            assert kept <= prev
+        prev = kept
+
+
 def test_spgemm_pinned_order_by_hand():
     """Products are summed in ascending k from +0.0: (0 + 1e16) + 1 + (-1e16) = 0 in binary64
     (1e16 + 1 rounds back to 1e16), whereas summing the last two first would give 1."""

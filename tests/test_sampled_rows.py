@@ -27,6 +27,8 @@ PLANS = {
         omgr.LevelPlan((1,), nmax=-1)])),
     "two_quasi_impes": (lambda: pm.two_phase(7, 6, 5, 1), _plan([
         omgr.LevelPlan((0,), nmax=4), omgr.LevelPlan((1,), nmax=-1, coupling="quasi_impes")])),
+    "two_drop_tol": (lambda: pm.two_phase(7, 6, 5, 1), _plan([
+        omgr.LevelPlan((0,), drop_tol=0.05), omgr.LevelPlan((1,), nmax=-1)])),
     "three_drop2": (lambda: pm.three_phase(5, 4, 4, 3), _plan([
         omgr.LevelPlan((0,), nmax=2), omgr.LevelPlan((3,), nmax=1),
         omgr.LevelPlan((1,), nmax=0)])),
