@@ -8,7 +8,7 @@ unknowns, 92,914,761 nonzeros), paper reduction order (displacement, saturation,
 pressure), FP32 hierarchy inside FP64 FGMRES(64).
 
     python bench.py [--steps K] [--warmup W] [--size 64] [--precision fp32|fp64]
-                    [--plan paper|satfirst] [--no-cpu-baseline]
+                    [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
 
 Prints one JSON line.  The dominant kernel's duration is measured live with HIP events
 recorded on its own stream around every launch inside the timed steps.
@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--size", type=int, default=None, help="cells per side (64 two, 96 three)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
+    ap.add_argument("--drop-tol", type=float, default=None,
+                    help="tolerance form of G on the displacement level instead of N_max = 4")
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-hierarchy step")
@@ -156,7 +158,15 @@ def main():
     b = torch.as_tensor(w.b).cuda()
     x = torch.zeros_like(b)
     work = m.Workspace(w.n, a.restart)
-    mk = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
+    mk0 = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
+
+    def mk(model, **kw):
+        opts = mk0(model, **kw)
+        if a.drop_tol is not None:
+            for L in opts.levels:
+                if 0 in L.f_labels:
+                    L.nmax, L.drop_tol = -1, float(a.drop_tol)
+        return opts
     stream = torch.cuda.current_stream()
 
     def step(prec, record=None):
@@ -233,6 +243,8 @@ def main():
             "reduction": (WORKLOADS[a.workload][3] if a.plan == "paper"
                           else "saturations -> displacement -> pressure AMG"),
             "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
+            "dropping": ("N_max = 4 on the displacement level" if a.drop_tol is None
+                         else f"tolerance {a.drop_tol} on the displacement level"),
             "rtol": 1e-6, "parallelism": "single GPU",
         },
         "iterations": info["iters"],

@@ -99,6 +99,11 @@ typedef struct {
                                   diagonal that the quasi-IMPES reduction described with
                                   that equation uses; W_p and residuals keep all of A_CF  */
   double global_omega;         /* weight of sweeps after the first (default 1.0)         */
+  double drop_tol;             /* >= 0: the tolerance form of G named beside eq.
+                                  drop_operator instead of N_max (nmax_drop must be < 0):
+                                  an entry off the sub-block diagonals is kept when it is
+                                  nonzero and its |value| >= drop_tol times the largest
+                                  |value| of its row; < 0: off (default)                */
 } mgr_level_opts;
 
 #define MGR_MAX_LEVELS 8

@@ -152,10 +152,13 @@ void transpose(const Csr &A, Csr &T, bool values, hipStream_t s);
 // S = A - diag(w) * B restricted to entries of B kept by the drop rule.
 //   keep rule: nmax < 0 keeps all of B; otherwise per row the entries whose column c has
 //   lrank[c] == lrank[row] plus the nmax largest |b| (ties: smaller column).
+//   tol >= 0 replaces the nmax rule: the lrank entries plus the nonzero entries with
+//   |b| >= tol * (largest |b| of the row).
 //   w may be null (w = 1).  If values == false, only the union pattern is formed.
 void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int *lrank,
-                Csr &S, bool values, hipStream_t s, int *dflag);
-void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag);
+                Csr &S, bool values, hipStream_t s, int *dflag, double tol = -1.0);
+void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag,
+               double tol = -1.0);
 
 struct CfSplit {
   int64_t n = 0, nF = 0, nC = 0;

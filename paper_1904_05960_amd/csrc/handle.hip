@@ -672,7 +672,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     DArr<int8_t> labC(nC, s);
     gather_labels(L->labels.p, L->cf.C.p, nC, labC.p, s);
     DArr<int> lrankC;
-    if (lo.nmax_drop >= 0) label_rank(labC.p, nC, lrankC, s, present & ~lo.f_label_mask);
+    const bool dropping = lo.nmax_drop >= 0 || lo.drop_tol >= 0.0;
+    if (dropping) label_rank(labC.p, nC, lrankC, s, present & ~lo.f_label_mask);
     const bool need_ff = lo.frelax != MGR_FRELAX_JACOBI;
     Csr Aff, Afc, Acc;
     L->dFF.alloc(L->cf.nF, s);
@@ -734,10 +735,10 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     spgemm(lo.coupling == MGR_COUPLING_QUASI_IMPES ? AcfQ : L->Acf, M, Acor, s, flag);
     trace("  A_cor done");
     Csr S;
-    merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag);
+    merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag, lo.drop_tol);
     trace("  S done");
     if (o.keep_setup) {
-      if (lo.nmax_drop >= 0) drop_only(Acor, lo.nmax_drop, lrankC.p, L->G, s, flag);
+      if (dropping) drop_only(Acor, lo.nmax_drop, lrankC.p, L->G, s, flag, lo.drop_tol);
       else copy_csr(Acor, L->G, s);
       L->Acor = std::move(Acor);
     }
@@ -867,6 +868,9 @@ void validate_opts(const mgr_opts &o) {
     require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
     require(lo.coupling == MGR_COUPLING_FULL || lo.coupling == MGR_COUPLING_QUASI_IMPES, MGR_ERR_ARG,
             "coupling");
+    require(!(lo.drop_tol >= 0.0 && lo.nmax_drop >= 0), MGR_ERR_ARG,
+            "drop_tol and nmax_drop select two forms of G: set one");
+    require(!(lo.drop_tol != lo.drop_tol), MGR_ERR_ARG, "drop_tol is NaN");
   }
 }
 
@@ -1141,6 +1145,7 @@ void mgr_default_opts(mgr_opts *o) {
     L.global_sweeps = 1;
     L.global_omega = 1.0;
     L.coupling = MGR_COUPLING_FULL;
+    L.drop_tol = -1.0;
   }
 }
 

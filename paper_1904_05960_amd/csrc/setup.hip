@@ -239,6 +239,29 @@ __global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *_
   }
 }
 
+// keep flags of the tolerance form of G: G lanes per row take the largest |b| of the row
+// (a maximum, exact in any order), then an entry is kept when it lies on a sub-block
+// diagonal, or is nonzero with |b| >= tol * max
+template <int G>
+__global__ void k_drop_tol(int64_t n, const int *__restrict__ brp, const int *__restrict__ bci,
+                           const double *__restrict__ bv, double tol,
+                           const int *__restrict__ lrank, unsigned char *__restrict__ keep) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (row >= n) return;
+  const int bs = brp[row], be = brp[row + 1];
+  double mx = 0.0;
+  for (int t = bs + l; t < be; t += G) mx = fmax(mx, fabs(bv[t]));
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, G));
+  const double thr = __dmul_rn(tol, mx);
+  const int myrank = lrank[row];
+  for (int t = bs + l; t < be; t += G) {
+    const double a = fabs(bv[t]);
+    keep[t] = lrank[bci[t]] == myrank || (a > 0.0 && a >= thr);
+  }
+}
+
 // two-pointer merge of row `row` of A with the kept entries of row `row` of B; MODE 0
 // counts, MODE 1 writes columns (and values when sv != null)
 template <int MODE>
@@ -651,7 +674,7 @@ void check_nonzero(const double *d, int64_t n, int *dflag, hipStream_t s) {
 }
 
 void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int *lrank, Csr &S,
-                bool values, hipStream_t s, int *dflag) {
+                bool values, hipStream_t s, int *dflag, double tol) {
   (void)dflag;
   const int64_t n = B.n;
   S.n = n;
@@ -659,7 +682,14 @@ void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int
   S.rp.alloc(n + 1, s);
   DArr<int> cnt(n + 1, s);
   DArr<unsigned char> keep;
-  if (nmax >= 0 && B.nnz > 0) {
+  if (tol >= 0.0 && B.nnz > 0) {
+    require(lrank != nullptr, MGR_ERR_ARG, "dropping needs per-label ranks");
+    keep.alloc(B.nnz, s);
+    constexpr int G = 16;
+    k_drop_tol<G><<<grid_for(n * G, 256), 256, 0, s>>>(n, B.rp.p, B.ci.p, B.v.p, tol, lrank,
+                                                       keep.p);
+    KCHK();
+  } else if (nmax >= 0 && B.nnz > 0) {
     require(lrank != nullptr, MGR_ERR_ARG, "dropping needs per-label ranks");
     keep.alloc(B.nnz, s);
     constexpr int G = 16;
@@ -686,9 +716,10 @@ void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int
   }
 }
 
-void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag) {
+void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag,
+               double tol) {
   Csr empty;
-  merge_drop(empty, B, nullptr, nmax, lrank, G, true, s, dflag);
+  merge_drop(empty, B, nullptr, nmax, lrank, G, true, s, dflag, tol);
   negate_f64(G.v.p, G.nnz, s);
 }
 

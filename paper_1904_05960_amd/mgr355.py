@@ -51,7 +51,7 @@ class mgr_level_opts(C.Structure):
                 ("frelax", C.c_int32), ("frelax_sweeps", C.c_int32), ("frelax_omega", C.c_double),
                 ("frelax_block", C.c_int32), ("global_smoother", C.c_int32),
                 ("global_sweeps", C.c_int32), ("coupling", C.c_int32),
-                ("global_omega", C.c_double)]
+                ("global_omega", C.c_double), ("drop_tol", C.c_double)]
 
 
 class mgr_opts(C.Structure):
@@ -227,6 +227,7 @@ class Level:
     global_sweeps: int = 1
     global_omega: float = 1.0
     coupling: str = "full"          # 'full' | 'quasi_impes'
+    drop_tol: float = -1.0          # >= 0: tolerance form of G (nmax must be < 0)
 
 
 @dataclass
@@ -265,6 +266,7 @@ class Options:
             c.global_sweeps = int(L.global_sweeps)
             c.global_omega = float(L.global_omega)
             c.coupling = COUPLING[L.coupling]
+            c.drop_tol = float(L.drop_tol)
         o.coarse = COARSE[self.coarse]
         for dst, src in ((o.amg_frelax, self.amg_frelax), (o.amg_coarse, self.amg_coarse)):
             dst.theta0, dst.max_levels, dst.coarse_size = src.theta0, src.max_levels, src.coarse_size

@@ -19,7 +19,7 @@ def oracle_plan(opts) -> omgr.Plan:
             frelax_sweeps=L.frelax_sweeps, frelax_omega=L.frelax_omega,
             frelax_block=L.frelax_block, global_smoother=L.global_smoother,
             global_sweeps=L.global_sweeps, global_omega=L.global_omega,
-            coupling=L.coupling))
+            coupling=L.coupling, drop_tol=L.drop_tol))
     a, c = opts.amg_frelax, opts.amg_coarse
     return omgr.Plan(levels=levels, coarse=opts.coarse,
                      amg_frelax=oamg.AMGOptions(a.theta0, a.max_levels, a.coarse_size, 3),

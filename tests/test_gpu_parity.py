@@ -35,6 +35,14 @@ def small_amg(opts, coarse_size=48):
     return opts
 
 
+def tol_plan(tol, model="two"):
+    """The paper plan with the tolerance form of G on the displacement level."""
+    opts = m.paper_plan(model)
+    opts.levels[0].nmax = -1
+    opts.levels[0].drop_tol = tol
+    return opts
+
+
 CASES = [
     ("biot_8x8x8_paper_dense", lambda: pm.biot_single_phase(8, 8, 8, 0),
      lambda: small_amg(m.paper_plan("biot1", coarse="dense"))),
@@ -50,6 +58,10 @@ CASES = [
      lambda: small_amg(m.paper_plan("three"))),
     ("two_9x7x6_quasi_impes", lambda: pm.two_phase(9, 7, 6, 1),
      lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
+    ("two_9x7x6_drop_tol", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(tol_plan(0.05))),
+    ("three_6x5x4_drop_tol", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(tol_plan(0.2, "three"))),
     ("channels_12x10x6_quasi_impes", lambda: pm.two_phase_channels(12, 10, 6, 2),
      lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
     ("three_6x5x4_quasi_impes", lambda: pm.three_phase(6, 5, 4, 3),
@@ -262,6 +274,11 @@ def test_error_paths():
     # an empty C set
     with pytest.raises(m.MgrError) as e:
         m.Preconditioner(A, labels, m.Options(levels=[m.Level((0, 2))], coarse="dense"))
+    assert e.value.status == m.MGR_ERR_ARG
+    # both forms of G on one level
+    with pytest.raises(m.MgrError) as e:
+        m.Preconditioner(A, labels, m.Options(levels=[m.Level((0,), nmax=4, drop_tol=0.1)],
+                                              coarse="dense"))
     assert e.value.status == m.MGR_ERR_ARG
     # an F block without full 3x3 node blocks: the nodal AMG, built on a second host thread
     # and stream, fails there and the error reaches the caller
