@@ -52,7 +52,7 @@ class LevelPlan:
     frelax_sweeps: int = 1
     frelax_omega: float = 1.0
     frelax_block: int = 1            # 3: nodal AMG on the F block
-    global_smoother: str = "none"    # 'none' | 'block_jacobi'
+    global_smoother: str = "none"    # 'none' | 'block_jacobi' | 'block_gs'
     global_sweeps: int = 1
     global_omega: float = 1.0
     coupling: str = "full"           # 'full' | 'quasi_impes' (A_CF of the coarse product)
@@ -85,6 +85,7 @@ class Level:
     amg: object = None          # F-relaxation AMG hierarchy
     ff_lu: tuple | None = None  # F-relaxation dense LU ('exact')
     blocks: tuple | None = None # global smoother: (rows per block, block inverses)
+    colors: np.ndarray | None = None  # block Gauss-Seidel: colour of every cell
 
 
 @dataclass
@@ -219,6 +220,62 @@ def same_cell_blocks(A: CSR, labels: np.ndarray):
     return rows, np.linalg.inv(D)
 
 
+def cell_graph(A: CSR, labels: np.ndarray):
+    """Graph of the same-cell blocks (cell = per-label rank of a row): cells e != f are
+    adjacent when A has an entry between a row of e and a row of f, in either direction.
+    Returns (indptr, indices), neighbours ascending."""
+    rank = label_rank(labels)
+    ncell = int(rank.max()) + 1
+    r, c = rank[A.row_ids()], rank[A.indices]
+    m = r != c
+    pairs = np.concatenate([np.stack([r[m], c[m]], 1), np.stack([c[m], r[m]], 1)])
+    pairs = np.unique(pairs, axis=0) if pairs.shape[0] else pairs.reshape(0, 2)
+    indptr = np.zeros(ncell + 1, dtype=np.int64)
+    np.cumsum(np.bincount(pairs[:, 0], minlength=ncell), out=indptr[1:])
+    return indptr, pairs[:, 1].astype(np.int64)
+
+
+def cell_priorities(ncell: int) -> np.ndarray:
+    """Colouring priorities: SplitMix64 of the cell index with a fixed salt."""
+    with np.errstate(over="ignore"):
+        salt = amg_mod.GOLDEN * np.uint64(977)
+        return amg_mod.splitmix64(np.arange(ncell, dtype=np.uint64) ^ salt)
+
+
+def jp_coloring(gptr: np.ndarray, gcol: np.ndarray, prio: np.ndarray) -> np.ndarray:
+    """Jones-Plassmann colouring by synchronous rounds: an uncoloured vertex whose
+    (priority, index) exceeds that of every uncoloured neighbour takes the smallest colour
+    not used by its neighbours coloured in earlier rounds.  Adjacent vertices never share a
+    colour; at most 64 colours."""
+    n = gptr.shape[0] - 1
+    color = np.full(n, -1, dtype=np.int64)
+    src = np.repeat(np.arange(n), np.diff(gptr))
+    dst = np.asarray(gcol, dtype=np.int64)
+    prio = np.asarray(prio, dtype=np.uint64)
+    while np.any(color < 0):
+        old = color.copy()
+        unc = old < 0
+        e = unc[src] & unc[dst]
+        beats = (prio[dst[e]] > prio[src[e]]) | ((prio[dst[e]] == prio[src[e]]) &
+                                                (dst[e] > src[e]))
+        loser = np.zeros(n, dtype=bool)
+        loser[src[e][beats]] = True
+        win = unc & ~loser
+        used = np.zeros(n, dtype=np.uint64)
+        ce = unc[src] & ~unc[dst]
+        if np.any(old[dst[ce]] >= 64):
+            raise ValueError("more than 64 colours")
+        np.bitwise_or.at(used, src[ce], np.left_shift(np.uint64(1), old[dst[ce]].astype(np.uint64)))
+        free = ~used & (used + np.uint64(1))          # lowest clear bit
+        k = np.zeros(n, dtype=np.int64)
+        nz = free != 0
+        k[nz] = np.log2(free[nz].astype(np.float64)).astype(np.int64)
+        if np.any(win & ~nz):
+            raise ValueError("more than 64 colours")
+        color[win] = k[win]
+    return color
+
+
 def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
     """Level loop of Sec. 5.2: A_{l+1} = A_CC - G(A_CF D_FF^{-1} A_FC) with labels_{l+1} =
     labels_l[C]; then the coarsest-grid solver (dense LU or AMG)."""
@@ -253,8 +310,11 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
             L.amg = amg_mod.setup(A_FF, opts)
         elif lp.frelax == "exact":
             L.ff_lu = sla.lu_factor(A_FF.to_dense())
-        if lp.global_smoother == "block_jacobi":
+        if lp.global_smoother in ("block_jacobi", "block_gs"):
             L.blocks = same_cell_blocks(cur, lab)
+        if lp.global_smoother == "block_gs":
+            gptr, gcol = cell_graph(cur, lab)
+            L.colors = jp_coloring(gptr, gcol, cell_priorities(gptr.shape[0] - 1))
         levels.append(L)
         cur, lab = S, lab[C]
     H = Hierarchy(levels=levels, coarse_A=cur, coarse_labels=lab, plan=plan)
@@ -272,6 +332,21 @@ def _block_jacobi(L: Level, v: np.ndarray) -> np.ndarray:
     return z
 
 
+def _block_gs(L: Level, v: np.ndarray, sweeps: int) -> np.ndarray:
+    """Multicolour block Gauss-Seidel from z = 0: per sweep, the cells of each colour in
+    ascending colour order take z_e += D_e^{-1} (v - A z)_e with the current z."""
+    rows, inv = L.blocks
+    z = np.zeros_like(v)
+    ncol = int(L.colors.max()) + 1
+    for _ in range(sweeps):
+        for c in range(ncol):
+            cells = np.flatnonzero(L.colors == c)
+            R = rows[cells]
+            r = v[R] - L.A.matvec(z)[R]
+            z[R] = z[R] + np.einsum("eij,ej->ei", inv[cells], r)
+    return z
+
+
 def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
     """z = M^{-1} v by Algorithm 2 (presmoothing form, eq. MGR-pre)."""
     if lvl == len(H.levels):
@@ -286,6 +361,8 @@ def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
         z = _block_jacobi(L, v)
         for _ in range(lp.global_sweeps - 1):
             z = z + lp.global_omega * _block_jacobi(L, v - A.matvec(z))
+    elif lp.global_smoother == "block_gs":
+        z = _block_gs(L, v, lp.global_sweeps)
     else:
         z = np.zeros_like(v)
     # F-relaxation: z <- z + Q M_FF^{-1} Q^T (v - A z)

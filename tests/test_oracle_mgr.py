@@ -254,6 +254,87 @@ def test_drop_tolerance_limits_and_nesting(seed):
         prev = kept
 
 
+def test_jp_coloring_by_hand():
+    """Jones-Plassmann rounds worked by hand: a path 0-1-2-3 with falling priorities colours
+    0, then 1 (beside colour 0), then 2, then 3: 0 1 0 1; a star whose centre has the lowest
+    priority colours the four leaves first (0) and the centre last (1); equal priorities
+    fall back to the larger index."""
+    path = (np.array([0, 1, 3, 5, 6]), np.array([1, 0, 2, 1, 3, 2]))
+    assert mgr.jp_coloring(*path, np.array([4, 3, 2, 1], dtype=np.uint64)).tolist() == [0, 1, 0, 1]
+    star = (np.array([0, 4, 5, 6, 7, 8]), np.array([1, 2, 3, 4, 0, 0, 0, 0]))
+    assert mgr.jp_coloring(*star, np.array([1, 5, 4, 3, 2], dtype=np.uint64)).tolist() == \
+        [1, 0, 0, 0, 0]
+    tri = (np.array([0, 1, 3, 4]), np.array([1, 0, 2, 1]))
+    assert mgr.jp_coloring(*tri, np.zeros(3, dtype=np.uint64)).tolist() == [0, 1, 0]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_jp_coloring_is_proper(seed):
+    """Every vertex gets a colour, no edge joins two of one colour, and at most
+    (largest degree + 1) colours are used, on random symmetric graphs."""
+    rng = np.random.default_rng(seed)
+    n = 300
+    Dg = rng.random((n, n)) < 0.03
+    Dg = np.triu(Dg, 1)
+    Dg = Dg | Dg.T
+    gptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(Dg.sum(1), out=gptr[1:])
+    gcol = np.nonzero(Dg)[1]
+    col = mgr.jp_coloring(gptr, gcol, mgr.cell_priorities(n))
+    assert np.all(col >= 0)
+    i, j = np.nonzero(Dg)
+    assert np.all(col[i] != col[j])
+    assert col.max() + 1 <= Dg.sum(1).max() + 1
+
+
+def _interleaved_block_system(rng, ncell, nb=2, dens=0.05):
+    """A block diagonally dominant matrix on ncell cells of nb interleaved unknowns with a
+    non-symmetric pattern, and its labels."""
+    n = ncell * nb
+    D = rng.standard_normal((n, n)) * (rng.random((n, n)) < dens)
+    for e in range(ncell):
+        r = slice(e * nb, (e + 1) * nb)
+        D[r, r] = rng.standard_normal((nb, nb)) + np.eye(nb) * (np.abs(D).sum(1).max() + 1.0)
+    labels = np.tile(np.arange(1, nb + 1, dtype=np.int8), ncell)
+    return D, labels
+
+
+def test_cell_graph_is_the_symmetrised_block_pattern():
+    rng = np.random.default_rng(7)
+    D, labels = _interleaved_block_system(rng, 40)
+    A = CSR.from_dense(D)
+    gptr, gcol = mgr.cell_graph(A, labels)
+    B = np.zeros((40, 40), dtype=bool)
+    for e in range(40):
+        for f in range(40):
+            B[e, f] = e != f and np.any(D[2 * e:2 * e + 2, 2 * f:2 * f + 2] != 0)
+    B = B | B.T
+    got = np.zeros_like(B)
+    for e in range(40):
+        got[e, gcol[gptr[e]:gptr[e + 1]]] = True
+    assert np.array_equal(got, B)
+
+
+def test_block_gs_sweep_equals_sequential_block_gauss_seidel():
+    """One multicolour sweep is textbook block Gauss-Seidel with the cells visited in
+    (colour, index) order; many sweeps converge to A^{-1} v."""
+    from types import SimpleNamespace
+    rng = np.random.default_rng(11)
+    ncell = 60
+    D, labels = _interleaved_block_system(rng, ncell, dens=0.04)
+    A = CSR.from_dense(D)
+    colors = mgr.jp_coloring(*mgr.cell_graph(A, labels), mgr.cell_priorities(ncell))
+    L = SimpleNamespace(A=A, blocks=mgr.same_cell_blocks(A, labels), colors=colors)
+    v = rng.standard_normal(2 * ncell)
+    z1 = mgr._block_gs(L, v, 1)
+    z = np.zeros_like(v)                                   # textbook form, cell by cell
+    for e in sorted(range(ncell), key=lambda e: (colors[e], e)):
+        r = slice(2 * e, 2 * e + 2)
+        z[r] = z[r] + np.linalg.solve(D[r, r], v[r] - D[r, :] @ z)
+    assert np.allclose(z1, z, rtol=1e-13, atol=1e-14)
+    assert np.allclose(mgr._block_gs(L, v, 60), np.linalg.solve(D, v), rtol=1e-10, atol=1e-12)
+
+
 def test_spgemm_pinned_order_by_hand():
     """Products are summed in ascending k from +0.0: (0 + 1e16) + 1 + (-1e16) = 0 in binary64
     (1e16 + 1 rounds back to 1e16), whereas summing the last two first would give 1."""
