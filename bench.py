@@ -9,6 +9,7 @@ pressure), FP32 hierarchy inside FP64 FGMRES(64).
 
     python bench.py [--steps K] [--warmup W] [--size 64] [--precision fp32|fp64]
                     [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
+                    [--global-smoother block_jacobi|block_gs] [--global-sweeps 3]
 
 Prints one JSON line.  The dominant kernel's duration is measured live with HIP events
 recorded on its own stream around every launch inside the timed steps.
@@ -130,6 +131,9 @@ def main():
     ap.add_argument("--size", type=int, default=None, help="cells per side (64 two, 96 three)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
+    ap.add_argument("--global-smoother", default="block_jacobi",
+                    choices=["block_jacobi", "block_gs"])
+    ap.add_argument("--global-sweeps", type=int, default=3)
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
     ap.add_argument("--restart", type=int, default=64)
@@ -161,6 +165,8 @@ def main():
     mk0 = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
 
     def mk(model, **kw):
+        if a.plan == "paper":
+            kw = dict(kw, global_smoother=a.global_smoother, global_sweeps=a.global_sweeps)
         opts = mk0(model, **kw)
         if a.drop_tol is not None:
             for L in opts.levels:
@@ -243,6 +249,7 @@ def main():
             "reduction": (WORKLOADS[a.workload][3] if a.plan == "paper"
                           else "saturations -> displacement -> pressure AMG"),
             "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
+            "global_smoother": f"{a.global_smoother} x{a.global_sweeps}",
             "dropping": ("N_max = 4 on the displacement level" if a.drop_tol is None
                          else f"tolerance {a.drop_tol} on the displacement level"),
             "rtol": 1e-6, "parallelism": "single GPU",

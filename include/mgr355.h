@@ -70,7 +70,7 @@ typedef struct {
 
 enum { MGR_INTERP_JACOBI = 0, MGR_INTERP_ZERO = 1 };
 enum { MGR_FRELAX_JACOBI = 0, MGR_FRELAX_AMG = 1, MGR_FRELAX_DENSE = 2 };
-enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1 };
+enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1, MGR_GSMOOTH_BLOCK_GS = 2 };
 enum { MGR_COARSE_AMG = 0, MGR_COARSE_DENSE = 1 };
 enum { MGR_COUPLING_FULL = 0, MGR_COUPLING_QUASI_IMPES = 1 };
 enum { MGR_PREC_FP64 = 0, MGR_PREC_FP32 = 1 };
@@ -88,7 +88,11 @@ typedef struct {
   int32_t frelax_block;        /* 1 scalar AMG, 3 nodal AMG with 3x3 block storage; the F
                                   rows must then come in consecutive triples with full
                                   3x3 block patterns                                     */
-  int32_t global_smoother;     /* MGR_GSMOOTH_*: block Jacobi over same-cell blocks, i.e.
+  int32_t global_smoother;     /* MGR_GSMOOTH_*: block Jacobi over same-cell blocks, or
+                                  multicolour block Gauss-Seidel over them (the hybrid
+                                  block Gauss-Seidel of the Sec. 5.3 remarks, cells
+                                  coloured by Jones-Plassmann rounds, sweeps in colour
+                                  order from z = 0; global_omega unused), i.e.
                                   rows of equal rank within their label; the level's rows
                                   must be interleaved cell by cell                       */
   int32_t global_sweeps;       /* default 1                                              */
@@ -334,7 +338,9 @@ enum {
                           (l = nlevels: the coarsest-grid AMG)                     CSR */
   MGR_X_AMG_P = 8,     /* AMG prolongator of level `sub`                           CSR */
   MGR_X_AMG_AGG = 9,   /* AMG aggregate id per node (-1: none)              int in col */
-  MGR_X_AMG_NLEV = 10  /* number of AMG levels in out[0]                               */
+  MGR_X_AMG_NLEV = 10, /* number of AMG levels in out[0]                               */
+  MGR_X_GS_COLOR = 11  /* colour of every same-cell block of level l (block
+                          Gauss-Seidel smoother)                            int in col */
 };
 /* Sizes of an object: out[0] = rows, out[1] = cols, out[2] = entries. [host out]
  * Requires opts.keep_setup = 1 for the CSR objects.  Errors: ARG. */

@@ -242,6 +242,14 @@ void trace(const std::string &msg);
 void set_last_error(const std::string &msg);
 // block-Jacobi inverses over consecutive nb x nb diagonal blocks (nb = 2 or 3)
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag);
+// multicolour block Gauss-Seidel (bgs.hip): colouring of the cells of nb interleaved rows
+// (color_ptr: host offsets per colour into `cells`; color: colour of every cell) and one
+// colour's update x_e += D_e^{-1} (b - A x)_e for its cells
+void bgs_setup(const Csr &A, int nb, std::vector<int> &color_ptr, DArr<int> &cells,
+               DArr<int> &color, hipStream_t s, int *dflag);
+template <class T>
+void bgs_color_sweep(const CsrV<T> &A, int nb, const int *cells, int ncells, const T *binv,
+                     const T *b, T *x, hipStream_t s);
 
 // ------------------------------------------------------------------------------------
 // apply kernels (apply.hip), T = float or double

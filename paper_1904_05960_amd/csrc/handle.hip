@@ -191,6 +191,8 @@ struct MgrLevel {
   Csr AF, AC;                // rows F and rows C of A_l (residuals of uncompacted levels)
   int nb_gs = 0;             // global smoother block size
   DArr<double> binv64;
+  std::vector<int> gs_ptr;   // block Gauss-Seidel: cells of colour c are gs_cells[ptr[c]..)
+  DArr<int> gs_cells, gs_color;
   Amg amg;                   // F-relaxation AMG
   DArr<double> ffinv64;      // dense F-relaxation inverse
   int nF = 0;
@@ -533,6 +535,14 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
       V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, r, (T)o.global_omega, z, true, s);
     }
     zero_z = false;
+  } else if (o.global_smoother == MGR_GSMOOTH_BLOCK_GS) {
+    const T *binv = Ptr<T>::of(L.tbinv);
+    V::fill(z, (T)0, n, s);
+    for (int sw = 0; sw < o.global_sweeps; ++sw)
+      for (size_t c = 0; c + 1 < L.gs_ptr.size(); ++c)
+        bgs_color_sweep<T>(A, L.nb_gs, L.gs_cells.p + L.gs_ptr[c], L.gs_ptr[c + 1] - L.gs_ptr[c],
+                           binv, v, z, s);
+    zero_z = false;
   }
   bool compactF = false;  // z_F held in eF, z otherwise untouched (z_C = 0)
   const T *dinvF = Ptr<T>::of(L.tdinvF);
@@ -754,7 +764,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       cast_values(L->ffinv64.p, L->tffinv, L->cf.nF * L->cf.nF, sz, s);
     }
     // global smoother
-    if (lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI) {
+    if (lo.global_smoother != MGR_GSMOOTH_NONE) {
       // rows interleaved cell by cell: labels periodic with the present labels distinct
       const int nb = __builtin_popcount(present);
       const bool ok = nb >= 2 && nb <= 3 && n % nb == 0 && labels_periodic(L->labels.p, n, nb, s) &&
@@ -765,6 +775,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       L->binv64.alloc(n * nb, s);
       block_diag_inverse(L->A, nb, L->binv64.p, s, flag);
       cast_values(L->binv64.p, L->tbinv, n * nb, sz, s);
+      if (lo.global_smoother == MGR_GSMOOTH_BLOCK_GS)
+        bgs_setup(L->A, nb, L->gs_ptr, L->gs_cells, L->gs_color, s, flag);
     }
     // apply copies and work vectors
     DArr<double> dinvF(L->cf.nF, s);
@@ -864,7 +876,7 @@ void validate_opts(const mgr_opts &o) {
     require(lo.interp == MGR_INTERP_JACOBI || lo.interp == MGR_INTERP_ZERO, MGR_ERR_ARG, "interp");
     require(lo.frelax >= 0 && lo.frelax <= 2, MGR_ERR_ARG, "frelax");
     require(lo.frelax_sweeps >= 1 && lo.frelax_sweeps <= 100, MGR_ERR_ARG, "frelax_sweeps");
-    require(lo.global_smoother == 0 || lo.global_smoother == 1, MGR_ERR_ARG, "global_smoother");
+    require(lo.global_smoother >= 0 && lo.global_smoother <= 2, MGR_ERR_ARG, "global_smoother");
     require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
     require(lo.coupling == MGR_COUPLING_FULL || lo.coupling == MGR_COUPLING_QUASI_IMPES, MGR_ERR_ARG,
             "coupling");
@@ -890,7 +902,8 @@ size_t handle_bytes(const mgr_handle *h) {
   for (auto &L : h->lv) {
     csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G); csr(L->AF); csr(L->AC);
     b += L->labels.bytes() + L->cf.F.bytes() + L->cf.C.bytes() + L->cf.map.bytes() +
-         L->dFF.bytes() + L->binv64.bytes() + L->ffinv64.bytes() + L->tA.bytes() +
+         L->dFF.bytes() + L->binv64.bytes() + L->gs_cells.bytes() + L->gs_color.bytes() +
+         L->ffinv64.bytes() + L->tA.bytes() +
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
          L->tAF.bytes() + L->tAC.bytes() +
          L->tffinv.bytes() + L->v.bytes() + L->z.bytes() + L->rF.bytes() + L->eF.bytes() +
@@ -1299,7 +1312,7 @@ mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t s
     const int nl = (int)h->lv.size();
     require(level >= 0 && level <= nl, MGR_ERR_ARG, "level out of range");
     const Amg *amg = nullptr;
-    if (what >= MGR_X_AMG_A) {
+    if (what >= MGR_X_AMG_A && what <= MGR_X_AMG_NLEV) {
       amg = level == nl ? &h->coarse_amg : &h->lv[level]->amg;
       require(!amg->lv.empty(), MGR_ERR_ARG, "no AMG hierarchy at this level");
       if (what == MGR_X_AMG_NLEV) { out[0] = (int64_t)amg->lv.size(); out[1] = out[2] = 0; return MGR_OK; }
@@ -1315,6 +1328,10 @@ mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t s
       case MGR_X_LEVEL_A: csr(level == nl ? h->coarseA : h->lv[level]->A); break;
       case MGR_X_F: out[0] = h->lv[level]->cf.nF; out[1] = 0; out[2] = out[0]; break;
       case MGR_X_C: out[0] = h->lv[level]->cf.nC; out[1] = 0; out[2] = out[0]; break;
+      case MGR_X_GS_COLOR:
+        require(h->lv[level]->gs_color.n > 0, MGR_ERR_ARG, "no block Gauss-Seidel at this level");
+        out[0] = (int64_t)h->lv[level]->gs_color.n; out[1] = 0; out[2] = out[0];
+        break;
       case MGR_X_WP: csr(h->lv[level]->Wp); break;
       case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
       case MGR_X_G: csr(h->lv[level]->G); break;
@@ -1353,11 +1370,14 @@ mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t 
       if (val && M.nnz)
         HIPCHK(hipMemcpyAsync(val, M.v.p, M.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
     };
-    const Amg *amg = (what >= MGR_X_AMG_A) ? (level == nl ? &h->coarse_amg : &h->lv[level]->amg) : nullptr;
+    const Amg *amg = (what >= MGR_X_AMG_A && what <= MGR_X_AMG_NLEV)
+                         ? (level == nl ? &h->coarse_amg : &h->lv[level]->amg)
+                         : nullptr;
     switch (what) {
       case MGR_X_LEVEL_A: csr(level == nl ? h->coarseA : h->lv[level]->A); break;
       case MGR_X_F: ints(h->lv[level]->cf.F.p, sz[0]); break;
       case MGR_X_C: ints(h->lv[level]->cf.C.p, sz[0]); break;
+      case MGR_X_GS_COLOR: ints(h->lv[level]->gs_color.p, sz[0]); break;
       case MGR_X_WP: csr(h->lv[level]->Wp); break;
       case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
       case MGR_X_G: csr(h->lv[level]->G); break;

@@ -22,12 +22,13 @@ STATUS_NAMES = {0: "OK", 1: "ARG", 2: "ALLOC", 3: "HIP", 4: "ZERO_PIVOT", 5: "NO
 
 INTERP = {"jacobi": 0, "zero": 1}
 FRELAX = {"jacobi": 0, "amg": 1, "dense": 2}
-GSMOOTH = {"none": 0, "block_jacobi": 1}
+GSMOOTH = {"none": 0, "block_jacobi": 1, "block_gs": 2}
 COARSE = {"amg": 0, "dense": 1}
 PREC = {"fp64": 0, "fp32": 1}
 COUPLING = {"full": 0, "quasi_impes": 1}
 
 X_LEVEL_A, X_F, X_C, X_WP, X_ACOR, X_G, X_COARSE, X_AMG_A, X_AMG_P, X_AMG_AGG, X_AMG_NLEV = range(11)
+X_GS_COLOR = 11
 MAX_LEVELS = 8
 
 
@@ -277,11 +278,13 @@ class Options:
 
 
 def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 3,
-               sat_nmax: int | None = None, **kw) -> Options:
+               sat_nmax: int | None = None, global_smoother: str = "block_jacobi",
+               **kw) -> Options:
     """Reduction order of Sec. 5.3: displacement first (one nodal AMG V-cycle, N_max = 4),
     then the saturations (Jacobi, Galerkin, with the global block smoother on the levels that
     hold only cell unknowns), pressure last (AMG).  `quasi_impes` uses the quasi-IMPES
-    coupling on the saturation levels; `global_sweeps` sets the block smoother's sweeps
+    coupling on the saturation levels; `global_smoother` is 'block_jacobi' or 'block_gs'
+    (multicolour block Gauss-Seidel); `global_sweeps` sets the block smoother's sweeps
     (three: the block-Jacobi sweeps stand in for the single, stronger ILU(1) step of
     Sec. 6); `sat_nmax` >= 0 applies the dropping operator on the saturation levels too.
     By default the two-phase saturation level is Galerkin (eq. coarse_grid_pressure); the
@@ -290,7 +293,7 @@ def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 3,
     distance-3 fill that makes the AMG setup several times slower and its V-cycle weaker."""
     if sat_nmax is None:
         sat_nmax = 4 if model == "three" else -1
-    sat = dict(nmax=sat_nmax, frelax="jacobi", global_smoother="block_jacobi",
+    sat = dict(nmax=sat_nmax, frelax="jacobi", global_smoother=global_smoother,
                global_sweeps=global_sweeps, coupling="quasi_impes" if quasi_impes else "full")
     if model == "biot1":
         levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3)]
@@ -356,7 +359,7 @@ class Preconditioner:
         import torch
         rows, cols, nnz = self.query(what, level, sub)
         dev = torch.device("cuda")
-        if what in (X_F, X_C, X_AMG_AGG):
+        if what in (X_F, X_C, X_AMG_AGG, X_GS_COLOR):
             col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
             _check(lib().mgr_export(self.h, what, level, sub, None, _ptr(col), None,
                                     _stream(stream)))

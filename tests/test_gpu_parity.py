@@ -62,6 +62,10 @@ CASES = [
      lambda: small_amg(tol_plan(0.05))),
     ("three_6x5x4_drop_tol", lambda: pm.three_phase(6, 5, 4, 3),
      lambda: small_amg(tol_plan(0.2, "three"))),
+    ("two_9x7x6_block_gs", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(m.paper_plan("two", global_smoother="block_gs", global_sweeps=2))),
+    ("three_6x5x4_block_gs", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(m.paper_plan("three", global_smoother="block_gs", global_sweeps=1))),
     ("channels_12x10x6_quasi_impes", lambda: pm.two_phase_channels(12, 10, 6, 2),
      lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
     ("three_6x5x4_quasi_impes", lambda: pm.three_phase(6, 5, 4, 3),
@@ -91,6 +95,9 @@ def compare_hierarchy(P, H: omgr.Hierarchy, tag):
         assert_csr_equal(P.export(m.X_G, l), L.G, f"{tag} G[{l}]")
         if L.amg is not None:
             compare_amg(P, l, L.amg, f"{tag} F-AMG[{l}]")
+        if L.colors is not None:
+            col = P.export(m.X_GS_COLOR, l)
+            assert np.array_equal(col, L.colors), f"{tag} block Gauss-Seidel colours[{l}]"
     nl = len(H.levels)
     assert_csr_equal(P.export(m.X_LEVEL_A, nl), H.coarse_A, f"{tag} coarse A")
     if H.coarse_amg is not None:
