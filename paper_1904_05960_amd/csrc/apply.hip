@@ -440,12 +440,26 @@ void VecOps<T>::interp(int64_t n, const int *map, const CsrV<T> &Wp, const T *eC
                                                    accumulate ? 1 : 0);
   KCHK();
 }
+// First l1-Jacobi sweep from zero and its residual: x = D^{-1} b in one pass, then
+// r = b - A x with one gather per entry (gathering d^{-1} and b at every entry costs twice
+// the gathers; the products and sums are the same)
+template <class T>
+__global__ void k_vmul(const T *__restrict__ a, const T *__restrict__ b, T *__restrict__ y,
+                       int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] * b[i];
+}
 template <class T>
 void VecOps<T>::l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r, hipStream_t s) {
-  if (A.rb)
-    launch_csr_stream<T, M_L1PRE>(A, nullptr, nullptr, b, dinv, nullptr, nullptr, r, x, 0, s);
-  else
+  if (A.rb) {
+    if (A.n > 0) {
+      k_vmul<T><<<grid_for(A.n, 256), 256, 0, s>>>(dinv, b, x, A.n);
+      KCHK();
+    }
+    launch_csr_stream<T, M_RESID>(A, x, x, b, nullptr, nullptr, nullptr, r, nullptr, 0, s);
+  } else {
     launch_csr<T, M_L1PRE>(A, A.n, nullptr, nullptr, nullptr, b, dinv, r, x, s);
+  }
 }
 template <class T>
 void VecOps<T>::l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,
@@ -462,7 +476,11 @@ void VecOps<T>::b_spmv(const Bsr3V<T> &A, const T *x, T *y, bool accumulate, hip
 }
 template <class T>
 void VecOps<T>::b_l1_pre(const Bsr3V<T> &A, const T *dinv, const T *b, T *x, T *r, hipStream_t s) {
-  launch_bsr3<T, M_L1PRE>(A, nullptr, b, dinv, r, x, s);
+  if (A.n > 0) {
+    k_vmul<T><<<grid_for(3 * A.n, 256), 256, 0, s>>>(dinv, b, x, 3 * A.n);
+    KCHK();
+  }
+  launch_bsr3<T, M_RESID>(A, x, b, nullptr, r, nullptr, s);
 }
 template <class T>
 void VecOps<T>::b_l1_post(const Bsr3V<T> &A, const T *dinv, const T *b, const T *x, T *y,
