@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(GJ_THREADS) k_gauss_jordan(double *__restrict_
     }
     const int p = s_idx[0];
     const double pv = s_val[0];
-    if (pv == 0.0 || !(pv == pv)) {
+    if (!(pv > 0.0)) {   // zero, or only NaN left in the column
       if (t == 0) s_fail = 1;
       __syncthreads();
       break;
@@ -93,6 +93,97 @@ __global__ void __launch_bounds__(GJ_THREADS) k_gauss_jordan(double *__restrict_
   }
 }
 
+// The same elimination for n <= GJ_LDS_N with the matrix held in LDS (rows padded to an odd
+// stride so that a column is read without bank conflicts): one pivot step is four barriers
+// and LDS traffic only; the pivot search is done by the first wavefront.
+constexpr int GJ_LDS_N = 128;
+__global__ void __launch_bounds__(GJ_THREADS) k_gauss_jordan_lds(double *__restrict__ A, int n,
+                                                                int *flag) {
+  __shared__ double sA[GJ_LDS_N * (GJ_LDS_N + 1)];
+  __shared__ double s_colk[GJ_LDS_N];
+  __shared__ int s_piv[GJ_LDS_N];
+  __shared__ int s_p;
+  __shared__ double s_pv;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  constexpr int NW = GJ_THREADS / 64;
+  const int ld = n | 1;
+  for (int i = w; i < n; i += NW)
+    for (int j = lane; j < n; j += 64) sA[i * ld + j] = A[(int64_t)i * n + j];
+  __syncthreads();
+  bool fail = false;
+  for (int k = 0; k < n; ++k) {
+    if (w == 0) {   // first row of largest |a| in column k
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        const double a = fabs(sA[i * ld + k]);
+        if (a > best) { best = a; bi = i; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        s_p = bi;
+        s_pv = best;
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    const double pv = s_pv;
+    if (!(pv > 0.0)) {   // zero, or only NaN left in the column
+      fail = true;
+      break;
+    }
+    if (t == 0) s_piv[k] = p;
+    if (p != k && t < n) {
+      const double x = sA[k * ld + t];
+      sA[k * ld + t] = sA[p * ld + t];
+      sA[p * ld + t] = x;
+    }
+    __syncthreads();
+    const double pivot = sA[k * ld + k];
+    double rk = 0.0, ck = 0.0;
+    if (t < n) {
+      rk = (t == k ? 1.0 : sA[k * ld + t]) / pivot;
+      ck = sA[t * ld + k];
+    }
+    __syncthreads();
+    if (t < n) {
+      sA[k * ld + t] = rk;
+      s_colk[t] = ck;
+    }
+    __syncthreads();
+    for (int i = w; i < n; i += NW) {
+      if (i == k) continue;
+      const double ci = s_colk[i];
+      for (int j = lane; j < n; j += 64) {
+        const double base = (j == k) ? 0.0 : sA[i * ld + j];
+        sA[i * ld + j] = base - ci * sA[k * ld + j];
+      }
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) atomicOr(flag, FLAG_ZERO_PIVOT);
+    return;
+  }
+  // undo the interchanges: columns k and piv[k], last step first
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = s_piv[k];
+    if (p != k && t < n) {
+      const double x = sA[t * ld + k];
+      sA[t * ld + k] = sA[t * ld + p];
+      sA[t * ld + p] = x;
+    }
+    __syncthreads();
+  }
+  for (int i = w; i < n; i += NW)
+    for (int j = lane; j < n; j += 64) A[(int64_t)i * n + j] = sA[i * ld + j];
+}
+
 }  // namespace
 
 void csr_to_dense(const Csr &A, double *D, hipStream_t s) {
@@ -105,10 +196,15 @@ void csr_to_dense(const Csr &A, double *D, hipStream_t s) {
 void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s) {
   require(n >= 1 && n <= 4096, MGR_ERR_UNSUPPORTED, "dense solve limited to 4096 unknowns");
   HIPCHK(hipMemcpyAsync(Inv, D, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  DArr<int> piv(n, s);
-  DArr<double> colk(n, s);
-  k_gauss_jordan<<<1, GJ_THREADS, 0, s>>>(Inv, n, piv.p, colk.p, dflag);
-  KCHK();
+  if (n <= GJ_LDS_N) {
+    k_gauss_jordan_lds<<<1, GJ_THREADS, 0, s>>>(Inv, n, dflag);
+    KCHK();
+  } else {
+    DArr<int> piv(n, s);
+    DArr<double> colk(n, s);
+    k_gauss_jordan<<<1, GJ_THREADS, 0, s>>>(Inv, n, piv.p, colk.p, dflag);
+    KCHK();
+  }
   check_flags(dflag, s, "dense inverse");
 }
 

@@ -112,13 +112,16 @@ void dfree(void *p, hipStream_t s) {
   g_cached_bytes += bin;
 }
 
+// lines of the setup's second host thread (the F-relaxation AMG) carry the tag "F"
+thread_local const char *t_trace_tag = " ";
+
 void trace(const std::string &msg) {
   static const bool on = std::getenv("MGR355_TRACE") != nullptr;
   if (!on) return;
   static auto t0 = std::chrono::steady_clock::now();
   const double ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  std::fprintf(stderr, "[mgr355 %10.3f ms] %s\n", ms, msg.c_str());
+  std::fprintf(stderr, "[mgr355 %10.3f ms %s] %s\n", ms, t_trace_tag, msg.c_str());
 }
 
 // ===================================================================================
@@ -709,6 +712,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       job->th = std::thread([J, bs, dev, ev, s2, o, A = std::move(Aff)]() mutable {
         try {
           HIPCHK(hipSetDevice(dev));
+          t_trace_tag = "F";
           HIPCHK(hipStreamWaitEvent(s2, ev, 0));
           DArr<int> f2(1, s2);
           clear_flag(f2.p, s2);

@@ -325,14 +325,32 @@ __global__ void k_transpose_scatter(int64_t n, const int *__restrict__ rp,
     if (tmp_v) tmp_v[pos] = v[e];
   }
 }
-// keys are unique within a row: the output position of an entry is its rank
-__global__ void k_rank_sort_rows(int64_t n, const int *__restrict__ rp,
-                                 const int *__restrict__ tk, const double *__restrict__ tv,
-                                 int *__restrict__ ok, double *__restrict__ ov) {
+// keys are unique within a row: the output position of an entry is its rank.  One
+// wavefront per row; rows of up to RS_LDS keys are compared from LDS.
+constexpr int RS_LDS = 2048;
+__global__ void __launch_bounds__(64) k_rank_sort_rows(int64_t n, const int *__restrict__ rp,
+                                                       const int *__restrict__ tk,
+                                                       const double *__restrict__ tv,
+                                                       int *__restrict__ ok,
+                                                       double *__restrict__ ov) {
+  __shared__ int sk[RS_LDS];
   const int64_t row = blockIdx.x;
   if (row >= n) return;
   const int s = rp[row], m = rp[row + 1] - s;
-  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+  if (m <= RS_LDS) {
+    for (int t = threadIdx.x; t < m; t += 64) sk[t] = tk[s + t];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int t = threadIdx.x; t < m; t += 64) {
+      const int key = sk[t];
+      int rank = 0;
+      for (int u = 0; u < m; ++u) rank += sk[u] < key;
+      ok[s + rank] = key;
+      if (tv) ov[s + rank] = tv[s + t];
+    }
+    return;
+  }
+  for (int t = threadIdx.x; t < m; t += 64) {
     const int key = tk[s + t];
     int rank = 0;
     for (int u = 0; u < m; ++u) rank += tk[s + u] < key;

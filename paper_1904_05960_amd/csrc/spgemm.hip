@@ -381,10 +381,12 @@ __global__ void k_max_ub(int nrows, const int *__restrict__ rows, const int64_t 
 }
 
 // Products with few output columns (coarse AMG levels, m <= DMAX): the row is accumulated
-// in a dense LDS array indexed by column instead of a hash table; one 64-lane workgroup per
-// row, lanes over the entries of the selected row of B, a barrier between consecutive k
-// (the same pinned order), then the flagged columns are written in ascending order.
-constexpr int DMAX = 8192;   // largest dense row: 96 KB of LDS per workgroup
+// in a dense LDS array indexed by column instead of a hash table; one 64-lane workgroup (one
+// wavefront) per row.  Symbolic: a bit per column, the products walked flat as in sym_row.
+// Numeric: the entries of the row of A are read 64 at a time, then PF steps at a time the
+// selected rows of B are loaded into registers before they are added in ascending k (the
+// same pinned order); the flagged columns are written in ascending order.
+constexpr int DMAX = 8192;   // largest dense row: 72 KB of LDS per workgroup
 
 template <int DM>
 __global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *__restrict__ arp,
@@ -392,17 +394,61 @@ __global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *_
                                                   const int *__restrict__ brp,
                                                   const int *__restrict__ bci,
                                                   int *__restrict__ cnt) {
-  __shared__ int flag[DM];
+  __shared__ unsigned bits[DM / 32];
+  __shared__ int s_excl[64], s_start[64];
   const int64_t row = blockIdx.x;
   if (row >= n) return;
   const int l = threadIdx.x;
-  for (int j = l; j < m; j += 64) flag[j] = 0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int w = l; w < (m + 31) / 32; w += 64) bits[w] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   int c = 0;
-  for (int e = arp[row]; e < arp[row + 1]; ++e) {
-    const int k = aci[e];
-    for (int q = brp[k] + l; q < brp[k + 1]; q += 64) c += atomicExch(&flag[bci[q]], 1) == 0;
+  const int as = arp[row], ae = arp[row + 1];
+  for (int c0 = as; c0 < ae; c0 += 64) {
+    const int e = c0 + l;
+    int len = 0, st = 0;
+    if (e < ae) {
+      const int k = aci[e];
+      st = brp[k];
+      len = brp[k + 1] - st;
+    }
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(inc, o, 64);
+      if (l >= o) inc += t;
+    }
+    s_excl[l] = inc - len;
+    s_start[l] = st;
+    const int total = __shfl(inc, 63, 64);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int nent = min(64, ae - c0);
+    constexpr int PU = 4;
+    for (int p0 = 0; p0 < total; p0 += PU * 64) {
+      int jj[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int p = p0 + u * 64 + l;
+        jj[u] = -1;
+        if (p < total) {
+          int lo = 0, hi = nent - 1;        // entry t with s_excl[t] <= p < s_excl[t+1]
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_excl[mid] <= p) lo = mid; else hi = mid - 1;
+          }
+          jj[u] = bci[s_start[lo] + (p - s_excl[lo])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        if (jj[u] < 0) continue;
+        const unsigned bit = 1u << (jj[u] & 31);
+        c += (atomicOr(&bits[jj[u] >> 5], bit) & bit) == 0u;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -420,7 +466,7 @@ __global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *_
                                                   int *__restrict__ cci, double *__restrict__ cv,
                                                   int *flagp) {
   __shared__ double acc[DM];
-  __shared__ int flag[DM];
+  __shared__ unsigned char flag[DM];
   const int64_t row = blockIdx.x;
   if (row >= n) return;
   const int l = threadIdx.x;
@@ -428,18 +474,53 @@ __global__ void __launch_bounds__(64) k_num_dense(int64_t n, int m, const int *_
     acc[j] = 0.0;
     flag[j] = 0;
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int e = arp[row]; e < arp[row + 1]; ++e) {      // ascending k
-    const int k = aci[e];
-    const double a = av[e];
-    for (int q = brp[k] + l; q < brp[k + 1]; q += 64) {  // distinct columns per step
-      const int j = bci[q];
-      acc[j] = __dadd_rn(acc[j], __dmul_rn(a, bv[q]));
-      flag[j] = 1;
+  const int as = arp[row], ae = arp[row + 1];
+  for (int c0 = as; c0 < ae; c0 += 64) {
+    const int e = c0 + l;
+    int k = 0, b0 = 0, b1 = 0;
+    double a = 0.0;
+    if (e < ae) {
+      k = aci[e];
+      a = av[e];
+      b0 = brp[k];
+      b1 = brp[k + 1];
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(64, ae - c0);
+    constexpr int PF = 8;
+    for (int t0 = 0; t0 < cnt; t0 += PF) {
+      int jj[PF], qa[PF], qb[PF];
+      double bb[PF], at[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int tt = (t0 + u < cnt) ? t0 + u : 0;
+        at[u] = __shfl(a, tt, 64);
+        qa[u] = __shfl(b0, tt, 64);
+        qb[u] = (t0 + u < cnt) ? __shfl(b1, tt, 64) : qa[u];
+        const int q = qa[u] + l;
+        const bool ok = q < qb[u];
+        jj[u] = ok ? bci[q] : -1;
+        bb[u] = ok ? bv[q] : 0.0;
+      }
+      // ascending k; the columns of one step are distinct
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (t0 + u < cnt) {
+          if (jj[u] >= 0) {
+            acc[jj[u]] = __dadd_rn(acc[jj[u]], __dmul_rn(at[u], bb[u]));
+            flag[jj[u]] = 1;
+          }
+          for (int q = qa[u] + 64 + l; q < qb[u]; q += 64) {   // rows of B longer than 64
+            const int j = bci[q];
+            acc[j] = __dadd_rn(acc[j], __dmul_rn(at[u], bv[q]));
+            flag[j] = 1;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
   }
   int o = crp[row];
   const int end = crp[row + 1];
@@ -602,7 +683,9 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
     DArr<int> cnt(n + 1, s);
     const int mm = (int)B.m;
 #define DSYM(DM) k_sym_dense<DM><<<(unsigned)n, 64, 0, s>>>(n, mm, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt.p)
-    if (mm <= 2048) DSYM(2048);
+    if (mm <= 128) DSYM(128);
+    else if (mm <= 512) DSYM(512);
+    else if (mm <= 2048) DSYM(2048);
     else if (mm <= 4096) DSYM(4096);
     else DSYM(DMAX);
 #undef DSYM
@@ -614,7 +697,9 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
 #define DNUM(DM)                                                                           \
   k_num_dense<DM><<<(unsigned)n, 64, 0, s>>>(n, mm, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, \
                                              B.v.p, C.rp.p, C.ci.p, C.v.p, dflag)
-      if (mm <= 2048) DNUM(2048);
+      if (mm <= 128) DNUM(128);
+      else if (mm <= 512) DNUM(512);
+      else if (mm <= 2048) DNUM(2048);
       else if (mm <= 4096) DNUM(4096);
       else DNUM(DMAX);
 #undef DNUM

@@ -52,9 +52,25 @@ def test_spgemm_pinned_order_cancellation():
     assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
 
 
+def test_spgemm_dense_accumulator_pinned_order():
+    # 70 products into one column (the dense-accumulator path, two chunks of the row of A):
+    # in ascending k every +1 is absorbed by 1e16 and the sum is exactly 0; another order
+    # would leave some of the ones
+    A = CSR([0, 70], list(range(70)), [1.0] * 70, (1, 70))
+    B = CSR(list(range(71)), [0] * 70, [1e16] + [1.0] * 68 + [-1e16], (70, 1))
+    exp = spgemm(A, B)
+    assert exp.data.tolist() == [0.0]
+    got = m.spgemm(dev(A), dev(B))
+    assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
+
+
 @pytest.mark.parametrize("case", [
     # (rows, inner, cols, density of A, density of B): which accumulation the product takes
-    ("dense accumulator, 2048-column table", 200, 500, 0.08, 300, 0.03),
+    ("dense accumulator, 128-column table, rows of A beyond 64 entries", 150, 400, 0.2, 100,
+     0.05),
+    ("dense accumulator, 512-column table", 200, 500, 0.08, 300, 0.03),
+    ("dense accumulator, rows of B beyond 64 entries", 30, 200, 0.3, 1000, 0.1),
+    ("dense accumulator, 4096-column table", 40, 1000, 0.1, 3000, 0.01),
     ("dense accumulator, 8192-column table", 40, 3000, 0.5, 6000, 0.002),
     ("LDS hash tables of 2048 and 4096 slots", 64, 2000, None, 30000, None),
     ("symbolic and numeric tables in global memory", 12, 4000, 0.8, 50000, 0.00025),
@@ -134,10 +150,15 @@ def test_spgemm_b3_rejects_partial_blocks():
         m.spgemm_b3(dev(A), dev(B))
 
 
-def test_transpose_random():
-    rng = np.random.default_rng(4)
-    A = rand_csr(rng, 333, 129, 0.05)
-    assert_csr_equal(m.transpose(dev(A)), transpose(A), "transpose")
+@pytest.mark.parametrize("shape", [
+    # (rows, cols, density): rows of the transpose of ~17, ~500 and 3000 entries (the last
+    # beyond the 2048 keys ranked from LDS)
+    (333, 129, 0.05), (1000, 50, 0.5), (3000, 4, 1.0)])
+def test_transpose_random(shape):
+    n, k, dens = shape
+    rng = np.random.default_rng(4 + n)
+    A = rand_csr(rng, n, k, dens)
+    assert_csr_equal(m.transpose(dev(A)), transpose(A), f"transpose {shape}")
 
 
 @pytest.mark.parametrize("nmax", [-1, 0, 1, 4])
