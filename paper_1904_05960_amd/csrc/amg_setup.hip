@@ -152,10 +152,14 @@ __global__ void k_remove(int64_t n, const int *__restrict__ near, int8_t *__rest
                          int *__restrict__ und) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  bool left = false;
   if (state[i] == UNDECIDED) {
     if (near[i]) state[i] = REMOVED;
-    else atomicAdd(und, 1);
+    else left = true;
   }
+  // one counter update per wavefront
+  const unsigned long long w = __ballot(left);
+  if (w && (int)(threadIdx.x & 63) == __ffsll((long long)w) - 1) atomicAdd(und, __popcll(w));
 }
 
 __global__ void k_is_state(int64_t n, const int8_t *__restrict__ state, int8_t s,

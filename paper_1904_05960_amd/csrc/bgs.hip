@@ -190,8 +190,7 @@ void bgs_setup(const Csr &A, int nb, std::vector<int> &color_ptr, DArr<int> &cel
   k_color_count<<<grid_for(ncell, 256), 256, 0, s>>>(ncell, color.p, cnt.p);
   KCHK();
   int hc[64];
-  HIPCHK(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(hc, cnt.p, sizeof(hc), s);
   int ncol = 0;
   for (int c = 0; c < 64; ++c)
     if (hc[c] > 0) ncol = c + 1;

@@ -141,6 +141,7 @@ void rowptr32_to_64(const int *in, int64_t *out, int64_t n1, hipStream_t s);
 void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 int read_flag(const int *dflag, hipStream_t s);      // synchronises
 void *pinned_scratch();                               // 256 pinned host bytes per thread
+void d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s);  // <= 256 bytes, waits
 void clear_flag(int *dflag, hipStream_t s);
 // throws the error that the raised device flags describe (synchronises)
 void check_flags(const int *dflag, hipStream_t s, const char *where);

@@ -677,8 +677,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     L->nF = (int)L->cf.nF;
     {
       int last = -1;
-      HIPCHK(hipMemcpyAsync(&last, L->cf.F.p + L->cf.nF - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      d2h_sync(&last, L->cf.F.p + L->cf.nF - 1, sizeof(int), s);
       L->f_prefix = last == L->cf.nF - 1;
     }
     const int64_t nC = L->cf.nC;

@@ -1,4 +1,6 @@
 // Device primitives: exclusive scans, reductions, fills, casts, streaming copy.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace mgr {
@@ -101,10 +103,9 @@ int64_t scan_generic(const T *in, T *out, int64_t n, hipStream_t s) {
   k_tile_scan<T><<<ntiles, SCAN_BLOCK, 0, s>>>(in, out, n, sums.p);
   KCHK();
   // the true total in 64 bits (the output type may be narrower)
-  int64_t *h = static_cast<int64_t *>(pinned_scratch());
-  HIPCHK(hipMemcpyAsync(h, sums.p + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return *h;
+  int64_t h = 0;
+  d2h_sync(&h, sums.p + ntiles, sizeof(int64_t), s);
+  return h;
 }
 
 template <class T>
@@ -148,8 +149,7 @@ T reduce_generic(const T *p, int64_t n, T init, Op op, hipStream_t s) {
   k_reduce<T, Op><<<1, 256, 0, s>>>(part.p, blocks, init, fin.p, op);
   KCHK();
   T h;
-  HIPCHK(hipMemcpyAsync(&h, fin.p, sizeof(T), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(&h, fin.p, sizeof(T), s);
   return h;
 }
 
@@ -276,18 +276,71 @@ void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
     KCHK();
   }
 }
-// small pinned host buffer for scalar reads (one per thread)
+// small pinned host buffer for the scalar reads of a solve loop (one per calling thread)
 void *pinned_scratch() {
   thread_local void *buf = nullptr;
   if (!buf) HIPCHK(hipHostMalloc(&buf, 256, hipHostMallocDefault));
   return buf;
 }
 
+// Reads of a few bytes that the host needs before it can go on (sizes, counts, flags: the
+// setup makes a few hundred of them, one after another).  The copy lands in a pinned buffer
+// taken from a pool shared by all host threads (the setup's helper threads come and go),
+// and the host polls the copy's completion event instead of blocking in the runtime: a
+// blocking wait is woken some tens of microseconds after the GPU is done, a poll within a
+// few.
+namespace {
+struct PinnedRead {
+  void *p = nullptr;
+  hipEvent_t ev = nullptr;
+  int dev = -1;
+};
+std::mutex g_pin_mu;
+std::vector<PinnedRead> g_pin_pool;   // kept until the process ends
+}  // namespace
+
+void d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  require(bytes <= 256, MGR_ERR_ARG, "d2h_sync: at most 256 bytes");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  PinnedRead b;
+  {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    for (size_t i = 0; i < g_pin_pool.size(); ++i)
+      if (g_pin_pool[i].dev == dev) {
+        b = g_pin_pool[i];
+        g_pin_pool[i] = g_pin_pool.back();
+        g_pin_pool.pop_back();
+        break;
+      }
+  }
+  struct Back {
+    PinnedRead &b;
+    ~Back() {
+      if (!b.p) return;
+      std::lock_guard<std::mutex> g(g_pin_mu);
+      g_pin_pool.push_back(b);
+    }
+  } back{b};
+  if (!b.p) {
+    b.dev = dev;
+    HIPCHK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    HIPCHK(hipHostMalloc(&b.p, 256, hipHostMallocDefault));
+  }
+  HIPCHK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(b.ev, s));
+  for (;;) {
+    const hipError_t e = hipEventQuery(b.ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) HIPCHK(e);
+  }
+  std::memcpy(dst, b.p, bytes);
+}
+
 int read_flag(const int *dflag, hipStream_t s) {
-  int *h = static_cast<int *>(pinned_scratch());
-  HIPCHK(hipMemcpyAsync(h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return *h;
+  int h = 0;
+  d2h_sync(&h, dflag, sizeof(int), s);
+  return h;
 }
 void clear_flag(int *dflag, hipStream_t s) { fill<int>(dflag, 0, 1, s); }
 

@@ -562,8 +562,7 @@ uint32_t label_mask(const int8_t *labels, int64_t n, hipStream_t s) {
     KCHK();
   }
   int h[2];
-  HIPCHK(hipMemcpyAsync(h, buf.p, sizeof(h), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(h, buf.p, sizeof(h), s);
   require(h[1] == 0, MGR_ERR_ARG, "labels must lie in [0, 7]");
   return (uint32_t)h[0];
 }
@@ -850,8 +849,7 @@ uint64_t pattern_hash(const Csr &A, hipStream_t s) {
     KCHK();
   }
   unsigned long long r = 0;
-  HIPCHK(hipMemcpyAsync(&r, h.p, sizeof(r), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(&r, h.p, sizeof(r), s);
   return r;
 }
 

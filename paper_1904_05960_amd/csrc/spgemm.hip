@@ -644,8 +644,7 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
       k_max_ub<<<grid_for(hretry2, 256), 256, 0, s>>>(hretry2, retry2.p, ub.p, mub.p);
       KCHK();
       unsigned long long hm = 0;
-      HIPCHK(hipMemcpyAsync(&hm, mub.p, sizeof(hm), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      d2h_sync(&hm, mub.p, sizeof(hm), s);
       const int64_t cap = std::min<int64_t>((int64_t)hm, bm);
       const int64_t ht = next_pow2(2 * std::max<int64_t>(cap, 32));
       require(ht <= (int64_t)1 << 22, MGR_ERR_UNSUPPORTED,
@@ -718,8 +717,7 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   k_bucket_s<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
   KCHK();
   int hc[NBS];
-  HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(hc, counts.p, sizeof(hc), s);
   const int g0 = lanes_for(meanB);
   for (int b = 0; b < NBS - 1; ++b)
     if (hc[b] > 0) dispatch_num(b, g0, hc[b], lists.p + (size_t)b * n, A, B, C, dflag, s);
@@ -1033,8 +1031,7 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
                                                 counts.p, n);
   KCHK();
   int hc[NBUCKET];
-  HIPCHK(hipMemcpyAsync(hc, counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  d2h_sync(hc, counts.p, sizeof(hc), s);
   if (hc[0] > 0) launch_num_b3<16, 64>(diagb, hc[0], lists.p, A, B, C, dflag, s);
   if (hc[1] > 0) launch_num_b3<32, 128>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
   if (hc[2] > 0) launch_num_b3<64, 256>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
