@@ -39,6 +39,8 @@ std::map<CacheKey, std::vector<void *>> g_cache;  // free blocks
 std::map<void *, size_t> g_live;                  // block -> bin size
 size_t g_cached_bytes = 0;
 size_t g_live_bytes = 0, g_peak_bytes = 0;        // bytes handed out (hook-less path)
+long g_misses = 0;                                // hipMalloc calls (for the setup trace)
+double g_miss_us = 0.0;
 
 size_t bin_of(size_t bytes) {
   if (bytes <= 512) return 512;
@@ -80,7 +82,10 @@ void *dalloc(size_t bytes, hipStream_t s) {
     return p;
   }
   void *p = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
   hipError_t e = hipMalloc(&p, bin);
+  ++g_misses;
+  g_miss_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   if (e != hipSuccess) {
     (void)hipGetLastError();
     (void)hipDeviceSynchronize();
@@ -866,7 +871,17 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   }
   HIPCHK(hipStreamSynchronize(s));
   check_flags(flag, s, "setup");
-  trace("setup done");
+  {
+    long misses;
+    double us;
+    {
+      std::lock_guard<std::mutex> g(g_cache_mu);
+      misses = g_misses;
+      us = g_miss_us;
+    }
+    trace("setup done (allocator: " + std::to_string(misses) + " hipMalloc calls so far, " +
+          std::to_string(us / 1000.0) + " ms)");
+  }
 }
 
 void validate_opts(const mgr_opts &o) {

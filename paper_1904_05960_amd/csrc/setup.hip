@@ -262,17 +262,18 @@ __global__ void k_drop_tol(int64_t n, const int *__restrict__ brp, const int *__
   }
 }
 
-// two-pointer merge of row `row` of A with the kept entries of row `row` of B; MODE 0
-// counts, MODE 1 writes columns (and values when sv != null)
+// Merge of row `row` of A with the kept entries of row `row` of B (S = A - w B, see
+// merge_drop); MODE 0 counts, MODE 1 writes columns (and values when sv != null).
+// Two-pointer form, for rows longer than the LDS staging below.
 template <int MODE>
-__global__ void k_merge_rows(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
-                             const double *__restrict__ av, const int *__restrict__ brp,
-                             const int *__restrict__ bci, const double *__restrict__ bv,
-                             const unsigned char *__restrict__ keep, const double *__restrict__ w,
-                             int *__restrict__ cnt, const int *__restrict__ srp,
-                             int *__restrict__ sci, double *__restrict__ sv) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (row >= n) return;
+__device__ void merge_row_serial(int64_t row, const int *__restrict__ arp,
+                                 const int *__restrict__ aci, const double *__restrict__ av,
+                                 const int *__restrict__ brp, const int *__restrict__ bci,
+                                 const double *__restrict__ bv,
+                                 const unsigned char *__restrict__ keep,
+                                 const double *__restrict__ w, int *__restrict__ cnt,
+                                 const int *__restrict__ srp, int *__restrict__ sci,
+                                 double *__restrict__ sv) {
   int pa = arp ? arp[row] : 0;
   const int ea = arp ? arp[row + 1] : 0;
   int pb = brp[row];
@@ -306,19 +307,124 @@ __global__ void k_merge_rows(int64_t n, const int *__restrict__ arp, const int *
   if (!MODE) cnt[row] = c;
 }
 
+// The same merge by G lanes per row with both rows staged in LDS (up to 8 G entries each).
+// An entry's output position is its rank in the union: an entry of A is preceded by the
+// entries of A before it and by the entries of B that are kept, not in A and of smaller
+// column; a kept entry of B that is not in A, by the entries of A of smaller column and
+// those entries of B before it (ob: prefix count over B).  The values are formed exactly as
+// in the two-pointer form.
+template <int MODE, int G>
+__global__ void __launch_bounds__(256) k_merge_rows(int64_t n, const int *__restrict__ arp,
+                                                    const int *__restrict__ aci,
+                                                    const double *__restrict__ av,
+                                                    const int *__restrict__ brp,
+                                                    const int *__restrict__ bci,
+                                                    const double *__restrict__ bv,
+                                                    const unsigned char *__restrict__ keep,
+                                                    const double *__restrict__ w,
+                                                    int *__restrict__ cnt,
+                                                    const int *__restrict__ srp,
+                                                    int *__restrict__ sci,
+                                                    double *__restrict__ sv) {
+  constexpr int RPB = 256 / G, MCAP = 8 * G;
+  __shared__ int s_a[RPB][MCAP], s_b[RPB][MCAP], s_ob[RPB][MCAP + 1];
+  const int g = threadIdx.x / G, l = threadIdx.x & (G - 1);
+  const int64_t row = blockIdx.x * (int64_t)RPB + g;
+  if (row >= n) return;   // whole groups leave; the groups never wait for each other
+  const int a0 = arp ? arp[row] : 0, la = arp ? arp[row + 1] - a0 : 0;
+  const int b0 = brp[row], lb = brp[row + 1] - b0;
+  if (la > MCAP || lb > MCAP) {
+    if (l == 0)
+      merge_row_serial<MODE>(row, arp, aci, av, brp, bci, bv, keep, w, cnt, srp, sci, sv);
+    return;
+  }
+  int *sa = s_a[g], *sb = s_b[g], *ob = s_ob[g];
+  for (int t = l; t < la; t += G) sa[t] = aci[a0 + t];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // columns of B, and ob[t] = number of kept entries of B before t whose column is not in A
+  int carry = 0;
+  for (int t0 = 0; t0 < lb; t0 += G) {
+    const int t = t0 + l;
+    int only = 0;
+    if (t < lb) {
+      const int cb = bci[b0 + t];
+      sb[t] = cb;
+      if (!keep || keep[b0 + t]) {
+        int lo = 0, hi = la;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (sa[mid] < cb) lo = mid + 1; else hi = mid;
+        }
+        only = !(lo < la && sa[lo] == cb);
+      }
+    }
+    int inc = only;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int y = __shfl_up(inc, o, G);
+      if (l >= o) inc += y;
+    }
+    if (t < lb) ob[t] = carry + inc - only;
+    carry += __shfl(inc, G - 1, G);
+  }
+  if (l == 0) ob[lb] = carry;
+  if (!MODE) {
+    if (l == 0) cnt[row] = la + carry;
+    return;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const double wr = w ? w[row] : 1.0;
+  const int obase = srp[row];
+  for (int t = l; t < la; t += G) {
+    const int ca = sa[t];
+    int lo = 0, hi = lb;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sb[mid] < ca) lo = mid + 1; else hi = mid;
+    }
+    const int pos = obase + t + ob[lo];
+    sci[pos] = ca;
+    if (sv) {
+      if (lo < lb && sb[lo] == ca && (!keep || keep[b0 + lo])) {
+        const double b = w ? __dmul_rn(wr, bv[b0 + lo]) : bv[b0 + lo];
+        sv[pos] = __dsub_rn(av[a0 + t], b);
+      } else {
+        sv[pos] = av[a0 + t];
+      }
+    }
+  }
+  for (int t = l; t < lb; t += G) {
+    if (ob[t + 1] == ob[t]) continue;   // dropped, or merged into an entry of A
+    const int cb = sb[t];
+    int lo = 0, hi = la;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sa[mid] < cb) lo = mid + 1; else hi = mid;
+    }
+    const int pos = obase + lo + ob[t];
+    sci[pos] = cb;
+    if (sv) sv[pos] = -(w ? __dmul_rn(wr, bv[b0 + t]) : bv[b0 + t]);
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // transpose: column counts, scatter, per-row ordering by source row
 __global__ void k_col_count(int64_t nnz, const int *__restrict__ ci, int *__restrict__ cnt) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
 }
+// 16 lanes per source row; the order of the entries within a row of the transpose is
+// fixed afterwards by k_rank_sort_rows
 __global__ void k_transpose_scatter(int64_t n, const int *__restrict__ rp,
                                     const int *__restrict__ ci, const double *__restrict__ v,
                                     const int *__restrict__ trp, int *__restrict__ fillpos,
                                     int *__restrict__ tmp_r, double *__restrict__ tmp_v) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 16;
+  const int l = threadIdx.x & 15;
   if (i >= n) return;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+  for (int e = rp[i] + l; e < rp[i + 1]; e += 16) {
     const int c = ci[e];
     const int pos = trp[c] + atomicAdd(&fillpos[c], 1);
     tmp_r[pos] = (int)i;
@@ -716,21 +822,32 @@ void merge_drop(const Csr &A, const Csr &B, const double *w, int nmax, const int
   }
   const int *arp = A.n ? A.rp.p : nullptr;
   const unsigned char *kp = keep.p;
+  // 16 lanes per row for short rows, 32 for longer ones
+  const bool wide = n > 0 && (double)(A.nnz + B.nnz) > 24.0 * (double)n;
+#define MERGE(MODE, G, ...)                                                           \
+  k_merge_rows<MODE, G><<<(unsigned)((n + 256 / G - 1) / (256 / G)), 256, 0, s>>>(__VA_ARGS__)
   if (n > 0) {
-    k_merge_rows<0><<<grid_for(n, 256), 256, 0, s>>>(n, arp, A.ci.p, nullptr, B.rp.p, B.ci.p,
-                                                     nullptr, kp, nullptr, cnt.p, nullptr,
-                                                     nullptr, nullptr);
+    if (wide)
+      MERGE(0, 32, n, arp, A.ci.p, nullptr, B.rp.p, B.ci.p, nullptr, kp, nullptr, cnt.p, nullptr,
+            nullptr, nullptr);
+    else
+      MERGE(0, 16, n, arp, A.ci.p, nullptr, B.rp.p, B.ci.p, nullptr, kp, nullptr, cnt.p, nullptr,
+            nullptr, nullptr);
     KCHK();
   }
   S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, n, s);
   S.ci.alloc(S.nnz, s);
   if (values) S.v.alloc(S.nnz, s);
   if (n > 0) {
-    k_merge_rows<1><<<grid_for(n, 256), 256, 0, s>>>(
-        n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p, values ? B.v.p : nullptr, kp,
-        w, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr);
+    if (wide)
+      MERGE(1, 32, n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p,
+            values ? B.v.p : nullptr, kp, w, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr);
+    else
+      MERGE(1, 16, n, arp, A.ci.p, values ? A.v.p : nullptr, B.rp.p, B.ci.p,
+            values ? B.v.p : nullptr, kp, w, nullptr, S.rp.p, S.ci.p, values ? S.v.p : nullptr);
     KCHK();
   }
+#undef MERGE
 }
 
 void drop_only(const Csr &B, int nmax, const int *lrank, Csr &G, hipStream_t s, int *dflag,
@@ -759,7 +876,7 @@ void transpose(const Csr &A, Csr &T, bool values, hipStream_t s) {
   DArr<int> tr(A.nnz, s);
   DArr<double> tv;
   if (values) tv.alloc(A.nnz, s);
-  k_transpose_scatter<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, T.rp.p,
+  k_transpose_scatter<<<grid_for(A.n * 16, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, T.rp.p,
                                                          fillpos.p, tr.p, values ? tv.p : nullptr);
   KCHK();
   k_rank_sort_rows<<<(unsigned)T.n, 64, 0, s>>>(T.n, T.rp.p, tr.p, values ? tv.p : nullptr,

@@ -388,6 +388,106 @@ __global__ void k_max_ub(int nrows, const int *__restrict__ rows, const int64_t 
 // same pinned order); the flagged columns are written in ascending order.
 constexpr int DMAX = 8192;   // largest dense row: 72 KB of LDS per workgroup
 
+// Products with at most TINY_M output columns (the last coarse levels, where a few output
+// rows carry most of the work): B is expanded to a dense row-major array with a presence
+// mask per row, and one lane per output column walks the row of A in ascending k, adding
+// a_ik b_kj wherever (k, j) is an entry of B: the same products, rounded and added in the
+// same order as in the accumulating forms, with every lane busy.
+constexpr int TINY_M = 128;
+
+__global__ void k_tiny_expand(int64_t nb, int m, const int *__restrict__ brp,
+                              const int *__restrict__ bci, const double *__restrict__ bv,
+                              double *__restrict__ bd, unsigned long long *__restrict__ bmask) {
+  const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
+  const int l = threadIdx.x & 63;
+  if (k >= nb) return;
+  unsigned long long m0 = 0ull, m1 = 0ull;
+  for (int q = brp[k] + l; q < brp[k + 1]; q += 64) {
+    const int j = bci[q];
+    bd[k * m + j] = bv[q];
+    if (j < 64) m0 |= 1ull << j;
+    else m1 |= 1ull << (j - 64);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 |= __shfl_xor(m0, o, 64);
+    m1 |= __shfl_xor(m1, o, 64);
+  }
+  if (l == 0) {
+    bmask[2 * k] = m0;
+    bmask[2 * k + 1] = m1;
+  }
+}
+
+// output pattern of a row: the union of the masks of the rows of B it selects
+__global__ void k_tiny_sym(int64_t n, const int *__restrict__ arp, const int *__restrict__ aci,
+                           const unsigned long long *__restrict__ bmask,
+                           unsigned long long *__restrict__ rmask, int *__restrict__ cnt) {
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
+  const int l = threadIdx.x & 63;
+  if (row >= n) return;
+  unsigned long long m0 = 0ull, m1 = 0ull;
+  for (int e = arp[row] + l; e < arp[row + 1]; e += 64) {
+    const int k = aci[e];
+    m0 |= bmask[2 * k];
+    m1 |= bmask[2 * k + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 |= __shfl_xor(m0, o, 64);
+    m1 |= __shfl_xor(m1, o, 64);
+  }
+  if (l == 0) {
+    rmask[2 * row] = m0;
+    rmask[2 * row + 1] = m1;
+    cnt[row] = __popcll(m0) + __popcll(m1);
+  }
+}
+
+template <int MW>
+__global__ void __launch_bounds__(MW) k_tiny_num(int64_t n, int m, const int *__restrict__ arp,
+                                                 const int *__restrict__ aci,
+                                                 const double *__restrict__ av,
+                                                 const double *__restrict__ bd,
+                                                 const unsigned long long *__restrict__ bmask,
+                                                 const unsigned long long *__restrict__ rmask,
+                                                 const int *__restrict__ crp,
+                                                 int *__restrict__ cci, double *__restrict__ cv) {
+  const int64_t row = blockIdx.x;
+  if (row >= n) return;
+  const int j = threadIdx.x, word = j >> 6, bit = j & 63;
+  const int as = arp[row], ae = arp[row + 1];
+  double acc = 0.0;
+  constexpr int U = 8;   // the loads of U steps are issued before they are added in order
+  for (int e0 = as; e0 < ae; e0 += U) {
+    int kk[U];
+    double aa[U], bb[U];
+    unsigned long long mm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e0 + u < ae;
+      kk[u] = ok ? aci[e0 + u] : 0;
+      aa[u] = ok ? av[e0 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e0 + u < ae;
+      mm[u] = ok ? bmask[2 * (int64_t)kk[u] + word] : 0ull;
+      bb[u] = (ok && j < m) ? bd[(int64_t)kk[u] * m + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if ((mm[u] >> bit) & 1ull) acc = __dadd_rn(acc, __dmul_rn(aa[u], bb[u]));
+  }
+  const unsigned long long r = rmask[2 * row + word];
+  if (j < m && ((r >> bit) & 1ull)) {
+    const int pos = crp[row] + (word ? __popcll(rmask[2 * row]) : 0) +
+                    __popcll(r & ((1ull << bit) - 1ull));
+    cci[pos] = j;
+    cv[pos] = acc;
+  }
+}
+
 template <int DM>
 __global__ void __launch_bounds__(64) k_sym_dense(int64_t n, int m, const int *__restrict__ arp,
                                                   const int *__restrict__ aci,
@@ -676,6 +776,32 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   }
   const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
   const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
+  if (B.m <= TINY_M && meanA * meanB >= 64.0 && B.n * B.m <= ((int64_t)1 << 24)) {
+    const int mm = (int)B.m;
+    DArr<double> bd(std::max<int64_t>(B.n * mm, 1), s);
+    DArr<unsigned long long> bmask(2 * std::max<int64_t>(B.n, 1), s), rmask(2 * n, s);
+    DArr<int> cnt(n + 1, s);
+    if (B.n > 0) {
+      k_tiny_expand<<<grid_for(B.n * 64, 256), 256, 0, s>>>(B.n, mm, B.rp.p, B.ci.p, B.v.p, bd.p,
+                                                            bmask.p);
+      KCHK();
+    }
+    k_tiny_sym<<<grid_for(n * 64, 256), 256, 0, s>>>(n, A.rp.p, A.ci.p, bmask.p, rmask.p, cnt.p);
+    KCHK();
+    C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
+    C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
+    C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
+    if (C.nnz > 0) {
+      if (mm <= 64)
+        k_tiny_num<64><<<(unsigned)n, 64, 0, s>>>(n, mm, A.rp.p, A.ci.p, A.v.p, bd.p, bmask.p,
+                                                  rmask.p, C.rp.p, C.ci.p, C.v.p);
+      else
+        k_tiny_num<128><<<(unsigned)n, 128, 0, s>>>(n, mm, A.rp.p, A.ci.p, A.v.p, bd.p, bmask.p,
+                                                    rmask.p, C.rp.p, C.ci.p, C.v.p);
+      KCHK();
+    }
+    return;
+  }
   if (B.m <= DMAX && meanA * meanB >= 64.0 && (double)B.m <= 64.0 * meanA * meanB) {
     // few output columns and many products per row: dense accumulation
     // tables sized to the column count: small ones leave room for several workgroups per CU

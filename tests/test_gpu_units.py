@@ -52,22 +52,31 @@ def test_spgemm_pinned_order_cancellation():
     assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
 
 
-def test_spgemm_dense_accumulator_pinned_order():
-    # 70 products into one column (the dense-accumulator path, two chunks of the row of A):
-    # in ascending k every +1 is absorbed by 1e16 and the sum is exactly 0; another order
-    # would leave some of the ones
+@pytest.mark.parametrize("ncols", [1, 200])
+def test_spgemm_wide_row_pinned_order(ncols):
+    # 70 products into column 0 from a row of A longer than one 64-entry chunk: in ascending
+    # k every +1 is absorbed by 1e16 and the sum is exactly 0; another order would leave some
+    # of the ones.  One output column takes the one-lane-per-column form, 200 (a second entry
+    # in column 199 for every fifth row of B) the dense accumulator.
     A = CSR([0, 70], list(range(70)), [1.0] * 70, (1, 70))
-    B = CSR(list(range(71)), [0] * 70, [1e16] + [1.0] * 68 + [-1e16], (70, 1))
+    rows, cols, vals = [], [], []
+    for k, v in enumerate([1e16] + [1.0] * 68 + [-1e16]):
+        rows.append(k); cols.append(0); vals.append(v)
+        if ncols > 1 and k % 5 == 0:
+            rows.append(k); cols.append(ncols - 1); vals.append(0.5)
+    indptr = np.zeros(71, dtype=np.int64)
+    np.add.at(indptr, np.asarray(rows) + 1, 1)
+    B = CSR(np.cumsum(indptr), cols, vals, (70, ncols))
     exp = spgemm(A, B)
-    assert exp.data.tolist() == [0.0]
-    got = m.spgemm(dev(A), dev(B))
-    assert got[1].tolist() == [0] and got[2].tolist() == [0.0]
+    assert exp.indices.tolist()[0] == 0 and exp.data.tolist()[0] == 0.0
+    assert_csr_equal(m.spgemm(dev(A), dev(B)), exp, f"pinned order, {ncols} columns")
 
 
 @pytest.mark.parametrize("case", [
     # (rows, inner, cols, density of A, density of B): which accumulation the product takes
-    ("dense accumulator, 128-column table, rows of A beyond 64 entries", 150, 400, 0.2, 100,
-     0.05),
+    ("one lane per output column, 65..128 columns, rows of A beyond 64 entries", 150, 400,
+     0.2, 100, 0.05),
+    ("one lane per output column, at most 64 columns", 120, 300, 0.3, 50, 0.1),
     ("dense accumulator, 512-column table", 200, 500, 0.08, 300, 0.03),
     ("dense accumulator, rows of B beyond 64 entries", 30, 200, 0.3, 1000, 0.1),
     ("dense accumulator, 4096-column table", 40, 1000, 0.1, 3000, 0.01),
@@ -172,6 +181,34 @@ def test_merge_drop_random(nmax):
     exp = merge_sub(A, G)
     got = m.merge_drop(dev(A), dev(B), None, nmax, torch.as_tensor(labels).cuda())
     assert_csr_equal(got, exp, f"merge_drop nmax={nmax}")
+
+
+@pytest.mark.parametrize("case", [
+    # (name, rows, row lengths of A, row lengths of B) of square matrices (the dropping
+    # operator pairs row and column labels): 16 lanes per row for short rows, 32 for long
+    # ones, rows beyond the LDS staging merged by one lane
+    ("32 lanes per row", 300, lambda i: 20 + 10 * (i % 5), lambda i: 30 + 17 * (i % 5)),
+    ("16 lanes per row, two rows beyond 128 entries", 300,
+     lambda i: 200 if i in (7, 100) else 3 + i % 4,
+     lambda i: 150 if i in (7, 100) else 2 + i % 6),
+    ("32 lanes per row, a row beyond 256 entries", 500,
+     lambda i: 300 if i == 3 else 40, lambda i: 400 if i == 3 else 40),
+])
+@pytest.mark.parametrize("nmax", [-1, 4])
+@pytest.mark.parametrize("scaled", [False, True])
+def test_merge_drop_row_lengths(case, nmax, scaled):
+    what, n, la, lb = case
+    rng = np.random.default_rng(n + nmax)
+    A = rows_csr(rng, [la(i) for i in range(n)], n)
+    B = rows_csr(rng, [lb(i) for i in range(n)], n)
+    B.data[:] = np.round(B.data * 3)                # ties in |b| for the dropping order
+    labels = np.tile(np.array([1, 2], dtype=np.int8), n // 2)
+    w = rng.standard_normal(n) if scaled else None
+    G = omgr.drop(B, labels, nmax) if nmax >= 0 else B
+    exp = merge_sub(A, G, w)
+    got = m.merge_drop(dev(A), dev(B), torch.as_tensor(w).cuda() if scaled else None, nmax,
+                       torch.as_tensor(labels).cuda() if nmax >= 0 else None)
+    assert_csr_equal(got, exp, f"merge_drop {what} nmax={nmax} scaled={scaled}")
 
 
 def test_merge_scaled_prolongator():
