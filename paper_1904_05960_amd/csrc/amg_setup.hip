@@ -67,7 +67,7 @@ __global__ void k_node_norms(int64_t nn, const int *__restrict__ rp, const int *
       const int s = rp[3 * I + r] + 3 * q;
       for (int c = 0; c < 3; ++c) acc = __dadd_rn(acc, __dmul_rn(v[s + c], v[s + c]));
     }
-    nci[nrp[I] + q] = ci[rp[3 * I] + 3 * q] / 3;
+    if (nci) nci[nrp[I] + q] = ci[rp[3 * I] + 3 * q] / 3;
     f[nrp[I] + q] = acc;
   }
 }
@@ -222,7 +222,7 @@ __global__ void k_tent_fill(int64_t nrows, int bs, const int *__restrict__ agg,
 }  // namespace
 
 void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t s,
-                    int *dflag) {
+                    int *dflag, const Bsr3 *blocks) {
   Csr S;  // directed strong graph, pattern only
   const double th2 = theta * theta;
   if (bs == 1) {
@@ -242,28 +242,35 @@ void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t
     KCHK();
   } else {
     require(bs == 3, MGR_ERR_ARG, "AMG block size must be 1 or 3");
-    DArr<int> nrp, nci_unused;
-    DArr<double> bv_unused;
-    int64_t nn, mn, nnzb;
-    csr_to_bsr3(A, nrp, nci_unused, bv_unused, nn, mn, nnzb, s, dflag, "strength A");
-    nci_unused.reset();
-    bv_unused.reset();
-    DArr<int> nci(nnzb, s);
+    // node pattern: that of the level's 3x3 block form when the caller has it
+    DArr<int> own_rp, own_ci;
+    int64_t nn, nnzb;
+    if (blocks) {
+      nn = blocks->nb;
+      nnzb = blocks->nnzb;
+    } else {
+      DArr<double> bv_unused;
+      int64_t mn;
+      csr_to_bsr3(A, own_rp, own_ci, bv_unused, nn, mn, nnzb, s, dflag, "strength A");
+    }
+    const int *nrp = blocks ? blocks->rp.p : own_rp.p;
+    const int *nci = blocks ? blocks->ci.p : own_ci.p;
     DArr<double> f(nnzb, s), fd(nn, s);
-    k_node_norms<16><<<grid_for(nn * 16, 256), 256, 0, s>>>(nn, A.rp.p, A.ci.p, A.v.p, nrp.p, nci.p, f.p);
+    k_node_norms<16><<<grid_for(nn * 16, 256), 256, 0, s>>>(nn, A.rp.p, A.ci.p, A.v.p, nrp,
+                                                            nullptr, f.p);
     KCHK();
-    k_node_diag<<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp.p, nci.p, f.p, fd.p);
+    k_node_diag<<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p);
     KCHK();
     const double th4 = th2 * th2;
     DArr<int> cnt(nn + 1, s);
-    k_strength_nodal<0><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp.p, nci.p, f.p, fd.p, th4, cnt.p,
+    k_strength_nodal<0><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4, cnt.p,
                                                          nullptr, nullptr);
     KCHK();
     S.n = S.m = nn;
     S.rp.alloc(nn + 1, s);
     S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, nn, s);
     S.ci.alloc(S.nnz, s);
-    k_strength_nodal<1><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp.p, nci.p, f.p, fd.p, th4,
+    k_strength_nodal<1><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4,
                                                          nullptr, S.rp.p, S.ci.p);
     KCHK();
   }

@@ -196,8 +196,9 @@ struct AmgGraph {
   int64_t n = 0;
   DArr<int> rp, ci;
 };
+// bs = 3: `blocks`, when given, is the 3x3 block form of A (its node pattern is used)
 void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t s,
-                    int *dflag);
+                    int *dflag, const Bsr3 *blocks = nullptr);
 void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
                     hipStream_t s);
 void tentative(const DArr<int> &agg, int64_t nnode, int bs, int64_t nagg, Csr &T,

@@ -296,7 +296,12 @@ void amg_setup(Csr &&A, int bs, mgr_amg_opts o, Amg &H, const mgr_opts &mo, hipS
     trace("amg level " + std::to_string(k) + " n=" + std::to_string(n) + " nnz=" +
           std::to_string(L.A.nnz) + " bs=" + std::to_string(bs));
     AmgGraph G;
-    strength_graph(L.A, bs, o.theta0 * std::ldexp(1.0, -k), G, s, dflag);
+    if (bs == 3 && !L.Ab64) {
+      // the block form serves the strength graph and the products of this level
+      L.Ab64 = std::make_unique<Bsr3>();
+      csr_to_bsr3(L.A, *L.Ab64, s, dflag, "AMG A");
+    }
+    strength_graph(L.A, bs, o.theta0 * std::ldexp(1.0, -k), G, s, dflag, L.Ab64.get());
     trace("  strength done");
     int64_t nagg = 0;
     DArr<int> agg;

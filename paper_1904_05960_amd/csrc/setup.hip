@@ -490,31 +490,52 @@ __global__ void k_gershgorin(int64_t n, const int *__restrict__ rp, const int *_
 }
 // per row, one pass in ascending column order: the diagonal d_i, 1 / sum_j |a_ij| (the l1
 // smoother) and the Gershgorin ratio sum_j |a_ij| / |a_ii|
-// G lanes per row load the row coalesced; every lane then adds the values in ascending
-// column order (the order of the sum is the row's, not the lanes')
+// G lanes per row load the row coalesced, G entries at a time, into LDS; the first lane of
+// the group then adds them in ascending column order (the order of the sum is the row's,
+// not the lanes').
 template <int G>
-__global__ void k_row_stats(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
-                            const double *__restrict__ v, double *__restrict__ d,
-                            double *__restrict__ q, double *__restrict__ l1inv, int *flag) {
+__global__ void __launch_bounds__(256) k_row_stats(int64_t n, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const double *__restrict__ v,
+                                                   double *__restrict__ d,
+                                                   double *__restrict__ q,
+                                                   double *__restrict__ l1inv, int *flag) {
+  __shared__ double s_abs[256];
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int l = threadIdx.x & (G - 1);
-  if (i >= n) return;
+  const int base = threadIdx.x - l;
+  if (i >= n) return;   // whole groups leave; the groups never wait for each other
   double rs = 0.0, di = 0.0;
+  int found = 0;
   const int e0 = rp[i], e1 = rp[i + 1];
   for (int c0 = e0; c0 < e1; c0 += G) {
     const int e = c0 + l;
     double x = 0.0;
-    int col = -1;
     if (e < e1) {
       x = v[e];
-      col = ci[e];
+      if (ci[e] == (int)i) {
+        di = x;
+        found = 1;
+      }
     }
-    const int cnt = min(G, e1 - c0);
-    for (int t = 0; t < cnt; ++t) {
-      const double y = __shfl(x, t, G);
-      const int cy = __shfl(col, t, G);
-      rs = __dadd_rn(rs, fabs(y));
-      if (cy == (int)i) di = y;
+    s_abs[threadIdx.x] = fabs(x);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (l == 0) {
+      const int cnt = min(G, e1 - c0);
+      for (int t = 0; t < cnt; ++t) rs = __dadd_rn(rs, s_abs[base + t]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  // the diagonal from the lane that held it
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const double od = __shfl_xor(di, o, G);
+    const int of = __shfl_xor(found, o, G);
+    if (of && !found) {
+      di = od;
+      found = 1;
     }
   }
   if (l != 0) return;
