@@ -232,7 +232,6 @@ struct mgr_handle {
   uint64_t pattern = 0;
   mgr::DArr<char> v0, z0;    // apply-precision level-0 vectors
   hipStream_t cap = nullptr; // private capture stream
-  hipStream_t s2 = nullptr;  // setup stream of the F-relaxation AMG (built concurrently)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   ~mgr_handle();
@@ -656,6 +655,37 @@ struct Jobs {
   ~Jobs() { join(); }
 };
 
+// Streams for the F-relaxation AMG setups built concurrently with the coarser levels, kept
+// in a pool per device and reused by later setups: the caching allocator keeps freed blocks
+// per stream, so blocks obtained on a pooled stream are found again by the next setup.
+// Pooled streams live until the process ends.
+std::mutex g_helper_mu;
+std::map<int, std::vector<hipStream_t>> g_helper_pool;
+
+struct HelperStream {
+  hipStream_t s = nullptr;
+  int dev = 0;
+  void acquire() {
+    HIPCHK(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> g(g_helper_mu);
+      auto &v = g_helper_pool[dev];
+      if (!v.empty()) {
+        s = v.back();
+        v.pop_back();
+        return;
+      }
+    }
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  }
+  ~HelperStream() {
+    if (!s) return;
+    (void)hipStreamSynchronize(s);
+    std::lock_guard<std::mutex> g(g_helper_mu);
+    g_helper_pool[dev].push_back(s);
+  }
+};
+
 void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   hipStream_t s = h->s;
   std::vector<hipEvent_t> events;
@@ -663,7 +693,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     std::vector<hipEvent_t> &e;
     ~EventGuard() { for (auto x : e) (void)hipEventDestroy(x); }
   } event_guard{events};
-  Jobs jobs;                 // declared last: joined before the events are destroyed
+  HelperStream helper;       // the stream of the concurrent F-relaxation AMG setups
+  Jobs jobs;                 // declared last: joined before the events and the stream go
   int *flag = h->dflag.p;
   const mgr_opts &o = h->opts;
   const size_t sz = esz(o);
@@ -707,7 +738,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
       // built on a second stream by a second host thread while this thread goes on with the
       // coarser levels (both are bound by sparse products and host synchronisation)
-      if (!h->s2) HIPCHK(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+      if (!helper.s) helper.acquire();
       hipEvent_t ev;
       HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
       HIPCHK(hipEventRecord(ev, s));
@@ -717,7 +748,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       AsyncAmg *J = job.get();
       J->level = L.get();
       const int bs = lo.frelax_block;
-      hipStream_t s2 = h->s2;
+      hipStream_t s2 = helper.s;
       job->th = std::thread([J, bs, dev, ev, s2, o, A = std::move(Aff)]() mutable {
         try {
           HIPCHK(hipSetDevice(dev));
@@ -950,13 +981,12 @@ mgr_status fail(const Error &e) {
 
 mgr_handle::~mgr_handle() {
   if (s) (void)hipStreamSynchronize(s);
-  if (s2) (void)hipStreamSynchronize(s2);
   mgr::destroy_graph(this);
   if (cap) (void)hipStreamDestroy(cap);
-  // the hierarchy's buffers are released before the stream that allocated some of them
+  // the hierarchy's buffers return to the allocator (every stream they were taken on is
+  // synchronised: the caller's above, the pooled setup streams at the end of the setup)
   lv.clear();
   coarse_amg.lv.clear();
-  if (s2) (void)hipStreamDestroy(s2);
 }
 
 // ===================================================================================

@@ -260,6 +260,22 @@ def test_spmv_long_and_empty_rows():
     assert info["iters"] == 2
 
 
+def test_repeated_setups_reuse_cached_blocks():
+    # setup and destroy of the same problem, the F-relaxation AMG built on a second stream:
+    # the blocks freed by one setup serve the next, so the cache stops growing
+    w = pm.biot_single_phase(6, 6, 6, 0)
+    A, labels, b = device_workload(w)
+    opts = small_amg(m.paper_plan("biot1"), coarse_size=24)
+    L = m.lib()
+    sizes = []
+    for _ in range(5):
+        P = m.Preconditioner(A, labels, opts)
+        P.close()
+        torch.cuda.synchronize()
+        sizes.append(L.mgr_cached_bytes())
+    assert sizes[2] == sizes[3] == sizes[4], sizes
+
+
 def test_error_paths():
     w = pm.biot_single_phase(3, 3, 3, 0)
     A, labels, b = device_workload(w)
