@@ -175,8 +175,30 @@ __global__ void k_check_nonzero(const double *__restrict__ d, int64_t n, int *fl
 // keep flags (only when dropping): G lanes per row of B; an entry off the sub-block
 // diagonals is kept when fewer than nmax other off-diagonal entries beat it (larger |b|,
 // or equal |b| and a smaller column).  Rows of up to G * MAXCH entries are held in the
-// lanes' registers (chunk c of lane l = entry c * G + l) and compared through shuffles;
-// longer rows compare against global memory.
+// lanes' registers (chunk c of lane l = entry c * G + l).  For nmax <= KTOP the lanes
+// reduce their candidates to the row's KTOP best by a butterfly over sorted lists, and an
+// entry is kept when it is among the first nmax of them: the same set as counting (the
+// order is total, and an entry whose |b| is NaN beats none and is beaten by none, so it
+// has rank 0); for larger nmax every entry counts the entries that beat it through
+// shuffles.  Longer rows compare against global memory.
+constexpr int KTOP = 4;
+__device__ __forceinline__ bool drop_beats(double a, int ca, double b, int cb) {
+  return a > b || (a == b && ca < cb);
+}
+// insert (v, c) into the sorted list (best first) of KTOP entries, dropping the last
+__device__ __forceinline__ void top_insert(double (&tv)[KTOP], int (&tc)[KTOP], double v, int c) {
+#pragma unroll
+  for (int k = 0; k < KTOP; ++k) {
+    if (drop_beats(v, c, tv[k], tc[k])) {
+      const double sv = tv[k];
+      const int sc = tc[k];
+      tv[k] = v;
+      tc[k] = c;
+      v = sv;
+      c = sc;
+    }
+  }
+}
 template <int G, int MAXCH>
 __global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *__restrict__ bci,
                             const double *__restrict__ bv, int nmax,
@@ -200,6 +222,46 @@ __global__ void k_drop_keep(int64_t n, const int *__restrict__ brp, const int *_
       av[c] = in ? fabs(bv[t]) : 0.0;
       el[c] = in && lrank[cc[c]] != myrank;
       rk[c] = 0;
+    }
+    if (nmax <= KTOP) {
+      // the lane's best KTOP candidates (|b| >= 0 > -1 marks an empty place), then the
+      // row's by merging the lists of lane groups of 2, 4, ..., G
+      double tv[KTOP];
+      int tc[KTOP];
+#pragma unroll
+      for (int k = 0; k < KTOP; ++k) {
+        tv[k] = -1.0;
+        tc[k] = 0x7fffffff;
+      }
+#pragma unroll
+      for (int c = 0; c < MAXCH; ++c)
+        if (el[c] && av[c] == av[c]) top_insert(tv, tc, av[c], cc[c]);
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) {
+        double ov[KTOP];
+        int oc[KTOP];
+#pragma unroll
+        for (int k = 0; k < KTOP; ++k) {
+          ov[k] = __shfl_xor(tv[k], o, G);
+          oc[k] = __shfl_xor(tc[k], o, G);
+        }
+#pragma unroll
+        for (int k = 0; k < KTOP; ++k) top_insert(tv, tc, ov[k], oc[k]);
+      }
+      // the nmax-th best (when the row has that many candidates) is the last one kept
+      const bool all = nmax > 0 && tv[nmax - 1] < 0.0;
+      const double thv = nmax > 0 ? tv[nmax - 1] : 0.0;
+      const int thc = nmax > 0 ? tc[nmax - 1] : 0;
+#pragma unroll
+      for (int c = 0; c < MAXCH; ++c) {
+        const int t = bs + c * G + l;
+        if (c < nch && t < be) {
+          const bool nan = !(av[c] == av[c]);
+          const bool top = nmax > 0 && (all || nan || !drop_beats(thv, thc, av[c], cc[c]));
+          keep[t] = !el[c] || top;
+        }
+      }
+      return;
     }
 #pragma unroll
     for (int c2 = 0; c2 < MAXCH; ++c2) {

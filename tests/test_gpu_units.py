@@ -170,7 +170,7 @@ def test_transpose_random(shape):
     assert_csr_equal(m.transpose(dev(A)), transpose(A), f"transpose {shape}")
 
 
-@pytest.mark.parametrize("nmax", [-1, 0, 1, 4])
+@pytest.mark.parametrize("nmax", [-1, 0, 1, 2, 4, 6])
 def test_merge_drop_random(nmax):
     rng = np.random.default_rng(10 + nmax)
     n = 200
