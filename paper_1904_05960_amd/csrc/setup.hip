@@ -709,17 +709,32 @@ __global__ void k_block_inv(int64_t nblk, int nb, const int *__restrict__ rp,
   }
 }
 
+// Pattern fingerprint (detects a changed pattern when values are updated): the sum over
+// i of two 32-bit finalizer mixes (the MurmurHash3 fmix32 steps) of (a[i], i), one per
+// half of a 64-bit word.  32-bit arithmetic only; sums in any order are equal.
+__device__ __forceinline__ uint32_t fmix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ unsigned long long hash_pair(uint32_t v, uint32_t i, uint32_t salt) {
+  const uint32_t lo = fmix32(v ^ fmix32(i ^ salt));
+  const uint32_t hi = fmix32(v + 0x9e3779b9u * (i + 1u) + salt);
+  return ((unsigned long long)hi << 32) | lo;
+}
 __global__ void k_hash(int64_t n, const int *__restrict__ a, unsigned long long salt,
                        unsigned long long *__restrict__ out) {
   unsigned long long acc = 0;
+  const uint32_t s32 = (uint32_t)salt;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    unsigned long long z = (unsigned long long)(uint32_t)a[i] ^ ((unsigned long long)i << 32) ^ salt;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    acc += z ^ (z >> 31);
-  }
-  atomicAdd(out, acc);
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += hash_pair((uint32_t)a[i], (uint32_t)i, s32);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
 }
 
 }  // namespace
@@ -1042,10 +1057,12 @@ void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
 uint64_t pattern_hash(const Csr &A, hipStream_t s) {
   DArr<unsigned long long> h(1, s);
   HIPCHK(hipMemsetAsync(h.p, 0, sizeof(unsigned long long), s));
-  k_hash<<<1024, 256, 0, s>>>(A.n + 1, A.rp.p, 0x1234567ull, h.p);
+  k_hash<<<std::min<unsigned>(grid_for(A.n + 1, 256), 8192), 256, 0, s>>>(A.n + 1, A.rp.p,
+                                                                       0x1234567ull, h.p);
   KCHK();
   if (A.nnz) {
-    k_hash<<<1024, 256, 0, s>>>(A.nnz, A.ci.p, 0x9876543ull, h.p);
+    k_hash<<<std::min<unsigned>(grid_for(A.nnz, 256), 8192), 256, 0, s>>>(A.nnz, A.ci.p,
+                                                                       0x9876543ull, h.p);
     KCHK();
   }
   unsigned long long r = 0;

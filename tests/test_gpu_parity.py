@@ -334,6 +334,18 @@ def test_setup_numeric_same_pattern_equals_fresh_setup():
     with pytest.raises(m.MgrError) as e:
         P.setup_numeric(A3)
     assert e.value.status == m.MGR_ERR_PATTERN
+    # same size and entry count, one column index moved by one place: the fingerprint of
+    # the pattern differs
+    ind = w1.indices.copy()
+    r = w1.n // 2
+    lo, hi = w1.indptr[r], w1.indptr[r + 1]
+    q = next(q for q in range(hi - 1, lo - 1, -1)
+             if ind[q] + 1 < w1.n and (q + 1 == hi or ind[q + 1] != ind[q] + 1))
+    ind[q] += 1
+    A4 = m.Matrix.from_host(w1.indptr, ind, w1.data)
+    with pytest.raises(m.MgrError) as e:
+        P.setup_numeric(A4)
+    assert e.value.status == m.MGR_ERR_PATTERN
     P.close()
     Pf.close()
 
