@@ -14,6 +14,9 @@ namespace mgr {
 namespace {
 
 enum { M_RESID = 0, M_SPMV = 1, M_SPMV_ADD = 2, M_L1PRE = 3, M_L1POST = 4 };
+// restriction that also forms the next level's first smoothing iterate: out = A x,
+// out2 = D^{-1} out with the next level's D (the product the separate pass would form)
+enum { M_SPMV_DX = 6 };
 
 template <class T, int G>
 __device__ __forceinline__ T group_sum(T v) {
@@ -90,6 +93,9 @@ __device__ __forceinline__ void csr_epilogue(int row, T acc, const int *__restri
     out[row] = bi - acc;
   } else if (MODE == M_L1POST) {
     out[row] = x[row] + dinv[row] * (b[row] - acc);
+  } else if (MODE == M_SPMV_DX) {
+    out[row] = acc;
+    out2[row] = dinv[row] * acc;
   } else {  // M_INTERP: x = eF (may be null), out = z
     const int i = oidx[row];
     const T base = accumulate ? out[i] : (x ? x[row] : (T)0);
@@ -270,6 +276,9 @@ __global__ void __launch_bounds__(256) k_bsr3(int64_t nb, const int *__restrict_
   const int64_t r = 3 * I;
   if (MODE == M_SPMV) {
     out[r] = a0; out[r + 1] = a1; out[r + 2] = a2;
+  } else if (MODE == M_SPMV_DX) {
+    out[r] = a0; out[r + 1] = a1; out[r + 2] = a2;
+    out2[r] = dinv[r] * a0; out2[r + 1] = dinv[r + 1] * a1; out2[r + 2] = dinv[r + 2] * a2;
   } else if (MODE == M_SPMV_ADD) {
     out[r] += a0; out[r + 1] += a1; out[r + 2] += a2;
   } else if (MODE == M_RESID) {
@@ -460,6 +469,37 @@ void VecOps<T>::l1_pre(const CsrV<T> &A, const T *dinv, const T *b, T *x, T *r, 
   } else {
     launch_csr<T, M_L1PRE>(A, A.n, nullptr, nullptr, nullptr, b, dinv, r, x, s);
   }
+}
+// restriction y = R r and the next level's x = D^{-1} y in one pass (matrices with row
+// blocks; otherwise two)
+template <class T>
+void VecOps<T>::spmv_dx(const CsrV<T> &R, const T *r, const T *dinv_next, T *y, T *x_next,
+                        hipStream_t s) {
+  if (R.rb) {
+    launch_csr_stream<T, M_SPMV_DX>(R, r, r, nullptr, dinv_next, nullptr, nullptr, y, x_next, 0,
+                                    s);
+    return;
+  }
+  spmv(R, r, y, false, s);
+  if (R.n > 0) {
+    k_vmul<T><<<grid_for(R.n, 256), 256, 0, s>>>(dinv_next, y, x_next, R.n);
+    KCHK();
+  }
+}
+template <class T>
+void VecOps<T>::b_spmv_dx(const Bsr3V<T> &R, const T *r, const T *dinv_next, T *y, T *x_next,
+                          hipStream_t s) {
+  launch_bsr3<T, M_SPMV_DX>(R, r, nullptr, dinv_next, y, x_next, s);
+}
+// the first sweep's residual when x = D^{-1} b was formed by the restriction above
+template <class T>
+void VecOps<T>::l1_pre_given(const CsrV<T> &A, const T *b, const T *x, T *r, hipStream_t s) {
+  if (A.rb) launch_csr_stream<T, M_RESID>(A, x, x, b, nullptr, nullptr, nullptr, r, nullptr, 0, s);
+  else launch_csr<T, M_RESID>(A, A.n, nullptr, nullptr, x, b, nullptr, r, nullptr, s);
+}
+template <class T>
+void VecOps<T>::b_l1_pre_given(const Bsr3V<T> &A, const T *b, const T *x, T *r, hipStream_t s) {
+  launch_bsr3<T, M_RESID>(A, x, b, nullptr, r, nullptr, s);
 }
 template <class T>
 void VecOps<T>::l1_post(const CsrV<T> &A, const T *dinv, const T *b, const T *x, T *y,

@@ -275,6 +275,14 @@ struct VecOps {
                        hipStream_t s);
   static void b_l1_post(const Bsr3V<T> &A, const T *dinv, const T *b, const T *x, T *y,
                         hipStream_t s);
+  // restriction y = R r that also writes the next level's first iterate D^{-1} y
+  static void spmv_dx(const CsrV<T> &R, const T *r, const T *dinv_next, T *y, T *x_next,
+                      hipStream_t s);
+  static void b_spmv_dx(const Bsr3V<T> &R, const T *r, const T *dinv_next, T *y, T *x_next,
+                        hipStream_t s);
+  // first sweep's residual r = b - A x with x = D^{-1} b already formed
+  static void l1_pre_given(const CsrV<T> &A, const T *b, const T *x, T *r, hipStream_t s);
+  static void b_l1_pre_given(const Bsr3V<T> &A, const T *b, const T *x, T *r, hipStream_t s);
   static void gemv(const T *M, int n, const T *x, T *y, hipStream_t s);
   static void gather(const int *idx, int64_t n, const T *x, T *y, hipStream_t s);
   static void scatter_add(const int *idx, int64_t n, const T *x, T *y, hipStream_t s);

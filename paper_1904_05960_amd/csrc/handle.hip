@@ -469,9 +469,10 @@ Bsr3V<T> bview(int64_t n, int64_t m, int64_t nnzb, const DArr<int> &rp, const DA
   return v;
 }
 
-// V-cycle from x = 0: y = V(b); y must not alias b
+// V-cycle from x = 0: y = V(b); y must not alias b.  `xready`: the level's first smoothing
+// iterate x = D^{-1} b was formed by the restriction that produced b.
 template <class T>
-void vcycle(const Amg &H, size_t k, const T *b, T *y, hipStream_t s) {
+void vcycle(const Amg &H, size_t k, const T *b, T *y, hipStream_t s, bool xready = false) {
   using V = VecOps<T>;
   if (k + 1 == H.lv.size()) {
     V::gemv(Ptr<T>::of(H.tcinv), H.nc, b, y, s);
@@ -490,10 +491,15 @@ void vcycle(const Amg &H, size_t k, const T *b, T *y, hipStream_t s) {
         (double)L.Ab_nnzb * (9 * sizeof(T) + 4) + (double)(L.nb + 1) * 4 + (double)L.A.n * sizeof(T) * 4;
     const bool prof = k == 0 && Prof::on(0);
     if (prof) Prof::begin(0, s);
-    V::b_l1_pre(A, dinv, b, x, r, s);
+    if (xready) V::b_l1_pre_given(A, b, x, r, s);
+    else V::b_l1_pre(A, dinv, b, x, r, s);
     if (prof) Prof::end(0, s, sweep_bytes + (double)L.A.n * sizeof(T));
-    V::b_spmv(R, r, bc, false, s);
-    vcycle<T>(H, k + 1, bc, yc, s);
+    const bool next_smooths = k + 2 < H.lv.size();   // the next level is not the coarsest
+    if (next_smooths)
+      V::b_spmv_dx(R, r, Ptr<T>::of(N.tdinv), bc, Ptr<T>::of(N.x), s);
+    else
+      V::b_spmv(R, r, bc, false, s);
+    vcycle<T>(H, k + 1, bc, yc, s, next_smooths);
     V::b_spmv(P, yc, x, true, s);
     if (prof) Prof::begin(0, s);
     V::b_l1_post(A, dinv, b, x, y, s);
@@ -502,9 +508,14 @@ void vcycle(const Amg &H, size_t k, const T *b, T *y, hipStream_t s) {
     auto A = view<T>(L.A, L.tA);
     auto P = view<T>(L.P, L.tP);
     auto R = view<T>(L.R, L.tR);
-    V::l1_pre(A, dinv, b, x, r, s);
-    V::spmv(R, r, bc, false, s);
-    vcycle<T>(H, k + 1, bc, yc, s);
+    if (xready) V::l1_pre_given(A, b, x, r, s);
+    else V::l1_pre(A, dinv, b, x, r, s);
+    const bool next_smooths = k + 2 < H.lv.size();   // the next level is not the coarsest
+    if (next_smooths)
+      V::spmv_dx(R, r, Ptr<T>::of(N.tdinv), bc, Ptr<T>::of(N.x), s);
+    else
+      V::spmv(R, r, bc, false, s);
+    vcycle<T>(H, k + 1, bc, yc, s, next_smooths);
     V::spmv(P, yc, x, true, s);
     V::l1_post(A, dinv, b, x, y, s);
   }
