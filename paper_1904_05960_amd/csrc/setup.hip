@@ -725,8 +725,11 @@ __device__ __forceinline__ unsigned long long hash_pair(uint32_t v, uint32_t i, 
   const uint32_t hi = fmix32(v + 0x9e3779b9u * (i + 1u) + salt);
   return ((unsigned long long)hi << 32) | lo;
 }
-__global__ void k_hash(int64_t n, const int *__restrict__ a, unsigned long long salt,
-                       unsigned long long *__restrict__ out) {
+// per-block partial sums (no atomics), then one block adds them to *out
+__global__ void __launch_bounds__(256) k_hash(int64_t n, const int *__restrict__ a,
+                                              unsigned long long salt,
+                                              unsigned long long *__restrict__ part) {
+  __shared__ unsigned long long sw[4];
   unsigned long long acc = 0;
   const uint32_t s32 = (uint32_t)salt;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -734,7 +737,20 @@ __global__ void k_hash(int64_t n, const int *__restrict__ a, unsigned long long 
     acc += hash_pair((uint32_t)a[i], (uint32_t)i, s32);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+}
+__global__ void __launch_bounds__(256) k_hash_sum(const unsigned long long *__restrict__ part,
+                                                  int np, unsigned long long *__restrict__ out) {
+  __shared__ unsigned long long sw[4];
+  unsigned long long acc = 0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out += (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
 
 }  // namespace
@@ -1055,14 +1071,19 @@ void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
 }
 
 uint64_t pattern_hash(const Csr &A, hipStream_t s) {
-  DArr<unsigned long long> h(1, s);
-  HIPCHK(hipMemsetAsync(h.p, 0, sizeof(unsigned long long), s));
-  k_hash<<<std::min<unsigned>(grid_for(A.n + 1, 256), 8192), 256, 0, s>>>(A.n + 1, A.rp.p,
-                                                                       0x1234567ull, h.p);
+  constexpr unsigned NB = 2048;
+  DArr<unsigned long long> h(1, s), part(NB, s);
+  fill<unsigned long long>(h.p, 0ull, 1, s);
+  const unsigned g0 = std::min<unsigned>(grid_for(A.n + 1, 256), NB);
+  k_hash<<<g0, 256, 0, s>>>(A.n + 1, A.rp.p, 0x1234567ull, part.p);
+  KCHK();
+  k_hash_sum<<<1, 256, 0, s>>>(part.p, (int)g0, h.p);
   KCHK();
   if (A.nnz) {
-    k_hash<<<std::min<unsigned>(grid_for(A.nnz, 256), 8192), 256, 0, s>>>(A.nnz, A.ci.p,
-                                                                       0x9876543ull, h.p);
+    const unsigned g1 = std::min<unsigned>(grid_for(A.nnz, 256), NB);
+    k_hash<<<g1, 256, 0, s>>>(A.nnz, A.ci.p, 0x9876543ull, part.p);
+    KCHK();
+    k_hash_sum<<<1, 256, 0, s>>>(part.p, (int)g1, h.p);
     KCHK();
   }
   unsigned long long r = 0;
