@@ -306,7 +306,9 @@ void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
     fill<int>(und.p, 0, 1, s);
     k_remove<<<gs, 256, 0, s>>>(n, a.p, state.p, und.p);
     KCHK();
-    if (read_flag(und.p, s) == 0) break;
+    // the count is read after every second round: a round with no undecided node left
+    // changes nothing, so the rounds run past the last useful one are harmless
+    if ((round & 1) && read_flag(und.p, s) == 0) break;
   }
   // roots numbered in node order
   DArr<int> fl(n, s), pos(n + 1, s);
