@@ -129,6 +129,9 @@ inline unsigned grid_for(int64_t work, int block) {
 // primitives (prims.hip)
 int64_t exclusive_scan_i32(const int *in, int *out, int64_t n, hipStream_t s);   // out[n]=total
 int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// no readback; the 64-bit total goes to *total64 (device) when given
+void exclusive_scan_i32_async(const int *in, int *out, int64_t n, hipStream_t s,
+                              int64_t *total64 = nullptr);
 template <class T> void fill(T *p, T val, int64_t n, hipStream_t s);
 int64_t reduce_max_i64(const int64_t *p, int64_t n, hipStream_t s);
 int64_t reduce_sum_i32(const int *p, int64_t n, hipStream_t s);

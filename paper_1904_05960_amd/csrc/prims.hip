@@ -52,7 +52,8 @@ __global__ void k_tile_sum(const T *__restrict__ in, int64_t n, int64_t *__restr
 
 template <class T>
 __global__ void k_tile_scan(const T *__restrict__ in, T *__restrict__ out, int64_t n,
-                            const int64_t *__restrict__ tile_base) {
+                            const int64_t *__restrict__ tile_base,
+                            int64_t *__restrict__ total64 = nullptr) {
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int64_t vals[SCAN_ITEMS];
   int64_t s = 0;
@@ -68,7 +69,10 @@ __global__ void k_tile_scan(const T *__restrict__ in, T *__restrict__ out, int64
     if (base + k < n) out[base + k] = (T)off;
     off += vals[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) out[n] = (T)off;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) {
+    out[n] = (T)off;
+    if (total64) *total64 = off;
+  }
 }
 
 // in-place-safe scan of int64 tile sums into an exclusive prefix (recursive)
@@ -206,6 +210,23 @@ int64_t exclusive_scan_i32(const int *in, int *out, int64_t n, hipStream_t s) {
   int64_t t = scan_generic<int>(in, out, n, s);
   require(t <= 0x7fffffffLL, MGR_ERR_UNSUPPORTED, "prefix sum exceeds 2^31 (matrix too large)");
   return t;
+}
+// the same scan with nothing read back: out[n] is written, and the total in 64 bits into
+// *total64 (device memory) when given
+void exclusive_scan_i32_async(const int *in, int *out, int64_t n, hipStream_t s,
+                              int64_t *total64) {
+  if (n == 0) {
+    fill<int>(out, 0, 1, s);
+    if (total64) fill<int64_t>(total64, 0, 1, s);
+    return;
+  }
+  const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  DArr<int64_t> sums(ntiles + 1, s);
+  k_tile_sum<int><<<ntiles, SCAN_BLOCK, 0, s>>>(in, n, sums.p);
+  KCHK();
+  scan_i64_impl(sums.p, sums.p, ntiles, s);
+  k_tile_scan<int><<<ntiles, SCAN_BLOCK, 0, s>>>(in, out, n, sums.p, total64);
+  KCHK();
 }
 int64_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
   return scan_generic<int64_t>(in, out, n, s);

@@ -983,7 +983,7 @@ void transpose(const Csr &A, Csr &T, bool values, hipStream_t s) {
     k_col_count<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.nnz, A.ci.p, cnt.p);
     KCHK();
   }
-  exclusive_scan_i32(cnt.p, T.rp.p, T.n, s);
+  exclusive_scan_i32_async(cnt.p, T.rp.p, T.n, s);   // the total is A.nnz
   T.ci.alloc(T.nnz, s);
   if (values) T.v.alloc(T.nnz, s);
   if (A.nnz == 0) return;

@@ -712,31 +712,45 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
   DArr<int64_t> ub(n, s);
   k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, arp, aci, brp, ub.p);
   KCHK();
-  DArr<int> cnt(n + 1, s), retry(n, s), nretry(2, s);
-  fill<int>(nretry.p, 0, 2, s);
+  DArr<int> cnt(n + 1, s), retry(n, s);
+  // read back together: the retry counts of passes 1 and 2 (two ints) and the total
+  DArr<int64_t> rbk(2, s);
+  int *nretry_p = reinterpret_cast<int *>(rbk.p);
+  fill<int>(nretry_p, 0, 2, s);
   // symbolic pass 1: tables of <= 512 slots, 64 / G rows per workgroup
   const double meanA = (double)annz / (double)std::max<int64_t>(n, 1);
   const double meanB = (double)bnnz / (double)std::max<int64_t>(bn, 1);
   const double prods = meanA * meanB;
   if (prods > 256) {
     k_sym_lds<64, 512><<<(unsigned)n, 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp, bci, cnt.p,
-                                                  retry.p, nretry.p);
+                                                  retry.p, nretry_p);
   } else if (prods > 64) {
     k_sym_lds<32, 512><<<(unsigned)((n + 1) / 2), 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp,
-                                                              bci, cnt.p, retry.p, nretry.p);
+                                                              bci, cnt.p, retry.p, nretry_p);
   } else {
     k_sym_lds<16, 512><<<(unsigned)((n + 3) / 4), 64, 0, s>>>(n, nullptr, ub.p, arp, aci, brp,
-                                                              bci, cnt.p, retry.p, nretry.p);
+                                                              bci, cnt.p, retry.p, nretry_p);
   }
   KCHK();
-  int hretry = read_flag(nretry.p, s);
-  if (hretry > 0) {
+  // the scan assumes that pass 1 counted every row; it is repeated when some did not fit
+  exclusive_scan_i32_async(cnt.p, crp, n, s, rbk.p + 1);
+  int64_t hb[2];
+  d2h_sync(hb, rbk.p, sizeof(hb), s);
+  const int hretry = reinterpret_cast<const int *>(hb)[0];
+  if (hretry == 0) {
+    require(hb[1] <= 0x7fffffffLL, MGR_ERR_UNSUPPORTED,
+            "prefix sum exceeds 2^31 (matrix too large)");
+    cnnz = hb[1];
+    if (ub_out) *ub_out = std::move(ub);
+    return;
+  }
+  {
     // pass 2: 4096-slot tables, one row per workgroup
     DArr<int> retry2(hretry, s);
     k_sym_lds<64, SYM_HT><<<(unsigned)hretry, 64, 0, s>>>(hretry, retry.p, ub.p, arp, aci, brp,
-                                                          bci, cnt.p, retry2.p, nretry.p + 1);
+                                                          bci, cnt.p, retry2.p, nretry_p + 1);
     KCHK();
-    const int hretry2 = read_flag(nretry.p + 1, s);
+    const int hretry2 = read_flag(nretry_p + 1, s);
     if (hretry2 > 0) {
       // pass 3: tables in global memory sized by the largest row
       DArr<unsigned long long> mub(1, s);
