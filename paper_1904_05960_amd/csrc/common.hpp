@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -145,6 +146,12 @@ void stream_copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 int read_flag(const int *dflag, hipStream_t s);      // synchronises
 void *pinned_scratch();                               // 256 pinned host bytes per thread
 void d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s);  // <= 256 bytes, waits
+struct D2HPart {
+  void *dst;
+  const void *src;
+  size_t bytes;
+};
+void d2h_sync_parts(const D2HPart *parts, int np, hipStream_t s);  // one wait for all parts
 void clear_flag(int *dflag, hipStream_t s);
 // throws the error that the raised device flags describe (synchronises)
 void check_flags(const int *dflag, hipStream_t s, const char *where);
@@ -222,9 +229,19 @@ void dense_inverse(double *D, double *Inv, int n, int *dflag, hipStream_t s);
 // Symbolic sparse product: crp (n + 1, caller-allocated) gets the row pointers of the
 // pattern of A B (A: n rows; B: bn x bm), cnnz its size; ub_out, when given, receives the
 // number of products of every row (sum of the lengths of the rows of B it selects).
+// Optional bucketing of the output rows run right after the row pointers are formed
+// (`launch` zeroes and fills `counts` on the stream, given the per-row product bounds); the
+// counts are then read back together with the symbolic totals into `host`.
+struct SymBucket {
+  std::function<void(const int64_t *ub)> launch;
+  const int *counts = nullptr;
+  int *host = nullptr;
+  int nc = 0;
+};
 void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
                      const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
-                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out = nullptr);
+                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out = nullptr,
+                     const SymBucket *bk = nullptr);
 // C = A B on 3x3 block matrices: the scalar product of their expansions, bit for bit (B's
 // blocks diagonal when diagb).
 void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s, int *dflag);

@@ -321,7 +321,14 @@ std::vector<PinnedRead> g_pin_pool;   // kept until the process ends
 }  // namespace
 
 void d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
-  require(bytes <= 256, MGR_ERR_ARG, "d2h_sync: at most 256 bytes");
+  const D2HPart part{dst, src, bytes};
+  d2h_sync_parts(&part, 1, s);
+}
+
+void d2h_sync_parts(const D2HPart *parts, int np, hipStream_t s) {
+  size_t total = 0;
+  for (int i = 0; i < np; ++i) total += (parts[i].bytes + 15) / 16 * 16;
+  require(total <= 256, MGR_ERR_ARG, "d2h_sync: at most 256 bytes");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   PinnedRead b;
@@ -348,14 +355,24 @@ void d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
     HIPCHK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
     HIPCHK(hipHostMalloc(&b.p, 256, hipHostMallocDefault));
   }
-  HIPCHK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyDeviceToHost, s));
+  size_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    if (parts[i].bytes)
+      HIPCHK(hipMemcpyAsync(static_cast<char *>(b.p) + off, parts[i].src, parts[i].bytes,
+                            hipMemcpyDeviceToHost, s));
+    off += (parts[i].bytes + 15) / 16 * 16;
+  }
   HIPCHK(hipEventRecord(b.ev, s));
   for (;;) {
     const hipError_t e = hipEventQuery(b.ev);
     if (e == hipSuccess) break;
     if (e != hipErrorNotReady) HIPCHK(e);
   }
-  std::memcpy(dst, b.p, bytes);
+  off = 0;
+  for (int i = 0; i < np; ++i) {
+    if (parts[i].bytes) std::memcpy(parts[i].dst, static_cast<char *>(b.p) + off, parts[i].bytes);
+    off += (parts[i].bytes + 15) / 16 * 16;
+  }
 }
 
 int read_flag(const int *dflag, hipStream_t s) {

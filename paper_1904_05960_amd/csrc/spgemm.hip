@@ -708,7 +708,8 @@ int lanes_for(double mean) { return mean > 48 ? 64 : mean > 24 ? 32 : mean > 6 ?
 
 void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, const int *brp,
                      const int *bci, int64_t bn, int64_t bm, int64_t bnnz, int *crp,
-                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out) {
+                     int64_t &cnnz, hipStream_t s, int *dflag, DArr<int64_t> *ub_out,
+                     const SymBucket *bk) {
   DArr<int64_t> ub(n, s);
   k_upper_bound<<<grid_for(n * 16, 256), 256, 0, s>>>(n, arp, aci, brp, ub.p);
   KCHK();
@@ -734,8 +735,12 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
   KCHK();
   // the scan assumes that pass 1 counted every row; it is repeated when some did not fit
   exclusive_scan_i32_async(cnt.p, crp, n, s, rbk.p + 1);
+  if (bk) bk->launch(ub.p);
   int64_t hb[2];
-  d2h_sync(hb, rbk.p, sizeof(hb), s);
+  const D2HPart parts[2] = {{hb, rbk.p, sizeof(hb)},
+                            {bk ? bk->host : nullptr, bk ? bk->counts : nullptr,
+                             bk ? bk->nc * sizeof(int) : 0}};
+  d2h_sync_parts(parts, 2, s);
   const int hretry = reinterpret_cast<const int *>(hb)[0];
   if (hretry == 0) {
     require(hb[1] <= 0x7fffffffLL, MGR_ERR_UNSUPPORTED,
@@ -774,6 +779,10 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
     }
   }
   cnnz = exclusive_scan_i32(cnt.p, crp, n, s);
+  if (bk) {
+    bk->launch(ub.p);
+    d2h_sync(bk->host, bk->counts, bk->nc * sizeof(int), s);
+  }
   if (ub_out) *ub_out = std::move(ub);
 }
 
@@ -846,18 +855,23 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
     }
     return;
   }
+  // rows bucketed by output length for the numeric phase (read back with the symbolic totals)
+  DArr<int> lists((size_t)NBS * n, s), counts(NBS, s);
+  int hc[NBS] = {};
+  SymBucket bk;
+  bk.launch = [&](const int64_t *) {
+    fill<int>(counts.p, 0, NBS, s);
+    k_bucket_s<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
+    KCHK();
+  };
+  bk.counts = counts.p;
+  bk.host = hc;
+  bk.nc = NBS;
   spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnz, B.rp.p, B.ci.p, B.n, B.m, B.nnz, C.rp.p, C.nnz, s,
-                  dflag);
+                  dflag, nullptr, &bk);
   C.ci.alloc(C.nnz, s);
   C.v.alloc(C.nnz, s);
   if (C.nnz == 0) return;
-  // numeric phase by output row length
-  DArr<int> lists((size_t)NBS * n, s), counts(NBS, s);
-  fill<int>(counts.p, 0, NBS, s);
-  k_bucket_s<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, lists.p, counts.p, n);
-  KCHK();
-  int hc[NBS];
-  d2h_sync(hc, counts.p, sizeof(hc), s);
   const int g0 = lanes_for(meanB);
   for (int b = 0; b < NBS - 1; ++b)
     if (hc[b] > 0) dispatch_num(b, g0, hc[b], lists.p + (size_t)b * n, A, B, C, dflag, s);
@@ -1158,20 +1172,26 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
     return;
   }
   DArr<int64_t> ub;
+  // rows by output block count; LDS tables of twice that (<= 21 KB per 64-lane workgroup,
+  // so that several workgroups share a CU), rows beyond 256 blocks in global memory (read
+  // back with the symbolic totals)
+  DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
+  int hc[NBUCKET] = {};
+  SymBucket bk;
+  bk.launch = [&](const int64_t *ubp) {
+    fill<int>(counts.p, 0, NBUCKET, s);
+    k_bucket_b3<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, A.rp.p, ubp, diagb ? 1 : 0, lists.p,
+                                                  counts.p, n);
+    KCHK();
+  };
+  bk.counts = counts.p;
+  bk.host = hc;
+  bk.nc = NBUCKET;
   spgemm_symbolic(n, A.rp.p, A.ci.p, A.nnzb, B.rp.p, B.ci.p, B.nb, B.mb, B.nnzb, C.rp.p, C.nnzb,
-                  s, dflag, &ub);
+                  s, dflag, &ub, &bk);
   C.ci.alloc(std::max<int64_t>(C.nnzb, 1), s);
   C.v.alloc(std::max<int64_t>(9 * C.nnzb, 1), s);
   if (C.nnzb == 0) return;
-  // rows by output block count; LDS tables of twice that (<= 21 KB per 64-lane workgroup,
-  // so that several workgroups share a CU), rows beyond 256 blocks in global memory
-  DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
-  fill<int>(counts.p, 0, NBUCKET, s);
-  k_bucket_b3<<<grid_for(n, 256), 256, 0, s>>>(n, C.rp.p, A.rp.p, ub.p, diagb ? 1 : 0, lists.p,
-                                                counts.p, n);
-  KCHK();
-  int hc[NBUCKET];
-  d2h_sync(hc, counts.p, sizeof(hc), s);
   if (hc[0] > 0) launch_num_b3<16, 64>(diagb, hc[0], lists.p, A, B, C, dflag, s);
   if (hc[1] > 0) launch_num_b3<32, 128>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
   if (hc[2] > 0) launch_num_b3<64, 256>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
