@@ -4,8 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <functional>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <utility>
