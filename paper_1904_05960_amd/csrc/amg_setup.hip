@@ -71,36 +71,63 @@ __global__ void k_node_norms(int64_t nn, const int *__restrict__ rp, const int *
     f[nrp[I] + q] = acc;
   }
 }
+// 16 lanes per node row; the lane that holds the diagonal entry hands it to the others
+constexpr int NG = 16;
 __global__ void k_node_diag(int64_t nn, const int *__restrict__ nrp, const int *__restrict__ nci,
                             const double *__restrict__ f, double *__restrict__ fd) {
-  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / NG;
+  const int l = threadIdx.x & (NG - 1);
   if (I >= nn) return;
   double x = 0.0;
-  for (int e = nrp[I]; e < nrp[I + 1]; ++e)
-    if (nci[e] == I) x = f[e];
-  fd[I] = x;
+  int found = 0;
+  for (int e = nrp[I] + l; e < nrp[I + 1]; e += NG)
+    if (nci[e] == I) {
+      x = f[e];
+      found = 1;
+    }
+#pragma unroll
+  for (int o = NG / 2; o > 0; o >>= 1) {
+    const double ox = __shfl_xor(x, o, NG);
+    const int of = __shfl_xor(found, o, NG);
+    if (of && !found) {
+      x = ox;
+      found = 1;
+    }
+  }
+  if (l == 0) fd[I] = x;
 }
+// 16 lanes per node row, the row taken 16 entries at a time; strong entries are written in
+// row order (each lane's place from a ballot of its group)
 template <int MODE>
 __global__ void k_strength_nodal(int64_t nn, const int *__restrict__ nrp, const int *__restrict__ nci,
                                  const double *__restrict__ f, const double *__restrict__ fd,
                                  double th4, int *__restrict__ cnt, const int *__restrict__ srp,
                                  int *__restrict__ sci) {
-  int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / NG;
+  const int l = threadIdx.x & (NG - 1);
   if (I >= nn) return;
   const double fi = fd[I];
   int c = 0;
   const int o = MODE ? srp[I] : 0;
-  for (int e = nrp[I]; e < nrp[I + 1]; ++e) {
-    const int J = nci[e];
-    if (J == I) continue;
-    const double x = f[e];
-    const bool strong = x != 0.0 && __dmul_rn(x, x) >= __dmul_rn(th4, __dmul_rn(fi, fd[J]));
-    if (strong) {
-      if (MODE) sci[o + c] = J;
-      ++c;
+  const int e0 = nrp[I], e1 = nrp[I + 1];
+  for (int c0 = e0; c0 < e1; c0 += NG) {
+    const int e = c0 + l;
+    bool strong = false;
+    int J = 0;
+    if (e < e1) {
+      J = nci[e];
+      if (J != I) {
+        const double x = f[e];
+        strong = x != 0.0 && __dmul_rn(x, x) >= __dmul_rn(th4, __dmul_rn(fi, fd[J]));
+      }
     }
+    const uint64_t b = __ballot(strong);
+    const int base = (int)(threadIdx.x & 63) & ~(NG - 1);
+    const uint32_t gb = (uint32_t)((b >> base) & ((1ull << NG) - 1));
+    if (MODE && strong) sci[o + c + __popc(gb & ((1u << l) - 1))] = J;
+    c += __popc(gb);
   }
-  if (!MODE) cnt[I] = c;
+  if (!MODE && l == 0) cnt[I] = c;
 }
 
 __global__ void k_prio(int64_t n, unsigned long long salt, unsigned long long *__restrict__ prio,
@@ -259,18 +286,18 @@ void strength_graph(const Csr &A, int bs, double theta, AmgGraph &G, hipStream_t
     k_node_norms<16><<<grid_for(nn * 16, 256), 256, 0, s>>>(nn, A.rp.p, A.ci.p, A.v.p, nrp,
                                                             nullptr, f.p);
     KCHK();
-    k_node_diag<<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p);
+    k_node_diag<<<grid_for(nn * NG, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p);
     KCHK();
     const double th4 = th2 * th2;
     DArr<int> cnt(nn + 1, s);
-    k_strength_nodal<0><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4, cnt.p,
+    k_strength_nodal<0><<<grid_for(nn * NG, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4, cnt.p,
                                                          nullptr, nullptr);
     KCHK();
     S.n = S.m = nn;
     S.rp.alloc(nn + 1, s);
     S.nnz = exclusive_scan_i32(cnt.p, S.rp.p, nn, s);
     S.ci.alloc(S.nnz, s);
-    k_strength_nodal<1><<<grid_for(nn, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4,
+    k_strength_nodal<1><<<grid_for(nn * NG, 256), 256, 0, s>>>(nn, nrp, nci, f.p, fd.p, th4,
                                                          nullptr, S.rp.p, S.ci.p);
     KCHK();
   }

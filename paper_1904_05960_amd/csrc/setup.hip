@@ -528,14 +528,29 @@ __global__ void __launch_bounds__(64) k_rank_sort_rows(int64_t n, const int *__r
 }
 
 // ---------------------------------------------------------------------------------
+// 16 lanes per row; the lane that holds the diagonal entry hands it to the others
 __global__ void k_diag(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
                        const double *__restrict__ v, double *__restrict__ d) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 16;
+  const int l = threadIdx.x & 15;
   if (i >= n) return;
   double x = 0.0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e)
-    if (ci[e] == i) x = v[e];
-  d[i] = x;
+  int found = 0;
+  for (int e = rp[i] + l; e < rp[i + 1]; e += 16)
+    if (ci[e] == i) {
+      x = v[e];
+      found = 1;
+    }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    const double ox = __shfl_xor(x, o, 16);
+    const int of = __shfl_xor(found, o, 16);
+    if (of && !found) {
+      x = ox;
+      found = 1;
+    }
+  }
+  if (l == 0) d[i] = x;
 }
 // rs_i / |a_ii| with rs_i summed in ascending column order
 __global__ void k_gershgorin(int64_t n, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -1000,7 +1015,7 @@ void transpose(const Csr &A, Csr &T, bool values, hipStream_t s) {
 
 void diag_of(const Csr &A, double *d, hipStream_t s) {
   if (A.n == 0) return;
-  k_diag<<<grid_for(A.n, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d);
+  k_diag<<<grid_for(A.n * 16, 256), 256, 0, s>>>(A.n, A.rp.p, A.ci.p, A.v.p, d);
   KCHK();
 }
 
