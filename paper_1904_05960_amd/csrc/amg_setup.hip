@@ -138,25 +138,34 @@ __global__ void k_prio(int64_t n, unsigned long long salt, unsigned long long *_
   state[i] = (grp[i + 1] == grp[i]) ? ISOLATED : UNDECIDED;
 }
 
+// The graph kernels below take G lanes per node (G = 1 for short rows, 16 for the long rows
+// of the coarse levels); maxima, ORs and the first best neighbour do not depend on how a
+// row is split among lanes.
 // out[i] = max(val[i], max over neighbours) where val = prio masked to undecided nodes (MODE 0)
 // or a previous max (MODE 1)
-template <int MODE>
+template <int MODE, int G>
 __global__ void k_rowmax(int64_t n, const int *__restrict__ grp, const int *__restrict__ gci,
                          const unsigned long long *__restrict__ prio,
                          const int8_t *__restrict__ state, const unsigned long long *__restrict__ in,
                          unsigned long long *__restrict__ out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (i >= n) return;
   auto val = [&](int64_t j) -> unsigned long long {
     if (MODE == 0) return state[j] == UNDECIDED ? prio[j] : 0ull;
     return in[j];
   };
-  unsigned long long m = val(i);
-  for (int e = grp[i]; e < grp[i + 1]; ++e) {
+  unsigned long long m = l == 0 ? val(i) : 0ull;
+  for (int e = grp[i] + l; e < grp[i + 1]; e += G) {
     unsigned long long x = val(gci[e]);
     m = x > m ? x : m;
   }
-  out[i] = m;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(m, o, G);
+    m = x > m ? x : m;
+  }
+  if (l == 0) out[i] = m;
 }
 __global__ void k_select(int64_t n, const unsigned long long *__restrict__ prio,
                          const unsigned long long *__restrict__ m2, int8_t *__restrict__ state,
@@ -167,13 +176,17 @@ __global__ void k_select(int64_t n, const unsigned long long *__restrict__ prio,
   if (sel) state[i] = SELECTED;
   isnew[i] = sel;
 }
+template <int G>
 __global__ void k_rowany(int64_t n, const int *__restrict__ grp, const int *__restrict__ gci,
                          const int *__restrict__ in, int *__restrict__ out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (i >= n) return;
-  int a = in[i];
-  for (int e = grp[i]; e < grp[i + 1] && !a; ++e) a = in[gci[e]];
-  out[i] = a;
+  int a = l == 0 ? in[i] : 0;
+  for (int e = grp[i] + l; e < grp[i + 1] && !a; e += G) a = in[gci[e]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) a |= __shfl_xor(a, o, G);
+  if (l == 0) out[i] = a != 0;
 }
 __global__ void k_remove(int64_t n, const int *__restrict__ near, int8_t *__restrict__ state,
                          int *__restrict__ und) {
@@ -201,22 +214,34 @@ __global__ void k_root_ids(int64_t n, const int8_t *__restrict__ state, const in
 }
 // best neighbour by priority among candidates; PASS 1: candidates are roots, PASS 2:
 // candidates are nodes aggregated after pass 1 (agg1)
-template <int PASS>
+// (the first neighbour in row order among those of the largest priority)
+template <int PASS, int G>
 __global__ void k_agg_pass(int64_t n, const int *__restrict__ grp, const int *__restrict__ gci,
                            const unsigned long long *__restrict__ prio,
                            const int8_t *__restrict__ state, const int *__restrict__ agg1,
                            int *__restrict__ agg) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
   if (i >= n) return;
-  if (state[i] == ISOLATED || agg1[i] >= 0) return;
-  int best = -1;
+  if (state[i] == ISOLATED || agg1[i] >= 0) return;   // uniform over the node's lanes
+  int best = -1, be = 0x7fffffff;
   unsigned long long bp = 0;
-  for (int e = grp[i]; e < grp[i + 1]; ++e) {
+  for (int e = grp[i] + l; e < grp[i + 1]; e += G) {
     const int j = gci[e];
     const bool cand = (PASS == 1) ? state[j] == SELECTED : agg1[j] >= 0;
-    if (cand && (best < 0 || prio[j] > bp)) { best = j; bp = prio[j]; }
+    if (cand && (best < 0 || prio[j] > bp)) { best = j; bp = prio[j]; be = e; }
   }
-  if (best >= 0) agg[i] = agg1[best];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const int ob = __shfl_xor(best, o, G), oe = __shfl_xor(be, o, G);
+    const unsigned long long op = __shfl_xor(bp, o, G);
+    if (ob >= 0 && (best < 0 || op > bp || (op == bp && oe < be))) {
+      best = ob;
+      bp = op;
+      be = oe;
+    }
+  }
+  if (l == 0 && best >= 0) agg[i] = agg1[best];
 }
 __global__ void k_leftover_flags(int64_t n, const int8_t *__restrict__ state,
                                  const int *__restrict__ agg, int *__restrict__ fl) {
@@ -319,17 +344,34 @@ void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
   const unsigned long long salt = GOLDEN * (unsigned long long)(level + 1);
   k_prio<<<gs, 256, 0, s>>>(n, salt, prio.p, G.rp.p, state.p);
   KCHK();
+  // 16 lanes per node for the long rows of the coarse levels' graphs
+  const bool wide = n > 0 && (double)G.ci.n > 16.0 * (double)n;
+  const unsigned gw = grid_for(n * 16, 256);
   for (int round = 0; round < 100000; ++round) {
-    k_rowmax<0><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, nullptr, m1.p);
-    KCHK();
-    k_rowmax<1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, m1.p, m2.p);
-    KCHK();
+    if (wide) {
+      k_rowmax<0, 16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, nullptr, m1.p);
+      KCHK();
+      k_rowmax<1, 16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, m1.p, m2.p);
+      KCHK();
+    } else {
+      k_rowmax<0, 1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, nullptr, m1.p);
+      KCHK();
+      k_rowmax<1, 1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, m1.p, m2.p);
+      KCHK();
+    }
     k_select<<<gs, 256, 0, s>>>(n, prio.p, m2.p, state.p, a.p);
     KCHK();
-    k_rowany<<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, a.p, b.p);
-    KCHK();
-    k_rowany<<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, b.p, a.p);
-    KCHK();
+    if (wide) {
+      k_rowany<16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, a.p, b.p);
+      KCHK();
+      k_rowany<16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, b.p, a.p);
+      KCHK();
+    } else {
+      k_rowany<1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, a.p, b.p);
+      KCHK();
+      k_rowany<1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, b.p, a.p);
+      KCHK();
+    }
     fill<int>(und.p, 0, 1, s);
     k_remove<<<gs, 256, 0, s>>>(n, a.p, state.p, und.p);
     KCHK();
@@ -347,10 +389,12 @@ void mis2_aggregate(const AmgGraph &G, int level, DArr<int> &agg, int64_t &nagg,
   KCHK();
   agg.alloc(n, s);
   HIPCHK(hipMemcpyAsync(agg.p, agg1.p, n * sizeof(int), hipMemcpyDeviceToDevice, s));
-  k_agg_pass<1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
+  if (wide) k_agg_pass<1, 16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
+  else k_agg_pass<1, 1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
   KCHK();
   HIPCHK(hipMemcpyAsync(agg1.p, agg.p, n * sizeof(int), hipMemcpyDeviceToDevice, s));
-  k_agg_pass<2><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
+  if (wide) k_agg_pass<2, 16><<<gw, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
+  else k_agg_pass<2, 1><<<gs, 256, 0, s>>>(n, G.rp.p, G.ci.p, prio.p, state.p, agg1.p, agg.p);
   KCHK();
   k_leftover_flags<<<gs, 256, 0, s>>>(n, state.p, agg.p, fl.p);
   KCHK();
