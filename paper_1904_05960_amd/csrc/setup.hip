@@ -157,12 +157,14 @@ __global__ void k_extract_fill(int64_t n, const int *__restrict__ rp, const int 
   }
 }
 
+// 8 lanes per row
 __global__ void k_scale_rows_div(int64_t n, const int *__restrict__ rp, double *__restrict__ v,
                                  const double *__restrict__ d) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 8;
+  const int l = threadIdx.x & 7;
   if (i >= n) return;
   const double di = d[i];
-  for (int e = rp[i]; e < rp[i + 1]; ++e) v[e] = __ddiv_rn(v[e], di);
+  for (int e = rp[i] + l; e < rp[i + 1]; e += 8) v[e] = __ddiv_rn(v[e], di);
 }
 
 __global__ void k_check_nonzero(const double *__restrict__ d, int64_t n, int *flag) {
@@ -915,7 +917,7 @@ void same_entity_filter(const Csr &Acf, const int *C, const int *F, const int *r
 
 void scale_rows_div(Csr &M, const double *d, hipStream_t s) {
   if (M.n == 0) return;
-  k_scale_rows_div<<<grid_for(M.n, 256), 256, 0, s>>>(M.n, M.rp.p, M.v.p, d);
+  k_scale_rows_div<<<grid_for(M.n * 8, 256), 256, 0, s>>>(M.n, M.rp.p, M.v.p, d);
   KCHK();
 }
 
