@@ -156,17 +156,6 @@ def test_nodal_tentative_unknown_approach():
     assert np.array_equal(T, exp)
 
 
-def test_nodal_strength_matches_scalar_on_kron():
-    """For A = A_s (x) I_3 the squared Frobenius norm of block (I, J) is 3 a_IJ^2, so the
-    nodal test with theta reproduces the scalar strength graph of A_s."""
-    As = poisson3d(4)
-    D = np.kron(As.to_dense(), np.eye(3))
-    A3 = CSR.from_dense(D, np.kron(As.to_dense() != 0, np.ones((3, 3), dtype=bool)))
-    g1 = amg.strength_graph(As, 0.2, 1)
-    g3 = amg.strength_graph(A3, 0.2, 3)
-    assert np.array_equal(g1[0], g3[0]) and np.array_equal(g1[1], g3[1])
-
-
 def test_vcycle_contracts_on_poisson():
     """Textbook behaviour: the SA-AMG V-cycle with l1-Jacobi is a convergent iteration on the
     3D Poisson problem."""
