@@ -3,11 +3,14 @@
 One step = the whole hot path on one synthetic Jacobian already resident in HBM:
 mgr_setup (C/F splits, W_p, A_cor by pinned-order SpGEMM, G, coarse operators, both AMG
 hierarchies, FP32 cast, graph capture on first apply) + fgmres_solve to rtol = 1e-6 +
-mgr_destroy.  Default workload: two-phase poromechanics on a 64^3 cell grid (1,348,163
-unknowns, 92,914,761 nonzeros), paper reduction order (displacement, saturation,
-pressure), FP32 hierarchy inside FP64 FGMRES(64).
+mgr_destroy.  Default workload: three-phase poromechanics on a 96^3 cell grid (5,392,227
+unknowns, 371,569,257 nonzeros), four-level MGR in the paper's reduction order
+(displacement with an FP32 3x3-block AMG F-relaxation, then gas saturation, water
+saturation, pressure AMG), FP32 hierarchy inside FP64 FGMRES(64).  The two-phase 64^3
+case (1,348,163 unknowns) is also timed and reported under "two_phase_64".
 
-    python bench.py [--steps K] [--warmup W] [--size 64] [--precision fp32|fp64]
+    python bench.py [--steps K] [--warmup W] [--workload three|two] [--size 96]
+                    [--precision fp32|fp64]
                     [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
                     [--global-smoother block_jacobi|block_gs] [--global-sweeps 3]
 
@@ -72,10 +75,12 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(size_full_n, restart, workload="two"):
+def cpu_baseline(size_full_n, restart, workload, gpu_iters):
     """The oracle (FP64, NumPy/SciPy, untuned) on a bounded sample of the same workload
-    recipe (24^3 two-phase, 20^3 three-phase): setup + FGMRES to 1e-6, scaled linearly by
-    unknowns."""
+    recipe (24^3 two-phase, 20^3 three-phase): setup + FGMRES to 1e-6.  Its setup time is
+    scaled by unknowns; its time per FGMRES iteration is scaled by unknowns and multiplied
+    by the iteration count of the GPU run at full size (the sample itself needs a
+    different number of iterations)."""
     from oracle import krylov as okry
     from oracle import mgr as omgr
     from oracle.sparse import CSR
@@ -94,13 +99,16 @@ def cpu_baseline(size_full_n, restart, workload="two"):
     cpu = (c1.user - c0.user) + (c1.system - c0.system)
     wall = t2 - t0
     scale = size_full_n / w.n
+    per_it = (t2 - t1) / max(r.iters, 1)
+    value = ((t1 - t0) + per_it * gpu_iters) * scale
     return {
-        "value": round(wall * 1e3 * scale, 1), "unit": "ms",
+        "value": round(value * 1e3, 1), "unit": "ms",
         "cores": max(1, round(cpu / wall)),
         "kind": "oracle",
         "sample": (f"oracle setup + FGMRES({restart}) to 1e-6 on the {w.name} grid of the same "
-                   f"recipe ({w.n} unknowns, {r.iters} iterations, setup {1e3*(t1-t0):.0f} ms, "
-                   f"solve {1e3*(t2-t1):.0f} ms), scaled by unknowns x{scale:.2f}"),
+                   f"recipe ({w.n} unknowns: setup {1e3*(t1-t0):.0f} ms, {r.iters} iterations "
+                   f"in {1e3*(t2-t1):.0f} ms = {1e3*per_it:.1f} ms each); value = (setup + "
+                   f"{gpu_iters} iterations, the GPU run's count) x {scale:.2f} (unknowns ratio)"),
         "host_cpus": os.cpu_count(),
     }
 
@@ -122,13 +130,72 @@ def stream_copy_gbs(m, torch, nbytes=1 << 30, reps=5):
     return 2.0 * nbytes * reps / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
 
 
+def make_opts(m, a, model, precision):
+    mk0 = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
+    kw = dict(precision=precision)
+    if a.plan == "paper":
+        kw.update(global_smoother=a.global_smoother, global_sweeps=a.global_sweeps)
+    opts = mk0(model, **kw)
+    if a.drop_tol is not None:
+        for L in opts.levels:
+            if 0 in L.f_labels:
+                L.nmax, L.drop_tol = -1, float(a.drop_tol)
+    return opts
+
+
+class Case:
+    """One workload resident in HBM, with the step (setup + FGMRES to 1e-6 + destroy)."""
+
+    def __init__(self, m, torch, a, workload, size):
+        t = time.perf_counter()
+        self.w = WORKLOADS[workload][0](size)
+        print(f"[bench] generated {self.w.name}: n={self.w.n} nnz={self.w.nnz} in "
+              f"{time.perf_counter()-t:.1f}s", file=sys.stderr, flush=True)
+        self.m, self.torch, self.a, self.model = m, torch, a, WORKLOADS[workload][2]
+        w = self.w
+        self.A = m.Matrix.from_host(w.indptr, w.indices, w.data)
+        self.labels = torch.as_tensor(w.labels).cuda()
+        self.b = torch.as_tensor(w.b).cuda()
+        self.x = torch.zeros_like(self.b)
+        self.work = m.Workspace(w.n, a.restart)
+        self.stream = torch.cuda.current_stream()
+
+    def step(self, prec, record=None):
+        m, torch = self.m, self.torch
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(self.stream)
+        P = m.Preconditioner(self.A, self.labels, make_opts(m, self.a, self.model, prec))
+        ev[1].record(self.stream)
+        self.x.zero_()
+        _, info = m.fgmres(self.A, self.b, x=self.x, M=P, restart=self.a.restart, rtol=1e-6,
+                           maxit=1000, work=self.work)
+        ev[2].record(self.stream)
+        P.close()
+        if record is not None:
+            record.append((ev, info))
+        return info
+
+    def errors(self):
+        import numpy as np
+        xs = self.x.cpu().numpy()
+        w = self.w
+        true = float(np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b))
+        err = float(np.linalg.norm(xs - w.x_true) / np.linalg.norm(w.x_true))
+        return true, err
+
+    def close(self):
+        del self.A, self.labels, self.b, self.x, self.work
+        self.torch.cuda.synchronize()
+        self.torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="two", choices=sorted(WORKLOADS))
-    ap.add_argument("--size", type=int, default=None, help="cells per side (64 two, 96 three)")
+    ap.add_argument("--workload", default="three", choices=sorted(WORKLOADS))
+    ap.add_argument("--size", type=int, default=None, help="cells per side (96 three, 64 two)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
     ap.add_argument("--global-smoother", default="block_jacobi",
@@ -139,6 +206,8 @@ def main():
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-hierarchy step")
+    ap.add_argument("--no-two-phase", action="store_true",
+                    help="skip the extra two-phase 64^3 measurement")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -151,45 +220,12 @@ def main():
     from paper_1904_05960_amd import mgr355 as m
 
     torch.cuda.set_device(0)
-    t = time.perf_counter()
     if a.size is None:
         a.size = 64 if a.workload == "two" else 96
-    w = WORKLOADS[a.workload][0](a.size)
-    print(f"[bench] generated {w.name}: n={w.n} nnz={w.nnz} in {time.perf_counter()-t:.1f}s",
-          file=sys.stderr, flush=True)
-    A = m.Matrix.from_host(w.indptr, w.indices, w.data)
-    labels = torch.as_tensor(w.labels).cuda()
-    b = torch.as_tensor(w.b).cuda()
-    x = torch.zeros_like(b)
-    work = m.Workspace(w.n, a.restart)
-    mk0 = m.paper_plan if a.plan == "paper" else m.saturation_first_plan
-
-    def mk(model, **kw):
-        if a.plan == "paper":
-            kw = dict(kw, global_smoother=a.global_smoother, global_sweeps=a.global_sweeps)
-        opts = mk0(model, **kw)
-        if a.drop_tol is not None:
-            for L in opts.levels:
-                if 0 in L.f_labels:
-                    L.nmax, L.drop_tol = -1, float(a.drop_tol)
-        return opts
-    stream = torch.cuda.current_stream()
-
-    def step(prec, record=None):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record(stream)
-        P = m.Preconditioner(A, labels, mk(WORKLOADS[a.workload][2], precision=prec))
-        ev[1].record(stream)
-        x.zero_()
-        _, info = m.fgmres(A, b, x=x, M=P, restart=a.restart, rtol=1e-6, maxit=1000, work=work)
-        ev[2].record(stream)
-        P.close()
-        if record is not None:
-            record.append((ev, info))
-        return info
+    c = Case(m, torch, a, a.workload, a.size)
 
     for i in range(a.warmup):
-        step(a.precision)
+        c.step(a.precision)
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     m.profile_enable(1, True)            # HIP events around every outer SpMV launch
@@ -197,7 +233,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        step(a.precision, rec)
+        c.step(a.precision, rec)
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, spmv_ms, spmv_bytes = m.profile_read(1)
@@ -206,30 +243,57 @@ def main():
     setup_ms = [r[0][0].elapsed_time(r[0][1]) for r in rec]
     solve_ms = [r[0][1].elapsed_time(r[0][2]) for r in rec]
     info = rec[-1][1]
-    xs = x.cpu().numpy()
-    true = float(np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b))
-    err = float(np.linalg.norm(xs - w.x_true) / np.linalg.norm(w.x_true))
+    true, err = c.errors()
     print(f"[bench] timed {a.steps} steps: {ms_step:.1f} ms/step, iters {info['iters']}",
           file=sys.stderr, flush=True)
 
     compare = None
     if not a.no_compare:
         other = "fp64" if a.precision == "fp32" else "fp32"
+        c.step(other)                     # warm-up of the other precision
         r2 = []
-        step(other, r2)
+        for _ in range(3):
+            c.step(other, r2)
         torch.cuda.synchronize()
-        compare = {"precision": other, "ms": round(r2[0][0][0].elapsed_time(r2[0][0][2]), 2),
-                   "iters": r2[0][1]["iters"], "true_relres": r2[0][1]["true_relres"]}
+        tot = [r[0][0].elapsed_time(r[0][2]) for r in r2]
+        compare = {"precision": other, "ms": round(float(np.median(tot)), 2),
+                   "of": "median of 3 steps after 1 warm-up",
+                   "iters": r2[-1][1]["iters"], "true_relres": r2[-1][1]["true_relres"]}
+        print(f"[bench] {other} hierarchy: {compare['ms']} ms/step", file=sys.stderr, flush=True)
+    c.close()
+
+    two = None
+    if not a.no_two_phase and not (a.workload == "two" and a.size == 64):
+        c2 = Case(m, torch, a, "two", 64)
+        c2.step(a.precision)
+        r3 = []
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(5):
+            c2.step(a.precision, r3)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t2r, _ = c2.errors()
+        two = {"workload": WORKLOADS["two"][4].format(n=64), "unknowns": c2.w.n,
+               "nnz": c2.w.nnz, "ms_per_step": round((t3 - t2) * 1e3 / 5, 2),
+               "setup_ms": round(float(np.median([r[0][0].elapsed_time(r[0][1]) for r in r3])), 2),
+               "solve_ms": round(float(np.median([r[0][1].elapsed_time(r[0][2]) for r in r3])), 2),
+               "iterations": r3[-1][1]["iters"], "true_relres": t2r}
+        print(f"[bench] two-phase 64^3: {two['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+        c2.close()
 
     copy_gbs = stream_copy_gbs(m, torch)
     avg_launch_ms = spmv_ms / max(launches, 1)
     bytes_per_launch = spmv_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    # counter traffic is recorded for the default workload only
+    # counter traffic is recorded for the default sizes of the two workloads
     traffic = None
-    if a.workload == "two" and a.size == 64:
+    prof = {("two", 64): "spmv_outer_twophase_64.md",
+            ("three", 96): "spmv_outer_threephase_96.md"}.get((a.workload, a.size))
+    if prof is not None:
         traffic = traffic_from_profile(
-            "spmv64_twophase_64.md", os.path.join(ROOT, "paper_1904_05960_amd", "csrc", "krylov.hip"))
+            prof, os.path.join(ROOT, "paper_1904_05960_amd", "csrc", "krylov.hip"))
+    w = c.w
     out = {
         "metric": "MGR-FGMRES time-to-1e-6 relative FP64 residual (setup + solve)",
         "value": round(ms_step, 2),
@@ -250,8 +314,9 @@ def main():
                           else "saturations -> displacement -> pressure AMG"),
             "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
             "global_smoother": f"{a.global_smoother} x{a.global_sweeps}",
-            "dropping": ("N_max = 4 on the displacement level" if a.drop_tol is None
-                         else f"tolerance {a.drop_tol} on the displacement level"),
+            "dropping": ("N_max = 4 on the displacement and saturation levels"
+                         if a.workload == "three" else "N_max = 4 on the displacement level")
+            if a.drop_tol is None else f"tolerance {a.drop_tol} on the displacement level",
             "rtol": 1e-6, "parallelism": "single GPU",
         },
         "iterations": info["iters"],
@@ -260,6 +325,7 @@ def main():
         "setup_ms": round(float(np.median(setup_ms)), 2),
         "solve_ms": round(float(np.median(solve_ms)), 2),
         "compare_other_precision": compare,
+        "two_phase_64": two,
         "roofline": {
             "kernel": "outer FP64 CSR-stream SpMV (k_spmv_stream, 2048-entry row blocks)",
             "bound": "hbm",
@@ -275,7 +341,7 @@ def main():
         },
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.n, a.restart, a.workload)
+        out["cpu_baseline"] = cpu_baseline(w.n, a.restart, a.workload, info["iters"])
     print(json.dumps(out), flush=True)
 
 
