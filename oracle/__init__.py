@@ -17,6 +17,9 @@ Modules
             coarsest (pressure) grid: strength, MIS(2), aggregation, smoothed P, Galerkin
             coarse operators, l1-Jacobi V-cycle, dense LU at the coarsest level
   krylov  - flexible GMRES(m) with modified Gram-Schmidt and Givens rotations
+  ilu     - ILU(k) pattern by levels of fill, factors by synchronous fine-grained
+            fixed-point sweeps, triangular solves exact or by Jacobi sweeps (the global
+            smoother of Sec. 5.3 / Sec. 6)
 
 Parity pins: every function is checked in tests/ against closed forms, identities of
 Sec. 5.1, brute force on tiny inputs, or textbook special cases.  End-to-end iteration

@@ -26,7 +26,14 @@ Readings where the paper is silent (each also listed in the design notes):
     ILU/Gauss-Seidel smoothers of Sec. 5.3): first sweep z = D_B^{-1} v, later sweeps
     z += omega D_B^{-1} (v - A z);
   * the quasi-IMPES option keeps, of A_CF, only the same-entity entries in the coarse
-    product ("its diagonal" under the field-ordered view of Sec. 5.3).
+    product ("its diagonal" under the field-ordered view of Sec. 5.3);
+  * the ILU global smoother (the paper's pointwise ILU(1)) is the fine-grained ILU(k) of
+    ilu.py on the whole level matrix (one GPU has no processor-local blocks) after left
+    scaling by the inverses of the same-cell diagonal blocks, D_B^{-1} A (the scaled
+    product taken with the pinned order of sparse.spgemm): in SI units the pressure rows'
+    own entries are 10^4-10^7 times smaller than their saturation entries, and pointwise
+    pivots on the unscaled rows make the factorisation unstable.  First step
+    z = (LU)^{-1} D_B^{-1} v, later steps z += omega (LU)^{-1} D_B^{-1} (v - A z).
 """
 from __future__ import annotations
 
@@ -36,6 +43,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import amg as amg_mod
+from . import ilu as ilu_mod
 from .sparse import CSR, diagonal, merge_sub, spgemm, submatrix
 
 
@@ -57,6 +65,9 @@ class LevelPlan:
     global_omega: float = 1.0
     coupling: str = "full"           # 'full' | 'quasi_impes' (A_CF of the coarse product)
     drop_tol: float = -1.0           # >= 0: tolerance form of G instead of nmax
+    ilu_level: int = 1               # global_smoother 'ilu': ILU(k) pattern
+    ilu_sweeps: int = 3              # fixed-point sweeps of the factorisation
+    ilu_tri_sweeps: int = 3          # Jacobi sweeps per triangular solve (< 0: exact)
 
 
 @dataclass
@@ -86,6 +97,7 @@ class Level:
     ff_lu: tuple | None = None  # F-relaxation dense LU ('exact')
     blocks: tuple | None = None # global smoother: (rows per block, block inverses)
     colors: np.ndarray | None = None  # block Gauss-Seidel: colour of every cell
+    ilu: object = None          # global smoother 'ilu': the incomplete factors
 
 
 @dataclass
@@ -220,6 +232,15 @@ def same_cell_blocks(A: CSR, labels: np.ndarray):
     return rows, np.linalg.inv(D)
 
 
+def block_diagonal(rows: np.ndarray, inv: np.ndarray, n: int) -> CSR:
+    """The block-diagonal matrix D_B^{-1} with the dense inverses of the same-cell blocks
+    (every entry of a block kept, zeros included)."""
+    nb = rows.shape[1]
+    r = np.repeat(rows, nb, axis=1).ravel()
+    c = np.tile(rows, (1, nb)).ravel()
+    return CSR.from_coo(r, c, inv.reshape(-1), (n, n))
+
+
 def cell_graph(A: CSR, labels: np.ndarray):
     """Graph of the same-cell blocks (cell = per-label rank of a row): cells e != f are
     adjacent when A has an entry between a row of e and a row of f, in either direction.
@@ -310,11 +331,14 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
             L.amg = amg_mod.setup(A_FF, opts)
         elif lp.frelax == "exact":
             L.ff_lu = sla.lu_factor(A_FF.to_dense())
-        if lp.global_smoother in ("block_jacobi", "block_gs"):
+        if lp.global_smoother in ("block_jacobi", "block_gs", "ilu"):
             L.blocks = same_cell_blocks(cur, lab)
         if lp.global_smoother == "block_gs":
             gptr, gcol = cell_graph(cur, lab)
             L.colors = jp_coloring(gptr, gcol, cell_priorities(gptr.shape[0] - 1))
+        if lp.global_smoother == "ilu":
+            L.ilu = ilu_mod.ilu_factor(spgemm(block_diagonal(*L.blocks, cur.shape[0]), cur),
+                                       lp.ilu_level, lp.ilu_sweeps)
         levels.append(L)
         cur, lab = S, lab[C]
     H = Hierarchy(levels=levels, coarse_A=cur, coarse_labels=lab, plan=plan)
@@ -363,6 +387,11 @@ def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
             z = z + lp.global_omega * _block_jacobi(L, v - A.matvec(z))
     elif lp.global_smoother == "block_gs":
         z = _block_gs(L, v, lp.global_sweeps)
+    elif lp.global_smoother == "ilu":
+        z = ilu_mod.ilu_solve(L.ilu, _block_jacobi(L, v), lp.ilu_tri_sweeps)
+        for _ in range(lp.global_sweeps - 1):
+            r = _block_jacobi(L, v - A.matvec(z))
+            z = z + lp.global_omega * ilu_mod.ilu_solve(L.ilu, r, lp.ilu_tri_sweeps)
     else:
         z = np.zeros_like(v)
     # F-relaxation: z <- z + Q M_FF^{-1} Q^T (v - A z)
