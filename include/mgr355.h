@@ -145,12 +145,17 @@ void mgr_default_opts(mgr_opts *o);
 mgr_status mgr_setup(const mgr_csr *A, const int8_t *labels, const mgr_opts *opts,
                      void *stream, mgr_handle **out);
 
-/* Recompute every value of the hierarchy of `h` for a new matrix with exactly the same
- * pattern as the one given to mgr_setup (e.g. the next Newton step), reusing the symbolic
- * work: C/F split, patterns of W_p and A_cor.  Value-dependent decisions (G, AMG strength
- * and aggregates) are recomputed, so the result equals a fresh mgr_setup.
- * Synchronises `stream`.  Errors: PATTERN (row pointer or column arrays differ), ARG,
- * ZERO_PIVOT, ALLOC, HIP. */
+/* Rebuild the hierarchy of `h` for a new matrix with exactly the same pattern as the one
+ * given to mgr_setup (e.g. the next Newton step), keeping the handle, its options, labels
+ * and captured-graph stream: the pattern is checked against the original by a hash, then
+ * every level is rebuilt from the new values (the symbolic work is redone too, since G and
+ * the AMG aggregates depend on values), so the result equals a fresh mgr_setup.  Waits for
+ * the setup stream and for the last apply of the handle before releasing the old
+ * hierarchy.  Synchronises `stream`.  Errors: PATTERN (size or row pointer / column arrays
+ * differ; the old hierarchy is kept and stays usable), ARG, ZERO_PIVOT, ALLOC, HIP; after
+ * any error other than PATTERN and ARG the handle holds no hierarchy: mgr_apply and
+ * fgmres_solve reject it with ARG until a later mgr_setup_numeric succeeds, and it must
+ * still be destroyed. */
 mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream);
 
 /* z = M^{-1} v (Algorithm 2).  v and z are FP64 vectors of length n; they may not alias.
@@ -224,7 +229,10 @@ mgr_status mgr_batch_solve(int32_t k, const mgr_csr *A, const int8_t *const *lab
                            const fgmres_opts *o, double *relres, int32_t *iters,
                            fgmres_result *res, void *stream);
 
-/* Free every device allocation of the handle.  NULL is ignored. */
+/* Free every device allocation of the handle, after waiting for the setup stream and for
+ * the stream of the handle's last mgr_apply / fgmres_solve (applies of one handle on
+ * different streams must be ordered by the caller: they share the handle's work vectors).
+ * NULL is ignored. */
 void mgr_destroy(mgr_handle *h);
 
 /* Bytes of device memory the handle holds. [host out] */
@@ -237,8 +245,9 @@ mgr_status mgr_estimate_footprint(int64_t n, int64_t nnz, const mgr_opts *opts,
                                   size_t *bytes);
 
 /* Route every device allocation of the library through caller functions (e.g. a caching
- * allocator).  Pass NULLs to restore the default (stream-ordered hipMallocAsync).  Not
- * thread-safe with respect to concurrent calls. [host] */
+ * allocator).  Pass NULLs to restore the default: the library's own caching allocator over
+ * hipMalloc (described with mgr_release_cache below).  Not thread-safe with respect to
+ * concurrent calls. [host] */
 void mgr_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
                        void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx);
 

@@ -234,6 +234,8 @@ struct mgr_handle {
   hipStream_t cap = nullptr; // private capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipEvent_t used_ev = nullptr; // recorded after every apply, on the caller's stream
+  bool valid = true;            // false after a failed mgr_setup_numeric
   ~mgr_handle();
 };
 
@@ -635,6 +637,14 @@ void apply_typed(mgr_handle *h, const double *v, double *z, hipStream_t s,
     apply_level<T>(h, 0, v0, z0, s);
   }
   cast_from(z0, z, h->n, s);
+  // the last stream that read the hierarchy: destroy and refresh wait for it
+  if (!h->used_ev) HIPCHK(hipEventCreateWithFlags(&h->used_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(h->used_ev, s));
+}
+
+void wait_uses(mgr_handle *h) {
+  if (h->s) HIPCHK(hipStreamSynchronize(h->s));
+  if (h->used_ev) HIPCHK(hipEventSynchronize(h->used_ev));
 }
 
 void destroy_graph(mgr_handle *h) {
@@ -992,6 +1002,10 @@ mgr_status fail(const Error &e) {
 
 mgr_handle::~mgr_handle() {
   if (s) (void)hipStreamSynchronize(s);
+  if (used_ev) {
+    (void)hipEventSynchronize(used_ev);
+    (void)hipEventDestroy(used_ev);
+  }
   mgr::destroy_graph(this);
   if (cap) (void)hipStreamDestroy(cap);
   // the hierarchy's buffers return to the allocator (every stream they were taken on is
@@ -1058,6 +1072,8 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   require(m >= 1 && m <= 64, MGR_ERR_ARG, "restart must be in [1, 64]");
   require(o->maxit >= 1, MGR_ERR_ARG, "maxit must be positive");
   require(!M || M->n == n, MGR_ERR_ARG, "preconditioner size differs from A");
+  require(!M || M->valid, MGR_ERR_ARG,
+          "the preconditioner holds no setup: its last mgr_setup_numeric failed");
   const size_t need = fg_layout(n, m, nullptr, nullptr);
   DArr<char> own;
   char *base = static_cast<char *>(work);
@@ -1264,7 +1280,8 @@ mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
       require(pattern_hash(tmp, s) == h->pattern, MGR_ERR_PATTERN,
               "sparsity pattern differs from the original matrix");
     }
-    HIPCHK(hipStreamSynchronize(h->s));
+    wait_uses(h);
+    h->valid = false;
     destroy_graph(h);
     h->lv.clear();
     h->coarseA = Csr();
@@ -1277,6 +1294,7 @@ mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
     HIPCHK(hipMemcpyAsync(lab.p, h->labels0.p, h->n, hipMemcpyDeviceToDevice, s));
     build(h, A, lab.p);
     HIPCHK(hipStreamSynchronize(s));
+    h->valid = true;
   } catch (const Error &e) {
     return fail(e);
   } catch (const std::exception &e) {
@@ -1290,6 +1308,7 @@ mgr_status mgr_apply(mgr_handle *h, const double *v, double *z, void *stream) {
   t_err.clear();
   if (!h || !v || !z) { t_err = "null argument"; return MGR_ERR_ARG; }
   try {
+    require(h->valid, MGR_ERR_ARG, "the handle holds no setup: its last mgr_setup_numeric failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (h->opts.precision == MGR_PREC_FP32) apply_typed<float>(h, v, z, s);
     else apply_typed<double>(h, v, z, s);

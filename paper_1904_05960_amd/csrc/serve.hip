@@ -230,7 +230,11 @@ void worker(mgr_server *S, int slot) {
               rescan = true;
               break;
             }
+            // a cached setup this request will use is marked busy first, so that making
+            // room never evicts it
+            if (cached) c->second.busy = true;
             if (S->used + need > S->cfg.budget_bytes && !make_room(S, need)) {
+              if (cached) c->second.busy = false;
               break;  // strict FIFO for memory: the head blocks the requests behind it
             }
             R = q;
@@ -239,7 +243,6 @@ void worker(mgr_server *S, int slot) {
             S->used += need;
             S->peak_used = std::max(S->peak_used, S->used);
             S->key_busy[key] = 1;
-            if (cached) c->second.busy = true;
             S->queue.erase(it);
             break;
           }
@@ -272,14 +275,39 @@ void worker(mgr_server *S, int slot) {
     }
     if (hit && R->r.refresh_setup) {
       st_code = mgr_setup_numeric(h, &R->A, st);
-      if (st_code == MGR_ERR_PATTERN) hit = false;  // a new pattern under the same key
+      if (st_code != MGR_OK) {
+        // the refresh left no usable setup: drop the cache entry.  A new pattern under the
+        // same key goes back to the head of the queue, to be admitted again with the
+        // footprint of a fresh setup; any other failure completes the request.
+        const bool requeue = st_code == MGR_ERR_PATTERN;
+        std::lock_guard<std::mutex> g(S->mu);
+        auto c = S->cache.find(key);
+        if (c != S->cache.end() && c->second.h == h) {
+          S->used -= c->second.bytes;
+          S->cache.erase(c);
+        }
+        mgr_destroy(h);
+        h = nullptr;
+        S->used -= R->reserve;
+        R->reserve = 0;
+        S->key_busy[key] = 0;
+        if (requeue) {
+          S->queue.push_front(R->ticket);
+        } else {
+          res.status = st_code;
+          res.t_end_ms = S->now_ms();
+          res.setup_reused = 0;
+          res.batch = 1;
+          ++S->misses;
+          ++S->completed;
+          R->done = true;
+        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
+        continue;
+      }
     }
-    mgr_handle *old = nullptr;
-    if (!hit) {
-      if (h) old = h;
-      h = nullptr;
-      st_code = mgr_setup(&R->A, R->r.labels, &S->cfg.opts, st, &h);
-    }
+    if (!hit) st_code = mgr_setup(&R->A, R->r.labels, &S->cfg.opts, st, &h);
     res.setup_reused = hit ? 1 : 0;
     res.batch = 1;
     const double t_setup = S->now_ms();
@@ -313,16 +341,11 @@ void worker(mgr_server *S, int slot) {
     {
       std::lock_guard<std::mutex> g(S->mu);
       S->used -= R->reserve;
-      if (old) {
-        auto c = S->cache.find(key);
-        if (c != S->cache.end() && c->second.h == old) {
-          S->used -= c->second.bytes;
-          S->cache.erase(c);
-        }
-        mgr_destroy(old);
-      }
       if (h) {
-        const bool keep = S->cfg.cache_setups && !R->r.last_use && st_code != MGR_ERR_ARG;
+        // a setup is kept when it was built (a solve that failed to converge still leaves
+        // a valid setup)
+        const bool keep = S->cfg.cache_setups && !R->r.last_use &&
+                          (st_code == MGR_OK || st_code == MGR_ERR_NOT_CONVERGED);
         auto c = S->cache.find(key);
         if (keep) {
           if (c == S->cache.end()) {

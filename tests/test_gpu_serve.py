@@ -146,3 +146,77 @@ def test_small_requests_are_batched(ens):
         bb = b.cpu().numpy()
         rel = np.linalg.norm(bb - M @ x.cpu().numpy()) / np.linalg.norm(bb)
         assert rel <= 1e-6 * 1.001, (ri, rel, r)
+
+
+def test_cache_hit_never_evicts_its_own_setup(ens):
+    """A request whose key has a cached setup reserves only its workspace.  When making
+    room for it must evict something, its own (idle) setup is not a candidate: the request
+    waits for memory instead and then reuses the setup."""
+    R1 = min(ens, key=lambda r: r.n)
+    R2 = max(ens, key=lambda r: r.n)
+    ws = lambda R: m.lib().fgmres_workspace_bytes(R.n, 30)  # noqa: E731
+    probe = serve.Server(opts(), 8 << 30, slots=1)
+    A, b = R1.step(0, 21)
+    x = torch.zeros_like(b)
+    torch.cuda.current_stream().synchronize()
+    fp1 = probe.wait(probe.submit(A, R1.labels, b, x, key=1))["footprint"]
+    probe.close()
+    est2 = m.estimate_footprint(R2.n, R2.A0.nnz, opts()) + ws(R2)
+
+    def run(budget):
+        srv = serve.Server(opts(), budget, slots=2)
+        A0, b0 = R1.step(0, 21)
+        x0 = torch.zeros_like(b0)
+        torch.cuda.current_stream().synchronize()
+        r0 = srv.wait(srv.submit(A0, R1.labels, b0, x0, key=1))
+        A2, b2 = R2.step(0, 22)
+        A1, b1 = R1.step(1, 23)
+        x2, x1 = torch.zeros_like(b2), torch.zeros_like(b1)
+        torch.cuda.current_stream().synchronize()
+        t2 = srv.submit(A2, R2.labels, b2, x2, key=2)
+        t1 = srv.submit(A1, R1.labels, b1, x1, key=1)
+        r1, r2 = srv.wait(t1), srv.wait(t2)
+        st = srv.stats()
+        srv.close()
+        return r0, r1, r2, x1, st
+
+    # key 2 fits beside the cached key-1 setup; key 1's workspace then does not
+    budget = fp1 + est2 + ws(R1) - 1
+    r0, r1, r2, x1, st = run(budget)
+    q0, q1, q2, y1, _ = run(8 << 30)
+    assert r0["status"] == r1["status"] == r2["status"] == 0
+    assert r1["setup_reused"] and q1["setup_reused"]
+    assert r1["iters"] == q1["iters"]
+    assert torch.equal(x1, y1)
+    assert st["peak_reserved_bytes"] <= budget
+
+
+def test_failed_refresh_drops_the_setup(ens):
+    """A refresh that fails (here a zero on the diagonal of A_FF: ZERO_PIVOT) leaves no
+    half-built setup in the cache: the next request of that key builds a fresh one."""
+    R = min(ens, key=lambda r: r.n)
+    rp = R.A0.row_ptr.cpu().numpy()
+    ci = R.A0.col.cpu().numpy()
+    lab = R.labels.cpu().numpy()
+    r = int(np.flatnonzero(lab == 0)[len(np.flatnonzero(lab == 0)) // 2])
+    q = int(rp[r] + np.flatnonzero(ci[rp[r]:rp[r + 1]] == r)[0])
+    srv = serve.Server(opts(), 8 << 30, slots=1)
+    A, b = R.step(0, 31)
+    x = torch.zeros_like(b)
+    torch.cuda.current_stream().synchronize()
+    assert srv.wait(srv.submit(A, R.labels, b, x, key=5))["status"] == 0
+    val = R.A0.val.clone()
+    val[q] = 0.0
+    Az = m.Matrix(R.A0.row_ptr, R.A0.col, val)
+    bz = Az.spmv(R.x_true)
+    xz = torch.zeros_like(bz)
+    torch.cuda.current_stream().synchronize()
+    res = srv.wait(srv.submit(Az, R.labels, bz, xz, key=5, refresh=True))
+    assert res["status"] == m.MGR_ERR_ZERO_PIVOT
+    A1, b1 = R.step(1, 32)
+    x1 = torch.zeros_like(b1)
+    torch.cuda.current_stream().synchronize()
+    res = srv.wait(srv.submit(A1, R.labels, b1, x1, key=5))
+    srv.close()
+    assert res["status"] == 0 and not res["setup_reused"]
+    assert res["true_relres"] <= 1e-6
