@@ -202,6 +202,25 @@ mgr_status fgmres_solve(const mgr_csr *A, mgr_handle *M, const double *b, double
                         const fgmres_opts *o, void *work, size_t work_bytes,
                         fgmres_result *res, void *stream);
 
+/* fgmres_solve for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same solve, the same launches in
+ * the same order and bitwise the same x and res, with the Krylov workspace in a static
+ * device array of fgmres_noalloc_max_bytes() = 64 MiB per device (held from the
+ * library's first use on that device until the process ends) instead of a caller or
+ * library allocation.  Nothing is allocated or created inside the call: read-backs go to
+ * host stack memory and the host waits on `stream` itself.
+ *   A, M, b, x, o, res   as for fgmres_solve.  M, when not NULL, must have been applied at
+ *          least once (mgr_apply or fgmres_solve), which captures its graph.
+ * The static workspace keeps the last call's contents; the solve writes every part of it
+ * before reading it, so nothing needs clearing.  Every call on one device shares that
+ * device's array: calls that overlap on one device (other streams or host threads) race
+ * and must be serialised by the caller.
+ * Errors: ARG (fgmres_workspace_bytes(n, restart) above the static size, an M that has
+ * not been applied yet, and those of fgmres_solve), NOT_CONVERGED, HIP. */
+size_t fgmres_noalloc_max_bytes(void);
+mgr_status fgmres_solve_noalloc(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
+                                const fgmres_opts *o, fgmres_result *res, void *stream);
+
 /* Batched solve of k independent systems A_i x_i = b_i (i < k) of any sizes under one set
  * of options, for small systems whose solves are bound by launch latency.  The systems are
  * placed on the diagonal of one block-diagonal matrix, which gets one MGR setup (Sec. 5:

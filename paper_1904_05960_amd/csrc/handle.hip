@@ -1054,18 +1054,22 @@ size_t fg_layout(int64_t n, int m, char *base, FgWork *w) {
   return off;
 }
 
-double host_norm(const double *r, int64_t n, FgWork &W, hipStream_t s) {
+// `hostv`: pinned or pageable host memory for the read-back
+double host_norm(const double *r, int64_t n, FgWork &W, double *hostv, hipStream_t s) {
   const int nb = norm2_partials(r, n, W.partial, s);
   reduce_partials(W.partial, nb, 1, W.red, false, s);
-  double *v = static_cast<double *>(pinned_scratch());
-  HIPCHK(hipMemcpyAsync(v, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hostv, W.red, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return std::sqrt(*v);
+  return std::sqrt(*hostv);
 }
 
+// `noalloc`: the caller's workspace is used and nothing is allocated or created: the
+// read-backs land in pageable memory on the host stack and the host waits on the stream
+// instead of on events (the launches, their order and the results are those of the
+// pipelined default path).
 mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
                        const fgmres_opts *o, void *work, size_t work_bytes, fgmres_result *res,
-                       hipStream_t s) {
+                       hipStream_t s, bool noalloc = false) {
   require(A && b && x && o, MGR_ERR_ARG, "null argument");
   const int64_t n = A->nrows;
   const int m = o->restart;
@@ -1074,9 +1078,14 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   require(!M || M->n == n, MGR_ERR_ARG, "preconditioner size differs from A");
   require(!M || M->valid, MGR_ERR_ARG,
           "the preconditioner holds no setup: its last mgr_setup_numeric failed");
+  if (noalloc && M)
+    require(M->used_ev && (M->gexec || !M->opts.use_graph), MGR_ERR_ARG,
+            "the preconditioner has not been applied yet (its first application captures "
+            "its graph and creates its event): call mgr_apply or fgmres_solve with it once");
   const size_t need = fg_layout(n, m, nullptr, nullptr);
   DArr<char> own;
   char *base = static_cast<char *>(work);
+  require(base || !noalloc, MGR_ERR_ARG, "no workspace");
   if (!base) {
     own.alloc(need, s);
     base = own.p;
@@ -1103,7 +1112,9 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
     else spmv64_avg(*A, xx, bb, yy, avg, s);
     if (prof) Prof::end(1, s, spmv_bytes + (bb ? (double)n * 8.0 : 0.0));
   };
-  const double bnorm = host_norm(b, n, W, s);
+  double host_buf[32];
+  double *hb = noalloc ? host_buf : static_cast<double *>(pinned_scratch());
+  const double bnorm = host_norm(b, n, W, hb, s);
   fgmres_result R{};
   if (res) { R.history = res->history; R.history_cap = res->history_cap; }
   auto push = [&](double v) {
@@ -1120,8 +1131,7 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   int its = 0;
   bool first = true;
   // per-step residual estimates land in two pinned slots, each with its completion event
-  double *slot[2] = {static_cast<double *>(pinned_scratch()) + 8,
-                     static_cast<double *>(pinned_scratch()) + 16};
+  double *slot[2] = {hb + 8, hb + 16};
   hipEvent_t ev[2] = {nullptr, nullptr};
   struct EvGuard {
     hipEvent_t *e;
@@ -1130,10 +1140,11 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } ev_guard{ev};
-  for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  if (!noalloc)
+    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
   for (;;) {
     matvec(x, b, W.r);  // r = b - A x
-    const double beta = host_norm(W.r, n, W, s);
+    const double beta = host_norm(W.r, n, W, hb, s);
     R.true_relres = beta / bnorm;
     push(beta / bnorm);
     if (beta <= tol) { R.converged = 1; break; }
@@ -1166,7 +1177,7 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
       reduce_partials(W.partial, nb, 1, W.hn2, false, s);
       givens_step(W.H, W.cs, W.sn, W.g, W.h1, W.h2, W.hn2, j, ldh, W.scal, nullptr, s);
       HIPCHK(hipMemcpyAsync(slot[j & 1], W.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipEventRecord(ev[j & 1], s));
+      if (!noalloc) HIPCHK(hipEventRecord(ev[j & 1], s));
     };
     int k = 0;
     step(0, false);
@@ -1181,7 +1192,8 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
           scale_vec_copy(W.w, W.scal + 2, vn, Ptr<double>::of(M->v0), n, s);
         step(j + 1, M != nullptr);
       }
-      HIPCHK(hipEventSynchronize(ev[j & 1]));
+      if (noalloc) HIPCHK(hipStreamSynchronize(s));
+      else HIPCHK(hipEventSynchronize(ev[j & 1]));
       ++its;
       const double *sc = slot[j & 1];
       R.est_relres = sc[0] / bnorm;
@@ -1328,6 +1340,59 @@ mgr_status fgmres_solve(const mgr_csr *A, mgr_handle *M, const double *b, double
   t_err.clear();
   try {
     return fgmres_impl(A, M, b, x, o, work, work_bytes, res, static_cast<hipStream_t>(stream));
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+}  // extern "C"
+
+// Workspace of fgmres_solve_noalloc: one array per device, held from the library's load on
+// that device until the process ends.  Host code never passes `scratch` itself (in host
+// code the name is a host-side stand-in, not a device address): it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+void *scratch_on_current_device() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  require(dev >= 0 && dev < kMaxDevices, MGR_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(MGR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+size_t fgmres_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+mgr_status fgmres_solve_noalloc(const mgr_csr *A, mgr_handle *M, const double *b, double *x,
+                                const fgmres_opts *o, fgmres_result *res, void *stream) {
+  t_err.clear();
+  try {
+    require(A && o, MGR_ERR_ARG, "null argument");
+    require(o->restart >= 1 && o->restart <= 64, MGR_ERR_ARG, "restart must be in [1, 64]");
+    const size_t need = fgmres_workspace_bytes(A->nrows, o->restart);
+    if (need > kNoAllocBytes)
+      throw Error(MGR_ERR_ARG, "fgmres_solve_noalloc: the system needs " + std::to_string(need) +
+                                   " bytes of workspace; the static workspace holds " +
+                                   std::to_string(kNoAllocBytes));
+    void *ws = scratch_on_current_device();
+    return fgmres_impl(A, M, b, x, o, ws, kNoAllocBytes, res, static_cast<hipStream_t>(stream),
+                       true);
   } catch (const Error &e) {
     return fail(e);
   }

@@ -120,6 +120,9 @@ def lib():
         "fgmres_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
         "fgmres_solve": (st, [C.POINTER(mgr_csr), vp, vp, vp, C.POINTER(fgmres_opts), vp,
                               C.c_size_t, C.POINTER(fgmres_result), vp]),
+        "fgmres_noalloc_max_bytes": (C.c_size_t, []),
+        "fgmres_solve_noalloc": (st, [C.POINTER(mgr_csr), vp, vp, vp, C.POINTER(fgmres_opts),
+                                      C.POINTER(fgmres_result), vp]),
         "mgr_batch_solve": (st, [C.c_int32, C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(vp),
                                  C.POINTER(vp), C.POINTER(mgr_opts), C.POINTER(fgmres_opts),
                                  C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -427,6 +430,24 @@ def fgmres(A: Matrix, b, x=None, M: Preconditioner | None = None, restart=30, rt
                 true_relres=r.true_relres, est_relres=r.est_relres, status=st)
     if history:
         info["history"] = [hist[i] for i in range(r.history_len)]
+    if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
+        raise MgrError(st, lib().mgr_last_error().decode())
+    return x, info
+
+
+def fgmres_noalloc(A: Matrix, b, x=None, M: Preconditioner | None = None, restart=30,
+                   rtol=1e-6, maxit=1000, stream=None, raise_on_fail=True):
+    """fgmres with the library's static per-device workspace (fgmres_solve_noalloc): no
+    allocation inside the call.  M, when given, must have been applied once before."""
+    import torch
+    if x is None:
+        x = torch.zeros_like(b)
+    o = fgmres_opts(int(restart), int(maxit), float(rtol))
+    r = fgmres_result()
+    st = lib().fgmres_solve_noalloc(C.byref(A.c), M.h if M is not None else None, _ptr(b),
+                                    _ptr(x), C.byref(o), C.byref(r), _stream(stream))
+    info = dict(iters=r.iters, restarts=r.restarts, converged=bool(r.converged),
+                true_relres=r.true_relres, est_relres=r.est_relres, status=st)
     if st not in (MGR_OK, MGR_ERR_NOT_CONVERGED) or (st != MGR_OK and raise_on_fail):
         raise MgrError(st, lib().mgr_last_error().decode())
     return x, info
