@@ -12,7 +12,8 @@ case (1,348,163 unknowns) is also timed and reported under "two_phase_64".
     python bench.py [--steps K] [--warmup W] [--workload three|two] [--size 96]
                     [--precision fp32|fp64]
                     [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
-                    [--global-smoother block_jacobi|block_gs] [--global-sweeps 3]
+                    [--global-smoother block_jacobi|block_gs|ilu] [--global-sweeps 3]
+                    [--ilu-level 1] [--ilu-sweeps 3] [--ilu-tri-sweeps 3]
 
 Prints one JSON line.  The dominant kernel's duration is measured live with HIP events
 recorded on its own stream around every launch inside the timed steps.
@@ -140,6 +141,13 @@ def make_opts(m, a, model, precision):
         for L in opts.levels:
             if 0 in L.f_labels:
                 L.nmax, L.drop_tol = -1, float(a.drop_tol)
+    if a.coarse_size is not None:
+        opts.amg_frelax = m.AMG(coarse_size=a.coarse_size)
+        opts.amg_coarse = m.AMG(coarse_size=a.coarse_size)
+    for L in opts.levels:
+        if L.global_smoother == "ilu":
+            L.ilu_level, L.ilu_sweeps = a.ilu_level, a.ilu_sweeps
+            L.ilu_tri_sweeps = a.ilu_tri_sweeps
     return opts
 
 
@@ -199,7 +207,12 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--plan", default="paper", choices=["paper", "satfirst"])
     ap.add_argument("--global-smoother", default="block_jacobi",
-                    choices=["block_jacobi", "block_gs"])
+                    choices=["block_jacobi", "block_gs", "ilu"])
+    ap.add_argument("--coarse-size", type=int, default=None,
+                    help="AMG coarsest-grid size of both AMG hierarchies (default 256)")
+    ap.add_argument("--ilu-level", type=int, default=1)
+    ap.add_argument("--ilu-sweeps", type=int, default=3)
+    ap.add_argument("--ilu-tri-sweeps", type=int, default=3)
     ap.add_argument("--global-sweeps", type=int, default=3)
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
@@ -313,7 +326,9 @@ def main():
             "reduction": (WORKLOADS[a.workload][3] if a.plan == "paper"
                           else "saturations -> displacement -> pressure AMG"),
             "hierarchy_precision": a.precision, "krylov": f"FGMRES({a.restart}) FP64, CGS2",
-            "global_smoother": f"{a.global_smoother} x{a.global_sweeps}",
+            "global_smoother": f"{a.global_smoother} x{a.global_sweeps}" + (
+                f" (ILU({a.ilu_level}), {a.ilu_sweeps} factor sweeps, {a.ilu_tri_sweeps} "
+                f"triangular sweeps)" if a.global_smoother == "ilu" else ""),
             "dropping": ("N_max = 4 on the displacement and saturation levels"
                          if a.workload == "three" else "N_max = 4 on the displacement level")
             if a.drop_tol is None else f"tolerance {a.drop_tol} on the displacement level",

@@ -70,7 +70,8 @@ typedef struct {
 
 enum { MGR_INTERP_JACOBI = 0, MGR_INTERP_ZERO = 1 };
 enum { MGR_FRELAX_JACOBI = 0, MGR_FRELAX_AMG = 1, MGR_FRELAX_DENSE = 2 };
-enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1, MGR_GSMOOTH_BLOCK_GS = 2 };
+enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1, MGR_GSMOOTH_BLOCK_GS = 2,
+       MGR_GSMOOTH_ILU = 3 };
 enum { MGR_COARSE_AMG = 0, MGR_COARSE_DENSE = 1 };
 enum { MGR_COUPLING_FULL = 0, MGR_COUPLING_QUASI_IMPES = 1 };
 enum { MGR_PREC_FP64 = 0, MGR_PREC_FP32 = 1 };
@@ -108,6 +109,15 @@ typedef struct {
                                   an entry off the sub-block diagonals is kept when it is
                                   nonzero and its |value| >= drop_tol times the largest
                                   |value| of its row; < 0: off (default)                */
+  /* MGR_GSMOOTH_ILU: the pointwise ILU(k) global smoother of the Sec. 5.3 remarks and
+     Sec. 6 by the fine-grained fixed-point method (Chow and Patel), factorising the level
+     matrix left-scaled by its same-cell block inverses, D_B^{-1} A_l; one step is
+     z (+)= (LU)^{-1} D_B^{-1} (v - A_l z), the first from z = 0, later ones weighted by
+     global_omega; the rows must be interleaved cell by cell as for block Jacobi         */
+  int32_t ilu_level;           /* k of ILU(k): 0 or 1 (default 1)                        */
+  int32_t ilu_sweeps;          /* fixed-point sweeps of the factorisation, 0..100 (3)    */
+  int32_t ilu_tri_sweeps;      /* Jacobi sweeps per triangular solve, 0..100 (3)         */
+  int32_t reserved0;           /* must be 0                                              */
 } mgr_level_opts;
 
 #define MGR_MAX_LEVELS 8
@@ -367,8 +377,11 @@ enum {
   MGR_X_AMG_P = 8,     /* AMG prolongator of level `sub`                           CSR */
   MGR_X_AMG_AGG = 9,   /* AMG aggregate id per node (-1: none)              int in col */
   MGR_X_AMG_NLEV = 10, /* number of AMG levels in out[0]                               */
-  MGR_X_GS_COLOR = 11  /* colour of every same-cell block of level l (block
+  MGR_X_GS_COLOR = 11, /* colour of every same-cell block of level l (block
                           Gauss-Seidel smoother)                            int in col */
+  MGR_X_ILU = 12       /* ILU global smoother of level l: the factors on the ILU(k)
+                          pattern of D_B^{-1} A_l (l_ij below the diagonal, u_ij on
+                          and above)                                               CSR */
 };
 /* Sizes of an object: out[0] = rows, out[1] = cols, out[2] = entries. [host out]
  * Requires opts.keep_setup = 1 for the CSR objects.  Errors: ARG. */
@@ -416,6 +429,16 @@ mgr_status mgr_transpose(const mgr_csr *A, mgr_owned_csr **T, int64_t sizes[3], 
 mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, int32_t nmax,
                           const int8_t *labels_c, mgr_owned_csr **S, int64_t sizes[3],
                           void *stream);
+/* Incomplete factors of A on its ILU(level) pattern (level 0 or 1: A's pattern, or A's
+ * united with the level-1 fill of strict_lower(A) * strict_upper(A)), after `sweeps`
+ * synchronous fixed-point sweeps from l_ij = a_ij / a_jj, u_ij = a_ij (the fine-grained
+ * ILU named for the global smoother in the Sec. 5.3 remarks): one CSR holding l_ij below
+ * the diagonal and u_ij on and above it, +0.0 on fill before the sweeps.  Each component
+ * s_ij = a_ij - sum_{m < min(i,j)} l_im u_mj is accumulated in ascending m with separate
+ * roundings.  Errors: ARG, ZERO_PIVOT (missing or zero diagonal), UNSUPPORTED (a row of
+ * the pattern longer than 256, or level > 1). */
+mgr_status mgr_ilu(const mgr_csr *A, int32_t level, int32_t sweeps, mgr_owned_csr **F,
+                   int64_t sizes[3], void *stream);
 /* Strength graph (bs = 1 scalar, 3 nodal), SplitMix64 priorities of AMG level `level`,
  * MIS(2) and aggregation; agg receives nrows/bs aggregate ids (-1 = none). */
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,

@@ -210,10 +210,41 @@ def drop(Acor: CSR, labels_c: np.ndarray, nmax: int, tol: float = -1.0) -> CSR:
     return CSR(indptr, c[keep], Acor.data[keep], Acor.shape)
 
 
+def small_inverse(D: np.ndarray) -> np.ndarray:
+    """Inverses of a stack of 1x1, 2x2 or 3x3 matrices by their closed form, the adjugate
+    over the determinant: cofactors as differences of two products, the determinant by
+    cofactor expansion along the first row ((b00 c00 + b01 c01) + b02 c02), each entry of
+    the adjugate divided by it; every operation separately rounded, in this order."""
+    nb = D.shape[1]
+    B = D.reshape(D.shape[0], nb * nb)
+    if nb == 1:
+        det = B[:, 0]
+        adj = np.ones_like(B)
+    elif nb == 2:
+        det = B[:, 0] * B[:, 3] - B[:, 1] * B[:, 2]
+        adj = np.stack([B[:, 3], -B[:, 1], -B[:, 2], B[:, 0]], axis=1)
+    elif nb == 3:
+        c00 = B[:, 4] * B[:, 8] - B[:, 5] * B[:, 7]
+        c01 = B[:, 5] * B[:, 6] - B[:, 3] * B[:, 8]
+        c02 = B[:, 3] * B[:, 7] - B[:, 4] * B[:, 6]
+        det = (B[:, 0] * c00 + B[:, 1] * c01) + B[:, 2] * c02
+        adj = np.stack([c00, B[:, 2] * B[:, 7] - B[:, 1] * B[:, 8],
+                        B[:, 1] * B[:, 5] - B[:, 2] * B[:, 4],
+                        c01, B[:, 0] * B[:, 8] - B[:, 2] * B[:, 6],
+                        B[:, 2] * B[:, 3] - B[:, 0] * B[:, 5],
+                        c02, B[:, 1] * B[:, 6] - B[:, 0] * B[:, 7],
+                        B[:, 0] * B[:, 4] - B[:, 1] * B[:, 3]], axis=1)
+    else:
+        raise ValueError("blocks of 1, 2 or 3 unknowns")
+    if np.any(~np.isfinite(det)) or np.any(det == 0.0):
+        raise ZeroPivot("singular same-cell block")
+    return (adj / det[:, None]).reshape(D.shape)
+
+
 def same_cell_blocks(A: CSR, labels: np.ndarray):
     """Global-smoother blocks: rows grouped by their per-label rank (one block per cell).
     Returns (rows, inverses): rows[e] lists block e's rows ascending, inverses[e] is the
-    dense inverse of the diagonal block A[rows[e], rows[e]]."""
+    inverse of the diagonal block A[rows[e], rows[e]] (small_inverse)."""
     rank = label_rank(labels)
     nblk = int(rank.max()) + 1
     sizes = np.bincount(rank, minlength=nblk)
@@ -229,7 +260,7 @@ def same_cell_blocks(A: CSR, labels: np.ndarray):
     m = rank[r] == rank[c]
     D = np.zeros((nblk, nb, nb))
     D[rank[r[m]], slot[r[m]], slot[c[m]]] = A.data[m]
-    return rows, np.linalg.inv(D)
+    return rows, small_inverse(D)
 
 
 def block_diagonal(rows: np.ndarray, inv: np.ndarray, n: int) -> CSR:

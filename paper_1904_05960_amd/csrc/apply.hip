@@ -17,6 +17,8 @@ enum { M_RESID = 0, M_SPMV = 1, M_SPMV_ADD = 2, M_L1PRE = 3, M_L1POST = 4 };
 // restriction that also forms the next level's first smoothing iterate: out = A x,
 // out2 = D^{-1} out with the next level's D (the product the separate pass would form)
 enum { M_SPMV_DX = 6 };
+// scaled residual out = D^{-1} (b - A x) (Jacobi sweeps on a triangular factor)
+enum { M_RESID_SCALE = 7 };
 
 template <class T, int G>
 __device__ __forceinline__ T group_sum(T v) {
@@ -57,6 +59,8 @@ __global__ void __launch_bounds__(256) k_csr(int64_t nw, const int *__restrict__
     const T bi = b[t];
     out2[t] = dinv[t] * bi;       // x
     out[t] = bi - acc;            // r
+  } else if (MODE == M_RESID_SCALE) {
+    out[t] = dinv[t] * (b[t] - acc);
   } else {                        // M_L1POST: y = x + D^{-1}(b - A x)
     out[t] = x[t] + dinv[t] * (b[t] - acc);
   }
@@ -96,6 +100,8 @@ __device__ __forceinline__ void csr_epilogue(int row, T acc, const int *__restri
   } else if (MODE == M_SPMV_DX) {
     out[row] = acc;
     out2[row] = dinv[row] * acc;
+  } else if (MODE == M_RESID_SCALE) {
+    out[row] = dinv[row] * (b[row] - acc);
   } else {  // M_INTERP: x = eF (may be null), out = z
     const int i = oidx[row];
     const T base = accumulate ? out[i] : (x ? x[row] : (T)0);
@@ -570,6 +576,21 @@ template <class T>
 void VecOps<T>::fill(T *p, T val, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_fillv<T><<<grid_for(n, 256), 256, 0, s>>>(p, val, n);
+  KCHK();
+}
+
+template <class T>
+void VecOps<T>::resid_scale(const CsrV<T> &A, const T *dinv, const T *x, const T *b, T *out,
+                            hipStream_t s) {
+  if (A.rb)
+    launch_csr_stream<T, M_RESID_SCALE>(A, x, x, b, dinv, nullptr, nullptr, out, nullptr, 0, s);
+  else
+    launch_csr<T, M_RESID_SCALE>(A, A.n, nullptr, nullptr, x, b, dinv, out, nullptr, s);
+}
+template <class T>
+void VecOps<T>::vmul(const T *a, const T *b, T *y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_vmul<T><<<grid_for(n, 256), 256, 0, s>>>(a, b, y, n);
   KCHK();
 }
 

@@ -264,6 +264,13 @@ void trace(const std::string &msg);
 void set_last_error(const std::string &msg);
 // block-Jacobi inverses over consecutive nb x nb diagonal blocks (nb = 2 or 3)
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag);
+// fine-grained ILU(k) global smoother (ilu.hip)
+void block_scale(const Csr &A, int nb, const double *binv, Csr &As, hipStream_t s, int *dflag);
+void ilu_pattern_values(const Csr &As, int level, Csr &S, hipStream_t s, int *dflag);
+void ilu_factor(Csr &S, int sweeps, DArr<int> &dpos, hipStream_t s, int *dflag);
+void ilu_split(const Csr &S, const DArr<int> &dpos, Csr &Lo, Csr &Up, DArr<double> &dinv,
+               hipStream_t s);
+template <class T> void axpy(int64_t n, T alpha, const T *x, T *y, hipStream_t s);
 // multicolour block Gauss-Seidel (bgs.hip): colouring of the cells of nb interleaved rows
 // (color_ptr: host offsets per colour into `cells`; color: colour of every cell) and one
 // colour's update x_e += D_e^{-1} (b - A x)_e for its cells
@@ -313,6 +320,10 @@ struct VecOps {
   static void block_jacobi(int64_t nblk, int nb, const T *inv, const T *v, T omega, T *z,
                            bool accumulate, hipStream_t s);
   static void fill(T *p, T val, int64_t n, hipStream_t s);
+  // out = dinv .* (b - A x)
+  static void resid_scale(const CsrV<T> &A, const T *dinv, const T *x, const T *b, T *out,
+                          hipStream_t s);
+  static void vmul(const T *a, const T *b, T *y, int64_t n, hipStream_t s);
 };
 void cast_to(const double *in, float *out, int64_t n, hipStream_t s);
 void cast_to(const double *in, double *out, int64_t n, hipStream_t s);

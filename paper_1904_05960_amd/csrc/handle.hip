@@ -203,11 +203,14 @@ struct MgrLevel {
   DArr<int> gs_cells, gs_color;
   Amg amg;                   // F-relaxation AMG
   DArr<double> ffinv64;      // dense F-relaxation inverse
+  Csr iluS;                  // ILU smoother: factors on the ILU(k) pattern (keep_setup)
+  Csr iluL, iluU;            // strictly lower / upper parts of the factors
+  DArr<double> ilu_dinv64;   // 1 / u_ii
   int nF = 0;
   // apply-precision copies
-  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv, tAF, tAC;
+  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv, tAF, tAC, tiluL, tiluU, tilu_dinv;
   // work vectors
-  DArr<char> v, z, rF, eF, rfull;
+  DArr<char> v, z, rF, eF, rfull, ilu_w;
 };
 
 template <class T> struct Ptr {
@@ -560,6 +563,43 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
       V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, r, (T)o.global_omega, z, true, s);
     }
     zero_z = false;
+  } else if (o.global_smoother == MGR_GSMOOTH_ILU) {
+    const T *binv = Ptr<T>::of(L.tbinv);
+    CsrV<T> Lo = fp64 ? view64<T>(L.iluL) : view<T>(L.iluL, L.tiluL);
+    CsrV<T> Up = fp64 ? view64<T>(L.iluU) : view<T>(L.iluU, L.tiluU);
+    const T *dU = fp64 ? reinterpret_cast<const T *>(L.ilu_dinv64.p) : Ptr<T>::of(L.tilu_dinv);
+    T *w = Ptr<T>::of(L.ilu_w);
+    T *c = w, *ya = w + n, *yb = w + 2 * n, *za = w + 3 * n, *zb = w + 4 * n;
+    const int t = o.ilu_tri_sweeps;
+    // out = (LU)^{-1} D_B^{-1} r with t Jacobi sweeps per triangular factor; out may be r
+    auto smooth = [&](const T *r, T *out) {
+      V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, r, (T)1, c, false, s);
+      const T *y = c;
+      for (int k = 0; k < t; ++k) {
+        T *dst = (k & 1) ? yb : ya;
+        V::resid(Lo, n, nullptr, nullptr, y, c, dst, s);
+        y = dst;
+      }
+      if (t == 0) {
+        V::vmul(dU, y, out, n, s);
+        return;
+      }
+      V::vmul(dU, y, za, n, s);
+      const T *zp = za;
+      for (int k = 0; k < t; ++k) {
+        T *dst = k + 1 == t ? out : ((k & 1) ? za : zb);
+        V::resid_scale(Up, dU, zp, y, dst, s);
+        zp = dst;
+      }
+    };
+    smooth(v, z);
+    for (int sw = 1; sw < o.global_sweeps; ++sw) {
+      T *r = Ptr<T>::of(L.rfull) + 2 * nC;
+      V::resid(A, n, nullptr, nullptr, z, v, r, s);
+      smooth(r, r);
+      axpy<T>(n, (T)o.global_omega, r, z, s);
+    }
+    zero_z = false;
   } else if (o.global_smoother == MGR_GSMOOTH_BLOCK_GS) {
     const T *binv = Ptr<T>::of(L.tbinv);
     V::fill(z, (T)0, n, s);
@@ -842,6 +882,25 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       cast_values(L->binv64.p, L->tbinv, n * nb, sz, s);
       if (lo.global_smoother == MGR_GSMOOTH_BLOCK_GS)
         bgs_setup(L->A, nb, L->gs_ptr, L->gs_cells, L->gs_color, s, flag);
+      if (lo.global_smoother == MGR_GSMOOTH_ILU) {
+        Csr As, S;
+        block_scale(L->A, nb, L->binv64.p, As, s, flag);
+        ilu_pattern_values(As, lo.ilu_level, S, s, flag);
+        DArr<int> dpos;
+        ilu_factor(S, lo.ilu_sweeps, dpos, s, flag);
+        ilu_split(S, dpos, L->iluL, L->iluU, L->ilu_dinv64, s);
+        make_rowblocks(L->iluL, s);
+        make_rowblocks(L->iluU, s);
+        if (sz == 4) {
+          cast_values(L->iluL.v.p, L->tiluL, L->iluL.nnz, sz, s);
+          cast_values(L->iluU.v.p, L->tiluU, L->iluU.nnz, sz, s);
+          cast_values(L->ilu_dinv64.p, L->tilu_dinv, n, sz, s);
+        }
+        L->ilu_w.alloc(std::max<int64_t>(5 * n, 1) * sz, s);
+        if (o.keep_setup) L->iluS = std::move(S);
+        trace("  ILU(" + std::to_string(lo.ilu_level) + ") smoother: " +
+              std::to_string(L->iluL.nnz + L->iluU.nnz + n) + " factor entries");
+      }
     }
     // apply copies and work vectors
     DArr<double> dinvF(L->cf.nF, s);
@@ -921,6 +980,9 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->AC.v.reset();
         L->binv64.reset();
         L->ffinv64.reset();
+        L->iluL.v.reset();
+        L->iluU.v.reset();
+        L->ilu_dinv64.reset();
       }
       L->dFF.reset();
     }
@@ -951,7 +1013,11 @@ void validate_opts(const mgr_opts &o) {
     require(lo.interp == MGR_INTERP_JACOBI || lo.interp == MGR_INTERP_ZERO, MGR_ERR_ARG, "interp");
     require(lo.frelax >= 0 && lo.frelax <= 2, MGR_ERR_ARG, "frelax");
     require(lo.frelax_sweeps >= 1 && lo.frelax_sweeps <= 100, MGR_ERR_ARG, "frelax_sweeps");
-    require(lo.global_smoother >= 0 && lo.global_smoother <= 2, MGR_ERR_ARG, "global_smoother");
+    require(lo.global_smoother >= 0 && lo.global_smoother <= 3, MGR_ERR_ARG, "global_smoother");
+    require(lo.ilu_level == 0 || lo.ilu_level == 1, MGR_ERR_ARG, "ilu_level must be 0 or 1");
+    require(lo.ilu_sweeps >= 0 && lo.ilu_sweeps <= 100, MGR_ERR_ARG, "ilu_sweeps");
+    require(lo.ilu_tri_sweeps >= 0 && lo.ilu_tri_sweeps <= 100, MGR_ERR_ARG, "ilu_tri_sweeps");
+    require(lo.reserved0 == 0, MGR_ERR_ARG, "reserved0 must be 0");
     require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
     require(lo.coupling == MGR_COUPLING_FULL || lo.coupling == MGR_COUPLING_QUASI_IMPES, MGR_ERR_ARG,
             "coupling");
@@ -982,7 +1048,9 @@ size_t handle_bytes(const mgr_handle *h) {
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
          L->tAF.bytes() + L->tAC.bytes() +
          L->tffinv.bytes() + L->v.bytes() + L->z.bytes() + L->rF.bytes() + L->eF.bytes() +
-         L->rfull.bytes();
+         L->rfull.bytes() + L->iluS.bytes() + L->iluL.bytes() + L->iluU.bytes() +
+         L->ilu_dinv64.bytes() + L->tiluL.bytes() + L->tiluU.bytes() + L->tilu_dinv.bytes() +
+         L->ilu_w.bytes();
     amg(L->amg);
   }
   csr(h->coarseA);
@@ -1251,6 +1319,10 @@ void mgr_default_opts(mgr_opts *o) {
     L.global_omega = 1.0;
     L.coupling = MGR_COUPLING_FULL;
     L.drop_tol = -1.0;
+    L.ilu_level = 1;
+    L.ilu_sweeps = 3;
+    L.ilu_tri_sweeps = 3;
+    L.reserved0 = 0;
   }
 }
 
@@ -1483,6 +1555,11 @@ mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t s
       case MGR_X_WP: csr(h->lv[level]->Wp); break;
       case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
       case MGR_X_G: csr(h->lv[level]->G); break;
+      case MGR_X_ILU:
+        require(h->lv[level]->iluS.rp.p != nullptr, MGR_ERR_ARG,
+                "no ILU smoother kept at this level (set keep_setup)");
+        csr(h->lv[level]->iluS);
+        break;
       case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
       case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;
       case MGR_X_AMG_P:
@@ -1529,6 +1606,11 @@ mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t 
       case MGR_X_WP: csr(h->lv[level]->Wp); break;
       case MGR_X_ACOR: csr(h->lv[level]->Acor); break;
       case MGR_X_G: csr(h->lv[level]->G); break;
+      case MGR_X_ILU:
+        require(h->lv[level]->iluS.rp.p != nullptr, MGR_ERR_ARG,
+                "no ILU smoother kept at this level (set keep_setup)");
+        csr(h->lv[level]->iluS);
+        break;
       case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
       case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;
       case MGR_X_AMG_P: csr(amg->lv[sub]->P); break;

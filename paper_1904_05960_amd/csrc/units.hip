@@ -126,6 +126,32 @@ mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, i
   return MGR_OK;
 }
 
+mgr_status mgr_ilu(const mgr_csr *A, int32_t level, int32_t sweeps, mgr_owned_csr **F,
+                   int64_t sizes[3], void *stream) {
+  if (!A || !F || !sizes) return MGR_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    require(sweeps >= 0 && sweeps <= 100000, MGR_ERR_ARG, "sweeps out of range");
+    DArr<int> flag(1, s);
+    clear_flag(flag.p, s);
+    Csr a;
+    import_csr(A, a, s, flag.p);
+    require(a.n == a.m, MGR_ERR_ARG, "A must be square");
+    auto out = std::make_unique<mgr_owned_csr>();
+    out->s = s;
+    ilu_pattern_values(a, level, out->M, s, flag.p);
+    DArr<int> dpos;
+    ilu_factor(out->M, sweeps, dpos, s, flag.p);
+    check_flags(flag.p, s, "ILU");
+    HIPCHK(hipStreamSynchronize(s));
+    sizes_of(out->M, sizes);
+    *F = out.release();
+  } catch (const Error &e) {
+    return ufail(e);
+  }
+  return MGR_OK;
+}
+
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,
                          int32_t *agg, int64_t *nagg, void *stream) {
   if (!A || !agg || !nagg) return MGR_ERR_ARG;

@@ -22,13 +22,14 @@ STATUS_NAMES = {0: "OK", 1: "ARG", 2: "ALLOC", 3: "HIP", 4: "ZERO_PIVOT", 5: "NO
 
 INTERP = {"jacobi": 0, "zero": 1}
 FRELAX = {"jacobi": 0, "amg": 1, "dense": 2}
-GSMOOTH = {"none": 0, "block_jacobi": 1, "block_gs": 2}
+GSMOOTH = {"none": 0, "block_jacobi": 1, "block_gs": 2, "ilu": 3}
 COARSE = {"amg": 0, "dense": 1}
 PREC = {"fp64": 0, "fp32": 1}
 COUPLING = {"full": 0, "quasi_impes": 1}
 
 X_LEVEL_A, X_F, X_C, X_WP, X_ACOR, X_G, X_COARSE, X_AMG_A, X_AMG_P, X_AMG_AGG, X_AMG_NLEV = range(11)
 X_GS_COLOR = 11
+X_ILU = 12
 MAX_LEVELS = 8
 
 
@@ -52,7 +53,9 @@ class mgr_level_opts(C.Structure):
                 ("frelax", C.c_int32), ("frelax_sweeps", C.c_int32), ("frelax_omega", C.c_double),
                 ("frelax_block", C.c_int32), ("global_smoother", C.c_int32),
                 ("global_sweeps", C.c_int32), ("coupling", C.c_int32),
-                ("global_omega", C.c_double), ("drop_tol", C.c_double)]
+                ("global_omega", C.c_double), ("drop_tol", C.c_double),
+                ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32),
+                ("ilu_tri_sweeps", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class mgr_opts(C.Structure):
@@ -147,6 +150,8 @@ def lib():
         "mgr_transpose": (st, [C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
                                 C.POINTER(vp), C.POINTER(C.c_int64), vp]),
+        "mgr_ilu": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, C.POINTER(vp),
+                         C.POINTER(C.c_int64), vp]),
         "mgr_aggregate": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_double, C.c_int32, vp,
                                C.POINTER(C.c_int64), vp]),
         "mgr_owned_export": (st, [vp, vp, vp, vp, vp]),
@@ -232,6 +237,9 @@ class Level:
     global_omega: float = 1.0
     coupling: str = "full"          # 'full' | 'quasi_impes'
     drop_tol: float = -1.0          # >= 0: tolerance form of G (nmax must be < 0)
+    ilu_level: int = 1              # global_smoother 'ilu': ILU(k), k = 0 or 1
+    ilu_sweeps: int = 3             # fixed-point sweeps of the factorisation
+    ilu_tri_sweeps: int = 3         # Jacobi sweeps per triangular solve
 
 
 @dataclass
@@ -271,6 +279,9 @@ class Options:
             c.global_omega = float(L.global_omega)
             c.coupling = COUPLING[L.coupling]
             c.drop_tol = float(L.drop_tol)
+            c.ilu_level = int(L.ilu_level)
+            c.ilu_sweeps = int(L.ilu_sweeps)
+            c.ilu_tri_sweeps = int(L.ilu_tri_sweeps)
         o.coarse = COARSE[self.coarse]
         for dst, src in ((o.amg_frelax, self.amg_frelax), (o.amg_coarse, self.amg_coarse)):
             dst.theta0, dst.max_levels, dst.coarse_size = src.theta0, src.max_levels, src.coarse_size
@@ -524,6 +535,16 @@ def merge_drop(A: Matrix, B: Matrix, w=None, nmax=-1, labels_c=None, stream=None
     _check(lib().mgr_merge_drop(C.byref(A.c), C.byref(B.c), _ptr(w), int(nmax), _ptr(labels_c),
                                 C.byref(h), sz, _stream(stream)))
     return _owned_to_host(h, sz, stream)
+
+
+def ilu(A: Matrix, level: int, sweeps: int, stream=None):
+    """Incomplete factors of A on its ILU(level) pattern after `sweeps` fixed-point sweeps
+    (mgr_ilu): (indptr, indices, data, shape) on the host."""
+    h = C.c_void_p()
+    sizes = (C.c_int64 * 3)()
+    _check(lib().mgr_ilu(C.byref(A.c), int(level), int(sweeps), C.byref(h), sizes,
+                         _stream(stream)))
+    return _owned_to_host(h, sizes, stream)
 
 
 def aggregate(A: Matrix, bs: int, theta: float, level: int, stream=None):

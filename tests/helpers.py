@@ -19,7 +19,8 @@ def oracle_plan(opts) -> omgr.Plan:
             frelax_sweeps=L.frelax_sweeps, frelax_omega=L.frelax_omega,
             frelax_block=L.frelax_block, global_smoother=L.global_smoother,
             global_sweeps=L.global_sweeps, global_omega=L.global_omega,
-            coupling=L.coupling, drop_tol=L.drop_tol))
+            coupling=L.coupling, drop_tol=L.drop_tol, ilu_level=L.ilu_level,
+            ilu_sweeps=L.ilu_sweeps, ilu_tri_sweeps=L.ilu_tri_sweeps))
     a, c = opts.amg_frelax, opts.amg_coarse
     return omgr.Plan(levels=levels, coarse=opts.coarse,
                      amg_frelax=oamg.AMGOptions(a.theta0, a.max_levels, a.coarse_size, 3),
@@ -52,3 +53,94 @@ def assert_csr_equal(got, exp: CSR, what=""):
                              f"{v[i]!r} vs {exp.data[i]!r}")
     # +0.0 and -0.0 compare equal above; check the sign bits too
     assert np.array_equal(np.signbit(v), np.signbit(exp.data)), f"{what}: signs of zeros differ"
+
+
+def fp32_copy(H):
+    """A copy of an oracle hierarchy (MGR or AMG) whose every floating-point array holds
+    float32: applying it with float32 input runs the oracle's algorithm in single precision
+    throughout (NumPy/SciPy keep float32 operands in float32), the reference for what an
+    FP32 hierarchy can reach."""
+    import copy
+    import dataclasses
+
+    H = copy.deepcopy(H)
+    seen = set()
+
+    def walk(o):
+        if id(o) in seen:
+            return o
+        seen.add(id(o))
+        if isinstance(o, CSR):
+            o.data = o.data.astype(np.float32)
+            return o
+        if isinstance(o, np.ndarray):
+            return o.astype(np.float32) if o.dtype == np.float64 else o
+        if isinstance(o, tuple):
+            return tuple(walk(x) for x in o)
+        if isinstance(o, list):
+            for i, x in enumerate(o):
+                o[i] = walk(x)
+            return o
+        if dataclasses.is_dataclass(o) and not isinstance(o, type):
+            for f in dataclasses.fields(o):
+                v = getattr(o, f.name)
+                if f.name in ("plan", "opts"):
+                    continue
+                setattr(o, f.name, walk(v))
+            return o
+        return o
+
+    return walk(H)
+
+
+def block_errors(z, z_ref, labels):
+    """Relative 2-norm error of z against z_ref within each unknown type (label)."""
+    out = {}
+    for t in np.unique(labels):
+        sel = labels == t
+        den = np.linalg.norm(z_ref[sel])
+        out[int(t)] = float(np.linalg.norm(z[sel] - z_ref[sel]) / (den if den > 0 else 1.0))
+    return out
+
+
+def row_reversed_copy(H):
+    """A copy of an oracle hierarchy whose every CSR matrix stores each row's entries in
+    descending column order: its products sum every row in the opposite order (SciPy's
+    matvec adds a row's entries in storage order), an equally valid FP64 evaluation of the
+    same algorithm.  The spread between the two is the rounding noise of the method
+    itself."""
+    import copy
+    import dataclasses
+
+    H = copy.deepcopy(H)
+    seen = set()
+
+    def rev(M: CSR):
+        n = M.shape[0]
+        lens = np.diff(M.indptr)
+        start = np.repeat(M.indptr[:-1], lens)
+        end = np.repeat(M.indptr[1:], lens)
+        pos = np.arange(M.nnz, dtype=np.int64)
+        perm = start + (end - 1 - pos)
+        M.indices = M.indices[perm]
+        M.data = M.data[perm]
+        assert M.shape[0] == n
+
+    def walk(o):
+        if id(o) in seen:
+            return
+        seen.add(id(o))
+        if isinstance(o, CSR):
+            rev(o)
+        elif isinstance(o, (list, tuple)):
+            for x in o:
+                walk(x)
+        elif dataclasses.is_dataclass(o) and not isinstance(o, type):
+            if type(o).__name__ == "ILUFactors":
+                return              # factors are addressed by position; kept as they are
+            for f in dataclasses.fields(o):
+                if f.name not in ("plan", "opts"):
+                    walk(getattr(o, f.name))
+
+    walk(H)
+    return H

@@ -4,8 +4,17 @@ Bars (from the method and its arithmetic):
   * integer/index work (C/F split, aggregates, every sparsity pattern) - bit-exact;
   * setup values (W_p, A_cor, G, coarse operators, AMG P and Galerkin products) - bit-exact:
     both sides take every product and sum in the same order with separate roundings;
-  * preconditioner application in FP64 - relative 2-norm difference <= 1e-12 (different
-    summation orders in SpMV and a dense inverse in place of LU at the coarsest grids);
+  * preconditioner application in FP64 - relative 2-norm difference <= 1e-12 over the whole
+    vector, and within every unknown type (displacement, each saturation, pressure)
+    separately <= max(1e-12, 16 x the spread of the oracle against itself), so that an error
+    confined to a block that carries little of the vector's norm is still seen.  The spread
+    is the block's difference between the oracle and the same oracle with every row summed
+    in the opposite order: the rounding noise of the method on that block (a saturation
+    block is formed by residuals and corrections that nearly cancel: spreads up to 3.6e-12
+    on the channelised case, 1e-12 on the two-phase ones, 1e-14 and less elsewhere);
+  * preconditioner application with the FP32 hierarchy - within every unknown type, at most
+    16 times the error of the oracle's own algorithm run in single precision (every stored
+    value and every operation in float32), and never below 16 unit roundoffs (2^-24);
   * FGMRES - iteration count within +-1 of the oracle (CGS2 on the GPU, MGS in the oracle),
     true FP64 relative residual <= rtol.
 """
@@ -16,7 +25,8 @@ from oracle import amg as oamg
 from oracle import krylov as okry
 from oracle import mgr as omgr
 from oracle.sparse import CSR
-from tests.helpers import assert_csr_equal, device_workload, oracle_csr, oracle_plan
+from tests.helpers import (assert_csr_equal, block_errors, device_workload, fp32_copy,
+                           oracle_csr, oracle_plan, row_reversed_copy)
 from workloads import poromech as pm
 
 pytestmark = pytest.mark.gpu
@@ -43,9 +53,30 @@ def tol_plan(tol, model="two"):
     return opts
 
 
+def ilu_plan(model, level, steps, tri=3, sweeps=3):
+    """The paper plan with the fine-grained ILU(level) global smoother on the levels that
+    hold only cell unknowns."""
+    opts = m.paper_plan(model, global_smoother="ilu", global_sweeps=steps)
+    for L in opts.levels:
+        if L.global_smoother == "ilu":
+            L.ilu_level, L.ilu_sweeps, L.ilu_tri_sweeps = level, sweeps, tri
+    return opts
+
+
+def galerkin_plan(model, coarse):
+    """The paper plan with no dropping on the displacement level (N_max = -1)."""
+    opts = m.paper_plan(model, coarse=coarse) if model == "biot1" else m.paper_plan(model)
+    opts.levels[0].nmax = -1
+    return opts
+
+
 CASES = [
     ("biot_8x8x8_paper_dense", lambda: pm.biot_single_phase(8, 8, 8, 0),
      lambda: small_amg(m.paper_plan("biot1", coarse="dense"))),
+    ("biot_8x8x8_galerkin_dense", lambda: pm.biot_single_phase(8, 8, 8, 0),
+     lambda: small_amg(galerkin_plan("biot1", "dense"))),
+    ("biot_8x8x8_galerkin_amg", lambda: pm.biot_single_phase(8, 8, 8, 0),
+     lambda: small_amg(galerkin_plan("biot1", "amg"))),
     ("biot_8x8x8_paper_amg", lambda: pm.biot_single_phase(8, 8, 8, 0),
      lambda: small_amg(m.paper_plan("biot1", coarse="amg"))),
     ("two_9x7x6_paper", lambda: pm.two_phase(9, 7, 6, 1),
@@ -70,6 +101,14 @@ CASES = [
      lambda: small_amg(m.paper_plan("two", quasi_impes=True, global_sweeps=3))),
     ("three_6x5x4_quasi_impes", lambda: pm.three_phase(6, 5, 4, 3),
      lambda: small_amg(m.paper_plan("three", quasi_impes=True, global_sweeps=2))),
+    ("two_9x7x6_ilu1", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(ilu_plan("two", level=1, steps=1))),
+    ("two_9x7x6_ilu0_two_steps", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(ilu_plan("two", level=0, steps=2, tri=2))),
+    ("three_6x5x4_ilu1", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(ilu_plan("three", level=1, steps=1))),
+    ("channels_12x10x6_ilu1", lambda: pm.two_phase_channels(12, 10, 6, 2),
+     lambda: small_amg(ilu_plan("two", level=1, steps=1, tri=4))),
 ]
 
 
@@ -123,20 +162,85 @@ def test_setup_bit_exact(case):
     compare_hierarchy(P, H, tag)
 
 
+def test_ilu_smoother_factors(case):
+    """ILU global smoother: the factors on the ILU(k) pattern of D_B^{-1} A_l, bit for bit
+    (closed-form block inverses, the pinned-order product, synchronous sweeps with the
+    component sums in ascending order on both sides)."""
+    tag, w, opts, A, labels, b, P, H = case
+    levels = [l for l, L in enumerate(H.levels) if L.ilu is not None]
+    if not levels:
+        pytest.skip("no ILU smoother in this plan")
+    for l in levels:
+        S = H.levels[l].ilu.S
+        log(f"  {tag}: ILU factors of level {l}: {S.nnz} entries")
+        assert_csr_equal(P.export(m.X_ILU, l), S, f"{tag} ILU[{l}]")
+
+
+# Cases whose coarsest grid is solved densely and is ill-conditioned: two FP64 direct
+# solvers (the GPU's Gauss-Jordan inverse, the oracle's LAPACK LU) each have forward error
+# up to about kappa(S_c) u, and differ by that much (for the Galerkin 8^3 pressure grid,
+# kappa_2 = 4.1e6: Gauss-Jordan and an unblocked LU both differ from LAPACK's LU by 2e-11 in
+# the oracle's own arithmetic).  Their bar is max(1e-12, 32 kappa_2(S_c) u).
+KAPPA_BAR = {"biot_8x8x8_galerkin_dense"}
+
+
+def apply_bar(tag, H):
+    """Whole-vector bar (the block bars come from the oracle's own spread)."""
+    if tag not in KAPPA_BAR:
+        return 1e-12
+    kappa = np.linalg.cond(H.coarse_A.to_dense())
+    return max(1e-12, 32.0 * kappa * np.finfo(np.float64).eps)
+
+
 def test_apply_fp64_matches_oracle(case):
     tag, w, opts, A, labels, b, P, H = case
+    bar = apply_bar(tag, H)
+    Hr = row_reversed_copy(H)
     rng = np.random.default_rng(5)
     for trial in range(3):
         v = rng.standard_normal(w.n) * np.where(w.labels == 0, 1e7, 1e-3)
         z_ref = omgr.apply(H, v)
         z = P.apply(torch.as_tensor(v).cuda()).cpu().numpy()
         err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
-        log(f"  {tag}: apply rel err {err:.3e}")
-        assert err <= 1e-12
+        blk = block_errors(z, z_ref, w.labels)
+        spread = block_errors(omgr.apply(Hr, v), z_ref, w.labels)
+        log(f"  {tag}: apply rel err {err:.3e}; per unknown type (gpu / oracle spread) "
+            + " ".join(f"{t}:{e:.2e}/{spread[t]:.1e}" for t, e in blk.items()))
+        assert err <= bar
+        for t, e in blk.items():
+            bar_t = max(bar, 16.0 * spread[t])
+            assert e <= bar_t, (tag, t, e, bar_t)
+
+
+U32 = 2.0 ** -24
+
+
+def test_apply_fp32_matches_oracle(case):
+    """The FP32 hierarchy (values cast after the FP64 setup, FP32 vectors and arithmetic
+    inside the apply) against the FP64 oracle, per unknown type."""
+    tag, w, opts, A, labels, b, P, H = case
+    import copy
+    o32 = copy.deepcopy(opts)
+    o32.precision = "fp32"
+    P32 = m.Preconditioner(A, labels, o32)
+    H32 = fp32_copy(H)
+    rng = np.random.default_rng(15)
+    for trial in range(3):
+        v = rng.standard_normal(w.n) * np.where(w.labels == 0, 1e7, 1e-3)
+        z_ref = omgr.apply(H, v)
+        z_o32 = omgr.apply(H32, v.astype(np.float32)).astype(np.float64)
+        z = P32.apply(torch.as_tensor(v).cuda()).cpu().numpy()
+        got = block_errors(z, z_ref, w.labels)
+        ref = block_errors(z_o32, z_ref, w.labels)
+        log(f"  {tag}: FP32 apply per unknown type (gpu / oracle in float32) "
+            + " ".join(f"{t}:{got[t]:.2e}/{ref[t]:.2e}" for t in got))
+        for t in got:
+            assert got[t] <= 16.0 * max(ref[t], U32), (tag, t, got[t], ref[t])
+    P32.close()
 
 
 # the channelized case stalls above 1e-8 (in the oracle too); it is compared at 1e-6
-FGMRES_RTOL = {"channels_12x10x6_quasi_impes": 1e-6}
+FGMRES_RTOL = {"channels_12x10x6_quasi_impes": 1e-6, "channels_12x10x6_ilu1": 1e-6}
 
 
 def test_fgmres_matches_oracle(case):
@@ -205,20 +309,40 @@ def test_exactness_pin_one_iteration():
     P.close()
 
 
-def test_fp32_hierarchy_iterations_within_one():
-    w = pm.two_phase(12, 11, 10, 4)
+@pytest.mark.parametrize("model", ["two", "three"])
+def test_fp32_hierarchy_iterations_within_one(model):
+    """FP32 hierarchy inside FP64 FGMRES against the FP64 hierarchy and the FP64 oracle:
+    iterations within one, true FP64 residual at the target, and the solution error against
+    the oracle's solution reported per unknown type.  Two solutions that meet the same
+    residual tolerance on these Jacobians can differ by as much as either differs from the
+    exact solution (the oracle's own x is 12% / 8% from x_true at rtol 1e-6); the FP32
+    solution must be at least ten times closer to the oracle's than that."""
+    w = pm.two_phase(12, 11, 10, 4) if model == "two" else pm.three_phase(10, 9, 8, 3)
     A, labels, b = device_workload(w)
+    opts = small_amg(m.paper_plan(model))
+    H = omgr.setup(oracle_csr(w), w.labels, oracle_plan(opts))
+    ref = okry.fgmres(oracle_csr(w).matvec, lambda v: omgr.apply(H, v), w.b, restart=30,
+                      rtol=1e-6, maxit=400)
+    assert ref.converged
+    ref_err = np.linalg.norm(ref.x - w.x_true) / np.linalg.norm(w.x_true)
     res = {}
     for prec in ("fp64", "fp32"):
-        P = m.Preconditioner(A, labels, small_amg(m.paper_plan("two", precision=prec)))
+        P = m.Preconditioner(A, labels, small_amg(m.paper_plan(model, precision=prec)))
         x, info = m.fgmres(A, b, M=P, restart=30, rtol=1e-6, maxit=400)
         xs = x.cpu().numpy()
         true = np.linalg.norm(w.b - w.scipy() @ xs) / np.linalg.norm(w.b)
-        res[prec] = (info["iters"], true)
-        log(f"  {prec}: iters {info['iters']} true relres {true:.2e}")
+        err = np.linalg.norm(xs - ref.x) / np.linalg.norm(ref.x)
+        blk = block_errors(xs, ref.x, w.labels)
+        res[prec] = (info["iters"], true, err)
+        log(f"  {model} {prec}: iters {info['iters']} (oracle {ref.iters}) true relres "
+            f"{true:.2e}; ||x - x_oracle||/||x_oracle|| {err:.2e}; per unknown type "
+            + " ".join(f"{t}:{e:.2e}" for t, e in blk.items()))
         assert true <= 1e-6 * 1.0000001
         P.close()
     assert abs(res["fp64"][0] - res["fp32"][0]) <= 1
+    assert abs(res["fp64"][0] - ref.iters) <= 1
+    log(f"  {model}: ||x_oracle - x_true||/||x_true|| {ref_err:.2e}")
+    assert res["fp32"][2] <= 0.1 * ref_err
 
 
 def test_spmv_ragged_matches_scipy():

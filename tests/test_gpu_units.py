@@ -239,3 +239,53 @@ def test_aggregation_elasticity(bs, level):
     agg, nagg = m.aggregate(dev(Auu), bs, theta, level)
     assert nagg == nagg_o
     assert np.array_equal(agg, agg_o)
+
+
+def ilu_matrix(rng, n, dens, dominance=1.5):
+    D = (rng.random((n, n)) < dens) * rng.standard_normal((n, n))
+    np.fill_diagonal(D, 0.0)
+    D[np.arange(n), np.arange(n)] = dominance * (np.abs(D).sum(axis=1) + 1.0)
+    # explicit zeros in the pattern as well
+    mask = (D != 0) | (rng.random((n, n)) < dens * 0.2)
+    return CSR.from_dense(D, mask)
+
+
+@pytest.mark.parametrize("n,dens", [(1, 1.0), (37, 0.15), (400, 0.02), (1500, 0.004)])
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("sweeps", [0, 1, 3])
+def test_ilu_bit_exact(n, dens, level, sweeps):
+    """mgr_ilu against the oracle's fine-grained ILU: the ILU(level) pattern and the factors
+    after `sweeps` synchronous sweeps, bit for bit (same component equations, ascending m,
+    separate roundings)."""
+    from oracle import ilu as oilu
+    rng = np.random.default_rng(n + 7 * level + 31 * sweeps)
+    A = ilu_matrix(rng, n, dens)
+    exp = oilu.ilu_factor(A, level, sweeps).S
+    assert_csr_equal(m.ilu(dev(A), level, sweeps), exp, f"ILU({level}) n={n} sweeps={sweeps}")
+
+
+def test_ilu_long_rows_and_many_sweeps():
+    """Rows up to 200 entries (a dense band) and enough sweeps to reach the fixed point."""
+    from oracle import ilu as oilu
+    rng = np.random.default_rng(77)
+    n = 260
+    D = np.zeros((n, n))
+    for i in range(n):
+        lo, hi = max(0, i - 100), min(n, i + 100)
+        D[i, lo:hi] = rng.standard_normal(hi - lo)
+    D[np.arange(n), np.arange(n)] = 2.0 * np.abs(D).sum(axis=1)
+    A = CSR.from_dense(D)
+    for level, sweeps in ((0, 2), (1, 1)):
+        exp = oilu.ilu_factor(A, level, sweeps).S
+        assert_csr_equal(m.ilu(dev(A), level, sweeps), exp, f"band ILU({level})")
+
+
+def test_ilu_errors():
+    A = CSR.from_dense(np.array([[0.0, 1.0], [1.0, 2.0]]), np.array([[False, True], [True, True]]))
+    with pytest.raises(m.MgrError) as e:
+        m.ilu(dev(A), 0, 1)
+    assert e.value.status == m.MGR_ERR_ZERO_PIVOT
+    B = CSR.from_dense(np.eye(3))
+    with pytest.raises(m.MgrError) as e:
+        m.ilu(dev(B), 2, 1)
+    assert e.value.status == m.MGR_ERR_UNSUPPORTED

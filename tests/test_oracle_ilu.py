@@ -236,3 +236,21 @@ def test_synchronous_sweeps_hand_worked():
         L, U = factors_dense(ilu.ilu_factor(A, 0, sw))
         assert (L[1, 0], L[2, 1], U[1, 1], U[2, 2]) == (l21, l32, u22, u33), sw
         assert (U[0, 0], U[0, 1], U[1, 2]) == (4.0, 1.0, 1.0)
+
+
+def test_small_inverse_closed_form():
+    """adj(B)/det(B) for 1x1, 2x2 and 3x3 blocks: B @ inv(B) = I to rounding, exact on a
+    hand-worked 2x2 block, singular blocks rejected."""
+    rng = np.random.default_rng(50)
+    for nb in (1, 2, 3):
+        D = rng.standard_normal((40, nb, nb)) + 3.0 * np.eye(nb)
+        inv = omgr.small_inverse(D)
+        assert np.allclose(np.einsum("eij,ejk->eik", D, inv), np.eye(nb)[None], atol=1e-13)
+    # [[2, 1], [4, 3]]: det 2, inverse [[1.5, -0.5], [-2, 1]]
+    inv = omgr.small_inverse(np.array([[[2.0, 1.0], [4.0, 3.0]]]))
+    assert inv[0].tolist() == [[1.5, -0.5], [-2.0, 1.0]]
+    # 3x3 with a known integer inverse: [[1,2,0],[0,1,0],[0,0,2]] -> [[1,-2,0],[0,1,0],[0,0,.5]]
+    inv = omgr.small_inverse(np.array([[[1.0, 2.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 2.0]]]))
+    assert inv[0].tolist() == [[1.0, -2.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 0.5]]
+    with pytest.raises(omgr.ZeroPivot):
+        omgr.small_inverse(np.array([[[1.0, 2.0], [2.0, 4.0]]]))
