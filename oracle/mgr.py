@@ -68,6 +68,8 @@ class LevelPlan:
     ilu_level: int = 1               # global_smoother 'ilu': ILU(k) pattern
     ilu_sweeps: int = 3              # fixed-point sweeps of the factorisation
     ilu_tri_sweeps: int = 3          # Jacobi sweeps per triangular solve (< 0: exact)
+    restrict: str = "injection"      # 'injection' (W_r = 0) | 'jacobi' (W_r = -A_CF D_FF^-1)
+    dff_block: int = 1               # D_FF: pointwise (1) or diagonal blocks of 2 or 3 F rows
 
 
 @dataclass
@@ -90,7 +92,10 @@ class Level:
     A_CF: CSR
     A_CC: CSR
     Wp: CSR                     # W_p (F rows x C cols)
-    Acor: CSR                   # A_CF D_FF^{-1} A_FC (before dropping)
+    Acor: CSR                   # the correction term of the coarse grid before dropping:
+                                # A_CF D_FF^{-1} A_FC (injection) or, with Jacobi
+                                # restriction, A_CF M + N A_FC - N A_FF M
+                                # (M = D_FF^{-1} A_FC, N = A_CF D_FF^{-1})
     G: CSR                      # G(A_cor)
     plan: LevelPlan
     amg: object = None          # F-relaxation AMG hierarchy
@@ -98,6 +103,8 @@ class Level:
     blocks: tuple | None = None # global smoother: (rows per block, block inverses)
     colors: np.ndarray | None = None  # block Gauss-Seidel: colour of every cell
     ilu: object = None          # global smoother 'ilu': the incomplete factors
+    Wr: CSR | None = None       # W_r = -A_CF D_FF^{-1} (Jacobi restriction)
+    dff_inv: np.ndarray | None = None  # block D_FF: inverses of the F-row blocks
 
 
 @dataclass
@@ -263,6 +270,20 @@ def same_cell_blocks(A: CSR, labels: np.ndarray):
     return rows, small_inverse(D)
 
 
+def ff_block_inverses(A_FF: CSR, nb: int) -> np.ndarray:
+    """Inverses (small_inverse) of the diagonal blocks of A_FF made of nb consecutive F rows
+    (the three displacement components of a node, in node-major order)."""
+    nF = A_FF.shape[0]
+    if nF % nb:
+        raise ValueError("F rows do not come in blocks of %d" % nb)
+    D = np.zeros((nF // nb, nb, nb))
+    r = A_FF.row_ids()
+    c = A_FF.indices
+    m = (r // nb) == (c // nb)
+    D[r[m] // nb, r[m] % nb, c[m] % nb] = A_FF.data[m]
+    return small_inverse(D)
+
+
 def block_diagonal(rows: np.ndarray, inv: np.ndarray, n: int) -> CSR:
     """The block-diagonal matrix D_B^{-1} with the dense inverses of the same-cell blocks
     (every entry of a block kept, zeros included)."""
@@ -341,7 +362,16 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
         d = diagonal(A_FF)
         if np.any(~np.isfinite(d)) or np.any(d == 0.0):
             raise ZeroPivot("zero or missing diagonal in A_FF")
-        if lp.interp == "jacobi":
+        Dinv = None                              # block D_FF^{-1} as a CSR, when blocked
+        dff_inv = None
+        if lp.dff_block > 1:
+            dff_inv = ff_block_inverses(A_FF, lp.dff_block)
+            Dinv = block_diagonal(np.arange(F.shape[0]).reshape(-1, lp.dff_block), dff_inv,
+                                  F.shape[0])
+        if lp.interp == "jacobi" and Dinv is not None:
+            M = spgemm(Dinv, A_FC)                 # block D_FF^{-1} A_FC
+            Wp = CSR(M.indptr, M.indices, -M.data, M.shape)
+        elif lp.interp == "jacobi":
             M, Wp = jacobi_interpolation(A_FC, d)
         elif lp.interp == "zero":
             M = CSR(np.zeros(F.shape[0] + 1, dtype=np.int64), [], [], A_FC.shape)
@@ -352,11 +382,25 @@ def setup(A: CSR, labels: np.ndarray, plan: Plan) -> Hierarchy:
             Wp = CSR(M.indptr, M.indices, -M.data, M.shape)
         else:
             raise ValueError(lp.interp)
-        Acor = spgemm(coupling_block(A_CF, lab, F, C, lp.coupling), M)
+        Acf_c = coupling_block(A_CF, lab, F, C, lp.coupling)
+        Acor = spgemm(Acf_c, M)
+        Wr = None
+        if lp.restrict == "jacobi":
+            # R~ = [W_r I], W_r = -N, N = A_CF D_FF^{-1} (Sec. 5.1, Jacobi restriction): the
+            # coarse grid R~ A P~ = A_CC - (A_CF M + N A_FC - N A_FF M)
+            if lp.coupling != "full" or lp.interp != "jacobi":
+                raise ValueError("Jacobi restriction needs full coupling and Jacobi W_p")
+            N = (spgemm(A_CF, Dinv) if Dinv is not None else
+                 CSR(A_CF.indptr, A_CF.indices, A_CF.data / d[A_CF.indices], A_CF.shape))
+            Wr = CSR(N.indptr, N.indices, -N.data, N.shape)
+            B1 = merge_sub(Acor, spgemm(N, A_FC), -np.ones(Acor.shape[0]))   # A_CF M + N A_FC
+            Acor = merge_sub(B1, spgemm(spgemm(N, A_FF), M))                  # - N A_FF M
+        elif lp.restrict != "injection":
+            raise ValueError(lp.restrict)
         G = drop(Acor, lab[C], lp.nmax, lp.drop_tol)
         S = merge_sub(A_CC, G)
         L = Level(A=cur, labels=lab, F=F, C=C, dFF=d, A_FF=A_FF, A_FC=A_FC, A_CF=A_CF,
-                  A_CC=A_CC, Wp=Wp, Acor=Acor, G=G, plan=lp)
+                  A_CC=A_CC, Wp=Wp, Acor=Acor, G=G, plan=lp, Wr=Wr, dff_inv=dff_inv)
         if lp.frelax == "amg":
             opts = amg_mod.AMGOptions(**{**plan.amg_frelax.__dict__, "block": lp.frelax_block})
             L.amg = amg_mod.setup(A_FF, opts)
@@ -426,7 +470,13 @@ def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
     else:
         z = np.zeros_like(v)
     # F-relaxation: z <- z + Q M_FF^{-1} Q^T (v - A z)
-    if lp.frelax == "jacobi":
+    if lp.frelax == "jacobi" and L.dff_inv is not None:
+        nb = lp.dff_block
+        for _ in range(lp.frelax_sweeps):
+            r = v - A.matvec(z)
+            rF = r[L.F].reshape(-1, nb)
+            z[L.F] = z[L.F] + lp.frelax_omega * np.einsum("eij,ej->ei", L.dff_inv, rF).ravel()
+    elif lp.frelax == "jacobi":
         for _ in range(lp.frelax_sweeps):
             r = v - A.matvec(z)
             z[L.F] = z[L.F] + lp.frelax_omega * (r[L.F] / L.dFF)
@@ -438,9 +488,10 @@ def apply(H: Hierarchy, v: np.ndarray, lvl: int = 0) -> np.ndarray:
         z[L.F] = z[L.F] + sla.lu_solve(L.ff_lu, r[L.F])
     else:
         raise ValueError(lp.frelax)
-    # restrict the residual by injection, recurse, interpolate, correct
+    # restrict the residual (injection, or R~ = [W_r I]), recurse, interpolate, correct
     r = v - A.matvec(z)
-    eC = apply(H, r[L.C], lvl + 1)
+    rC = r[L.C] if L.Wr is None else r[L.C] + L.Wr.matvec(r[L.F])
+    eC = apply(H, rC, lvl + 1)
     z[L.F] = z[L.F] + L.Wp.matvec(eC)
     z[L.C] = z[L.C] + eC
     return z
