@@ -51,10 +51,16 @@ typedef enum {
 
 /* ---------------------------------------------------------------------------------- */
 typedef struct {
-  int64_t nrows, ncols;        /* [host]                                              */
+  int64_t nrows, ncols;        /* [host] rows / columns; of blocks when block > 1     */
   const int64_t *row_ptr;      /* nrows + 1 entries, row_ptr[0] = 0, nondecreasing     */
-  const int32_t *col;          /* row_ptr[nrows] entries                               */
-  const double *val;           /* row_ptr[nrows] entries                               */
+  const int32_t *col;          /* row_ptr[nrows] entries (block columns when block > 1) */
+  const double *val;           /* row_ptr[nrows] entries; when block > 1,
+                                  row_ptr[nrows] * block^2 values, each block's
+                                  entries row-major                                    */
+  int32_t block;               /* [host] 0 or 1: CSR; 2 or 3: BSR with block x block
+                                  blocks (scalar row br*block + r, column bc*block + c);
+                                  a zero-initialised descriptor is CSR                 */
+  int32_t reserved;            /* must be 0                                            */
 } mgr_csr;
 
 /* Algebraic multigrid used for F-relaxation and for the coarsest grid.  Smoothed
@@ -74,6 +80,7 @@ enum { MGR_GSMOOTH_NONE = 0, MGR_GSMOOTH_BLOCK_JACOBI = 1, MGR_GSMOOTH_BLOCK_GS 
        MGR_GSMOOTH_ILU = 3 };
 enum { MGR_COARSE_AMG = 0, MGR_COARSE_DENSE = 1 };
 enum { MGR_COUPLING_FULL = 0, MGR_COUPLING_QUASI_IMPES = 1 };
+enum { MGR_RESTRICT_INJECTION = 0, MGR_RESTRICT_JACOBI = 1 };
 enum { MGR_PREC_FP64 = 0, MGR_PREC_FP32 = 1 };
 
 /* One reduction level (Sec. 5.2, Algorithm 2). */
@@ -117,7 +124,19 @@ typedef struct {
   int32_t ilu_level;           /* k of ILU(k): 0 or 1 (default 1)                        */
   int32_t ilu_sweeps;          /* fixed-point sweeps of the factorisation, 0..100 (3)    */
   int32_t ilu_tri_sweeps;      /* Jacobi sweeps per triangular solve, 0..100 (3)         */
-  int32_t reserved0;           /* must be 0                                              */
+  int32_t restrict_;           /* MGR_RESTRICT_INJECTION (W_r = 0, eq. injective_rp,
+                                  default) or MGR_RESTRICT_JACOBI: R~ = [W_r I] with
+                                  W_r = -A_CF D_FF^{-1} (Sec. 5.1); the coarse grid is then
+                                  A_CC - G(A_CF M + N A_FC - N A_FF M), M = D_FF^{-1} A_FC,
+                                  N = A_CF D_FF^{-1} (each product in the pinned order), and
+                                  the restricted residual r_C + W_r r_F.  Needs
+                                  MGR_COUPLING_FULL and MGR_INTERP_JACOBI               */
+  int32_t dff_block;           /* D_FF: 1 pointwise diagonal (eq. injective_rp, default);
+                                  2 or 3: the diagonal blocks of that many consecutive F
+                                  rows (a node's displacement components; the dense
+                                  blocks of the Sec. 5.3 remark), inverted by their
+                                  closed form, for W_p, W_r and Jacobi F-relaxation     */
+  int32_t reserved1;           /* must be 0                                              */
 } mgr_level_opts;
 
 #define MGR_MAX_LEVELS 8
@@ -379,9 +398,10 @@ enum {
   MGR_X_AMG_NLEV = 10, /* number of AMG levels in out[0]                               */
   MGR_X_GS_COLOR = 11, /* colour of every same-cell block of level l (block
                           Gauss-Seidel smoother)                            int in col */
-  MGR_X_ILU = 12       /* ILU global smoother of level l: the factors on the ILU(k)
+  MGR_X_ILU = 12,      /* ILU global smoother of level l: the factors on the ILU(k)
                           pattern of D_B^{-1} A_l (l_ij below the diagonal, u_ij on
                           and above)                                               CSR */
+  MGR_X_WR = 13        /* W_r = -A_CF D_FF^{-1} (Jacobi restriction)               CSR */
 };
 /* Sizes of an object: out[0] = rows, out[1] = cols, out[2] = entries. [host out]
  * Requires opts.keep_setup = 1 for the CSR objects.  Errors: ARG. */

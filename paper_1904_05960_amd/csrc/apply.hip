@@ -109,6 +109,58 @@ __device__ __forceinline__ void csr_epilogue(int row, T acc, const int *__restri
   }
 }
 
+// Row-local operands of a row's epilogue, loaded before the block's barrier so that their
+// latency overlaps the window's gathers instead of following the LDS sums.
+template <class T>
+struct RowPre {
+  int s = 0, e = 0, oi = 0;
+  T bv = 0, dv = 0, xv = 0, ov = 0;
+};
+template <class T, int MODE>
+__device__ __forceinline__ void row_prefetch(int row, int base, const int *__restrict__ rp,
+                                             const int *__restrict__ bidx,
+                                             const int *__restrict__ oidx,
+                                             const T *__restrict__ x, const T *__restrict__ b,
+                                             const T *__restrict__ dinv, const T *out,
+                                             int accumulate, RowPre<T> &p) {
+  p.s = rp[row] - base;
+  p.e = rp[row + 1] - base;
+  if (MODE == M_RESID) p.bv = b[bidx ? bidx[row] : row];
+  if (MODE == M_L1PRE || MODE == M_L1POST || MODE == M_RESID_SCALE) p.bv = b[row];
+  if (MODE == M_L1PRE || MODE == M_L1POST || MODE == M_SPMV_DX || MODE == M_RESID_SCALE)
+    p.dv = dinv[row];
+  if (MODE == M_L1POST) p.xv = x[row];
+  if (MODE == M_SPMV_ADD) p.ov = out[row];
+  if (MODE == M_INTERP) {
+    p.oi = oidx[row];
+    p.ov = accumulate ? out[p.oi] : (x ? x[row] : (T)0);
+  }
+}
+// the same results as csr_epilogue, from prefetched operands
+template <class T, int MODE>
+__device__ __forceinline__ void csr_epilogue_pre(int row, T acc, const RowPre<T> &p,
+                                                 T *__restrict__ out, T *__restrict__ out2) {
+  if (MODE == M_RESID) {
+    out[row] = p.bv - acc;
+  } else if (MODE == M_SPMV) {
+    out[row] = acc;
+  } else if (MODE == M_SPMV_ADD) {
+    out[row] = p.ov + acc;
+  } else if (MODE == M_L1PRE) {
+    out2[row] = p.dv * p.bv;
+    out[row] = p.bv - acc;
+  } else if (MODE == M_L1POST) {
+    out[row] = p.xv + p.dv * (p.bv - acc);
+  } else if (MODE == M_SPMV_DX) {
+    out[row] = acc;
+    out2[row] = p.dv * acc;
+  } else if (MODE == M_RESID_SCALE) {
+    out[row] = p.dv * (p.bv - acc);
+  } else {  // M_INTERP
+    out[p.oi] = p.ov + acc;
+  }
+}
+
 template <class T, int MODE, int G>
 __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
                                                    const int *__restrict__ rp,
@@ -131,6 +183,11 @@ __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
   const int t = threadIdx.x;
   if (cnt <= scap<T>) {
     constexpr int PER = SNNZ / SB;
+    // this thread's first row of the sum phase and its epilogue operands
+    const int prow = r0 + t / G;
+    RowPre<T> pre;
+    if (prow < r1)
+      row_prefetch<T, MODE>(prow, base, rp, bidx, oidx, x, b, dinv, out, accumulate, pre);
     for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
       int c[PER];
       T vv[PER], xv[PER];
@@ -160,12 +217,14 @@ __global__ void __launch_bounds__(SB) k_csr_stream(const int *__restrict__ rb,
     // G lanes per row (G ~ mean row length / 8, so that the block's rows take about one
     // pass of its 256 threads)
     const int l = t & (G - 1);
-    for (int row = r0 + t / G; row < r1; row += SB / G) {
-      const int s0 = rp[row] - base, e1 = rp[row + 1] - base;
+    for (int row = prow; row < r1; row += SB / G) {
+      RowPre<T> p;
+      if (row == prow) p = pre;
+      else row_prefetch<T, MODE>(row, base, rp, bidx, oidx, x, b, dinv, out, accumulate, p);
       T acc = 0;
-      for (int e = s0 + l; e < e1; e += G) acc += prod[e];
+      for (int e = p.s + l; e < p.e; e += G) acc += prod[e];
       if (G > 1) acc = group_sum<T, G>(acc);
-      if (l == 0) csr_epilogue<T, MODE>(row, acc, bidx, oidx, x, b, dinv, out, out2, accumulate);
+      if (l == 0) csr_epilogue_pre<T, MODE>(row, acc, p, out, out2);
     }
     return;
   }

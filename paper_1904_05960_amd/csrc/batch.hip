@@ -448,6 +448,8 @@ extern "C" mgr_status mgr_batch_solve(int32_t k, const mgr_csr *A, const int8_t 
     int64_t N = 0;
     for (int i = 0; i < k; ++i) {
       const mgr_csr &M = A[i];
+      require(M.block <= 1, MGR_ERR_ARG,
+              "mgr_batch_solve: system " + std::to_string(i) + " is not a CSR matrix");
       require(M.nrows > 0 && M.nrows == M.ncols && M.row_ptr && M.col && M.val && labels[i] &&
                   b[i] && x[i],
               MGR_ERR_ARG, "mgr_batch_solve: system " + std::to_string(i) +

@@ -266,11 +266,18 @@ void set_last_error(const std::string &msg);
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag);
 // fine-grained ILU(k) global smoother (ilu.hip)
 void block_scale(const Csr &A, int nb, const double *binv, Csr &As, hipStream_t s, int *dflag);
+// row pointers and columns of the block-diagonal n x n matrix of nb x nb blocks
+void block_diag_pattern(int64_t n, int nb, int *rp, int *ci, hipStream_t s);
 void ilu_pattern_values(const Csr &As, int level, Csr &S, hipStream_t s, int *dflag);
 void ilu_factor(Csr &S, int sweeps, DArr<int> &dpos, hipStream_t s, int *dflag);
 void ilu_split(const Csr &S, const DArr<int> &dpos, Csr &Lo, Csr &Up, DArr<double> &dinv,
                hipStream_t s);
 template <class T> void axpy(int64_t n, T alpha, const T *x, T *y, hipStream_t s);
+// y[idx[i]] += alpha * x[i]
+template <class T>
+void scatter_axpy(const int *idx, int64_t n, T alpha, const T *x, T *y, hipStream_t s);
+// M_ik /= d_k (column scaling by division, IEEE rounding)
+void scale_cols_div(Csr &M, const double *d, hipStream_t s);
 // multicolour block Gauss-Seidel (bgs.hip): colouring of the cells of nb interleaved rows
 // (color_ptr: host offsets per colour into `cells`; color: colour of every cell) and one
 // colour's update x_e += D_e^{-1} (b - A x)_e for its cells
@@ -365,6 +372,12 @@ void spmv64_avg(const mgr_csr &A, const double *x, const double *b, double *y, d
                 hipStream_t s);
 // CSR-stream SpMV (FP64, int64 row pointers): row blocks of about 2048 entries
 int64_t stream_blocks(int64_t nnz);
+int64_t bsr_stream_blocks(int64_t nnzb, int bs);
+void bsr_rowblocks64(const mgr_csr &A, int64_t nnzb, int *rb, hipStream_t s);
+void bsr_spmv64_stream(const mgr_csr &A, int64_t nnzb, const int *rb, const double *x,
+                       const double *b, double *y, hipStream_t s);
+// scalar rows of a CSR or BSR descriptor
+inline int64_t scalar_rows(const mgr_csr &A) { return A.nrows * (A.block > 1 ? A.block : 1); }
 void rowblocks64(const mgr_csr &A, int64_t nnz, int *rb, hipStream_t s);
 void spmv64_stream(const mgr_csr &A, int64_t nnz, const int *rb, const double *x, const double *b,
                    double *y, hipStream_t s);

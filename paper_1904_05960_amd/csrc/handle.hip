@@ -203,12 +203,16 @@ struct MgrLevel {
   DArr<int> gs_cells, gs_color;
   Amg amg;                   // F-relaxation AMG
   DArr<double> ffinv64;      // dense F-relaxation inverse
+  Csr Wr;                    // W_r = -A_CF D_FF^{-1} (Jacobi restriction)
+  int dffb = 1;              // D_FF block size
+  DArr<double> dffinv64;     // block D_FF: inverses of the F-row blocks
   Csr iluS;                  // ILU smoother: factors on the ILU(k) pattern (keep_setup)
   Csr iluL, iluU;            // strictly lower / upper parts of the factors
   DArr<double> ilu_dinv64;   // 1 / u_ii
   int nF = 0;
   // apply-precision copies
-  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv, tAF, tAC, tiluL, tiluU, tilu_dinv;
+  DArr<char> tA, tAcf, tWp, tdinvF, tbinv, tffinv, tAF, tAC, tiluL, tiluU, tilu_dinv, tWr,
+      tdffinv;
   // work vectors
   DArr<char> v, z, rF, eF, rfull, ilu_w;
 };
@@ -611,7 +615,23 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
   }
   bool compactF = false;  // z_F held in eF, z otherwise untouched (z_C = 0)
   const T *dinvF = Ptr<T>::of(L.tdinvF);
-  if (o.frelax == MGR_FRELAX_JACOBI) {
+  if (o.frelax == MGR_FRELAX_JACOBI && L.dffb > 1) {
+    // block D_FF: z_F += omega D_FF^{-1} (v - A z)_F with the F-row blocks' inverses
+    const T *dfi = Ptr<T>::of(L.tdffinv);
+    for (int sw = 0; sw < o.frelax_sweeps; ++sw) {
+      if (zero_z) {
+        V::fill(z, (T)0, n, s);
+        V::gather(L.cf.F.p, nF, v, rF, s);
+        zero_z = false;
+      } else if (sub) {
+        V::resid(AF, nF, nullptr, L.cf.F.p, z, v, rF, s);
+      } else {
+        V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      }
+      V::block_jacobi(nF / L.dffb, L.dffb, dfi, rF, (T)1, eF, false, s);
+      scatter_axpy<T>(L.cf.F.p, nF, (T)o.frelax_omega, eF, z, s);
+    }
+  } else if (o.frelax == MGR_FRELAX_JACOBI) {
     int sw0 = 0;
     if (zero_z) {
       V::jacobi_first(n, L.cf.map.p, dinvF, (T)o.frelax_omega, v, z, s);
@@ -638,8 +658,25 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
     if (zero_z) compactF = true;
     else V::scatter_add(L.cf.F.p, nF, eF, z, s);
   }
+  if (o.restrict_ == MGR_RESTRICT_JACOBI) {
+    // restrict by R~ = [W_r I]: r_C + W_r r_F of the full residual
+    if (compactF) {
+      V::fill(z, (T)0, n, s);
+      V::scatter_add(L.cf.F.p, nF, eF, z, s);
+      compactF = false;
+    }
+    CsrV<T> Wr = fp64 ? view64<T>(L.Wr) : view<T>(L.Wr, L.tWr);
+    if (sub) {
+      V::resid(AF, nF, nullptr, L.cf.F.p, z, v, rF, s);
+      V::resid(AC, nC, nullptr, L.cf.C.p, z, v, rC, s);
+    } else {
+      V::resid(A, nF, L.cf.F.p, L.cf.F.p, z, v, rF, s);
+      V::resid(A, nC, L.cf.C.p, L.cf.C.p, z, v, rC, s);
+    }
+    V::spmv(Wr, rF, rC, true, s);
+  }
   // restrict the residual by injection
-  if (compactF) V::resid(Acf, nC, nullptr, L.cf.C.p, eF, v, rC, s);
+  else if (compactF) V::resid(Acf, nC, nullptr, L.cf.C.p, eF, v, rC, s);
   else if (sub) V::resid(AC, nC, nullptr, L.cf.C.p, z, v, rC, s);
   else V::resid(A, nC, L.cf.C.p, L.cf.C.p, z, v, rC, s);
   apply_level<T>(h, l + 1, rC, eC, s);
@@ -788,12 +825,23 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     DArr<int> lrankC;
     const bool dropping = lo.nmax_drop >= 0 || lo.drop_tol >= 0.0;
     if (dropping) label_rank(labC.p, nC, lrankC, s, present & ~lo.f_label_mask);
-    const bool need_ff = lo.frelax != MGR_FRELAX_JACOBI;
+    const bool jac_r = lo.restrict_ == MGR_RESTRICT_JACOBI;
+    const bool need_ff = lo.frelax != MGR_FRELAX_JACOBI || jac_r || lo.dff_block > 1;
     Csr Aff, Afc, Acc;
     L->dFF.alloc(L->cf.nF, s);
     extract_blocks(L->A, L->cf, need_ff ? &Aff : nullptr, Afc, L->Acf, Acc, L->dFF.p, s);
     check_nonzero(L->dFF.p, L->cf.nF, flag, s);
     check_flags(flag, s, "D_FF");
+    // block D_FF: closed-form inverses of the diagonal blocks of dff_block consecutive F rows
+    L->dffb = lo.dff_block;
+    if (lo.dff_block > 1) {
+      require(L->cf.nF % lo.dff_block == 0, MGR_ERR_ARG, "F rows not in blocks of dff_block");
+      L->dffinv64.alloc(L->cf.nF * lo.dff_block, s);
+      block_diag_inverse(Aff, lo.dff_block, L->dffinv64.p, s, flag);
+    }
+    // A_FF for the Jacobi restriction's triple product (the F-relaxation AMG takes Aff)
+    Csr AffR;
+    if (jac_r) copy_csr(Aff, AffR, s);
     // F-relaxation AMG: A_FF is ready
     if (lo.frelax == MGR_FRELAX_AMG) {
       require(lo.frelax_block == 1 || lo.frelax_block == 3, MGR_ERR_ARG, "frelax_block must be 1 or 3");
@@ -828,8 +876,11 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     }
     // W_p = -D_FF^{-1} A_FC (eq. injective_rp); M = -W_p
     Csr M;
-    if (lo.interp == MGR_INTERP_JACOBI) {
-      M = std::move(Afc);
+    if (lo.interp == MGR_INTERP_JACOBI && lo.dff_block > 1) {
+      block_scale(Afc, lo.dff_block, L->dffinv64.p, M, s, flag);   // block D_FF^{-1} A_FC
+    } else if (lo.interp == MGR_INTERP_JACOBI) {
+      M = jac_r ? Csr() : std::move(Afc);
+      if (jac_r) copy_csr(Afc, M, s);
       scale_rows_div(M, L->dFF.p, s);
     } else {
       M.n = L->cf.nF;
@@ -848,6 +899,38 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     }
     Csr Acor;
     spgemm(lo.coupling == MGR_COUPLING_QUASI_IMPES ? AcfQ : L->Acf, M, Acor, s, flag);
+    if (jac_r) {
+      // N = A_CF D_FF^{-1}; correction A_CF M + N A_FC - N A_FF M (Jacobi restriction)
+      Csr N;
+      if (lo.dff_block > 1) {
+        // A_CF (block D_FF^{-1}) as the pinned-order product with the block-diagonal matrix
+        Csr Bd;
+        Bd.n = Bd.m = L->cf.nF;
+        Bd.nnz = L->cf.nF * lo.dff_block;
+        Bd.rp.alloc(Bd.n + 1, s);
+        Bd.ci.alloc(std::max<int64_t>(Bd.nnz, 1), s);
+        Bd.v.alloc(std::max<int64_t>(Bd.nnz, 1), s);
+        block_diag_pattern(Bd.n, lo.dff_block, Bd.rp.p, Bd.ci.p, s);
+        if (Bd.nnz)
+          HIPCHK(hipMemcpyAsync(Bd.v.p, L->dffinv64.p, Bd.nnz * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        spgemm(L->Acf, Bd, N, s, flag);
+      } else {
+        copy_csr(L->Acf, N, s);
+        scale_cols_div(N, L->dFF.p, s);
+      }
+      Csr NAfc, NAff, T3, B1, B2;
+      spgemm(N, Afc, NAfc, s, flag);
+      DArr<double> minus1(std::max<int64_t>(nC, 1), s);
+      fill<double>(minus1.p, -1.0, nC, s);
+      merge_drop(Acor, NAfc, minus1.p, -1, nullptr, B1, true, s, flag);   // A_CF M + N A_FC
+      spgemm(N, AffR, NAff, s, flag);
+      spgemm(NAff, M, T3, s, flag);
+      merge_drop(B1, T3, nullptr, -1, nullptr, B2, true, s, flag);       // - N A_FF M
+      Acor = std::move(B2);
+      negate_f64(N.v.p, N.nnz, s);
+      L->Wr = std::move(N);
+    }
     trace("  A_cor done");
     Csr S;
     merge_drop(Acc, Acor, nullptr, lo.nmax_drop, lrankC.p, S, true, s, flag, lo.drop_tol);
@@ -908,10 +991,12 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     cast_values(dinvF.p, L->tdinvF, L->cf.nF, sz, s);
     // the level matrix itself is read by the V-cycle unless the F-relaxation is a solve that
     // starts from z = 0 (then the residual uses A_CF only)
-    const bool needs_A = lo.global_smoother != MGR_GSMOOTH_NONE || lo.frelax == MGR_FRELAX_JACOBI;
+    const bool needs_A = lo.global_smoother != MGR_GSMOOTH_NONE || lo.frelax == MGR_FRELAX_JACOBI ||
+                         jac_r;
     L->needs_A = needs_A;
     // rows F and rows C of A_l for the residuals of levels that are not compacted
-    const bool need_sub = lo.frelax == MGR_FRELAX_JACOBI || lo.global_smoother != MGR_GSMOOTH_NONE;
+    const bool need_sub = lo.frelax == MGR_FRELAX_JACOBI || lo.global_smoother != MGR_GSMOOTH_NONE ||
+                          jac_r;
     if (need_sub) {
       gather_rows(L->A, L->cf.F.p, L->cf.nF, L->AF, s);
       gather_rows(L->A, L->cf.C.p, nC, L->AC, s);
@@ -921,10 +1006,13 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (needs_A) make_rowblocks(L->A, s);
     make_rowblocks(L->Acf, s);
     make_rowblocks(L->Wp, s);
+    if (jac_r) make_rowblocks(L->Wr, s);
+    if (lo.dff_block > 1) cast_values(L->dffinv64.p, L->tdffinv, L->cf.nF * lo.dff_block, sz, s);
     if (sz == 4) {
       if (needs_A) cast_values(L->A.v.p, L->tA, L->A.nnz, sz, s);
       cast_values(L->Acf.v.p, L->tAcf, L->Acf.nnz, sz, s);
       cast_values(L->Wp.v.p, L->tWp, L->Wp.nnz, sz, s);
+      if (jac_r) cast_values(L->Wr.v.p, L->tWr, L->Wr.nnz, sz, s);
       if (need_sub) {
         cast_values(L->AF.v.p, L->tAF, L->AF.nnz, sz, s);
         cast_values(L->AC.v.p, L->tAC, L->AC.nnz, sz, s);
@@ -983,6 +1071,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->iluL.v.reset();
         L->iluU.v.reset();
         L->ilu_dinv64.reset();
+        L->Wr.v.reset();
+        L->dffinv64.reset();
       }
       L->dFF.reset();
     }
@@ -1017,7 +1107,13 @@ void validate_opts(const mgr_opts &o) {
     require(lo.ilu_level == 0 || lo.ilu_level == 1, MGR_ERR_ARG, "ilu_level must be 0 or 1");
     require(lo.ilu_sweeps >= 0 && lo.ilu_sweeps <= 100, MGR_ERR_ARG, "ilu_sweeps");
     require(lo.ilu_tri_sweeps >= 0 && lo.ilu_tri_sweeps <= 100, MGR_ERR_ARG, "ilu_tri_sweeps");
-    require(lo.reserved0 == 0, MGR_ERR_ARG, "reserved0 must be 0");
+    require(lo.restrict_ == MGR_RESTRICT_INJECTION || lo.restrict_ == MGR_RESTRICT_JACOBI,
+            MGR_ERR_ARG, "restrict_");
+    require(lo.restrict_ == MGR_RESTRICT_INJECTION ||
+                (lo.coupling == MGR_COUPLING_FULL && lo.interp == MGR_INTERP_JACOBI),
+            MGR_ERR_ARG, "Jacobi restriction needs full coupling and Jacobi interpolation");
+    require(lo.dff_block >= 1 && lo.dff_block <= 3, MGR_ERR_ARG, "dff_block must be 1, 2 or 3");
+    require(lo.reserved1 == 0, MGR_ERR_ARG, "reserved1 must be 0");
     require(lo.global_sweeps >= 1 && lo.global_sweeps <= 100, MGR_ERR_ARG, "global_sweeps");
     require(lo.coupling == MGR_COUPLING_FULL || lo.coupling == MGR_COUPLING_QUASI_IMPES, MGR_ERR_ARG,
             "coupling");
@@ -1048,7 +1144,8 @@ size_t handle_bytes(const mgr_handle *h) {
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
          L->tAF.bytes() + L->tAC.bytes() +
          L->tffinv.bytes() + L->v.bytes() + L->z.bytes() + L->rF.bytes() + L->eF.bytes() +
-         L->rfull.bytes() + L->iluS.bytes() + L->iluL.bytes() + L->iluU.bytes() +
+         L->rfull.bytes() + L->Wr.bytes() + L->dffinv64.bytes() + L->tWr.bytes() +
+         L->tdffinv.bytes() + L->iluS.bytes() + L->iluL.bytes() + L->iluU.bytes() +
          L->ilu_dinv64.bytes() + L->tiluL.bytes() + L->tiluU.bytes() + L->tilu_dinv.bytes() +
          L->ilu_w.bytes();
     amg(L->amg);
@@ -1139,7 +1236,10 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
                        const fgmres_opts *o, void *work, size_t work_bytes, fgmres_result *res,
                        hipStream_t s, bool noalloc = false) {
   require(A && b && x && o, MGR_ERR_ARG, "null argument");
-  const int64_t n = A->nrows;
+  require(A->block >= 0 && A->block <= 3 && A->reserved == 0, MGR_ERR_ARG,
+          "matrix block size must be 0..3 and reserved 0");
+  const int bs = A->block > 1 ? A->block : 1;
+  const int64_t n = scalar_rows(*A);
   const int m = o->restart;
   require(m >= 1 && m <= 64, MGR_ERR_ARG, "restart must be in [1, 64]");
   require(o->maxit >= 1, MGR_ERR_ARG, "maxit must be positive");
@@ -1162,21 +1262,31 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   }
   FgWork W;
   fg_layout(n, m, base, &W);
+  // entries (blocks when bs > 1)
   int64_t nnz = 0;
   if (n) {
-    HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + A->nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   }
-  // row blocks fit the workspace unless rows average more than 2048 entries; such
-  // matrices use the lanes-per-row kernel
-  const bool streamed = stream_blocks(nnz) + 1 <= n + 2;
-  if (streamed) rowblocks64(*A, nnz, W.rb, s);
+  // row blocks fit the workspace unless rows average more than 2048 entries; such CSR
+  // matrices use the lanes-per-row kernel (BSR windows always fit: one per >= 227 values)
+  const int64_t K = bs > 1 ? bsr_stream_blocks(nnz, bs) : stream_blocks(nnz);
+  const bool streamed = K + 1 <= n + 2;
+  require(bs == 1 || streamed, MGR_ERR_UNSUPPORTED, "BSR block rows longer than supported");
+  if (streamed) {
+    if (bs > 1) bsr_rowblocks64(*A, nnz, W.rb, s);
+    else rowblocks64(*A, nnz, W.rb, s);
+  }
   const double avg = n ? (double)nnz / (double)n : 0.0;
-  const double spmv_bytes = (double)nnz * 12.0 + (double)n * (8.0 + 8.0 + 8.0);
+  // algorithmic bytes: values and column indices, row pointers, x and y once
+  const double spmv_bytes =
+      bs > 1 ? (double)nnz * (8.0 * bs * bs + 4.0) + (double)A->nrows * 8.0 + (double)n * 16.0
+             : (double)nnz * 12.0 + (double)n * (8.0 + 8.0 + 8.0);
   auto matvec = [&](const double *xx, const double *bb, double *yy) {
     const bool prof = Prof::on(1);
     if (prof) Prof::begin(1, s);
-    if (streamed) spmv64_stream(*A, nnz, W.rb, xx, bb, yy, s);
+    if (bs > 1) bsr_spmv64_stream(*A, nnz, W.rb, xx, bb, yy, s);
+    else if (streamed) spmv64_stream(*A, nnz, W.rb, xx, bb, yy, s);
     else spmv64_avg(*A, xx, bb, yy, avg, s);
     if (prof) Prof::end(1, s, spmv_bytes + (bb ? (double)n * 8.0 : 0.0));
   };
@@ -1322,7 +1432,9 @@ void mgr_default_opts(mgr_opts *o) {
     L.ilu_level = 1;
     L.ilu_sweeps = 3;
     L.ilu_tri_sweeps = 3;
-    L.reserved0 = 0;
+    L.restrict_ = MGR_RESTRICT_INJECTION;
+    L.dff_block = 1;
+    L.reserved1 = 0;
   }
 }
 
@@ -1335,12 +1447,15 @@ mgr_status mgr_setup(const mgr_csr *A, const int8_t *labels, const mgr_opts *opt
   try {
     validate_opts(*opts);
     require(A->nrows >= 1, MGR_ERR_ARG, "empty matrix");
+    require(A->block >= 0 && A->block <= 3 && A->reserved == 0, MGR_ERR_ARG,
+            "matrix block size must be 0..3 and reserved 0");
+    const int64_t n = scalar_rows(*A);
     h->opts = *opts;
     h->s = s;
     h->dflag.alloc(1, s);
     clear_flag(h->dflag.p, s);
-    h->labels0.alloc(A->nrows, s);
-    HIPCHK(hipMemcpyAsync(h->labels0.p, labels, A->nrows, hipMemcpyDeviceToDevice, s));
+    h->labels0.alloc(n, s);
+    HIPCHK(hipMemcpyAsync(h->labels0.p, labels, n, hipMemcpyDeviceToDevice, s));
     build(h.get(), A, labels);
   } catch (const Error &e) {
     return fail(e);
@@ -1357,7 +1472,9 @@ mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
   if (!h || !A) { t_err = "null argument"; return MGR_ERR_ARG; }
   hipStream_t s = static_cast<hipStream_t>(stream);
   try {
-    require(A->nrows == h->n, MGR_ERR_PATTERN, "size differs from the original matrix");
+    require(A->block >= 0 && A->block <= 3 && A->reserved == 0, MGR_ERR_ARG,
+            "matrix block size must be 0..3 and reserved 0");
+    require(scalar_rows(*A) == h->n, MGR_ERR_PATTERN, "size differs from the original matrix");
     {
       Csr tmp;
       import_csr(A, tmp, s, h->dflag.p);
@@ -1457,7 +1574,7 @@ mgr_status fgmres_solve_noalloc(const mgr_csr *A, mgr_handle *M, const double *b
   try {
     require(A && o, MGR_ERR_ARG, "null argument");
     require(o->restart >= 1 && o->restart <= 64, MGR_ERR_ARG, "restart must be in [1, 64]");
-    const size_t need = fgmres_workspace_bytes(A->nrows, o->restart);
+    const size_t need = fgmres_workspace_bytes(scalar_rows(*A), o->restart);
     if (need > kNoAllocBytes)
       throw Error(MGR_ERR_ARG, "fgmres_solve_noalloc: the system needs " + std::to_string(need) +
                                    " bytes of workspace; the static workspace holds " +
@@ -1560,6 +1677,11 @@ mgr_status mgr_query(const mgr_handle *h, int32_t what, int32_t level, int32_t s
                 "no ILU smoother kept at this level (set keep_setup)");
         csr(h->lv[level]->iluS);
         break;
+      case MGR_X_WR:
+        require(h->lv[level]->Wr.rp.p != nullptr, MGR_ERR_ARG,
+                "no Jacobi restriction at this level");
+        csr(h->lv[level]->Wr);
+        break;
       case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
       case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;
       case MGR_X_AMG_P:
@@ -1610,6 +1732,11 @@ mgr_status mgr_export(const mgr_handle *h, int32_t what, int32_t level, int32_t 
         require(h->lv[level]->iluS.rp.p != nullptr, MGR_ERR_ARG,
                 "no ILU smoother kept at this level (set keep_setup)");
         csr(h->lv[level]->iluS);
+        break;
+      case MGR_X_WR:
+        require(h->lv[level]->Wr.rp.p != nullptr, MGR_ERR_ARG,
+                "no Jacobi restriction at this level");
+        csr(h->lv[level]->Wr);
         break;
       case MGR_X_COARSE: csr(level + 1 == nl ? h->coarseA : h->lv[level + 1]->A); break;
       case MGR_X_AMG_A: csr(amg->lv[sub]->A); break;

@@ -189,6 +189,17 @@ __global__ void k_axpy(int64_t n, T alpha, const T *__restrict__ x, T *__restric
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) y[i] = y[i] + alpha * x[i];
 }
+template <class T>
+__global__ void k_scatter_axpy(const int *__restrict__ idx, int64_t n, T alpha,
+                               const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] = y[idx[i]] + alpha * x[i];
+}
+__global__ void k_scale_cols_div(int64_t nnz, const int *__restrict__ ci,
+                                 const double *__restrict__ d, double *__restrict__ v) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nnz) v[e] = v[e] / d[ci[e]];
+}
 
 template <int MODE>
 void split_part(const Csr &S, Csr &out, hipStream_t s) {
@@ -264,6 +275,11 @@ void ilu_factor(Csr &S, int sweeps, DArr<int> &dpos, hipStream_t s, int *dflag) 
   }
 }
 
+void block_diag_pattern(int64_t n, int nb, int *rp, int *ci, hipStream_t s) {
+  k_blockdiag_pattern<<<grid_for(n + 1, 256), 256, 0, s>>>(n, nb, rp, ci);
+  KCHK();
+}
+
 void block_scale(const Csr &A, int nb, const double *binv, Csr &As, hipStream_t s, int *dflag) {
   const int64_t n = A.n;
   Csr Bd;
@@ -298,5 +314,22 @@ void axpy(int64_t n, T alpha, const T *x, T *y, hipStream_t s) {
 }
 template void axpy<float>(int64_t, float, const float *, float *, hipStream_t);
 template void axpy<double>(int64_t, double, const double *, double *, hipStream_t);
+
+template <class T>
+void scatter_axpy(const int *idx, int64_t n, T alpha, const T *x, T *y, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_axpy<T><<<grid_for(n, 256), 256, 0, s>>>(idx, n, alpha, x, y);
+  KCHK();
+}
+template void scatter_axpy<float>(const int *, int64_t, float, const float *, float *,
+                                  hipStream_t);
+template void scatter_axpy<double>(const int *, int64_t, double, const double *, double *,
+                                   hipStream_t);
+
+void scale_cols_div(Csr &M, const double *d, hipStream_t s) {
+  if (M.nnz <= 0) return;
+  k_scale_cols_div<<<grid_for(M.nnz, 256), 256, 0, s>>>(M.nnz, M.ci.p, d, M.v.p);
+  KCHK();
+}
 
 }  // namespace mgr

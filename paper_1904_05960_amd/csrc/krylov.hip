@@ -85,6 +85,17 @@ __global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
   const int64_t cnt = rp[r1] - base;
   const int t = threadIdx.x;
   if (cnt <= SCAP) {
+    constexpr int G = 8;
+    // the first row of this thread's sum phase: its extent and b entry are loaded now, so
+    // that their latency overlaps the gathers
+    const int prow = r0 + t / G;
+    int ps = 0, pe = 0;
+    double pb = 0.0;
+    if (prow < r1) {
+      ps = (int)(rp[prow] - base);
+      pe = (int)(rp[prow + 1] - base);
+      if (b) pb = b[prow];
+    }
     // all loads of a thread issued before any gather is consumed: PER independent chains
     constexpr int PER = SNNZ / SB;
     for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
@@ -112,15 +123,20 @@ __global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
       }
     }
     __syncthreads();
-    constexpr int G = 8;
     const int l = t & (G - 1);
-    for (int row = r0 + t / G; row < r1; row += SB / G) {
-      const int s = (int)(rp[row] - base), e1 = (int)(rp[row + 1] - base);
+    for (int row = prow; row < r1; row += SB / G) {
+      int s = ps, e1 = pe;
+      double bv = pb;
+      if (row != prow) {
+        s = (int)(rp[row] - base);
+        e1 = (int)(rp[row + 1] - base);
+        bv = b ? b[row] : 0.0;
+      }
       double acc = 0.0;
       for (int e = s + l; e < e1; e += G) acc += prod[e];
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-      if (l == 0) y[row] = b ? b[row] - acc : acc;
+      if (l == 0) y[row] = b ? bv - acc : acc;
     }
     return;
   }
@@ -138,6 +154,131 @@ __global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
       y[row] = b ? b[row] - tot : tot;
     }
     __syncthreads();
+  }
+}
+
+// BSR variant (b x b row-major blocks, b = 2 or 3): block k owns the block rows whose
+// first block lies in the k-th window of SNNZ / b^2 blocks; the window's b^2 values per
+// block are read as one contiguous, coalesced stream, each multiplied by the x entry of
+// its block column and staged in LDS; then every scalar row (br, r) sums the b entries of
+// its row in each block from LDS with 8 lanes.  A window whose block rows hold more than
+// SCAP values (a block row longer than (SCAP - SNNZ) / b^2 + 1 blocks) sums each scalar row
+// directly.
+template <int B>
+__global__ void k_bsr_rowblocks(int64_t nbr, const int64_t *__restrict__ rp, int64_t K,
+                                int *__restrict__ rb) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k > K) return;
+  if (k == K) { rb[k] = (int)nbr; return; }
+  const int64_t target = k * (SNNZ / (B * B));
+  int64_t lo = 0, hi = nbr;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  rb[k] = (int)lo;
+}
+
+template <int B>
+__global__ void __launch_bounds__(SB) k_bsr_stream(const int *__restrict__ rb,
+                                                   const int64_t *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const double *__restrict__ v,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ y) {
+  constexpr int BB = B * B;
+  __shared__ double prod[SCAP];
+  const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int64_t base = rp[r0];                 // first block of the window
+  const int64_t cnt = (rp[r1] - base) * BB;    // values of the window
+  const int t = threadIdx.x;
+  if (cnt <= SCAP) {
+    constexpr int G = 8;
+    // the first scalar row of this thread's sum phase: block-row extent and b entry now
+    const int nsr = (r1 - r0) * B;
+    const int psr = t / G;
+    int ps = 0, plen = 0;
+    double pb = 0.0;
+    if (psr < nsr) {
+      const int br = r0 + psr / B;
+      ps = (int)(rp[br] - base);
+      plen = (int)(rp[br + 1] - rp[br]) * B;
+      if (b) pb = b[(int64_t)br * B + psr % B];
+    }
+    constexpr int PER = SNNZ / SB;
+    const double *vb = v + base * BB;
+    for (int e0 = 0; e0 < cnt; e0 += PER * SB) {
+      int c[PER];
+      double vv[PER], xv[PER];
+      // raw loads first (block column and value), all in flight together; the column
+      // arithmetic waits for them in the gather loop
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = e0 + u * SB + t;
+        c[u] = 0;
+        vv[u] = 0.0;
+        if (q < cnt) {
+          c[u] = ci[base + q / BB];
+          vv[u] = vb[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = e0 + u * SB + t;
+        xv[u] = (q < cnt) ? x[(int64_t)c[u] * B + (q % BB) % B] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int q = e0 + u * SB + t;
+        if (q < cnt) prod[q] = vv[u] * xv[u];
+      }
+    }
+    __syncthreads();
+    const int l = t & (G - 1);
+    for (int sr = psr; sr < nsr; sr += SB / G) {
+      const int br = r0 + sr / B, r = sr % B;
+      int s0 = ps, len = plen;
+      double bv = pb;
+      if (sr != psr) {
+        s0 = (int)(rp[br] - base);
+        len = (int)(rp[br + 1] - rp[br]) * B;
+        bv = b ? b[(int64_t)br * B + r] : 0.0;
+      }
+      double acc = 0.0;
+      for (int k = l; k < len; k += G) {
+        const int e = s0 + k / B;
+        acc += prod[e * BB + r * B + k % B];
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+      if (l == 0) y[(int64_t)br * B + r] = b ? bv - acc : acc;
+    }
+    return;
+  }
+  static_assert(SB == 256, "the fallback sums four wave partials");
+  __shared__ double part[SB / 64];
+  for (int br = r0; br < r1; ++br) {
+    const int64_t e0 = rp[br], len = (rp[br + 1] - e0) * B;
+    for (int r = 0; r < B; ++r) {
+      double acc = 0.0;
+      for (int64_t k = t; k < len; k += SB) {
+        const int64_t e = e0 + k / B;
+        const int c = (int)(k % B);
+        acc += v[e * BB + r * B + c] * x[(int64_t)ci[e] * B + c];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if ((t & 63) == 0) part[t >> 6] = acc;
+      __syncthreads();
+      if (t == 0) {
+        const double tot = (part[0] + part[1]) + (part[2] + part[3]);
+        const int64_t row = (int64_t)br * B + r;
+        y[row] = b ? b[row] - tot : tot;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -466,11 +607,49 @@ void spmv64_stream(const mgr_csr &A, int64_t nnz, const int *rb, const double *x
   KCHK();
 }
 
+// BSR: windows of SNNZ / b^2 blocks (nnzb = number of blocks)
+int64_t bsr_stream_blocks(int64_t nnzb, int bs) {
+  const int64_t wb = SNNZ / (bs * bs);
+  return (nnzb + wb - 1) / wb;
+}
+
+void bsr_rowblocks64(const mgr_csr &A, int64_t nnzb, int *rb, hipStream_t s) {
+  const int64_t K = bsr_stream_blocks(nnzb, A.block);
+  if (A.block == 2)
+    k_bsr_rowblocks<2><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
+  else
+    k_bsr_rowblocks<3><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
+  KCHK();
+}
+
+void bsr_spmv64_stream(const mgr_csr &A, int64_t nnzb, const int *rb, const double *x,
+                       const double *b, double *y, hipStream_t s) {
+  const int64_t K = bsr_stream_blocks(nnzb, A.block);
+  if (K == 0) {   // no blocks: y = b (or 0)
+    const int64_t n = A.nrows * A.block;
+    if (n == 0) return;
+    if (b) HIPCHK(hipMemcpyAsync(y, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else HIPCHK(hipMemsetAsync(y, 0, n * sizeof(double), s));
+    return;
+  }
+  if (A.block == 2)
+    k_bsr_stream<2><<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
+  else
+    k_bsr_stream<3><<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
+  KCHK();
+}
+
 void spmv64(const mgr_csr &A, const double *x, double *y, hipStream_t s) {
   int64_t nnz = 0;
   if (A.nrows) {
     HIPCHK(hipMemcpyAsync(&nnz, A.row_ptr + A.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+  }
+  if (A.block > 1) {
+    DArr<int> rb(bsr_stream_blocks(nnz, A.block) + 1, s);
+    bsr_rowblocks64(A, nnz, rb.p, s);
+    bsr_spmv64_stream(A, nnz, rb.p, x, nullptr, y, s);
+    return;
   }
   DArr<int> rb(stream_blocks(nnz) + 1, s);
   rowblocks64(A, nnz, rb.p, s);

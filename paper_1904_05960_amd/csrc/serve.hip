@@ -68,7 +68,7 @@ namespace {
 
 size_t fresh_setup_bytes(const mgr_server *S, const mgr_csr &A, int64_t nnz) {
   size_t b = 0;
-  mgr_estimate_footprint(A.nrows, nnz, &S->cfg.opts, &b);
+  mgr_estimate_footprint(mgr::scalar_rows(A), nnz, &S->cfg.opts, &b);
   return b;
 }
 
@@ -95,7 +95,7 @@ bool make_room(mgr_server *S, size_t need) {
 
 // bytes a batched request adds for its share of the union (matrix copy and vectors)
 size_t union_bytes(const mgr_server::Req *q) {
-  return (size_t)q->r.nnz * 12 + (size_t)q->A.nrows * 40;
+  return (size_t)q->r.nnz * 12 + (size_t)mgr::scalar_rows(q->A) * 40;
 }
 
 // With R admitted (no cached setup, small): take further admissible small requests
@@ -108,11 +108,12 @@ void gather_batch(mgr_server *S, mgr_server::Req *R, std::vector<mgr_server::Req
   for (auto it = S->queue.begin(); it != S->queue.end() && (int)batch.size() < cap;) {
     mgr_server::Req *q = S->reqs[*it].get();
     const uint64_t key = q->r.key;
-    bool take = !S->key_busy[key] && !blocked[key] && q->A.nrows <= S->cfg.batch_rows &&
+    bool take = !S->key_busy[key] && !blocked[key] && q->A.block <= 1 &&
+                mgr::scalar_rows(q->A) <= S->cfg.batch_rows &&
                 S->cache.find(key) == S->cache.end();
     size_t need = 0;
     if (take) {
-      need = fgmres_workspace_bytes(q->A.nrows, S->cfg.fopts.restart) +
+      need = fgmres_workspace_bytes(mgr::scalar_rows(q->A), S->cfg.fopts.restart) +
              fresh_setup_bytes(S, q->A, q->r.nnz) + union_bytes(q);
       take = S->used + need <= S->cfg.budget_bytes;
     }
@@ -211,7 +212,7 @@ void worker(mgr_server *S, int slot) {
             const int64_t nnz = q->r.nnz;
             auto c = S->cache.find(key);
             if (c != S->cache.end() && !c->second.busy &&
-                (c->second.n != q->A.nrows || c->second.nnz != nnz)) {
+                (c->second.n != mgr::scalar_rows(q->A) || c->second.nnz != nnz)) {
               // the key now names a matrix of another size: drop the stale setup
               mgr_destroy(c->second.h);
               S->used -= c->second.bytes;
@@ -219,7 +220,7 @@ void worker(mgr_server *S, int slot) {
               c = S->cache.end();
             }
             const bool cached = c != S->cache.end() && !c->second.busy;
-            size_t need = fgmres_workspace_bytes(q->A.nrows, S->cfg.fopts.restart);
+            size_t need = fgmres_workspace_bytes(mgr::scalar_rows(q->A), S->cfg.fopts.restart);
             if (!cached) need += fresh_setup_bytes(S, q->A, nnz);
             if (need > S->cfg.budget_bytes) {
               q->res.status = MGR_ERR_ALLOC;
@@ -252,7 +253,7 @@ void worker(mgr_server *S, int slot) {
       }
       if (!R) break;
       R->res.t_admit_ms = S->now_ms();
-      if (!hit && S->cfg.batch_rows > 0 && R->A.nrows <= S->cfg.batch_rows)
+      if (!hit && S->cfg.batch_rows > 0 && R->A.block <= 1 && mgr::scalar_rows(R->A) <= S->cfg.batch_rows)
         gather_batch(S, R, batch);
     }
     if (batch.size() > 1) {
@@ -311,7 +312,7 @@ void worker(mgr_server *S, int slot) {
     res.setup_reused = hit ? 1 : 0;
     res.batch = 1;
     const double t_setup = S->now_ms();
-    const size_t need_ws = fgmres_workspace_bytes(R->A.nrows, S->cfg.fopts.restart);
+    const size_t need_ws = fgmres_workspace_bytes(mgr::scalar_rows(R->A), S->cfg.fopts.restart);
     if (st_code == MGR_OK && need_ws > work_bytes) {
       if (work) mgr::dfree(work, st);
       try {
@@ -352,7 +353,7 @@ void worker(mgr_server *S, int slot) {
             mgr_server::Entry e;
             e.h = h;
             e.bytes = fp;
-            e.n = R->A.nrows;
+            e.n = mgr::scalar_rows(R->A);
             e.nnz = R->r.nnz;
             S->cache[key] = e;
             S->used += fp;

@@ -1068,7 +1068,61 @@ void copy_csr(const Csr &A, Csr &B, hipStream_t s) {
   }
 }
 
+// BSR (b x b row-major blocks, block rows and columns) to scalar CSR: scalar row br*b + r
+// holds, for every block of block row br in order, the b entries of the block's row r
+// (zeros included), so the columns stay sorted
+__global__ void k_bsr_rowptr(int64_t nbr, int bs, const int64_t *__restrict__ brp,
+                             int *__restrict__ rp, int *flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i > nbr * bs) return;
+  const int64_t br = i / bs, r = i % bs;
+  const int64_t v = i == nbr * bs ? brp[nbr] * bs * bs
+                                  : brp[br] * bs * bs + r * (brp[br + 1] - brp[br]) * bs;
+  if (v < 0 || v > 0x7fffffffLL) atomicOr(flag, FLAG_OVERFLOW);
+  rp[i] = (int)v;
+}
+__global__ void k_bsr_expand(int64_t nbr, int bs, const int64_t *__restrict__ brp,
+                             const int *__restrict__ bci, const double *__restrict__ bv,
+                             const int *__restrict__ rp, int *__restrict__ ci,
+                             double *__restrict__ v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // scalar row
+  if (i >= nbr * bs) return;
+  const int64_t br = i / bs;
+  const int r = (int)(i % bs);
+  int o = rp[i];
+  for (int64_t e = brp[br]; e < brp[br + 1]; ++e)
+    for (int c = 0; c < bs; ++c) {
+      ci[o] = bci[e] * bs + c;
+      v[o] = bv[e * bs * bs + r * bs + c];
+      ++o;
+    }
+}
+
 void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
+  require(A->block >= 0 && A->block <= 3, MGR_ERR_ARG, "matrix block size must be 0..3");
+  if (A->block > 1) {
+    const int bs = A->block;
+    int64_t nnzb = 0;
+    HIPCHK(hipMemcpyAsync(&nnzb, A->row_ptr + A->nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t nnz = nnzb * bs * bs;
+    require(nnzb >= 0 && nnz < 0x7fffffffLL, MGR_ERR_UNSUPPORTED, "nnz must be below 2^31");
+    B.n = A->nrows * bs;
+    B.m = A->ncols * bs;
+    B.nnz = nnz;
+    B.rp.alloc(B.n + 1, s);
+    B.ci.alloc(std::max<int64_t>(nnz, 1), s);
+    B.v.alloc(std::max<int64_t>(nnz, 1), s);
+    k_bsr_rowptr<<<grid_for(B.n + 1, 256), 256, 0, s>>>(A->nrows, bs, A->row_ptr, B.rp.p, dflag);
+    KCHK();
+    if (B.n > 0) {
+      k_bsr_expand<<<grid_for(B.n, 256), 256, 0, s>>>(A->nrows, bs, A->row_ptr, A->col, A->val,
+                                                      B.rp.p, B.ci.p, B.v.p);
+      KCHK();
+    }
+    check_flags(dflag, s, "block matrix import");
+    return;
+  }
   int64_t nnz = 0;
   HIPCHK(hipMemcpyAsync(&nnz, A->row_ptr + A->nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

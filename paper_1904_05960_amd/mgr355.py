@@ -30,6 +30,7 @@ COUPLING = {"full": 0, "quasi_impes": 1}
 X_LEVEL_A, X_F, X_C, X_WP, X_ACOR, X_G, X_COARSE, X_AMG_A, X_AMG_P, X_AMG_AGG, X_AMG_NLEV = range(11)
 X_GS_COLOR = 11
 X_ILU = 12
+X_WR = 13
 MAX_LEVELS = 8
 
 
@@ -41,7 +42,8 @@ class MgrError(RuntimeError):
 
 class mgr_csr(C.Structure):
     _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("row_ptr", C.c_void_p),
-                ("col", C.c_void_p), ("val", C.c_void_p)]
+                ("col", C.c_void_p), ("val", C.c_void_p), ("block", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class mgr_amg_opts(C.Structure):
@@ -55,7 +57,8 @@ class mgr_level_opts(C.Structure):
                 ("global_sweeps", C.c_int32), ("coupling", C.c_int32),
                 ("global_omega", C.c_double), ("drop_tol", C.c_double),
                 ("ilu_level", C.c_int32), ("ilu_sweeps", C.c_int32),
-                ("ilu_tri_sweeps", C.c_int32), ("reserved0", C.c_int32)]
+                ("ilu_tri_sweeps", C.c_int32), ("restrict_", C.c_int32),
+                ("dff_block", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class mgr_opts(C.Structure):
@@ -192,16 +195,20 @@ def _ptr(t):
 
 # ----------------------------------------------------------------------------------------
 class Matrix:
-    """Device CSR matrix (int64 row pointers, int32 columns, FP64 values) in torch tensors."""
+    """Device CSR matrix (int64 row pointers, int32 columns, FP64 values) in torch tensors,
+    or BSR with block x block row-major blocks (block = 2 or 3: row pointers and columns
+    over blocks, values nnzb * block^2).  `nrows` / `ncols` count scalar rows / columns."""
 
-    def __init__(self, row_ptr, col, val, ncols=None):
+    def __init__(self, row_ptr, col, val, ncols=None, block=1):
         import torch
         assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
-        assert val.dtype == torch.float64
-        self.row_ptr, self.col, self.val = row_ptr, col, val
-        self.nrows = row_ptr.numel() - 1
+        assert val.dtype == torch.float64 and block in (1, 2, 3)
+        self.row_ptr, self.col, self.val, self.block = row_ptr, col, val, block
+        nbr = row_ptr.numel() - 1
+        self.nrows = nbr * block
         self.ncols = self.nrows if ncols is None else ncols
-        self.c = mgr_csr(self.nrows, self.ncols, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+        self.c = mgr_csr(nbr, self.ncols // block, row_ptr.data_ptr(), col.data_ptr(),
+                         val.data_ptr(), block, 0)
 
     @staticmethod
     def from_host(indptr, indices, data, device="cuda", ncols=None):
@@ -210,9 +217,23 @@ class Matrix:
                       torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(device),
                       torch.as_tensor(np.asarray(data, dtype=np.float64)).to(device), ncols)
 
+    @staticmethod
+    def bsr_from_host(indptr, indices, blocks, device="cuda"):
+        """BSR from host arrays: block row pointers, block columns (sorted within a block
+        row), blocks of shape (nnzb, b, b)."""
+        import torch
+        blocks = np.ascontiguousarray(blocks, dtype=np.float64)
+        b = blocks.shape[1]
+        nbc = int(np.max(indices)) + 1 if len(indices) else 0
+        return Matrix(torch.as_tensor(np.asarray(indptr, dtype=np.int64)).to(device),
+                      torch.as_tensor(np.asarray(indices, dtype=np.int32)).to(device),
+                      torch.as_tensor(blocks.reshape(-1)).to(device),
+                      ncols=(len(indptr) - 1) * b, block=b)
+
     @property
     def nnz(self):
-        return int(self.col.numel())
+        """Scalar entries (stored zeros of blocks included)."""
+        return int(self.col.numel()) * self.block * self.block
 
     def spmv(self, x, y=None, stream=None):
         import torch
@@ -240,6 +261,8 @@ class Level:
     ilu_level: int = 1              # global_smoother 'ilu': ILU(k), k = 0 or 1
     ilu_sweeps: int = 3             # fixed-point sweeps of the factorisation
     ilu_tri_sweeps: int = 3         # Jacobi sweeps per triangular solve
+    restrict: str = "injection"     # 'injection' | 'jacobi' (W_r = -A_CF D_FF^{-1})
+    dff_block: int = 1              # D_FF pointwise (1) or blocks of 2 / 3 F rows
 
 
 @dataclass
@@ -282,6 +305,8 @@ class Options:
             c.ilu_level = int(L.ilu_level)
             c.ilu_sweeps = int(L.ilu_sweeps)
             c.ilu_tri_sweeps = int(L.ilu_tri_sweeps)
+            c.restrict_ = {"injection": 0, "jacobi": 1}[L.restrict]
+            c.dff_block = int(L.dff_block)
         o.coarse = COARSE[self.coarse]
         for dst, src in ((o.amg_frelax, self.amg_frelax), (o.amg_coarse, self.amg_coarse)):
             dst.theta0, dst.max_levels, dst.coarse_size = src.theta0, src.max_levels, src.coarse_size

@@ -20,7 +20,8 @@ def oracle_plan(opts) -> omgr.Plan:
             frelax_block=L.frelax_block, global_smoother=L.global_smoother,
             global_sweeps=L.global_sweeps, global_omega=L.global_omega,
             coupling=L.coupling, drop_tol=L.drop_tol, ilu_level=L.ilu_level,
-            ilu_sweeps=L.ilu_sweeps, ilu_tri_sweeps=L.ilu_tri_sweeps))
+            ilu_sweeps=L.ilu_sweeps, ilu_tri_sweeps=L.ilu_tri_sweeps, restrict=L.restrict,
+            dff_block=L.dff_block))
     a, c = opts.amg_frelax, opts.amg_coarse
     return omgr.Plan(levels=levels, coarse=opts.coarse,
                      amg_frelax=oamg.AMGOptions(a.theta0, a.max_levels, a.coarse_size, 3),

@@ -63,6 +63,16 @@ def ilu_plan(model, level, steps, tri=3, sweeps=3):
     return opts
 
 
+def variant_plan(model, restrict=None, dff=None, **kw):
+    """The paper plan with the Jacobi restriction and / or block D_FF on the given levels."""
+    opts = m.paper_plan(model, **kw)
+    for l, r in (restrict or {}).items():
+        opts.levels[l].restrict = r
+    for l, b in (dff or {}).items():
+        opts.levels[l].dff_block = b
+    return opts
+
+
 def galerkin_plan(model, coarse):
     """The paper plan with no dropping on the displacement level (N_max = -1)."""
     opts = m.paper_plan(model, coarse=coarse) if model == "biot1" else m.paper_plan(model)
@@ -109,6 +119,12 @@ CASES = [
      lambda: small_amg(ilu_plan("three", level=1, steps=1))),
     ("channels_12x10x6_ilu1", lambda: pm.two_phase_channels(12, 10, 6, 2),
      lambda: small_amg(ilu_plan("two", level=1, steps=1, tri=4))),
+    ("two_9x7x6_jacobi_restriction", lambda: pm.two_phase(9, 7, 6, 1),
+     lambda: small_amg(variant_plan("two", restrict={0: "jacobi", 1: "jacobi"}))),
+    ("biot_8x8x8_block_dff", lambda: pm.biot_single_phase(8, 8, 8, 0),
+     lambda: small_amg(variant_plan("biot1", dff={0: 3}, coarse="dense"))),
+    ("three_6x5x4_block_dff_jacobi_restriction", lambda: pm.three_phase(6, 5, 4, 3),
+     lambda: small_amg(variant_plan("three", dff={0: 3}, restrict={0: "jacobi", 2: "jacobi"}))),
 ]
 
 
@@ -132,6 +148,8 @@ def compare_hierarchy(P, H: omgr.Hierarchy, tag):
         assert_csr_equal(P.export(m.X_WP, l), L.Wp, f"{tag} W_p[{l}]")
         assert_csr_equal(P.export(m.X_ACOR, l), L.Acor, f"{tag} A_cor[{l}]")
         assert_csr_equal(P.export(m.X_G, l), L.G, f"{tag} G[{l}]")
+        if L.Wr is not None:
+            assert_csr_equal(P.export(m.X_WR, l), L.Wr, f"{tag} W_r[{l}]")
         if L.amg is not None:
             compare_amg(P, l, L.amg, f"{tag} F-AMG[{l}]")
         if L.colors is not None:
