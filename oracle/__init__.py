@@ -20,6 +20,9 @@ Modules
   ilu     - ILU(k) pattern by levels of fill, factors by synchronous fine-grained
             fixed-point sweeps, triangular solves exact or by Jacobi sweeps (the global
             smoother of Sec. 5.3 / Sec. 6)
+  assembly - residual F(x) and exact Jacobian of the two-phase poromechanics model of
+            Sec. 2-3 (Q1 displacement, TPFA upwind mass balances, backward Euler)
+  newton  - Newton's method with backtracking for one time step (Sec. 4, eq. newton)
 
 Parity pins: every function is checked in tests/ against closed forms, identities of
 Sec. 5.1, brute force on tiny inputs, or textbook special cases.  End-to-end iteration

@@ -422,7 +422,10 @@ def assemble(name, nx, ny, nz, model, logk10, E, nu, rng, sat_ranges=None,
     b = A @ x_true
 
     meta = dict(nnode=nnode, ncell=ncell, Nu=Nu, nf=nf, slots=list(slots), model=model,
-                nu=nu, gravity=bool(grav))
+                nu=nu, gravity=bool(grav),
+                # the state the Jacobian was taken at, and the cell properties
+                state=dict(p=p.ravel().copy(), **{"S_" + ph: S[ph].ravel().copy() for ph in S}),
+                perm=k.ravel().copy(), young=np.asarray(E, dtype=np.float64).ravel().copy())
     return Workload(name=name, nx=nx, ny=ny, nz=nz, model=model, indptr=indptr,
                     indices=indices, data=data, labels=labels, b=b, x_true=x_true,
                     fixed=fixed, meta=meta)
