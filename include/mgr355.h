@@ -480,6 +480,129 @@ mgr_status mgr_profile_enable(int32_t family, int32_t enable);
 mgr_status mgr_profile_read(int32_t family, int64_t *launches, double *total_ms,
                             double *bytes);
 
+/* ---------------------------------------------------------------------------------- */
+/* Residual and Jacobian of two-phase poromechanics, and Newton time steps (Sec. 2-4).
+ *
+ * The fully discrete system of Sec. 3 (eq. IBVP_G; F(x) = 0 of eq. IBVP_G_res) for the
+ * displacement / wetting saturation / pressure model of Sec. 2 on nx x ny x nz unit cubes:
+ * trilinear displacement, cell-wise constant (s, p), two-point fluxes with harmonic
+ * transmissibility and first-order upwinding on the phase potential (ties: the lower cell
+ * index is upwind), backward Euler.  Model choices: porosity phi0 + b eps_v(u) with eps_v
+ * the cell integral of div u; mixture weight (1 - phi0) rho_s + phi0 (rho_w s +
+ * rho_nw (1 - s)); rho_l = rho0_l exp(c_l (p - p_ref)); k_rw = max(s, 0)^2,
+ * k_rnw = max(1 - s, 0)^2; wells as fixed mass injection per phase and producers
+ * q_l = -WI rho_l lambda_l (p - p_bhp); a mass row is accumulation + outflow - source;
+ * Dirichlet displacement dofs are fixed at zero (their rows are K_dd u_d, their columns
+ * eliminated).  Unknowns: displacement dofs node-major (x/y/z interleaved, nodes x fastest),
+ * then (s, p) per cell (cells x fastest); rows in the same order, a cell's wetting-phase
+ * mass balance on its s row and non-wetting on its p row.  Labels: 0 displacement,
+ * 1 saturation, 2 pressure. */
+typedef struct {
+  int32_t nx, ny, nz;          /* cells per axis, >= 1                                  */
+  int32_t reserved;            /* 0                                                      */
+  double nu;                   /* Poisson ratio (Young's modulus is per cell)           */
+  double phi0;                 /* reference porosity                                     */
+  double biot;                 /* Biot coefficient b                                     */
+  double grav;                 /* gravity (m/s^2), pointing along -z                     */
+  double p_ref;                /* reference pressure of the densities (Pa)              */
+  double rho_solid;            /* grain density (kg/m^3)                                 */
+  double rho0[2];              /* wetting, non-wetting reference densities               */
+  double comp[2];              /* their compressibilities c_l (1/Pa)                     */
+  double visc[2];              /* their viscosities (Pa s)                               */
+  double dt;                   /* time step (s)                                          */
+} mgr_poro_params;
+
+typedef struct mgr_poro mgr_poro;
+
+/* Defaults: nu 0.25, phi0 0.2, b 1, g 9.81, p_ref 1e7, rho_s 2650, water 1000 kg/m^3,
+ * 4.5e-10 1/Pa, 1e-3 Pa s; oil 800, 1e-9, 5e-3; dt one day.  [host] */
+void mgr_poro_default_params(mgr_poro_params *p, int32_t nx, int32_t ny, int32_t nz);
+
+/* Build the model: copies the cell arrays (device or host pointers, ncell entries each;
+ * fixed: 3 * nnode bytes, nonzero = fixed displacement dof), builds the Jacobian pattern
+ * (owned; sorted columns) and the constant displacement-displacement block.  well_index and
+ * well_pbhp are given together or both NULL (no producers); inj_w / inj_nw (kg/s per
+ * cell) may be NULL.  Synchronises `stream`.  Errors: ARG (null arrays, parameters out of
+ * range, a non-positive Young's modulus), UNSUPPORTED (a grid whose Jacobian needs int64
+ * column indices), ALLOC, HIP. */
+mgr_status mgr_poro_create(const mgr_poro_params *prm, const double *perm, const double *young,
+                           const uint8_t *fixed, const double *well_index,
+                           const double *well_pbhp, const double *inj_w, const double *inj_nw,
+                           void *stream, mgr_poro **out);
+
+/* Change the time step of later assemblies.  Errors: ARG. [host] */
+mgr_status mgr_poro_set_dt(mgr_poro *P, double dt);
+
+/* Describe the owned Jacobian (values as of the last assembly) and its labels; the
+ * pointers stay valid until mgr_poro_destroy.  [host] */
+mgr_status mgr_poro_matrix(const mgr_poro *P, mgr_csr *A, const int8_t **labels);
+
+/* sizes[0] = n (unknowns), sizes[1] = Jacobian entries, sizes[2] = displacement dofs,
+ * sizes[3] = cells.  [host] */
+mgr_status mgr_poro_sizes(const mgr_poro *P, int64_t sizes[4]);
+
+/* Copy the Jacobian (n + 1 row pointers, entries' columns and values as of the last
+ * assembly) and the n labels into caller arrays (device or host; any may be NULL).
+ * Synchronises `stream`.  Errors: ARG, HIP. */
+mgr_status mgr_poro_export(const mgr_poro *P, int64_t *row_ptr, int32_t *col, double *val,
+                           int8_t *labels, void *stream);
+
+/* F = F(x) for the step from x_old to x (n entries each, n = 3 nnode + 2 ncell), and with
+ * with_jacobian != 0 the Jacobian values at x into the owned matrix.  norms [host, 6] may
+ * be NULL; otherwise it receives, per row type (momentum, wetting, non-wetting), the sum of
+ * squares and the largest magnitude of the residual in state units (momentum rows / the
+ * largest Young's modulus; mass rows of phase l * dt / (phi0 rho0_l)), and the call
+ * synchronises `stream`.  Errors: ARG, HIP. */
+mgr_status mgr_poro_assemble(mgr_poro *P, const double *x, const double *x_old, double *F,
+                             int32_t with_jacobian, double *norms, void *stream);
+
+#define MGR_NEWTON_MAX_RECORD 32
+
+typedef struct {
+  int32_t max_newton;          /* Newton iterations per time step, 0..32 (default 12)   */
+  int32_t max_backtracks;      /* halvings of the step per iteration (default 6)        */
+  double tol_flow;             /* converged when every mass residual in state units is  */
+  double tol_mech;             /*   <= tol_flow and every momentum one <= tol_mech      */
+                               /*   (defaults 1e-6 and 1e-10)                           */
+  double max_ds;               /* cap on |lambda ds| of any saturation (default 0.2)   */
+  double armijo;               /* sufficient decrease factor (default 1e-4)            */
+} mgr_newton_opts;
+
+typedef struct {
+  int32_t newton_iters;        /* linear solves done                                    */
+  int32_t linear_iters;        /* FGMRES iterations over all of them                    */
+  int32_t backtracks;          /* step halvings                                         */
+  int32_t converged;           /* 1 if the test above held at the end                   */
+  int32_t setups;              /* full MGR setups (1 when *h was NULL on entry)         */
+  int32_t linear_failures;     /* solves that reached maxit (their iterate is used)     */
+  int32_t lin_iters[MGR_NEWTON_MAX_RECORD];
+  double merit[MGR_NEWTON_MAX_RECORD + 1];   /* ||residual in state units||_2 before
+                                                every solve and at the end              */
+  double lambda[MGR_NEWTON_MAX_RECORD];
+  double assemble_ms, setup_ms, solve_ms;    /* host wall time of the phases           */
+} mgr_newton_stats;
+
+/* [host] */
+void mgr_newton_default_opts(mgr_newton_opts *o);
+
+/* One time step by Newton's method with backtracking (Sec. 4, eq. newton): at x^(k)
+ * assemble F and A, solve A d = F by fgmres_solve preconditioned with MGR, take
+ * x^(k+1) = x^(k) - lambda d where lambda starts at 1, is cut so no saturation moves by
+ * more than max_ds, and is halved while the merit (the 2-norm of the residual in state
+ * units) fails to fall by the factor (1 - armijo lambda); the last halving is accepted.
+ * The MGR hierarchy is *h: built with mgr_setup(opts = mo) when *h is NULL, else rebuilt
+ * with mgr_setup_numeric (the pattern never changes); the caller owns and destroys it.
+ *   x      n entries: the initial guess in (usually x_old), the new time level out.
+ *   x_old  the previous time level.
+ * Synchronises `stream`.  A linear solve that reaches maxit is counted and its iterate
+ * used.  Errors: ARG, ZERO_PIVOT and the other errors of mgr_setup / fgmres_solve, ALLOC,
+ * HIP; Newton's own non-convergence is reported in st->converged, not as an error. */
+mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
+                           const fgmres_opts *fo, double *x, const double *x_old,
+                           const mgr_newton_opts *no, mgr_newton_stats *st, void *stream);
+
+void mgr_poro_destroy(mgr_poro *P);
+
 #ifdef __cplusplus
 }
 #endif

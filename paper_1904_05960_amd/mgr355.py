@@ -105,6 +105,32 @@ class mgr_server_stats_t(C.Structure):
                 ("peak_reserved_bytes", C.c_size_t)]
 
 
+class mgr_poro_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved", C.c_int32),
+                ("nu", C.c_double), ("phi0", C.c_double), ("biot", C.c_double),
+                ("grav", C.c_double), ("p_ref", C.c_double), ("rho_solid", C.c_double),
+                ("rho0", C.c_double * 2), ("comp", C.c_double * 2), ("visc", C.c_double * 2),
+                ("dt", C.c_double)]
+
+
+NEWTON_MAX_RECORD = 32
+
+
+class mgr_newton_opts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("max_backtracks", C.c_int32),
+                ("tol_flow", C.c_double), ("tol_mech", C.c_double), ("max_ds", C.c_double),
+                ("armijo", C.c_double)]
+
+
+class mgr_newton_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("linear_iters", C.c_int32),
+                ("backtracks", C.c_int32), ("converged", C.c_int32), ("setups", C.c_int32),
+                ("linear_failures", C.c_int32), ("lin_iters", C.c_int32 * NEWTON_MAX_RECORD),
+                ("merit", C.c_double * (NEWTON_MAX_RECORD + 1)),
+                ("lambda_", C.c_double * NEWTON_MAX_RECORD), ("assemble_ms", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -169,6 +195,20 @@ def lib():
         "mgr_server_poll": (C.c_int32, [vp, C.c_uint64]),
         "mgr_server_stats": (st, [vp, C.POINTER(mgr_server_stats_t)]),
         "mgr_server_destroy": (None, [vp]),
+        "mgr_poro_default_params": (None, [C.POINTER(mgr_poro_params), C.c_int32, C.c_int32,
+                                           C.c_int32]),
+        "mgr_newton_default_opts": (None, [C.POINTER(mgr_newton_opts)]),
+        "mgr_poro_create": (st, [C.POINTER(mgr_poro_params), vp, vp, vp, vp, vp, vp, vp, vp,
+                                 C.POINTER(vp)]),
+        "mgr_poro_set_dt": (st, [vp, C.c_double]),
+        "mgr_poro_matrix": (st, [vp, C.POINTER(mgr_csr), C.POINTER(vp)]),
+        "mgr_poro_sizes": (st, [vp, C.POINTER(C.c_int64)]),
+        "mgr_poro_export": (st, [vp, vp, vp, vp, vp, vp]),
+        "mgr_poro_assemble": (st, [vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]),
+        "mgr_poro_newton": (st, [vp, C.POINTER(vp), C.POINTER(mgr_opts), C.POINTER(fgmres_opts),
+                                 vp, vp, C.POINTER(mgr_newton_opts),
+                                 C.POINTER(mgr_newton_stats), vp]),
+        "mgr_poro_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

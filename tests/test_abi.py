@@ -59,6 +59,42 @@ def test_struct_layouts_match_c(tmp_path):
     assert got == exp
 
 
+def test_poro_struct_layouts_match_c(tmp_path):
+    from paper_1904_05960_amd import mgr355 as m
+    src = tmp_path / "sz2.c"
+    src.write_text('#include "%s"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu\\n",'
+                   'sizeof(mgr_poro_params), offsetof(mgr_poro_params, dt),'
+                   'sizeof(mgr_newton_opts), sizeof(mgr_newton_stats),'
+                   'offsetof(mgr_newton_stats, merit), offsetof(mgr_newton_stats, solve_ms));}\n'
+                   % HEADER)
+    exe = tmp_path / "sz2"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    exp = [ctypes.sizeof(m.mgr_poro_params), m.mgr_poro_params.dt.offset,
+           ctypes.sizeof(m.mgr_newton_opts), ctypes.sizeof(m.mgr_newton_stats),
+           m.mgr_newton_stats.merit.offset, m.mgr_newton_stats.solve_ms.offset]
+    assert got == exp
+
+
+def test_poro_defaults_without_gpu():
+    from paper_1904_05960_amd import mgr355 as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.skip("library not built")
+    L = m.lib()
+    p = m.mgr_poro_params()
+    L.mgr_poro_default_params(ctypes.byref(p), 4, 3, 2)
+    assert (p.nx, p.ny, p.nz, p.reserved) == (4, 3, 2, 0)
+    assert p.rho0[0] == 1000.0 and p.visc[1] == 5.0e-3 and p.dt == 86400.0
+    o = m.mgr_newton_opts()
+    L.mgr_newton_default_opts(ctypes.byref(o))
+    assert o.max_newton == 12 and o.tol_flow == 1e-6 and o.max_ds == 0.2
+    h = ctypes.c_void_p()
+    assert L.mgr_poro_create(ctypes.byref(p), None, None, None, None, None, None, None, None,
+                             ctypes.byref(h)) == m.MGR_ERR_ARG
+    assert L.mgr_poro_set_dt(None, 1.0) == m.MGR_ERR_ARG
+
+
 def test_default_options_and_errors_without_gpu():
     """Host-side argument checks return documented statuses without touching the device."""
     from paper_1904_05960_amd import mgr355 as m

@@ -487,3 +487,54 @@ def closed_form_nnz(nx, ny, nz, model) -> int:
     fu = node_cell * 3 * nf
     ff = (ncell + 2 * faces) * nf * nf
     return uu + uf + fu + ff
+
+
+# ----------------------------------------------------------------------------------------
+# Time-stepping inputs: a channelised reservoir with a water line drive
+# ----------------------------------------------------------------------------------------
+def channel_reservoir(nx=32, ny=32, nz=8, seed=5, width=4, k_channel=-12.0,
+                      k_background=-14.5, noise=0.3, days_to_half_pv=100.0):
+    """Cell properties and the initial state of a two-phase time-stepping problem.
+
+    Permeability: binary channels (`channel_field`) with log10 k = k_channel inside and
+    k_background outside, plus N(0, noise^2) in log10.  Young's modulus U[5, 30] GPa per
+    z-layer, Poisson ratio 0.25.  Bottom fixed, lateral faces on rollers.  Wells: water
+    injected on the x = 0 column of cells at a total mass rate that puts half a pore volume
+    in over `days_to_half_pv` days, split in proportion to k; producers on the x = nx - 1
+    column with well index 2 k and bottom-hole pressure 0.2 MPa below the initial pressure.
+    Initial state: u = 0, s = 0.15, p = p_ref + rho_o g (depth of the cell centre).
+    Returns a dict of flat arrays in the model's unknown order."""
+    rng = np.random.default_rng(seed)
+    ch = channel_field(rng, (nz, ny, nx), width=width, fraction=0.3, max_amp=max(2.0, ny / 8))
+    logk = np.where(ch, k_channel, k_background) + noise * rng.standard_normal((nz, ny, nx))
+    k = 10.0 ** logk
+    Elayer = rng.uniform(5.0e9, 30.0e9, size=nz)
+    E = np.broadcast_to(Elayer[:, None, None], (nz, ny, nx)).copy()
+    nnx, nny, nnz_ = nx + 1, ny + 1, nz + 1
+    nnode = nnx * nny * nnz_
+    iz, iy, ix = np.meshgrid(np.arange(nnz_), np.arange(nny), np.arange(nnx), indexing="ij")
+    iz, iy, ix = iz.ravel(), iy.ravel(), ix.ravel()
+    fixed = np.zeros((nnode, 3), dtype=bool)
+    fixed[iz == 0, :] = True
+    fixed[(ix == 0) | (ix == nx), 0] = True
+    fixed[(iy == 0) | (iy == ny), 1] = True
+    ncell = nx * ny * nz
+    cx = np.arange(ncell) % nx
+    inj = cx == 0
+    prod = cx == nx - 1
+    pv = PHI0 * ncell
+    q_total = 0.5 * pv * PHASE["w"]["rho0"] / (days_to_half_pv * DT)
+    kf = k.ravel()
+    qw = np.zeros(ncell)
+    qw[inj] = q_total * kf[inj] / kf[inj].sum()
+    zc = (np.arange(ncell) // (nx * ny)).astype(np.float64) + 0.5
+    p0 = P_REF + PHASE["o"]["rho0"] * GRAV * (nz - zc)
+    wi = np.zeros(ncell)
+    wi[prod] = 2.0 * kf[prod]
+    pbhp = np.where(prod, p0 - 2.0e5, 0.0)
+    x0 = np.zeros(3 * nnode + 2 * ncell)
+    x0[3 * nnode::2] = 0.15
+    x0[3 * nnode + 1::2] = p0
+    return dict(nx=nx, ny=ny, nz=nz, perm=kf.copy(), young=E.ravel().copy(),
+                fixed=fixed.ravel(), wi=wi, pbhp=pbhp, qw=qw, qo=np.zeros(ncell), x0=x0,
+                nu=0.25, dt=DT)
