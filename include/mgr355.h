@@ -586,7 +586,10 @@ typedef struct {
 void mgr_newton_default_opts(mgr_newton_opts *o);
 
 /* One time step by Newton's method with backtracking (Sec. 4, eq. newton): at x^(k)
- * assemble F and A, solve A d = F by fgmres_solve preconditioned with MGR, take
+ * assemble F and A, scale both to state units row by row (D: momentum rows / the largest
+ * Young's modulus, mass rows of phase l * dt / (phi0 rho0_l); MGR is invariant to it, the
+ * FGMRES residual norm is not: unscaled, the momentum rows in newtons swamp the mass rows
+ * in kg/s), solve (D A) d = D F by fgmres_solve preconditioned with MGR, take
  * x^(k+1) = x^(k) - lambda d where lambda starts at 1, is cut so no saturation moves by
  * more than max_ds, and is halved while the merit (the 2-norm of the residual in state
  * units) fails to fall by the factor (1 - armijo lambda); the last halving is accepted.
@@ -596,7 +599,9 @@ void mgr_newton_default_opts(mgr_newton_opts *o);
  *   x_old  the previous time level.
  * Synchronises `stream`.  A linear solve that reaches maxit is counted and its iterate
  * used.  Errors: ARG, ZERO_PIVOT and the other errors of mgr_setup / fgmres_solve, ALLOC,
- * HIP; Newton's own non-convergence is reported in st->converged, not as an error. */
+ * HIP; Newton's own non-convergence is reported in st->converged, not as an error.
+ * The row-scaled copy D A lives in a second value array of P; the owned matrix of
+ * mgr_poro_matrix keeps the unscaled Jacobian of the last assembly. */
 mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
                            const fgmres_opts *fo, double *x, const double *x_old,
                            const mgr_newton_opts *no, mgr_newton_stats *st, void *stream);

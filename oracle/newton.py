@@ -12,7 +12,8 @@ this oracle takes (the same readings as the GPU driver):
     see assembly.normalised); the last trial is accepted either way;
   * converged when the largest momentum residual in state units is <= tol_mech and the
     largest mass residual in state units is <= tol_flow (tested before each solve).
-The linear solve is a callable (an exact sparse factorisation by default).
+The linear solve is a callable (an exact sparse factorisation by default); an iterative
+solver may row-scale the system first, which leaves the exact correction unchanged.
 """
 from __future__ import annotations
 

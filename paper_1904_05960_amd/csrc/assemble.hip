@@ -407,6 +407,25 @@ k_max_ds(const double *d, int64_t nu, int64_t ncell, double *partial) {
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Row scaling of the Newton system to state units (momentum rows / the largest Young's
+// modulus, mass rows of phase l * dt / (phi0 rho0_l)): sval = D val (a copy; the owned
+// Jacobian stays unscaled) and F = D F in place.  MGR is unchanged by it (each reduction
+// and smoother is invariant to row scaling); the FGMRES residual norm becomes one in which
+// displacement and mass residuals weigh alike.
+__global__ void k_scale_rows(const int64_t *rp, const double *val, double *sval, double *F,
+                             int64_t nu, int64_t n, double emax, double fw, double fo) {
+  const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (r >= n) return;
+  if (r < nu) {
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) sval[e] = val[e] / emax;
+    F[r] = F[r] / emax;
+  } else {
+    const double f = ((r - nu) & 1) ? fo : fw;
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) sval[e] = val[e] * f;
+    F[r] = F[r] * f;
+  }
+}
+
 // xt = x - lambda d   (d solves A d = F, so -d is the Newton correction)
 __global__ void k_step(const double *x, const double *d, double lambda, double *xt, int64_t n) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -467,7 +486,7 @@ struct mgr_poro {
   double emax = 0.0;
   bool has_wi = false, has_qw = false, has_qo = false;
   // Newton work
-  DArr<double> F, d, xt, partial;
+  DArr<double> F, d, xt, partial, sval;
   DArr<char> work;
   size_t work_bytes = 0;
 };
@@ -750,6 +769,8 @@ mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
     mgr_csr A;
     const int8_t *lab = nullptr;
     mgr_poro_matrix(P, &A, &lab);
+    if (!P->sval.p) P->sval.alloc(P->val.n, s);
+    A.val = P->sval.p;                       // the solves see the row-scaled Jacobian
     const size_t need = fgmres_workspace_bytes(k.n, fo->restart);
     if (P->work_bytes < need) {
       P->work.alloc(need, s);
@@ -759,9 +780,17 @@ mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
       ok = nr[1] <= no->tol_mech && std::max(nr[3], nr[5]) <= no->tol_flow;
       return std::sqrt(nr[0] + nr[2] + nr[4]);
     };
+    const double scale_w = k.dt / (k.phi0 * k.rho0[0]);
+    const double scale_nw = k.dt / (k.phi0 * k.rho0[1]);
+    auto scale_system = [&]() {
+      hipLaunchKernelGGL(k_scale_rows, dim3(grid_for(k.n, 256)), dim3(256), 0, s, P->rp.p,
+                         P->val.p, P->sval.p, P->F.p, k.nu, k.n, P->emax, scale_w, scale_nw);
+      KCHK();
+    };
     double nr[6];
     double t0 = now_ms();
     assemble(P, x, x_old, P->F.p, true, nr, s);
+    scale_system();
     st->assemble_ms += now_ms() - t0;
     bool ok = false;
     double m = merit_of(nr, ok);
@@ -818,8 +847,10 @@ mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
       m = mt;
       ok = okt;
       st->merit[it + 1] = m;
-      if (!ok && st->newton_iters < no->max_newton)
+      if (!ok && st->newton_iters < no->max_newton) {
         assemble(P, x, x_old, P->F.p, true, nullptr, s);   // Jacobian at the accepted point
+        scale_system();
+      }
       st->assemble_ms += now_ms() - t0;
     }
     HIPCHK(hipStreamSynchronize(s));

@@ -7,7 +7,8 @@
     displacement, on grids whose node and cell counts leave ragged last blocks;
   * the residual in state units (norms) against the oracle's;
   * a Newton time step: the same iteration count as the oracle's Newton with exact solves,
-    and the same converged state, at tight tolerances;
+    and the same converged state, at tight tolerances; the owned Jacobian unchanged by the
+    row scaling of the solves;
   * quadratic convergence and the smoother options on a channelised line drive;
   * argument errors."""
 import numpy as np
@@ -142,7 +143,17 @@ def test_newton_step_matches_oracle():
     opts = m.paper_plan("two", precision="fp64")
     st = M.newton(xg, xold, opts, rtol=1e-12, maxit=200,
                   nopts=poro.newton_opts(tol_flow=1e-10, tol_mech=1e-13))
+    # the solves use a row-scaled copy: the owned Jacobian (whose displacement block is
+    # written once, at creation) still equals the oracle's after a re-assembly
+    M.assemble(xg, xold)
+    rp, ci, val, _ = M.export()
     M.close()
+    xf = xg.cpu().numpy()
+    Jo = asm.jacobian(prm, props, xf).tocsr()
+    rows = np.repeat(np.arange(prm.n), np.diff(rp))
+    ref = np.asarray(Jo[rows, np.array(ci, dtype=np.int64)]).ravel()
+    rowmax = np.maximum.reduceat(np.abs(ref), rp[:-1])
+    assert np.all(np.abs(val - ref) <= 1e-13 * rowmax[rows])
     assert st["converged"]
     assert st["newton_iters"] == st_o.newton_iters
     assert np.allclose(st["lambdas"], st_o.lambdas, rtol=0, atol=0)
