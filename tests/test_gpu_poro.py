@@ -183,6 +183,22 @@ def test_line_drive_converges(kind):
     assert s.min() > 0.0 and s.max() < 1.0
 
 
+def test_time_step_control():
+    """With few Newton iterations allowed, a long step fails and is retried with dt halved;
+    the accepted steps still cover the whole interval and each converged."""
+    res = pm.channel_reservoir(16, 12, 4, seed=7)
+    res["dt"] = 20 * 86400.0
+    M = poro.model_from_reservoir(res)
+    x, rec = poro.simulate(M, res["x0"], 1, poro.smoother_options("ilu", "fp32"), rtol=1e-6,
+                           nopts=poro.newton_opts(max_newton=4))
+    dt_after = M.params.dt
+    M.close()
+    assert all(r["converged"] for r in rec)
+    assert sum(r["cuts"] for r in rec) >= 1
+    assert sum(r["dt"] for r in rec) == pytest.approx(20 * 86400.0, rel=1e-12)
+    assert dt_after == 20 * 86400.0
+
+
 def test_argument_errors():
     p = poro.default_params(0, 2, 2)
     z = np.zeros(4)
