@@ -2,8 +2,9 @@
 
 `Server` wraps mgr_server_* (include/mgr355.h): worker slots with their own HIP streams,
 HBM admission by footprint, a setup cache keyed by realization.  `run_stream` replays an
-ensemble of Jacobians (realizations of different mesh sizes, several Newton steps each with
-the same sparsity pattern) with Poisson arrivals and reports solves/s and p50/p99 latency.
+ensemble of Jacobians (realizations of different mesh sizes, several Newton steps each
+re-assembled on the device at a perturbed state, same sparsity pattern) with Poisson
+arrivals and reports solves/s and p50/p99 latency.
 
     python -m paper_1904_05960_amd.serve [--realizations 64] [--newton 8] [--nmin 16]
         [--nmax 80] [--rate 50] [--slots 4] [--budget-gb 200] [--precision fp32]
@@ -93,48 +94,87 @@ class Server:
 # ----------------------------------------------------------------------------------------
 # ensemble of requests
 class Realization:
-    """One permeability realization on the device, with its Newton-step variants."""
+    """One permeability realization on the device: the library's two-phase model of its
+    cells (mgr_poro_*), the state its base Jacobian is taken at, and its Newton steps."""
 
-    def __init__(self, idx: int, n: int, seed: int):
+    def __init__(self, idx: int, n: int, seed: int, perturbation: float = 0.1):
         import torch
         from workloads import poromech as pm
+        from . import poro
         w = pm.two_phase(n, n, n, seed)
         self.idx, self.n_cells, self.n = idx, n, w.n
-        self.A0 = m.Matrix.from_host(w.indptr, w.indices, w.data)
-        self.labels = torch.as_tensor(w.labels).cuda()
+        self.model = poro.Model(poro.default_params(n, n, n, nu=w.meta["nu"]), w.meta["perm"],
+                                w.meta["young"], w.fixed)
+        rp, ci, _, lab = self.model.export()
+        self.row_ptr = torch.as_tensor(rp).cuda()
+        self.col = torch.as_tensor(ci).cuda()
+        self.labels = torch.as_tensor(lab).cuda()
+        nu = self.model.nu
+        x0 = np.zeros(self.n)
+        x0[nu::2] = w.meta["state"]["S_w"]
+        x0[nu + 1::2] = w.meta["state"]["p"]
+        self.x0 = torch.as_tensor(x0).cuda()
+        self.nu = nu
+        self.perturbation = perturbation
+        self.free_u = torch.as_tensor(~w.fixed).cuda()
         self.x_true = torch.as_tensor(w.x_true).cuda()
-        self.row_len = torch.as_tensor(np.diff(w.indptr)).cuda()
-        self.flow_row = (self.labels != 0)
         self.nnz = int(w.nnz)
+        self._F = torch.empty(self.n, dtype=torch.float64, device="cuda")
 
     def input_bytes(self) -> int:
         """Device bytes of one materialized request (values, b, x)."""
         return 8 * self.nnz + 16 * self.n
 
-    def step(self, k: int, seed: int):
-        """Newton step k: the flow rows of the base Jacobian scaled by exp(0.1 z_i), z iid
-        N(0, 1) seeded by (realization, k) (k = 0: the base matrix); same pattern; b = A x_true."""
+    @property
+    def A0(self):
+        """The Jacobian at the base state (assembled once, on first use)."""
+        if getattr(self, "_A0", None) is None:
+            self._A0 = self.step(0, 0)[0]
+        return self._A0
+
+    def state(self, k: int, seed: int):
+        """The state of Newton step k: the base state (k = 0), or the base state perturbed
+        with iid normals seeded by (realization, k), scaled by `perturbation` times 1e4 Pa
+        for pressure, 0.01 for saturation (kept in [0.05, 0.95]) and 1e-5 m for the free
+        displacement dofs.  The default 0.1 keeps a cached setup of step 0 useful (at 24^3
+        cells: 36 FGMRES iterations against 32 with a fresh setup; with 1.0, 63 against 30,
+        and the gap widens with the mesh)."""
         import torch
         if k == 0:
-            val = self.A0.val
-        else:
-            g = torch.Generator(device="cuda")
-            g.manual_seed(seed)
-            z = torch.randn(self.n, generator=g, device="cuda", dtype=torch.float64)
-            scale = torch.where(self.flow_row, torch.exp(0.1 * z), torch.ones_like(z))
-            val = self.A0.val * torch.repeat_interleave(scale, self.row_len)
-        A = m.Matrix(self.A0.row_ptr, self.A0.col, val.contiguous())
+            return self.x0
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        z = torch.randn(self.n, generator=g, device="cuda", dtype=torch.float64)
+        x = self.x0.clone()
+        nu = self.nu
+        a = self.perturbation
+        x[:nu] += (a * 1e-5) * z[:nu] * self.free_u
+        x[nu::2] = (x[nu::2] + (a * 0.01) * z[nu::2]).clamp(0.05, 0.95)
+        x[nu + 1::2] += (a * 1e4) * z[nu + 1::2]
+        return x
+
+    def step(self, k: int, seed: int):
+        """Newton step k: the Jacobian re-assembled on the device at state(k, seed) (previous
+        time level: the base state), same pattern; b = A x_true."""
+        import torch
+        from . import mgr355 as mm
+        self.model.assemble(self.state(k, seed), self.x0, F=self._F)
+        val = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        mm._check(mm.lib().mgr_poro_export(self.model.h, None, None, mm._ptr(val), None,
+                                           mm._stream()))
+        A = m.Matrix(self.row_ptr, self.col, val)
         b = A.spmv(self.x_true)
         return A, b
 
 
-def build_ensemble(realizations: int, nmin: int, nmax: int, seed: int, log=print):
+def build_ensemble(realizations: int, nmin: int, nmax: int, seed: int, log=print,
+                   perturbation: float = 0.1):
     rng = np.random.default_rng(seed)
     sizes = rng.integers(nmin, nmax + 1, size=realizations)
     ens = []
     for i, n in enumerate(sizes):
         t = time.perf_counter()
-        ens.append(Realization(i, int(n), seed * 1000 + i))
+        ens.append(Realization(i, int(n), seed * 1000 + i, perturbation))
         log(f"[serve] realization {i}: {n}^3 cells, {ens[-1].n} unknowns "
             f"({time.perf_counter() - t:.1f}s)")
     return ens
@@ -183,6 +223,10 @@ def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
         res["latency_ms"] = res["t_end_ms"] - res["t_submit_ms"] + 1e3 * late[j]
         recs[j] = res
         held -= nb
+        done = sum(1 for r_ in recs if r_ is not None)
+        if done % 64 == 0 or done == len(order):
+            log(f"[serve] {done}/{len(order)} requests done, "
+                f"{time.perf_counter() - t0:.1f}s")
 
     # inputs are materialized on a stream of their own and only that stream is awaited: a
     # device-wide synchronisation is refused while a worker thread captures a V-cycle graph
@@ -275,12 +319,18 @@ def main(argv=None):
     ap.add_argument("--nmin", type=int, default=16)
     ap.add_argument("--nmax", type=int, default=80)
     ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--rates", default="",
+                    help="comma-separated arrival rates: replay the same ensemble at each "
+                         "(one JSON line per rate), e.g. to find where latency stops being "
+                         "queueing-dominated")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--refresh", action="store_true", help="recompute setups each step")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--perturbation", type=float, default=0.1,
+                    help="size of a Newton step's state change (1: 1e4 Pa, 0.01, 1e-5 m)")
     ap.add_argument("--compare-fp64-serial", action="store_true")
     ap.add_argument("--input-pool-gb", type=float, default=32.0)
     ap.add_argument("--batch-rows", type=int, default=0,
@@ -296,11 +346,25 @@ def main(argv=None):
     import torch
     torch.cuda.set_device(0)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
-    ens = build_ensemble(a.realizations, a.nmin, a.nmax, a.seed, log)
+    ens = build_ensemble(a.realizations, a.nmin, a.nmax, a.seed, log, a.perturbation)
     order = request_order(a.realizations, a.newton, a.seed)
+    pool = int(a.input_pool_gb * (1 << 30))
+    if a.rates:
+        for rate in [float(v) for v in a.rates.split(",")]:
+            srv = Server(m.paper_plan("two", precision=a.precision),
+                         int(a.budget_gb * (1 << 30)), a.slots, restart=a.restart,
+                         batch_rows=a.batch_rows, batch_max=a.batch_max)
+            recs, wall, _ = run_stream(srv, ens, order, rate, a.seed, a.newton, a.refresh,
+                                       log, pool, keep_x=False)
+            svc = np.array([r["t_end_ms"] - r["t_start_ms"] for r in recs])
+            print(json.dumps({"mode": "served", "rate_per_s": rate, "slots": a.slots,
+                              "precision": a.precision, **summarize(recs, wall),
+                              "service_p50_ms": float(np.percentile(svc, 50)),
+                              "service_p99_ms": float(np.percentile(svc, 99))}), flush=True)
+            srv.close()
+        return
     srv = Server(m.paper_plan("two", precision=a.precision), int(a.budget_gb * (1 << 30)),
                  a.slots, restart=a.restart, batch_rows=a.batch_rows, batch_max=a.batch_max)
-    pool = int(a.input_pool_gb * (1 << 30))
     recs, wall, _ = run_stream(srv, ens, order, a.rate, a.seed, a.newton, a.refresh, log,
                                pool, keep_x=False)
     out = {"metric": "served MGR-FGMRES solves (1e-6), p50/p99 latency", "mode": "served",
