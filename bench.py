@@ -136,6 +136,8 @@ def make_opts(m, a, model, precision):
     kw = dict(precision=precision)
     if a.plan == "paper":
         kw.update(global_smoother=a.global_smoother, global_sweeps=a.global_sweeps)
+        if a.sat_nmax is not None:
+            kw.update(sat_nmax=a.sat_nmax)
     opts = mk0(model, **kw)
     if a.drop_tol is not None:
         for L in opts.levels:
@@ -149,6 +151,14 @@ def make_opts(m, a, model, precision):
             L.ilu_level, L.ilu_sweeps = a.ilu_level, a.ilu_sweeps
             L.ilu_tri_sweeps = a.ilu_tri_sweeps
     return opts
+
+
+def dropping_text(a):
+    disp = ("N_max = 4" if a.drop_tol is None else f"tolerance {a.drop_tol}") + \
+        " on the displacement level"
+    sat = a.sat_nmax if a.sat_nmax is not None else (4 if a.workload == "three" else -1)
+    return disp + ("; Galerkin on the saturation levels" if sat < 0
+                   else f"; N_max = {sat} on the saturation levels")
 
 
 def to_bsr3(m, torch, A):
@@ -245,6 +255,9 @@ def main():
     ap.add_argument("--global-sweeps", type=int, default=3)
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
+    ap.add_argument("--sat-nmax", type=int, default=None,
+                    help="N_max on the saturation levels (-1: Galerkin; default: 4 for the "
+                         "three-phase model, Galerkin for two-phase)")
     ap.add_argument("--restart", type=int, default=64)
     ap.add_argument("--outer", default="bsr3", choices=["bsr3", "csr"],
                     help="outer FGMRES matrix of the three-phase workload: 3x3 blocks or CSR")
@@ -362,9 +375,7 @@ def main():
             "global_smoother": f"{a.global_smoother} x{a.global_sweeps}" + (
                 f" (ILU({a.ilu_level}), {a.ilu_sweeps} factor sweeps, {a.ilu_tri_sweeps} "
                 f"triangular sweeps)" if a.global_smoother == "ilu" else ""),
-            "dropping": ("N_max = 4 on the displacement and saturation levels"
-                         if a.workload == "three" else "N_max = 4 on the displacement level")
-            if a.drop_tol is None else f"tolerance {a.drop_tol} on the displacement level",
+            "dropping": dropping_text(a),
             "rtol": 1e-6, "parallelism": "single GPU",
         },
         "iterations": info["iters"],

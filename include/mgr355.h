@@ -459,6 +459,13 @@ mgr_status mgr_merge_drop(const mgr_csr *A, const mgr_csr *B, const double *w, i
  * the pattern longer than 256, or level > 1). */
 mgr_status mgr_ilu(const mgr_csr *A, int32_t level, int32_t sweeps, mgr_owned_csr **F,
                    int64_t sizes[3], void *stream);
+/* Inverse of the dense n x n row-major matrix D into Inv (n x n row-major; both device,
+ * not aliased): the coarsest-grid inverse of the setup, by Gauss-Jordan elimination with
+ * partial pivoting (first row of largest |a| in the column), FP64: the matrix in LDS for
+ * n <= 128, blocked in panels of 16 columns for n <= 512, streamed through global memory
+ * above.  Synchronises `stream`.  Errors: ARG (n outside [1, 4096]), ZERO_PIVOT (a column
+ * with no nonzero candidate: singular, or NaN). */
+mgr_status mgr_dense_inverse(const double *D, double *Inv, int32_t n, void *stream);
 /* Strength graph (bs = 1 scalar, 3 nodal), SplitMix64 priorities of AMG level `level`,
  * MIS(2) and aggregation; agg receives nrows/bs aggregate ids (-1 = none). */
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,

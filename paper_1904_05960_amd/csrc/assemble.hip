@@ -412,17 +412,22 @@ k_max_ds(const double *d, int64_t nu, int64_t ncell, double *partial) {
 // Jacobian stays unscaled) and F = D F in place.  MGR is unchanged by it (each reduction
 // and smoother is invariant to row scaling); the FGMRES residual norm becomes one in which
 // displacement and mass residuals weigh alike.
-__global__ void k_scale_rows(const int64_t *rp, const double *val, double *sval, double *F,
-                             int64_t nu, int64_t n, double emax, double fw, double fo) {
-  const int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+// One wavefront per row, its lanes striding the row's entries (coalesced).
+constexpr int kScaleThreads = 256;
+__global__ void __launch_bounds__(kScaleThreads)
+k_scale_rows(const int64_t *rp, const double *val, double *sval, double *F, int64_t nu,
+             int64_t n, double emax, double fw, double fo) {
+  const int64_t r = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) / 64;
+  const int l = threadIdx.x & 63;
   if (r >= n) return;
+  const int64_t e0 = rp[r], e1 = rp[r + 1];
   if (r < nu) {
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) sval[e] = val[e] / emax;
-    F[r] = F[r] / emax;
+    for (int64_t e = e0 + l; e < e1; e += 64) sval[e] = val[e] / emax;
+    if (l == 0) F[r] = F[r] / emax;
   } else {
     const double f = ((r - nu) & 1) ? fo : fw;
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) sval[e] = val[e] * f;
-    F[r] = F[r] * f;
+    for (int64_t e = e0 + l; e < e1; e += 64) sval[e] = val[e] * f;
+    if (l == 0) F[r] = F[r] * f;
   }
 }
 
@@ -783,7 +788,8 @@ mgr_status mgr_poro_newton(mgr_poro *P, mgr_handle **h, const mgr_opts *mo,
     const double scale_w = k.dt / (k.phi0 * k.rho0[0]);
     const double scale_nw = k.dt / (k.phi0 * k.rho0[1]);
     auto scale_system = [&]() {
-      hipLaunchKernelGGL(k_scale_rows, dim3(grid_for(k.n, 256)), dim3(256), 0, s, P->rp.p,
+      hipLaunchKernelGGL(k_scale_rows, dim3(grid_for(k.n * 64, kScaleThreads)),
+                         dim3(kScaleThreads), 0, s, P->rp.p,
                          P->val.p, P->sval.p, P->F.p, k.nu, k.n, P->emax, scale_w, scale_nw);
       KCHK();
     };

@@ -152,6 +152,21 @@ mgr_status mgr_ilu(const mgr_csr *A, int32_t level, int32_t sweeps, mgr_owned_cs
   return MGR_OK;
 }
 
+mgr_status mgr_dense_inverse(const double *D, double *Inv, int32_t n, void *stream) {
+  if (!D || !Inv) return MGR_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    require(n >= 1 && n <= 4096, MGR_ERR_ARG, "n must lie in [1, 4096]");
+    DArr<int> flag(1, s);
+    clear_flag(flag.p, s);
+    dense_inverse(const_cast<double *>(D), Inv, n, flag.p, s);
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const Error &e) {
+    return ufail(e);
+  }
+  return MGR_OK;
+}
+
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,
                          int32_t *agg, int64_t *nagg, void *stream) {
   if (!A || !agg || !nagg) return MGR_ERR_ARG;

@@ -179,6 +179,7 @@ def lib():
         "mgr_transpose": (st, [C.POINTER(mgr_csr), C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
                                 C.POINTER(vp), C.POINTER(C.c_int64), vp]),
+        "mgr_dense_inverse": (st, [vp, vp, C.c_int32, vp]),
         "mgr_ilu": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, C.POINTER(vp),
                          C.POINTER(C.c_int64), vp]),
         "mgr_aggregate": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_double, C.c_int32, vp,
@@ -610,6 +611,16 @@ def ilu(A: Matrix, level: int, sweeps: int, stream=None):
     _check(lib().mgr_ilu(C.byref(A.c), int(level), int(sweeps), C.byref(h), sizes,
                          _stream(stream)))
     return _owned_to_host(h, sizes, stream)
+
+
+def dense_inverse(D, stream=None):
+    """Inverse of a dense square FP64 device tensor by the setup's Gauss-Jordan kernels."""
+    import torch
+    n = int(D.shape[0])
+    D = D.contiguous()
+    Inv = torch.empty_like(D)
+    _check(lib().mgr_dense_inverse(_ptr(D), _ptr(Inv), n, _stream(stream)))
+    return Inv
 
 
 def aggregate(A: Matrix, bs: int, theta: float, level: int, stream=None):

@@ -10,7 +10,12 @@
     and the same converged state, at tight tolerances; the owned Jacobian unchanged by the
     row scaling of the solves;
   * quadratic convergence and the smoother options on a channelised line drive;
+  * at 64x64x16 cells, the Jacobian along a random direction against central differences
+    of the GPU residual (a property at any size);
+  * time-step cuts;
   * argument errors."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -181,6 +186,40 @@ def test_line_drive_converges(kind):
     assert rec[-1]["newton_iters"] >= 1 and last[-1] < 1e-2 * last[0]
     s = x.cpu().numpy()[nu::2]
     assert s.min() > 0.0 and s.max() < 1.0
+
+
+def test_jacobian_directional_derivative_at_size():
+    """At a size the oracle cannot assemble quickly (64x64x16 cells, 346,275 unknowns), a
+    property that holds at any size: the assembled Jacobian times a random direction equals
+    the central difference of the GPU residual along it, within the truncation and
+    rounding of the difference (momentum, wetting and non-wetting rows separately)."""
+    res = pm.channel_reservoir(64, 64, 16, seed=3)
+    M = poro.model_from_reservoir(res)
+    x = dev(res["x0"])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    nu = M.nu
+    x[:nu] = 1e-4 * torch.randn(nu, generator=g, device="cuda", dtype=torch.float64)
+    x[:nu] *= dev(~res["fixed"])
+    x[nu::2] = 0.15 + 0.7 * torch.rand(M.ncell, generator=g, device="cuda", dtype=torch.float64)
+    x[nu + 1::2] += 1e5 * torch.randn(M.ncell, generator=g, device="cuda", dtype=torch.float64)
+    x_old = x.clone()
+    x_old[nu + 1::2] += 1e4
+    M.assemble(x, x_old)
+    d = torch.randn(M.n, generator=g, device="cuda", dtype=torch.float64)
+    d[:nu] *= 1e-6 * dev(~res["fixed"])
+    d[nu::2] *= 1e-3
+    d[nu + 1::2] *= 1e2
+    Jd = torch.empty_like(d)
+    m._check(m.lib().mgr_spmv(C.byref(M.csr), m._ptr(d), m._ptr(Jd), m._stream()))
+    h = 1e-3
+    Fp = M.assemble(x + h * d, x_old, jacobian=False)
+    Fm = M.assemble(x - h * d, x_old, jacobian=False)
+    fd = (Fp - Fm) / (2 * h)
+    M.close()
+    for sl in (slice(0, nu), slice(nu, None, 2), slice(nu + 1, None, 2)):
+        a, b = Jd[sl], fd[sl]
+        assert float(torch.linalg.norm(a - b) / torch.linalg.norm(a)) < 1e-6
 
 
 def test_time_step_control():

@@ -289,3 +289,29 @@ def test_ilu_errors():
     with pytest.raises(m.MgrError) as e:
         m.ilu(dev(B), 2, 1)
     assert e.value.status == m.MGR_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n", [1, 60, 128, 129, 200, 245, 256, 257, 300, 512, 513, 700])
+def test_dense_inverse(n):
+    """The coarsest-grid inverse (LDS kernel up to 128, blocked panels up to 512, global
+    above) against LAPACK's: both are backward stable, so they agree to a few units of
+    kappa * u; and A X = I to that order.  Row-scaled random matrices, so that partial
+    pivoting has work to do."""
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) * np.exp(rng.uniform(-3, 3, size=(n, 1))) + 0.05 * np.eye(n)
+    X = m.dense_inverse(torch.as_tensor(A).cuda()).cpu().numpy()
+    ref = np.linalg.inv(A)
+    kappa = np.linalg.cond(A)
+    u = np.finfo(np.float64).eps / 2
+    assert np.abs(X - ref).max() <= 64 * n * kappa * u * np.abs(ref).max()
+    R = A @ X - np.eye(n)
+    assert np.abs(R).max() <= 64 * n * u * np.abs(A).max() * np.abs(X).max() * n
+
+
+@pytest.mark.parametrize("n", [100, 300])
+def test_dense_inverse_singular(n):
+    A = np.random.default_rng(1).standard_normal((n, n))
+    A[:, 7] = 0.0
+    with pytest.raises(m.MgrError) as e:
+        m.dense_inverse(torch.as_tensor(A).cuda())
+    assert e.value.status == m.MGR_ERR_ZERO_PIVOT
