@@ -386,7 +386,7 @@ def main():
         "compare_other_precision": compare,
         "two_phase_64": two,
         "roofline": {
-            "kernel": ("outer FP64 BSR3-stream SpMV (k_bsr_stream<3>, 227-block windows)"
+            "kernel": ("outer FP64 BSR3 SpMV (k_bsr3_lane, a lane per 3x3 block, 512-block windows)"
                        if c.outer_block == 3 else
                        "outer FP64 CSR-stream SpMV (k_spmv_stream, 2048-entry row blocks)"),
             "bound": "hbm",

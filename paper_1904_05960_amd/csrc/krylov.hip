@@ -157,20 +157,20 @@ __global__ void __launch_bounds__(SB) k_spmv_stream(const int *__restrict__ rb,
   }
 }
 
-// BSR variant (b x b row-major blocks, b = 2 or 3): block k owns the block rows whose
+// BSR variant (b x b row-major blocks; used for b = 2): block k owns the block rows whose
 // first block lies in the k-th window of SNNZ / b^2 blocks; the window's b^2 values per
 // block are read as one contiguous, coalesced stream, each multiplied by the x entry of
 // its block column and staged in LDS; then every scalar row (br, r) sums the b entries of
 // its row in each block from LDS with 8 lanes.  A window whose block rows hold more than
 // SCAP values (a block row longer than (SCAP - SNNZ) / b^2 + 1 blocks) sums each scalar row
 // directly.
-template <int B>
+template <int WB>
 __global__ void k_bsr_rowblocks(int64_t nbr, const int64_t *__restrict__ rp, int64_t K,
                                 int *__restrict__ rb) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k > K) return;
   if (k == K) { rb[k] = (int)nbr; return; }
-  const int64_t target = k * (SNNZ / (B * B));
+  const int64_t target = k * WB;
   int64_t lo = 0, hi = nbr;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -275,6 +275,127 @@ __global__ void __launch_bounds__(SB) k_bsr_stream(const int *__restrict__ rb,
       if (t == 0) {
         const double tot = (part[0] + part[1]) + (part[2] + part[3]);
         const int64_t row = (int64_t)br * B + r;
+        y[row] = b ? b[row] - tot : tot;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// 3x3 blocks, one lane per block: block k of the grid owns the block rows whose first block
+// lies in the k-th window of WB3 = 512 blocks.  Each lane takes two blocks of the window at
+// a time (its own nine values read as one 72-byte record, the block column, the three x
+// entries), issuing every load of both before using any, and forms each block's three row
+// partials (v_r0 x_0 + v_r1 x_1) + v_r2 x_2 into LDS; every scalar row then sums its blocks'
+// partials with 8 lanes.  One lane per block needs 13 memory instructions per wave and 64
+// blocks where a lane per value needs 27 (nine values, nine block columns, nine x
+// entries); its per-lane records are gathered through L1 at the full streaming rate.
+// Windows whose block rows hold more than PCAP3 blocks sum each scalar row directly.
+constexpr int WB3 = 2 * SB;
+constexpr int PCAP3 = 3 * SB;
+__global__ void __launch_bounds__(SB) k_bsr3_lane(const int *__restrict__ rb,
+                                                  const int64_t *__restrict__ rp,
+                                                  const int *__restrict__ ci,
+                                                  const double *__restrict__ v,
+                                                  const double *__restrict__ x,
+                                                  const double *__restrict__ b,
+                                                  double *__restrict__ y) {
+  __shared__ double part[PCAP3 * 3];
+  const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int64_t base = rp[r0];
+  const int nblk = (int)(rp[r1] - base);
+  const int t = threadIdx.x;
+  if (nblk <= PCAP3) {
+    constexpr int G = 8;
+    // the first scalar row of this thread's sum phase: block-row extent and b entry now
+    const int nsr = (r1 - r0) * 3;
+    const int psr = t / G;
+    int ps = 0, plen = 0;
+    double pb = 0.0;
+    if (psr < nsr) {
+      const int br = r0 + psr / 3;
+      ps = (int)(rp[br] - base);
+      plen = (int)(rp[br + 1] - rp[br]);
+      if (b) pb = b[(int64_t)br * 3 + psr % 3];
+    }
+    constexpr int BPL = 2;
+    for (int q0 = 0; q0 < nblk; q0 += BPL * SB) {
+      double a[BPL][9];
+      int cc[BPL];
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * SB + t;
+        cc[h] = 0;
+        if (e < nblk) {
+          const double *bv = v + (base + e) * 9;
+#pragma unroll
+          for (int u = 0; u < 9; ++u) a[h][u] = bv[u];
+          cc[h] = ci[base + e];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 9; ++u) a[h][u] = 0.0;
+        }
+      }
+      double xx[BPL][3];
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * SB + t;
+        xx[h][0] = xx[h][1] = xx[h][2] = 0.0;
+        if (e < nblk) {
+          const double *xc = x + (int64_t)cc[h] * 3;
+          xx[h][0] = xc[0];
+          xx[h][1] = xc[1];
+          xx[h][2] = xc[2];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * SB + t;
+        if (e < nblk) {
+          part[e * 3 + 0] = a[h][0] * xx[h][0] + a[h][1] * xx[h][1] + a[h][2] * xx[h][2];
+          part[e * 3 + 1] = a[h][3] * xx[h][0] + a[h][4] * xx[h][1] + a[h][5] * xx[h][2];
+          part[e * 3 + 2] = a[h][6] * xx[h][0] + a[h][7] * xx[h][1] + a[h][8] * xx[h][2];
+        }
+      }
+    }
+    __syncthreads();
+    const int l = t & (G - 1);
+    for (int sr = psr; sr < nsr; sr += SB / G) {
+      const int br = r0 + sr / 3, r = sr % 3;
+      int s0 = ps, len = plen;
+      double bvv = pb;
+      if (sr != psr) {
+        s0 = (int)(rp[br] - base);
+        len = (int)(rp[br + 1] - rp[br]);
+        bvv = b ? b[(int64_t)br * 3 + r] : 0.0;
+      }
+      double acc = 0.0;
+      for (int k = l; k < len; k += G) acc += part[(s0 + k) * 3 + r];
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+      if (l == 0) y[(int64_t)br * 3 + r] = b ? bvv - acc : acc;
+    }
+    return;
+  }
+  static_assert(SB == 256, "the fallback sums four wave partials");
+  __shared__ double fpart[SB / 64];
+  for (int br = r0; br < r1; ++br) {
+    const int64_t e0 = rp[br], len = (rp[br + 1] - e0) * 3;
+    for (int r = 0; r < 3; ++r) {
+      double acc = 0.0;
+      for (int64_t k = t; k < len; k += SB) {
+        const int64_t e = e0 + k / 3;
+        const int c = (int)(k % 3);
+        acc += v[e * 9 + r * 3 + c] * x[(int64_t)ci[e] * 3 + c];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if ((t & 63) == 0) fpart[t >> 6] = acc;
+      __syncthreads();
+      if (t == 0) {
+        const double tot = (fpart[0] + fpart[1]) + (fpart[2] + fpart[3]);
+        const int64_t row = (int64_t)br * 3 + r;
         y[row] = b ? b[row] - tot : tot;
       }
       __syncthreads();
@@ -609,16 +730,16 @@ void spmv64_stream(const mgr_csr &A, int64_t nnz, const int *rb, const double *x
 
 // BSR: windows of SNNZ / b^2 blocks (nnzb = number of blocks)
 int64_t bsr_stream_blocks(int64_t nnzb, int bs) {
-  const int64_t wb = SNNZ / (bs * bs);
+  const int64_t wb = bs == 3 ? WB3 : SNNZ / (bs * bs);
   return (nnzb + wb - 1) / wb;
 }
 
 void bsr_rowblocks64(const mgr_csr &A, int64_t nnzb, int *rb, hipStream_t s) {
   const int64_t K = bsr_stream_blocks(nnzb, A.block);
   if (A.block == 2)
-    k_bsr_rowblocks<2><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
+    k_bsr_rowblocks<SNNZ / 4><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
   else
-    k_bsr_rowblocks<3><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
+    k_bsr_rowblocks<WB3><<<grid_for(K + 1, 256), 256, 0, s>>>(A.nrows, A.row_ptr, K, rb);
   KCHK();
 }
 
@@ -635,7 +756,7 @@ void bsr_spmv64_stream(const mgr_csr &A, int64_t nnzb, const int *rb, const doub
   if (A.block == 2)
     k_bsr_stream<2><<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
   else
-    k_bsr_stream<3><<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
+    k_bsr3_lane<<<(unsigned)K, SB, 0, s>>>(rb, A.row_ptr, A.col, A.val, x, b, y);
   KCHK();
 }
 

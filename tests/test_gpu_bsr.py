@@ -1,6 +1,6 @@
 """Block (BSR) input at the C ABI: mgr_csr with block = 2 or 3.
   * the FP64 BSR SpMV against SciPy, entrywise within 1e-13 (|A| |x|)_i, on ragged block
-    rows (empty ones, rows longer than a streamed window);
+    rows (empty ones, rows longer than a streamed window, which take the direct path);
   * mgr_setup on a BSR3 matrix builds the same hierarchy, bit for bit, as on its scalar
     expansion (the CSR with every entry of every block, zeros included);
   * FGMRES with the BSR3 outer matrix converges like the CSR one (iterations within one,
@@ -56,7 +56,9 @@ def test_bsr_spmv_matches_scipy(b):
     nbr = 900
     lens = rng.integers(0, 30, size=nbr)
     lens[[3, 4]] = 0
-    lens[[100, 500]] = [300, 450]          # beyond one streamed window (2304 values)
+    # block rows longer than a window: 2x2 windows stage 576 blocks, the 3x3 kernel's 768
+    lens[[100, 500]] = [300, 450]
+    lens[[600, 700]] = [800, 890]
     lens[[200, 201]] = [26, 27]
     indptr, cols, blocks = random_bsr(rng, nbr, b, lens)
     A = m.Matrix.bsr_from_host(indptr, cols, blocks)
