@@ -458,6 +458,140 @@ __global__ void k_block_jacobi(int64_t nblk, int nb, const T *__restrict__ inv,
     z[r0 + r] = acc ? z[r0 + r] + omega * s : s;
   }
 }
+// One block-Jacobi sweep of a cell-blocked level (b x b row-major blocks, b = 2 or 3):
+// zout = zin + omega D_B^{-1} (rhs - A zin).  Block k of the grid owns the block rows (cells)
+// whose first block lies in the k-th window of 512 blocks.  One lane per block, two blocks
+// per lane at a time (each block's values read as one record, its block column and zin
+// entries, all loads before any use), each block's b row partials into LDS; then BG lanes
+// per cell sum its rows, form the cell's residual and apply the cell's block inverse, so the
+// residual never goes to memory.  Windows holding more than PCAPB blocks (a cell with
+// hundreds of neighbours) sum each cell directly with the whole workgroup.
+constexpr int PCAPB = 768;
+template <class T, int B, int BG>
+__global__ void __launch_bounds__(256) k_bsr_gs(const int *__restrict__ rb,
+                                                const int *__restrict__ rp,
+                                                const int *__restrict__ ci,
+                                                const T *__restrict__ v,
+                                                const T *__restrict__ zin,
+                                                const T *__restrict__ rhs,
+                                                const T *__restrict__ inv, T omega,
+                                                T *__restrict__ zout) {
+  constexpr int BB = B * B;
+  __shared__ T part[PCAPB * B];
+  const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  const int base = rp[r0];
+  const int nblk = rp[r1] - base;
+  const int t = threadIdx.x;
+  if (nblk <= PCAPB) {
+    constexpr int BPL = 2;
+    for (int q0 = 0; q0 < nblk; q0 += BPL * 256) {
+      T a[BPL][BB], xx[BPL][B];
+      int cc[BPL];
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * 256 + t;
+        cc[h] = 0;
+        if (e < nblk) {
+          const T *bv = v + (int64_t)(base + e) * BB;
+#pragma unroll
+          for (int u = 0; u < BB; ++u) a[h][u] = bv[u];
+          cc[h] = ci[base + e];
+        } else {
+#pragma unroll
+          for (int u = 0; u < BB; ++u) a[h][u] = 0;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * 256 + t;
+#pragma unroll
+        for (int c = 0; c < B; ++c) xx[h][c] = (e < nblk) ? zin[(int64_t)cc[h] * B + c] : (T)0;
+      }
+#pragma unroll
+      for (int h = 0; h < BPL; ++h) {
+        const int e = q0 + h * 256 + t;
+        if (e < nblk) {
+#pragma unroll
+          for (int r = 0; r < B; ++r) {
+            T pr = a[h][r * B] * xx[h][0];
+#pragma unroll
+            for (int c = 1; c < B; ++c) pr += a[h][r * B + c] * xx[h][c];
+            part[e * B + r] = pr;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int l = t & (BG - 1);
+    for (int I = r0 + t / BG; I < r1; I += 256 / BG) {
+      const int s0 = rp[I] - base, len = rp[I + 1] - rp[I];
+      T acc[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) acc[r] = 0;
+      for (int k = l; k < len; k += BG)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[r] += part[(s0 + k) * B + r];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int o = BG / 2; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, BG);
+      if (l == 0) {
+        const int64_t row = (int64_t)I * B;
+        T res[B];
+#pragma unroll
+        for (int r = 0; r < B; ++r) res[r] = rhs[row + r] - acc[r];
+        const T *Bi = inv + (int64_t)I * BB;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          T sr = 0;
+#pragma unroll
+          for (int c = 0; c < B; ++c) sr += Bi[r * B + c] * res[c];
+          zout[row + r] = zin[row + r] + omega * sr;
+        }
+      }
+    }
+    return;
+  }
+  __shared__ T fpart[4][B];
+  for (int I = r0; I < r1; ++I) {
+    const int e0 = rp[I], len = rp[I + 1] - e0;
+    T acc[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) acc[r] = 0;
+    for (int k = t; k < len; k += 256) {
+      const T *bv = v + (int64_t)(e0 + k) * BB;
+      const int64_t c0 = (int64_t)ci[e0 + k] * B;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc[r] += bv[r * B + c] * zin[c0 + c];
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      acc[r] = group_sum<T, 64>(acc[r]);
+      if ((t & 63) == 0) fpart[t >> 6][r] = acc[r];
+    }
+    __syncthreads();
+    if (t == 0) {
+      const int64_t row = (int64_t)I * B;
+      T res[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        res[r] = rhs[row + r] - ((fpart[0][r] + fpart[1][r]) + (fpart[2][r] + fpart[3][r]));
+      const T *Bi = inv + (int64_t)I * BB;
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        T sr = 0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) sr += Bi[r * B + c] * res[c];
+        zout[row + r] = zin[row + r] + omega * sr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <class T>
 __global__ void k_fillv(T *p, T val, int64_t n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -629,6 +763,28 @@ void VecOps<T>::block_jacobi(int64_t nblk, int nb, const T *inv, const T *v, T o
   if (nblk <= 0) return;
   k_block_jacobi<T><<<grid_for(nblk, 256), 256, 0, s>>>(nblk, nb, inv, v, omega, z,
                                                         accumulate ? 1 : 0);
+  KCHK();
+}
+
+template <class T>
+void VecOps<T>::bsr_gs_sweep(const BsrBV<T> &A, const T *zin, const T *b, const T *inv, T omega,
+                             T *zout, hipStream_t s) {
+  if (A.nbr <= 0) return;
+  if (A.nwin <= 0) {   // no blocks at all: zout = zin + omega D_B^{-1} b
+    HIPCHK(hipMemcpyAsync(zout, zin, A.nbr * A.b * sizeof(T), hipMemcpyDeviceToDevice, s));
+    block_jacobi(A.nbr, A.b, inv, b, omega, zout, true, s);
+    return;
+  }
+  const double avg = (double)A.nblk / (double)A.nbr;
+  const unsigned g = (unsigned)A.nwin;
+#define GSL(BSZ, GG) \
+  k_bsr_gs<T, BSZ, GG><<<g, 256, 0, s>>>(A.rb, A.rp, A.ci, A.v, zin, b, inv, omega, zout)
+  if (A.b == 2) {
+    if (avg < 12) GSL(2, 4); else GSL(2, 8);
+  } else {
+    if (avg < 12) GSL(3, 4); else GSL(3, 8);
+  }
+#undef GSL
   KCHK();
 }
 template <class T>

@@ -117,6 +117,24 @@ struct Bsr3V {
   const T *v = nullptr;
 };
 
+// b x b block CSR of a level whose rows are interleaved cell by cell (b = 2 or 3): block
+// row I = rows bI..bI+b-1, a block for every block column any of them touches, values
+// row-major per block (zeros stored), and the stream windows of its apply kernel.
+struct BsrB {
+  int64_t nbr = 0, nblk = 0, nwin = 0;
+  int b = 0;
+  DArr<int> rp, ci, rb;
+  DArr<double> v;
+  size_t bytes() const { return rp.bytes() + ci.bytes() + rb.bytes() + v.bytes(); }
+};
+template <class T>
+struct BsrBV {
+  int64_t nbr = 0, nblk = 0, nwin = 0;
+  int b = 0;
+  const int *rp = nullptr, *ci = nullptr, *rb = nullptr;
+  const T *v = nullptr;
+};
+
 // ------------------------------------------------------------------------------------
 // launch geometry
 inline unsigned grid_for(int64_t work, int block) {
@@ -250,6 +268,7 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
 void make_rowblocks(Csr &M, hipStream_t s);
 // rows `rows` (ascending, nr of them) of A as a CSR matrix of its own (columns unchanged)
 void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_t s);
+void csr_to_bsr_fill(const Csr &A, int b, BsrB &B, hipStream_t s);   // with its windows
 void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what);
 void bsr3_to_csr(const Bsr3 &B, Csr &C, hipStream_t s);
 // R = P^T (block pattern transposed, each block transposed)
@@ -326,6 +345,9 @@ struct VecOps {
                            T *z, hipStream_t s);
   static void block_jacobi(int64_t nblk, int nb, const T *inv, const T *v, T omega, T *z,
                            bool accumulate, hipStream_t s);
+  // one block-Jacobi sweep on a cell-blocked level: zout = zin + omega D_B^{-1} (b - A zin)
+  static void bsr_gs_sweep(const BsrBV<T> &A, const T *zin, const T *b, const T *inv, T omega,
+                           T *zout, hipStream_t s);
   static void fill(T *p, T val, int64_t n, hipStream_t s);
   // out = dinv .* (b - A x)
   static void resid_scale(const CsrV<T> &A, const T *dinv, const T *x, const T *b, T *out,

@@ -199,6 +199,8 @@ struct MgrLevel {
   Csr AF, AC;                // rows F and rows C of A_l (residuals of uncompacted levels)
   int nb_gs = 0;             // global smoother block size
   DArr<double> binv64;
+  BsrB gsb;                  // A_l as cell blocks for the block-Jacobi sweeps (FP64 values)
+  DArr<char> tgsb;           // their values in the apply precision
   std::vector<int> gs_ptr;   // block Gauss-Seidel: cells of colour c are gs_cells[ptr[c]..)
   DArr<int> gs_cells, gs_color;
   Amg amg;                   // F-relaxation AMG
@@ -559,12 +561,28 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
   bool zero_z = true;
   // global relaxation (block Jacobi over same-cell blocks)
   if (o.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI) {
+    // z = D_B^{-1} v, then z <- z + omega D_B^{-1} (v - A z) on the cell blocks of A_l, one
+    // kernel per sweep, alternating between z and a work vector so that the last lands in z
     const T *binv = Ptr<T>::of(L.tbinv);
-    V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, v, (T)1, z, false, s);
-    for (int sw = 1; sw < o.global_sweeps; ++sw) {
-      T *r = Ptr<T>::of(L.rfull) + 2 * nC;
-      V::resid(A, n, nullptr, nullptr, z, v, r, s);
-      V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, r, (T)o.global_omega, z, true, s);
+    const int extra = o.global_sweeps - 1;
+    T *tmp = Ptr<T>::of(L.rfull) + 2 * nC;
+    T *cur = (extra % 2 == 0) ? z : tmp;
+    V::block_jacobi(n / L.nb_gs, L.nb_gs, binv, v, (T)1, cur, false, s);
+    if (extra > 0) {
+      BsrBV<T> G;
+      G.nbr = L.gsb.nbr;
+      G.nblk = L.gsb.nblk;
+      G.nwin = L.gsb.nwin;
+      G.b = L.gsb.b;
+      G.rp = L.gsb.rp.p;
+      G.ci = L.gsb.ci.p;
+      G.rb = L.gsb.rb.p;
+      G.v = fp64 ? reinterpret_cast<const T *>(L.gsb.v.p) : Ptr<T>::of(L.tgsb);
+      for (int sw = 0; sw < extra; ++sw) {
+        T *nxt = (cur == z) ? tmp : z;
+        V::bsr_gs_sweep(G, cur, v, binv, (T)o.global_omega, nxt, s);
+        cur = nxt;
+      }
     }
     zero_z = false;
   } else if (o.global_smoother == MGR_GSMOOTH_ILU) {
@@ -963,6 +981,10 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       L->binv64.alloc(n * nb, s);
       block_diag_inverse(L->A, nb, L->binv64.p, s, flag);
       cast_values(L->binv64.p, L->tbinv, n * nb, sz, s);
+      if (lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI && lo.global_sweeps > 1) {
+        csr_to_bsr_fill(L->A, nb, L->gsb, s);
+        if (sz == 4) cast_values(L->gsb.v.p, L->tgsb, L->gsb.nblk * nb * nb, sz, s);
+      }
       if (lo.global_smoother == MGR_GSMOOTH_BLOCK_GS)
         bgs_setup(L->A, nb, L->gs_ptr, L->gs_cells, L->gs_color, s, flag);
       if (lo.global_smoother == MGR_GSMOOTH_ILU) {
@@ -1067,6 +1089,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->AF.v.reset();
         L->AC.v.reset();
         L->binv64.reset();
+        L->gsb.v.reset();
         L->ffinv64.reset();
         L->iluL.v.reset();
         L->iluU.v.reset();
@@ -1140,6 +1163,7 @@ size_t handle_bytes(const mgr_handle *h) {
     csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G); csr(L->AF); csr(L->AC);
     b += L->labels.bytes() + L->cf.F.bytes() + L->cf.C.bytes() + L->cf.map.bytes() +
          L->dFF.bytes() + L->binv64.bytes() + L->gs_cells.bytes() + L->gs_color.bytes() +
+         L->gsb.bytes() + L->tgsb.bytes() +
          L->ffinv64.bytes() + L->tA.bytes() +
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
          L->tAF.bytes() + L->tAC.bytes() +

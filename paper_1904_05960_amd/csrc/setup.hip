@@ -1359,6 +1359,184 @@ void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_
   }
 }
 
+// ---------------------------------------------------------------------------------
+// CSR -> b x b block CSR of a cell-interleaved level (every touched block stored whole)
+namespace {
+constexpr int kBsrWin = 512;   // blocks per stream window of the block sweep kernel
+
+// The block columns of block row I (a cell) are the distinct c / B of its B rows.  G lanes
+// per cell stage the cell's column indices (one contiguous range of the CSR arrays) in LDS.
+// An entry represents its block column when it is the first entry of that block column in
+// its row and no earlier row of the cell holds the block column (binary searches in the
+// sorted rows); representatives are marked in a bit mask.  Every block column has exactly
+// one representative, so the position of block column bc among the cell's blocks is the
+// number of representatives left of bc's lower bound in each row: popcounts of the mask.
+// The count pass writes the number of representatives; the fill pass scatters every value
+// into its block (the blocks are zeroed beforehand) and the representatives write the
+// block columns.  No lane works serially over a cell.  Cells beyond BCAP entries are
+// merged from global memory by one lane.
+constexpr int BG_LANES = 16;
+constexpr int BCAP = 512;
+
+// first position in s[lo, hi) whose value is >= key
+__device__ inline int lds_lower_bound(const int *s, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// number of set bits of mask in positions [a, b)
+__device__ inline int popc_range(const unsigned *mask, int a, int b) {
+  int n = 0;
+  for (int w = a >> 5; a < b && w <= (b - 1) >> 5; ++w) {
+    const int lo = max(a - w * 32, 0), hi = min(b - w * 32, 32);
+    const unsigned m = (hi == 32 ? 0xffffffffu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+    n += __popc(mask[w] & m);
+  }
+  return n;
+}
+
+template <int B, bool FILL>
+__global__ void __launch_bounds__(256) k_bsrb_rows(int64_t nbr, const int *__restrict__ rp,
+                                                   const int *__restrict__ ci,
+                                                   const double *__restrict__ v,
+                                                   int *__restrict__ cnt,
+                                                   const int *__restrict__ brp,
+                                                   int *__restrict__ bci,
+                                                   double *__restrict__ bv) {
+  constexpr int NGR = 256 / BG_LANES;
+  constexpr int NW = BCAP / 32;
+  __shared__ int s_c[NGR][BCAP];
+  __shared__ unsigned s_f[NGR][NW];
+  const int g = threadIdx.x / BG_LANES, l = threadIdx.x & (BG_LANES - 1);
+  const int64_t I = blockIdx.x * (int64_t)NGR + g;
+  if (I >= nbr) return;   // whole groups leave together
+  int rs[B + 1];
+  const int e0 = rp[I * B];
+#pragma unroll
+  for (int r = 0; r <= B; ++r) rs[r] = rp[I * B + r] - e0;
+  const int ne = rs[B];
+  const int o = FILL ? brp[I] : 0;
+  if (ne > BCAP) {   // long cell: merge from global memory by one lane
+    if (l == 0) {
+      int grs[B + 1];
+#pragma unroll
+      for (int r = 0; r <= B; ++r) grs[r] = rs[r] + e0;
+      int p[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) p[r] = grs[r];
+      int nb = 0;
+      for (;;) {
+        int mc = 0x7fffffff;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+          if (p[r] < grs[r + 1]) mc = min(mc, ci[p[r]] / B);
+        if (mc == 0x7fffffff) break;
+        if (FILL) bci[o + nb] = mc;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+          while (p[r] < grs[r + 1] && ci[p[r]] / B == mc) {
+            if (FILL) bv[(int64_t)(o + nb) * B * B + r * B + ci[p[r]] % B] = v[p[r]];
+            ++p[r];
+          }
+        ++nb;
+      }
+      if (!FILL) cnt[I] = nb;
+    }
+    return;
+  }
+  for (int k = l; k < ne; k += BG_LANES) s_c[g][k] = ci[e0 + k];
+  for (int w = l; w < NW; w += BG_LANES) s_f[g][w] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int k = l; k < ne; k += BG_LANES) {
+    int r = 0;
+#pragma unroll
+    for (int q = 1; q < B; ++q) r += (k >= rs[q]);
+    const int bc = s_c[g][k] / B;
+    bool rep = (k == rs[r]) || (s_c[g][k - 1] / B != bc);
+#pragma unroll
+    for (int q = 0; q < B - 1; ++q)
+      if (rep && q < r) {
+        const int lb = lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * B);
+        if (lb < rs[q + 1] && s_c[g][lb] < (bc + 1) * B) rep = false;
+      }
+    if (rep) atomicOr(&s_f[g][k >> 5], 1u << (k & 31));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (!FILL) {
+    if (l == 0) cnt[I] = popc_range(s_f[g], 0, ne);
+    return;
+  }
+  for (int k = l; k < ne; k += BG_LANES) {
+    int r = 0;
+#pragma unroll
+    for (int q = 1; q < B; ++q) r += (k >= rs[q]);
+    const int c = s_c[g][k], bc = c / B;
+    int pos = 0;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      pos += popc_range(s_f[g], rs[q], lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * B));
+    bv[(int64_t)(o + pos) * B * B + r * B + (c - bc * B)] = v[e0 + k];
+    if (s_f[g][k >> 5] & (1u << (k & 31))) bci[o + pos] = bc;
+  }
+}
+
+__global__ void k_bsrb_windows(int64_t nbr, const int *__restrict__ brp, int64_t K,
+                               int *__restrict__ rb) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k > K) return;
+  if (k == K) { rb[k] = (int)nbr; return; }
+  const int64_t target = k * (int64_t)kBsrWin;
+  int64_t lo = 0, hi = nbr;          // first block row whose first block is >= target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (brp[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  rb[k] = (int)lo;
+}
+}  // namespace
+
+void csr_to_bsr_fill(const Csr &A, int b, BsrB &B, hipStream_t s) {
+  require(b == 2 || b == 3, MGR_ERR_ARG, "block size must be 2 or 3");
+  require(A.n == A.m && A.n % b == 0, MGR_ERR_ARG, "block matrix: size not divisible by block");
+  B.b = b;
+  B.nbr = A.n / b;
+  B.rp.alloc(B.nbr + 1, s);
+  DArr<int> cnt(std::max<int64_t>(B.nbr, 1), s);
+  if (B.nbr > 0) {
+    const unsigned gr = grid_for(B.nbr * BG_LANES, 256);
+    if (b == 2)
+      k_bsrb_rows<2, false><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, nullptr, cnt.p, nullptr,
+                                               nullptr, nullptr);
+    else
+      k_bsrb_rows<3, false><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, nullptr, cnt.p, nullptr,
+                                               nullptr, nullptr);
+    KCHK();
+  }
+  B.nblk = exclusive_scan_i32(cnt.p, B.rp.p, B.nbr, s);
+  B.ci.alloc(std::max<int64_t>(B.nblk, 1), s);
+  B.v.alloc(std::max<int64_t>(B.nblk * b * b, 1), s);
+  fill<double>(B.v.p, 0.0, B.nblk * b * b, s);   // entries absent from A stay zero
+  if (B.nbr > 0) {
+    const unsigned gr = grid_for(B.nbr * BG_LANES, 256);
+    if (b == 2)
+      k_bsrb_rows<2, true><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, A.v.p, nullptr, B.rp.p,
+                                              B.ci.p, B.v.p);
+    else
+      k_bsrb_rows<3, true><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, A.v.p, nullptr, B.rp.p,
+                                              B.ci.p, B.v.p);
+    KCHK();
+  }
+  B.nwin = B.nblk > 0 ? (B.nblk + kBsrWin - 1) / kBsrWin : 0;
+  B.rb.alloc(B.nwin + 1, s);
+  k_bsrb_windows<<<grid_for(B.nwin + 1, 256), 256, 0, s>>>(B.nbr, B.rp.p, B.nwin, B.rb.p);
+  KCHK();
+}
+
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag) {
   require(A.n % nb == 0, MGR_ERR_UNSUPPORTED, "block smoother: size not divisible by block");
   const int64_t nblk = A.n / nb;

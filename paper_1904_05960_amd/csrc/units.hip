@@ -167,6 +167,40 @@ mgr_status mgr_dense_inverse(const double *D, double *Inv, int32_t n, void *stre
   return MGR_OK;
 }
 
+mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t b, int32_t *brow_ptr, int32_t *bcol,
+                          double *bval, int64_t capacity, int64_t *nblk, void *stream) {
+  if (!A || !nblk) return MGR_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    require(b == 2 || b == 3, MGR_ERR_ARG, "block size must be 2 or 3");
+    require(A->nrows == A->ncols && A->nrows % b == 0, MGR_ERR_ARG,
+            "A must be square with a multiple of b rows");
+    DArr<int> flag(1, s);
+    clear_flag(flag.p, s);
+    Csr a;
+    import_csr(A, a, s, flag.p);
+    check_flags(flag.p, s, "bsr import");
+    BsrB B;
+    csr_to_bsr_fill(a, b, B, s);
+    HIPCHK(hipStreamSynchronize(s));
+    *nblk = B.nblk;
+    if (bcol) {
+      require(brow_ptr && bval, MGR_ERR_ARG, "brow_ptr and bval needed with bcol");
+      require(capacity >= B.nblk, MGR_ERR_ARG, "capacity below the block count");
+      HIPCHK(hipMemcpyAsync(brow_ptr, B.rp.p, (B.nbr + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+      if (B.nblk) {
+        HIPCHK(hipMemcpyAsync(bcol, B.ci.p, B.nblk * sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(bval, B.v.p, B.nblk * b * b * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  } catch (const Error &e) {
+    return ufail(e);
+  }
+  return MGR_OK;
+}
+
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,
                          int32_t *agg, int64_t *nagg, void *stream) {
   if (!A || !agg || !nagg) return MGR_ERR_ARG;
