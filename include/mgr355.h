@@ -466,17 +466,20 @@ mgr_status mgr_ilu(const mgr_csr *A, int32_t level, int32_t sweeps, mgr_owned_cs
  * above.  Synchronises `stream`.  Errors: ARG (n outside [1, 4096]), ZERO_PIVOT (a column
  * with no nonzero candidate: singular, or NaN). */
 mgr_status mgr_dense_inverse(const double *D, double *Inv, int32_t n, void *stream);
-/* The b x b block CSR (b = 2 or 3) of a square CSR matrix whose unknowns are interleaved
- * cell by cell: the storage the block-Jacobi global smoother (Sec. 5.3 remarks) sweeps for
- * more than one sweep.  Block row I holds the distinct column blocks c / b of scalar rows
- * bI .. bI+b-1 in ascending order, each stored whole (row-major b x b values, entries absent
- * from A zero; an explicit zero of A keeps its block).  Called twice: with bcol == NULL
- * only *nblk is set; then brow_ptr (nrows/b + 1 int32), bcol (capacity int32) and bval
- * (capacity b b doubles), all device, receive the matrix when capacity >= *nblk.  Columns
- * of every row must ascend without repeats.  Synchronises `stream`.  Errors: ARG (b not 2
- * or 3, A not square, nrows not a multiple of b, capacity below the block count). */
-mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t b, int32_t *brow_ptr, int32_t *bcol,
-                          double *bval, int64_t capacity, int64_t *nblk, void *stream);
+/* The br x bc block CSR ((br, bc) = (2, 2), (3, 3) or (2, 3)) of a CSR matrix whose rows
+ * come in groups of br (the unknowns of a cell) and whose columns come in groups of bc: the
+ * storage of the level matrices for the block-Jacobi sweeps (Sec. 5.3 remarks on the
+ * global smoother) and of A_CF for the restriction of the residual (eq. MGR-pre).  Block
+ * row I holds the distinct column groups c / bc of scalar rows br I .. br I + br - 1 in
+ * ascending order, each stored whole (row-major br x bc values, entries absent from A zero;
+ * an explicit zero of A keeps its block).  Called twice: with bcol == NULL only *nblk is
+ * set; then brow_ptr (nrows/br + 1 int32), bcol (capacity int32) and bval (capacity br bc
+ * doubles), all device, receive the matrix when capacity >= *nblk.  Columns of every row
+ * must ascend without repeats.  Synchronises `stream`.  Errors: ARG (another shape, nrows
+ * not a multiple of br or ncols of bc, capacity below the block count). */
+mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t br, int32_t bc, int32_t *brow_ptr,
+                          int32_t *bcol, double *bval, int64_t capacity, int64_t *nblk,
+                          void *stream);
 /* Strength graph (bs = 1 scalar, 3 nodal), SplitMix64 priorities of AMG level `level`,
  * MIS(2) and aggregation; agg receives nrows/bs aggregate ids (-1 = none). */
 mgr_status mgr_aggregate(const mgr_csr *A, int32_t bs, double theta, int32_t level,

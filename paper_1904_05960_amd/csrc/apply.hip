@@ -458,26 +458,54 @@ __global__ void k_block_jacobi(int64_t nblk, int nb, const T *__restrict__ inv,
     z[r0 + r] = acc ? z[r0 + r] + omega * s : s;
   }
 }
-// One block-Jacobi sweep of a cell-blocked level (b x b row-major blocks, b = 2 or 3):
-// zout = zin + omega D_B^{-1} (rhs - A zin).  Block k of the grid owns the block rows (cells)
-// whose first block lies in the k-th window of 512 blocks.  One lane per block, two blocks
-// per lane at a time (each block's values read as one record, its block column and zin
-// entries, all loads before any use), each block's b row partials into LDS; then BG lanes
-// per cell sum its rows, form the cell's residual and apply the cell's block inverse, so the
-// residual never goes to memory.  Windows holding more than PCAPB blocks (a cell with
-// hundreds of neighbours) sum each cell directly with the whole workgroup.
+// Products of a cell-blocked matrix (BR x BC row-major blocks over cells of BR rows) with
+// one of two epilogues per cell:
+//   CB_SWEEP (BR = BC): one block-Jacobi sweep zout = zin + omega D_B^{-1} (rhs - A zin);
+//   CB_RESID: out = rhs[bidx] - A x (rhs gathered through bidx when given).
+// Block k of the grid owns the block rows (cells) whose first block lies in the k-th window
+// of 512 blocks.  One lane per block, two blocks per lane at a time (each block's values
+// read as one record, its block column and x entries, all loads before any use), each
+// block's BR row partials into LDS; then BG lanes per cell sum its rows and apply the
+// epilogue, so a sweep's residual never goes to memory.  Windows holding more than PCAPB
+// blocks (a cell with hundreds of neighbours) sum each cell directly with the whole
+// workgroup.
 constexpr int PCAPB = 768;
-template <class T, int B, int BG>
-__global__ void __launch_bounds__(256) k_bsr_gs(const int *__restrict__ rb,
-                                                const int *__restrict__ rp,
-                                                const int *__restrict__ ci,
-                                                const T *__restrict__ v,
-                                                const T *__restrict__ zin,
-                                                const T *__restrict__ rhs,
-                                                const T *__restrict__ inv, T omega,
-                                                T *__restrict__ zout) {
-  constexpr int BB = B * B;
-  __shared__ T part[PCAPB * B];
+enum { CB_SWEEP = 0, CB_RESID = 1 };
+template <class T, int BR, int BC, int MODE>
+__device__ inline void cell_epilogue(int64_t I, const T (&acc)[BR], const T *__restrict__ zin,
+                                     const T *__restrict__ rhs, const int *__restrict__ bidx,
+                                     const T *__restrict__ inv, T omega, T *__restrict__ zout) {
+  const int64_t row = I * BR;
+  T res[BR];
+#pragma unroll
+  for (int r = 0; r < BR; ++r) res[r] = rhs[bidx ? (int64_t)bidx[row + r] : row + r] - acc[r];
+  if (MODE == CB_RESID) {
+#pragma unroll
+    for (int r = 0; r < BR; ++r) zout[row + r] = res[r];
+    return;
+  }
+  const T *Bi = inv + I * BR * BR;
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    T sr = 0;
+#pragma unroll
+    for (int c = 0; c < BR; ++c) sr += Bi[r * BR + c] * res[c];
+    zout[row + r] = zin[row + r] + omega * sr;
+  }
+}
+
+template <class T, int BR, int BC, int BG, int MODE>
+__global__ void __launch_bounds__(256) k_bsr_cell(const int *__restrict__ rb,
+                                                  const int *__restrict__ rp,
+                                                  const int *__restrict__ ci,
+                                                  const T *__restrict__ v,
+                                                  const T *__restrict__ zin,
+                                                  const T *__restrict__ rhs,
+                                                  const int *__restrict__ bidx,
+                                                  const T *__restrict__ inv, T omega,
+                                                  T *__restrict__ zout) {
+  constexpr int BB = BR * BC;
+  __shared__ T part[PCAPB * BR];
   const int r0 = rb[blockIdx.x], r1 = rb[blockIdx.x + 1];
   if (r0 >= r1) return;
   const int base = rp[r0];
@@ -486,7 +514,7 @@ __global__ void __launch_bounds__(256) k_bsr_gs(const int *__restrict__ rb,
   if (nblk <= PCAPB) {
     constexpr int BPL = 2;
     for (int q0 = 0; q0 < nblk; q0 += BPL * 256) {
-      T a[BPL][BB], xx[BPL][B];
+      T a[BPL][BB], xx[BPL][BC];
       int cc[BPL];
 #pragma unroll
       for (int h = 0; h < BPL; ++h) {
@@ -506,18 +534,18 @@ __global__ void __launch_bounds__(256) k_bsr_gs(const int *__restrict__ rb,
       for (int h = 0; h < BPL; ++h) {
         const int e = q0 + h * 256 + t;
 #pragma unroll
-        for (int c = 0; c < B; ++c) xx[h][c] = (e < nblk) ? zin[(int64_t)cc[h] * B + c] : (T)0;
+        for (int c = 0; c < BC; ++c) xx[h][c] = (e < nblk) ? zin[(int64_t)cc[h] * BC + c] : (T)0;
       }
 #pragma unroll
       for (int h = 0; h < BPL; ++h) {
         const int e = q0 + h * 256 + t;
         if (e < nblk) {
 #pragma unroll
-          for (int r = 0; r < B; ++r) {
-            T pr = a[h][r * B] * xx[h][0];
+          for (int r = 0; r < BR; ++r) {
+            T pr = a[h][r * BC] * xx[h][0];
 #pragma unroll
-            for (int c = 1; c < B; ++c) pr += a[h][r * B + c] * xx[h][c];
-            part[e * B + r] = pr;
+            for (int c = 1; c < BC; ++c) pr += a[h][r * BC + c] * xx[h][c];
+            part[e * BR + r] = pr;
           }
         }
       }
@@ -526,67 +554,45 @@ __global__ void __launch_bounds__(256) k_bsr_gs(const int *__restrict__ rb,
     const int l = t & (BG - 1);
     for (int I = r0 + t / BG; I < r1; I += 256 / BG) {
       const int s0 = rp[I] - base, len = rp[I + 1] - rp[I];
-      T acc[B];
+      T acc[BR];
 #pragma unroll
-      for (int r = 0; r < B; ++r) acc[r] = 0;
+      for (int r = 0; r < BR; ++r) acc[r] = 0;
       for (int k = l; k < len; k += BG)
 #pragma unroll
-        for (int r = 0; r < B; ++r) acc[r] += part[(s0 + k) * B + r];
+        for (int r = 0; r < BR; ++r) acc[r] += part[(s0 + k) * BR + r];
 #pragma unroll
-      for (int r = 0; r < B; ++r)
+      for (int r = 0; r < BR; ++r)
 #pragma unroll
         for (int o = BG / 2; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, BG);
-      if (l == 0) {
-        const int64_t row = (int64_t)I * B;
-        T res[B];
-#pragma unroll
-        for (int r = 0; r < B; ++r) res[r] = rhs[row + r] - acc[r];
-        const T *Bi = inv + (int64_t)I * BB;
-#pragma unroll
-        for (int r = 0; r < B; ++r) {
-          T sr = 0;
-#pragma unroll
-          for (int c = 0; c < B; ++c) sr += Bi[r * B + c] * res[c];
-          zout[row + r] = zin[row + r] + omega * sr;
-        }
-      }
+      if (l == 0) cell_epilogue<T, BR, BC, MODE>(I, acc, zin, rhs, bidx, inv, omega, zout);
     }
     return;
   }
-  __shared__ T fpart[4][B];
+  __shared__ T fpart[4][BR];
   for (int I = r0; I < r1; ++I) {
     const int e0 = rp[I], len = rp[I + 1] - e0;
-    T acc[B];
+    T acc[BR];
 #pragma unroll
-    for (int r = 0; r < B; ++r) acc[r] = 0;
+    for (int r = 0; r < BR; ++r) acc[r] = 0;
     for (int k = t; k < len; k += 256) {
       const T *bv = v + (int64_t)(e0 + k) * BB;
-      const int64_t c0 = (int64_t)ci[e0 + k] * B;
+      const int64_t c0 = (int64_t)ci[e0 + k] * BC;
 #pragma unroll
-      for (int r = 0; r < B; ++r)
+      for (int r = 0; r < BR; ++r)
 #pragma unroll
-        for (int c = 0; c < B; ++c) acc[r] += bv[r * B + c] * zin[c0 + c];
+        for (int c = 0; c < BC; ++c) acc[r] += bv[r * BC + c] * zin[c0 + c];
     }
 #pragma unroll
-    for (int r = 0; r < B; ++r) {
+    for (int r = 0; r < BR; ++r) {
       acc[r] = group_sum<T, 64>(acc[r]);
       if ((t & 63) == 0) fpart[t >> 6][r] = acc[r];
     }
     __syncthreads();
     if (t == 0) {
-      const int64_t row = (int64_t)I * B;
-      T res[B];
+      T tot[BR];
 #pragma unroll
-      for (int r = 0; r < B; ++r)
-        res[r] = rhs[row + r] - ((fpart[0][r] + fpart[1][r]) + (fpart[2][r] + fpart[3][r]));
-      const T *Bi = inv + (int64_t)I * BB;
-#pragma unroll
-      for (int r = 0; r < B; ++r) {
-        T sr = 0;
-#pragma unroll
-        for (int c = 0; c < B; ++c) sr += Bi[r * B + c] * res[c];
-        zout[row + r] = zin[row + r] + omega * sr;
-      }
+      for (int r = 0; r < BR; ++r) tot[r] = (fpart[0][r] + fpart[1][r]) + (fpart[2][r] + fpart[3][r]);
+      cell_epilogue<T, BR, BC, MODE>(I, tot, zin, rhs, bidx, inv, omega, zout);
     }
     __syncthreads();
   }
@@ -770,21 +776,49 @@ template <class T>
 void VecOps<T>::bsr_gs_sweep(const BsrBV<T> &A, const T *zin, const T *b, const T *inv, T omega,
                              T *zout, hipStream_t s) {
   if (A.nbr <= 0) return;
+  require(A.br == A.bc && (A.br == 2 || A.br == 3), MGR_ERR_UNSUPPORTED, "sweep needs 2x2 or 3x3 blocks");
   if (A.nwin <= 0) {   // no blocks at all: zout = zin + omega D_B^{-1} b
-    HIPCHK(hipMemcpyAsync(zout, zin, A.nbr * A.b * sizeof(T), hipMemcpyDeviceToDevice, s));
-    block_jacobi(A.nbr, A.b, inv, b, omega, zout, true, s);
+    HIPCHK(hipMemcpyAsync(zout, zin, A.nbr * A.br * sizeof(T), hipMemcpyDeviceToDevice, s));
+    block_jacobi(A.nbr, A.br, inv, b, omega, zout, true, s);
     return;
   }
   const double avg = (double)A.nblk / (double)A.nbr;
   const unsigned g = (unsigned)A.nwin;
-#define GSL(BSZ, GG) \
-  k_bsr_gs<T, BSZ, GG><<<g, 256, 0, s>>>(A.rb, A.rp, A.ci, A.v, zin, b, inv, omega, zout)
-  if (A.b == 2) {
+#define GSL(BSZ, GG)                                                                        \
+  k_bsr_cell<T, BSZ, BSZ, GG, CB_SWEEP><<<g, 256, 0, s>>>(A.rb, A.rp, A.ci, A.v, zin, b,   \
+                                                          nullptr, inv, omega, zout)
+  if (A.br == 2) {
     if (avg < 12) GSL(2, 4); else GSL(2, 8);
   } else {
     if (avg < 12) GSL(3, 4); else GSL(3, 8);
   }
 #undef GSL
+  KCHK();
+}
+template <class T>
+void VecOps<T>::bsr_resid(const BsrBV<T> &A, const T *x, const T *b, const int *bidx, T *out,
+                          hipStream_t s) {
+  if (A.nbr <= 0) return;
+  const int shape = A.br * 10 + A.bc;
+  require(shape == 22 || shape == 33 || shape == 23, MGR_ERR_UNSUPPORTED, "unsupported cell block");
+  if (A.nwin <= 0) {   // no blocks at all: out = b[bidx]
+    if (bidx) gather(bidx, A.nbr * A.br, b, out, s);
+    else HIPCHK(hipMemcpyAsync(out, b, A.nbr * A.br * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  const double avg = (double)A.nblk / (double)A.nbr;
+  const unsigned g = (unsigned)A.nwin;
+#define RSL(R, C, GG)                                                                     \
+  k_bsr_cell<T, R, C, GG, CB_RESID><<<g, 256, 0, s>>>(A.rb, A.rp, A.ci, A.v, x, b, bidx,  \
+                                                      nullptr, (T)0, out)
+  if (shape == 22) {
+    if (avg < 12) RSL(2, 2, 4); else RSL(2, 2, 8);
+  } else if (shape == 33) {
+    if (avg < 12) RSL(3, 3, 4); else RSL(3, 3, 8);
+  } else {
+    if (avg < 12) RSL(2, 3, 4); else RSL(2, 3, 8);
+  }
+#undef RSL
   KCHK();
 }
 template <class T>

@@ -117,12 +117,13 @@ struct Bsr3V {
   const T *v = nullptr;
 };
 
-// b x b block CSR of a level whose rows are interleaved cell by cell (b = 2 or 3): block
-// row I = rows bI..bI+b-1, a block for every block column any of them touches, values
-// row-major per block (zeros stored), and the stream windows of its apply kernel.
+// br x bc block CSR of a matrix whose rows come in groups of br (the unknowns of a cell)
+// and whose columns come in groups of bc: block row I = rows br I .. br I + br - 1, a block
+// for every column group c / bc any of them touches, values row-major per block (zeros
+// stored), and the stream windows of its apply kernels.
 struct BsrB {
   int64_t nbr = 0, nblk = 0, nwin = 0;
-  int b = 0;
+  int br = 0, bc = 0;
   DArr<int> rp, ci, rb;
   DArr<double> v;
   size_t bytes() const { return rp.bytes() + ci.bytes() + rb.bytes() + v.bytes(); }
@@ -130,7 +131,7 @@ struct BsrB {
 template <class T>
 struct BsrBV {
   int64_t nbr = 0, nblk = 0, nwin = 0;
-  int b = 0;
+  int br = 0, bc = 0;
   const int *rp = nullptr, *ci = nullptr, *rb = nullptr;
   const T *v = nullptr;
 };
@@ -268,7 +269,8 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
 void make_rowblocks(Csr &M, hipStream_t s);
 // rows `rows` (ascending, nr of them) of A as a CSR matrix of its own (columns unchanged)
 void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_t s);
-void csr_to_bsr_fill(const Csr &A, int b, BsrB &B, hipStream_t s);   // with its windows
+// (br, bc) = (2, 2), (3, 3) or (2, 3); with the windows of the apply kernels
+void csr_to_bsr_fill(const Csr &A, int br, int bc, BsrB &B, hipStream_t s);
 void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what);
 void bsr3_to_csr(const Bsr3 &B, Csr &C, hipStream_t s);
 // R = P^T (block pattern transposed, each block transposed)
@@ -348,6 +350,9 @@ struct VecOps {
   // one block-Jacobi sweep on a cell-blocked level: zout = zin + omega D_B^{-1} (b - A zin)
   static void bsr_gs_sweep(const BsrBV<T> &A, const T *zin, const T *b, const T *inv, T omega,
                            T *zout, hipStream_t s);
+  // out_i = b[bidx ? bidx[i] : i] - (A x)_i on a cell-blocked matrix (any block shape)
+  static void bsr_resid(const BsrBV<T> &A, const T *x, const T *b, const int *bidx, T *out,
+                        hipStream_t s);
   static void fill(T *p, T val, int64_t n, hipStream_t s);
   // out = dinv .* (b - A x)
   static void resid_scale(const CsrV<T> &A, const T *dinv, const T *x, const T *b, T *out,

@@ -198,9 +198,13 @@ struct MgrLevel {
   Csr Acf, Wp, Acor, G;      // Acor / G only with keep_setup
   Csr AF, AC;                // rows F and rows C of A_l (residuals of uncompacted levels)
   int nb_gs = 0;             // global smoother block size
+  bool gsb_pending = false;  // gsb still to be built from A
   DArr<double> binv64;
   BsrB gsb;                  // A_l as cell blocks for the block-Jacobi sweeps (FP64 values)
   DArr<char> tgsb;           // their values in the apply precision
+  BsrB cfb;                  // A_CF as cell x F-group blocks for the compacted residual
+  DArr<char> tcfb;           // (when its blocks are mostly full), values as tgsb
+  bool cfb_pending = false;
   std::vector<int> gs_ptr;   // block Gauss-Seidel: cells of colour c are gs_cells[ptr[c]..)
   DArr<int> gs_cells, gs_color;
   Amg amg;                   // F-relaxation AMG
@@ -573,7 +577,7 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
       G.nbr = L.gsb.nbr;
       G.nblk = L.gsb.nblk;
       G.nwin = L.gsb.nwin;
-      G.b = L.gsb.b;
+      G.br = G.bc = L.gsb.br;
       G.rp = L.gsb.rp.p;
       G.ci = L.gsb.ci.p;
       G.rb = L.gsb.rb.p;
@@ -694,6 +698,19 @@ void apply_level(mgr_handle *h, size_t l, const T *v, T *z, hipStream_t s) {
     V::spmv(Wr, rF, rC, true, s);
   }
   // restrict the residual by injection
+  else if (compactF && L.cfb.nbr > 0) {
+    BsrBV<T> B;
+    B.nbr = L.cfb.nbr;
+    B.nblk = L.cfb.nblk;
+    B.nwin = L.cfb.nwin;
+    B.br = L.cfb.br;
+    B.bc = L.cfb.bc;
+    B.rp = L.cfb.rp.p;
+    B.ci = L.cfb.ci.p;
+    B.rb = L.cfb.rb.p;
+    B.v = fp64 ? reinterpret_cast<const T *>(L.cfb.v.p) : Ptr<T>::of(L.tcfb);
+    V::bsr_resid(B, eF, v, L.cf.C.p, rC, s);
+  }
   else if (compactF) V::resid(Acf, nC, nullptr, L.cf.C.p, eF, v, rC, s);
   else if (sub) V::resid(AC, nC, nullptr, L.cf.C.p, z, v, rC, s);
   else V::resid(A, nC, L.cf.C.p, L.cf.C.p, z, v, rC, s);
@@ -981,10 +998,8 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       L->binv64.alloc(n * nb, s);
       block_diag_inverse(L->A, nb, L->binv64.p, s, flag);
       cast_values(L->binv64.p, L->tbinv, n * nb, sz, s);
-      if (lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI && lo.global_sweeps > 1) {
-        csr_to_bsr_fill(L->A, nb, L->gsb, s);
-        if (sz == 4) cast_values(L->gsb.v.p, L->tgsb, L->gsb.nblk * nb * nb, sz, s);
-      }
+      // cell blocks for the fused sweeps: built after the coarser levels (below)
+      L->gsb_pending = lo.global_smoother == MGR_GSMOOTH_BLOCK_JACOBI && lo.global_sweeps > 1;
       if (lo.global_smoother == MGR_GSMOOTH_BLOCK_GS)
         bgs_setup(L->A, nb, L->gs_ptr, L->gs_cells, L->gs_color, s, flag);
       if (lo.global_smoother == MGR_GSMOOTH_ILU) {
@@ -1028,6 +1043,22 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (needs_A) make_rowblocks(L->A, s);
     make_rowblocks(L->Acf, s);
     make_rowblocks(L->Wp, s);
+    {
+      // the compacted residual r_C = v_C - A_CF e_F runs when the F-relaxation starts from
+      // z = 0 and the restriction is injection; cells of br C rows, groups of bc F columns
+      const bool compact = lo.global_smoother == MGR_GSMOOTH_NONE &&
+                           (lo.frelax == MGR_FRELAX_AMG || lo.frelax == MGR_FRELAX_DENSE) && !jac_r;
+      const int br = __builtin_popcount(present & ~lo.f_label_mask);
+      // F columns in groups: the nodal triples of a 3x3-block F-relaxation, else one of
+      // each F label
+      const int bc = lo.frelax_block > 1 ? lo.frelax_block
+                                         : __builtin_popcount(present & lo.f_label_mask);
+      const int shape = br * 10 + bc;
+      L->cfb_pending = compact && (shape == 22 || shape == 33 || shape == 23) && nC % br == 0 &&
+                       L->cf.nF % bc == 0 && L->Acf.nnz > 0;
+      L->cfb.br = br;
+      L->cfb.bc = bc;
+    }
     if (jac_r) make_rowblocks(L->Wr, s);
     if (lo.dff_block > 1) cast_values(L->dffinv64.p, L->tdffinv, L->cf.nF * lo.dff_block, sz, s);
     if (sz == 4) {
@@ -1068,6 +1099,28 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (o.keep_setup) h->coarseA = std::move(keep);
   }
   h->coarse_labels = std::move(lab);
+  // the cell-block copies of the levels (nothing in the setup reads them)
+  for (auto &L : h->lv)
+    if (L->gsb_pending) {
+      const int nb = L->nb_gs;
+      csr_to_bsr_fill(L->A, nb, nb, L->gsb, s);
+      if (sz == 4) cast_values(L->gsb.v.p, L->tgsb, L->gsb.nblk * nb * nb, sz, s);
+      L->gsb_pending = false;
+    }
+  // A_CF in cell blocks: kept when at least 70 % of the stored block entries are entries
+  // of A_CF (FP32 blocks take 4 br bc + 4 bytes against 8 per CSR entry)
+  for (auto &L : h->lv)
+    if (L->cfb_pending) {
+      const int br = L->cfb.br, bc = L->cfb.bc;
+      csr_to_bsr_fill(L->Acf, br, bc, L->cfb, s);
+      const double slots = (double)L->cfb.nblk * br * bc;
+      if (slots > 0 && (double)L->Acf.nnz >= 0.7 * slots) {
+        if (sz == 4) cast_values(L->cfb.v.p, L->tcfb, L->cfb.nblk * br * bc, sz, s);
+      } else {
+        L->cfb = BsrB();
+      }
+      L->cfb_pending = false;
+    }
   jobs.join();
   jobs.rethrow();
   for (auto &j : jobs.v) j->level->amg = std::move(j->amg);
@@ -1090,6 +1143,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->AC.v.reset();
         L->binv64.reset();
         L->gsb.v.reset();
+        L->cfb.v.reset();
         L->ffinv64.reset();
         L->iluL.v.reset();
         L->iluU.v.reset();
@@ -1098,6 +1152,12 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
         L->dffinv64.reset();
       }
       L->dFF.reset();
+      if (L->cfb.nbr > 0) {   // the compacted residual reads the cell blocks only
+        L->Acf.rp.reset();
+        L->Acf.ci.reset();
+        L->Acf.v.reset();
+        L->tAcf.reset();
+      }
     }
     if (sz == 4) h->cdense64.reset();
   }
@@ -1163,7 +1223,7 @@ size_t handle_bytes(const mgr_handle *h) {
     csr(L->A); csr(L->Acf); csr(L->Wp); csr(L->Acor); csr(L->G); csr(L->AF); csr(L->AC);
     b += L->labels.bytes() + L->cf.F.bytes() + L->cf.C.bytes() + L->cf.map.bytes() +
          L->dFF.bytes() + L->binv64.bytes() + L->gs_cells.bytes() + L->gs_color.bytes() +
-         L->gsb.bytes() + L->tgsb.bytes() +
+         L->gsb.bytes() + L->tgsb.bytes() + L->cfb.bytes() + L->tcfb.bytes() +
          L->ffinv64.bytes() + L->tA.bytes() +
          L->tAcf.bytes() + L->tWp.bytes() + L->tdinvF.bytes() + L->tbinv.bytes() +
          L->tAF.bytes() + L->tAC.bytes() +

@@ -1360,11 +1360,11 @@ void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_
 }
 
 // ---------------------------------------------------------------------------------
-// CSR -> b x b block CSR of a cell-interleaved level (every touched block stored whole)
+// CSR -> B x BC block CSR over cells of B rows (every touched block stored whole)
 namespace {
-constexpr int kBsrWin = 512;   // blocks per stream window of the block sweep kernel
+constexpr int kBsrWin = 512;   // blocks per stream window of the cell-block kernels
 
-// The block columns of block row I (a cell) are the distinct c / B of its B rows.  G lanes
+// The block columns of block row I (a cell) are the distinct c / BC of its B rows.  G lanes
 // per cell stage the cell's column indices (one contiguous range of the CSR arrays) in LDS.
 // An entry represents its block column when it is the first entry of that block column in
 // its row and no earlier row of the cell holds the block column (binary searches in the
@@ -1398,7 +1398,7 @@ __device__ inline int popc_range(const unsigned *mask, int a, int b) {
   return n;
 }
 
-template <int B, bool FILL>
+template <int B, int BC, bool FILL>
 __global__ void __launch_bounds__(256) k_bsrb_rows(int64_t nbr, const int *__restrict__ rp,
                                                    const int *__restrict__ ci,
                                                    const double *__restrict__ v,
@@ -1432,13 +1432,13 @@ __global__ void __launch_bounds__(256) k_bsrb_rows(int64_t nbr, const int *__res
         int mc = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < B; ++r)
-          if (p[r] < grs[r + 1]) mc = min(mc, ci[p[r]] / B);
+          if (p[r] < grs[r + 1]) mc = min(mc, ci[p[r]] / BC);
         if (mc == 0x7fffffff) break;
         if (FILL) bci[o + nb] = mc;
 #pragma unroll
         for (int r = 0; r < B; ++r)
-          while (p[r] < grs[r + 1] && ci[p[r]] / B == mc) {
-            if (FILL) bv[(int64_t)(o + nb) * B * B + r * B + ci[p[r]] % B] = v[p[r]];
+          while (p[r] < grs[r + 1] && ci[p[r]] / BC == mc) {
+            if (FILL) bv[(int64_t)(o + nb) * B * BC + r * BC + ci[p[r]] % BC] = v[p[r]];
             ++p[r];
           }
         ++nb;
@@ -1455,13 +1455,13 @@ __global__ void __launch_bounds__(256) k_bsrb_rows(int64_t nbr, const int *__res
     int r = 0;
 #pragma unroll
     for (int q = 1; q < B; ++q) r += (k >= rs[q]);
-    const int bc = s_c[g][k] / B;
-    bool rep = (k == rs[r]) || (s_c[g][k - 1] / B != bc);
+    const int bc = s_c[g][k] / BC;
+    bool rep = (k == rs[r]) || (s_c[g][k - 1] / BC != bc);
 #pragma unroll
     for (int q = 0; q < B - 1; ++q)
       if (rep && q < r) {
-        const int lb = lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * B);
-        if (lb < rs[q + 1] && s_c[g][lb] < (bc + 1) * B) rep = false;
+        const int lb = lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * BC);
+        if (lb < rs[q + 1] && s_c[g][lb] < (bc + 1) * BC) rep = false;
       }
     if (rep) atomicOr(&s_f[g][k >> 5], 1u << (k & 31));
   }
@@ -1475,12 +1475,12 @@ __global__ void __launch_bounds__(256) k_bsrb_rows(int64_t nbr, const int *__res
     int r = 0;
 #pragma unroll
     for (int q = 1; q < B; ++q) r += (k >= rs[q]);
-    const int c = s_c[g][k], bc = c / B;
+    const int c = s_c[g][k], bc = c / BC;
     int pos = 0;
 #pragma unroll
     for (int q = 0; q < B; ++q)
-      pos += popc_range(s_f[g], rs[q], lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * B));
-    bv[(int64_t)(o + pos) * B * B + r * B + (c - bc * B)] = v[e0 + k];
+      pos += popc_range(s_f[g], rs[q], lds_lower_bound(s_c[g], rs[q], rs[q + 1], bc * BC));
+    bv[(int64_t)(o + pos) * B * BC + r * BC + (c - bc * BC)] = v[e0 + k];
     if (s_f[g][k >> 5] & (1u << (k & 31))) bci[o + pos] = bc;
   }
 }
@@ -1500,37 +1500,38 @@ __global__ void k_bsrb_windows(int64_t nbr, const int *__restrict__ brp, int64_t
 }
 }  // namespace
 
-void csr_to_bsr_fill(const Csr &A, int b, BsrB &B, hipStream_t s) {
-  require(b == 2 || b == 3, MGR_ERR_ARG, "block size must be 2 or 3");
-  require(A.n == A.m && A.n % b == 0, MGR_ERR_ARG, "block matrix: size not divisible by block");
-  B.b = b;
-  B.nbr = A.n / b;
+void csr_to_bsr_fill(const Csr &A, int br, int bc, BsrB &B, hipStream_t s) {
+  const int shape = br * 10 + bc;
+  require(shape == 22 || shape == 33 || shape == 23, MGR_ERR_ARG,
+          "cell blocks must be 2x2, 3x3 or 2x3");
+  require(A.n % br == 0 && A.m % bc == 0, MGR_ERR_ARG,
+          "block matrix: sizes not divisible by the block shape");
+  B.br = br;
+  B.bc = bc;
+  B.nbr = A.n / br;
   B.rp.alloc(B.nbr + 1, s);
   DArr<int> cnt(std::max<int64_t>(B.nbr, 1), s);
+  const unsigned gr = grid_for(B.nbr * BG_LANES, 256);
+#define BSRB_ROWS(R, C, F, cntp, brpp, bcip, bvp)                                           \
+  k_bsrb_rows<R, C, F><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, F ? A.v.p : nullptr, cntp, \
+                                          brpp, bcip, bvp)
   if (B.nbr > 0) {
-    const unsigned gr = grid_for(B.nbr * BG_LANES, 256);
-    if (b == 2)
-      k_bsrb_rows<2, false><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, nullptr, cnt.p, nullptr,
-                                               nullptr, nullptr);
-    else
-      k_bsrb_rows<3, false><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, nullptr, cnt.p, nullptr,
-                                               nullptr, nullptr);
+    if (shape == 22) BSRB_ROWS(2, 2, false, cnt.p, nullptr, nullptr, nullptr);
+    else if (shape == 33) BSRB_ROWS(3, 3, false, cnt.p, nullptr, nullptr, nullptr);
+    else BSRB_ROWS(2, 3, false, cnt.p, nullptr, nullptr, nullptr);
     KCHK();
   }
   B.nblk = exclusive_scan_i32(cnt.p, B.rp.p, B.nbr, s);
   B.ci.alloc(std::max<int64_t>(B.nblk, 1), s);
-  B.v.alloc(std::max<int64_t>(B.nblk * b * b, 1), s);
-  fill<double>(B.v.p, 0.0, B.nblk * b * b, s);   // entries absent from A stay zero
+  B.v.alloc(std::max<int64_t>(B.nblk * br * bc, 1), s);
+  fill<double>(B.v.p, 0.0, B.nblk * br * bc, s);   // entries absent from A stay zero
   if (B.nbr > 0) {
-    const unsigned gr = grid_for(B.nbr * BG_LANES, 256);
-    if (b == 2)
-      k_bsrb_rows<2, true><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, A.v.p, nullptr, B.rp.p,
-                                              B.ci.p, B.v.p);
-    else
-      k_bsrb_rows<3, true><<<gr, 256, 0, s>>>(B.nbr, A.rp.p, A.ci.p, A.v.p, nullptr, B.rp.p,
-                                              B.ci.p, B.v.p);
+    if (shape == 22) BSRB_ROWS(2, 2, true, nullptr, B.rp.p, B.ci.p, B.v.p);
+    else if (shape == 33) BSRB_ROWS(3, 3, true, nullptr, B.rp.p, B.ci.p, B.v.p);
+    else BSRB_ROWS(2, 3, true, nullptr, B.rp.p, B.ci.p, B.v.p);
     KCHK();
   }
+#undef BSRB_ROWS
   B.nwin = B.nblk > 0 ? (B.nblk + kBsrWin - 1) / kBsrWin : 0;
   B.rb.alloc(B.nwin + 1, s);
   k_bsrb_windows<<<grid_for(B.nwin + 1, 256), 256, 0, s>>>(B.nbr, B.rp.p, B.nwin, B.rb.p);

@@ -167,21 +167,24 @@ mgr_status mgr_dense_inverse(const double *D, double *Inv, int32_t n, void *stre
   return MGR_OK;
 }
 
-mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t b, int32_t *brow_ptr, int32_t *bcol,
-                          double *bval, int64_t capacity, int64_t *nblk, void *stream) {
+mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t br, int32_t bc, int32_t *brow_ptr,
+                          int32_t *bcol, double *bval, int64_t capacity, int64_t *nblk,
+                          void *stream) {
   if (!A || !nblk) return MGR_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   try {
-    require(b == 2 || b == 3, MGR_ERR_ARG, "block size must be 2 or 3");
-    require(A->nrows == A->ncols && A->nrows % b == 0, MGR_ERR_ARG,
-            "A must be square with a multiple of b rows");
+    const int shape = br * 10 + bc;
+    require(shape == 22 || shape == 33 || shape == 23, MGR_ERR_ARG,
+            "block shape must be 2x2, 3x3 or 2x3");
+    require(A->nrows % br == 0 && A->ncols % bc == 0, MGR_ERR_ARG,
+            "rows must be a multiple of br and columns of bc");
     DArr<int> flag(1, s);
     clear_flag(flag.p, s);
     Csr a;
     import_csr(A, a, s, flag.p);
     check_flags(flag.p, s, "bsr import");
     BsrB B;
-    csr_to_bsr_fill(a, b, B, s);
+    csr_to_bsr_fill(a, br, bc, B, s);
     HIPCHK(hipStreamSynchronize(s));
     *nblk = B.nblk;
     if (bcol) {
@@ -190,7 +193,7 @@ mgr_status mgr_csr_to_bsr(const mgr_csr *A, int32_t b, int32_t *brow_ptr, int32_
       HIPCHK(hipMemcpyAsync(brow_ptr, B.rp.p, (B.nbr + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
       if (B.nblk) {
         HIPCHK(hipMemcpyAsync(bcol, B.ci.p, B.nblk * sizeof(int), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(bval, B.v.p, B.nblk * b * b * sizeof(double),
+        HIPCHK(hipMemcpyAsync(bval, B.v.p, B.nblk * br * bc * sizeof(double),
                               hipMemcpyDeviceToDevice, s));
       }
       HIPCHK(hipStreamSynchronize(s));

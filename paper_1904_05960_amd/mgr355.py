@@ -180,8 +180,8 @@ def lib():
         "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
                                 C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_dense_inverse": (st, [vp, vp, C.c_int32, vp]),
-        "mgr_csr_to_bsr": (st, [C.POINTER(mgr_csr), C.c_int32, vp, vp, vp, C.c_int64,
-                                C.POINTER(C.c_int64), vp]),
+        "mgr_csr_to_bsr": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, vp, vp, vp,
+                                C.c_int64, C.POINTER(C.c_int64), vp]),
         "mgr_ilu": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, C.POINTER(vp),
                          C.POINTER(C.c_int64), vp]),
         "mgr_aggregate": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_double, C.c_int32, vp,
@@ -625,20 +625,22 @@ def dense_inverse(D, stream=None):
     return Inv
 
 
-def csr_to_bsr(A: Matrix, b: int, stream=None):
-    """The b x b block CSR of a cell-interleaved square matrix, as the block-Jacobi sweeps
-    store a level: (block row pointer, block columns, blocks (nblk, b, b)) device tensors."""
+def csr_to_bsr(A: Matrix, br: int, bc: int | None = None, stream=None):
+    """The br x bc block CSR of a matrix over cells of br rows and column groups of bc
+    (bc = br by default), as the library stores cell-blocked operators: (block row pointer,
+    block columns, blocks (nblk, br, bc)) device tensors."""
     import torch
+    bc = br if bc is None else bc
     nb = C.c_int64()
-    _check(lib().mgr_csr_to_bsr(C.byref(A.c), int(b), None, None, None, 0, C.byref(nb),
-                                _stream(stream)))
-    k = int(nb.value)
-    brp = torch.empty(A.nrows // b + 1, dtype=torch.int32, device="cuda")
-    bci = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
-    bv = torch.empty(max(k, 1) * b * b, dtype=torch.float64, device="cuda")
-    _check(lib().mgr_csr_to_bsr(C.byref(A.c), int(b), _ptr(brp), _ptr(bci), _ptr(bv), k,
+    _check(lib().mgr_csr_to_bsr(C.byref(A.c), int(br), int(bc), None, None, None, 0,
                                 C.byref(nb), _stream(stream)))
-    return brp, bci[:k], bv[:k * b * b].view(k, b, b)
+    k = int(nb.value)
+    brp = torch.empty(A.nrows // br + 1, dtype=torch.int32, device="cuda")
+    bci = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+    bv = torch.empty(max(k, 1) * br * bc, dtype=torch.float64, device="cuda")
+    _check(lib().mgr_csr_to_bsr(C.byref(A.c), int(br), int(bc), _ptr(brp), _ptr(bci),
+                                _ptr(bv), k, C.byref(nb), _stream(stream)))
+    return brp, bci[:k], bv[:k * br * bc].view(k, br, bc)
 
 
 def aggregate(A: Matrix, bs: int, theta: float, level: int, stream=None):

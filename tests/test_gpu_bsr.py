@@ -149,58 +149,62 @@ def test_bsr_argument_errors():
     assert e.value.status == m.MGR_ERR_ARG
 
 
-def cell_matrix(rng, ncell, b, long_cells):
-    """Square CSR over ncell cells of b interleaved rows: each cell draws a set of column
-    blocks and each of its rows a random subset of their scalar columns (rows empty, rows
-    sharing none of their blocks, explicit zeros); `long_cells` maps cell -> block count."""
-    n = ncell * b
+def cell_matrix(rng, ncell, br, long_cells, bc=None, ngroup=None):
+    """CSR over ncell cells of br rows and ngroup column groups of bc: each cell draws a set
+    of column groups and each of its rows a random subset of their columns (rows empty,
+    rows sharing none of their blocks, explicit zeros); `long_cells` maps cell -> block
+    count (those cells' rows take every column of their groups)."""
+    bc = br if bc is None else bc
+    ngroup = ncell if ngroup is None else ngroup
     indptr, cols = [0], []
     for I in range(ncell):
         nbk = long_cells.get(I, int(rng.integers(0, 14)))
-        bks = np.sort(rng.choice(ncell, size=min(nbk, ncell), replace=False))
-        for r in range(b):
+        bks = np.sort(rng.choice(ngroup, size=min(nbk, ngroup), replace=False))
+        for r in range(br):
             dens = 1.0 if I in long_cells else rng.choice([0.0, 0.3, 0.9, 1.0])
-            keep = rng.random(len(bks) * b) < dens
-            cs = (bks[:, None] * b + np.arange(b)[None, :]).reshape(-1)[keep]
+            keep = rng.random(len(bks) * bc) < dens
+            cs = (bks[:, None] * bc + np.arange(bc)[None, :]).reshape(-1)[keep]
             cols.append(cs)
             indptr.append(indptr[-1] + len(cs))
     cols = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
     vals = rng.standard_normal(len(cols))
     vals[rng.random(len(cols)) < 0.05] = 0.0
-    return np.array(indptr, dtype=np.int64), cols, vals, n
+    return np.array(indptr, dtype=np.int64), cols, vals, ngroup * bc
 
 
-def bsr_by_definition(indptr, cols, vals, b):
-    nbr = (len(indptr) - 1) // b
+def bsr_by_definition(indptr, cols, vals, br, bc=None):
+    bc = br if bc is None else bc
+    nbr = (len(indptr) - 1) // br
     brp, bci, blocks = [0], [], []
     for I in range(nbr):
-        e0, e1 = indptr[I * b], indptr[I * b + b]
-        bc = np.unique(cols[e0:e1] // b)
-        where = {c: k for k, c in enumerate(bc)}
-        blk = np.zeros((len(bc), b, b))
-        for r in range(b):
-            for e in range(indptr[I * b + r], indptr[I * b + r + 1]):
-                blk[where[cols[e] // b], r, cols[e] % b] = vals[e]
-        bci.append(bc)
+        e0, e1 = indptr[I * br], indptr[I * br + br]
+        bk = np.unique(cols[e0:e1] // bc)
+        where = {c: k for k, c in enumerate(bk)}
+        blk = np.zeros((len(bk), br, bc))
+        for r in range(br):
+            for e in range(indptr[I * br + r], indptr[I * br + r + 1]):
+                blk[where[cols[e] // bc], r, cols[e] % bc] = vals[e]
+        bci.append(bk)
         blocks.append(blk)
-        brp.append(brp[-1] + len(bc))
+        brp.append(brp[-1] + len(bk))
     return (np.array(brp), np.concatenate(bci) if bci else np.zeros(0),
-            np.concatenate(blocks) if blocks else np.zeros((0, b, b)))
+            np.concatenate(blocks) if blocks else np.zeros((0, br, bc)))
 
 
-@pytest.mark.parametrize("b", [2, 3])
-def test_csr_to_bsr_matches_definition(b):
-    """The cell-block storage of the block-Jacobi sweeps, bit for bit: block columns, row
-    pointers and every value (absent entries zero, explicit zeros kept), on cells of
-    0 .. 13 blocks, full cells of 40, 60, 90 and 170 blocks (below and beyond the 512
-    entries staged in LDS; beyond are merged from global memory) and ragged, empty and
-    one-row cells."""
-    rng = np.random.default_rng(40 + b)
+@pytest.mark.parametrize("br,bc", [(2, 2), (3, 3), (2, 3)])
+def test_csr_to_bsr_matches_definition(br, bc):
+    """The cell-block storage of the block-Jacobi sweeps and of A_CF, bit for bit: block
+    columns, row pointers and every value (absent entries zero, explicit zeros kept), on
+    cells of 0 .. 13 blocks, full cells of 40, 60, 90 and 170 blocks (below and beyond the
+    512 entries staged in LDS; beyond are merged from global memory) and ragged, empty and
+    one-row cells; (2, 3) on a rectangular matrix."""
+    rng = np.random.default_rng(40 + 10 * br + bc)
     ncell = 700
-    ip, ci, v, n = cell_matrix(rng, ncell, b, {5: 90, 6: 170, 300: 40, 699: 60})
-    A = m.Matrix.from_host(ip, ci, v)
-    brp, bci, bv = m.csr_to_bsr(A, b)
-    erp, eci, ev = bsr_by_definition(ip, ci, v, b)
+    ngroup = 700 if br == bc else 560
+    ip, ci, v, m_cols = cell_matrix(rng, ncell, br, {5: 90, 6: 170, 300: 40, 699: 60}, bc, ngroup)
+    A = m.Matrix.from_host(ip, ci, v, ncols=m_cols)
+    brp, bci, bv = m.csr_to_bsr(A, br, bc)
+    erp, eci, ev = bsr_by_definition(ip, ci, v, br, bc)
     assert np.array_equal(brp.cpu().numpy(), erp)
     assert np.array_equal(bci.cpu().numpy(), eci)
     assert np.array_equal(bv.cpu().numpy(), ev)
@@ -209,14 +213,14 @@ def test_csr_to_bsr_matches_definition(b):
 def test_csr_to_bsr_errors():
     import ctypes as C
     ip, ci, v, n = cell_matrix(np.random.default_rng(1), 5, 2, {})
-    A = m.Matrix.from_host(ip, ci, v)          # 10 rows
-    for b in (1, 3, 4):                        # not 2 or 3; 10 rows not a multiple of 3
+    A = m.Matrix.from_host(ip, ci, v)          # 10 x 10
+    for br, bc in ((1, 1), (3, 3), (4, 4), (3, 2), (2, 3)):   # shapes; 10 not a multiple of 3
         with pytest.raises(m.MgrError):
-            m.csr_to_bsr(A, b)
+            m.csr_to_bsr(A, br, bc)
     brp, bci, bv = m.csr_to_bsr(A, 2)
     k = int(bci.numel())
     assert k > 0
     nb = C.c_int64()
-    st = m.lib().mgr_csr_to_bsr(C.byref(A.c), 2, brp.data_ptr(), bci.data_ptr(), bv.data_ptr(),
-                                k - 1, C.byref(nb), None)
+    st = m.lib().mgr_csr_to_bsr(C.byref(A.c), 2, 2, brp.data_ptr(), bci.data_ptr(),
+                                bv.data_ptr(), k - 1, C.byref(nb), None)
     assert st != 0 and nb.value == k          # capacity below the block count
