@@ -269,6 +269,10 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
 void make_rowblocks(Csr &M, hipStream_t s);
 // rows `rows` (ascending, nr of them) of A as a CSR matrix of its own (columns unchanged)
 void gather_rows(const Csr &A, const int *rows, int64_t nr, Csr &out, hipStream_t s);
+// windows of 512 blocks over a block row pointer: rb[k] = first block row whose first block
+// is at or beyond 512 k, rb[nwin] = nbr; returns nwin (0 without blocks)
+int64_t make_block_windows(const int *rp, int64_t nbr, int64_t nblk, DArr<int> &rb,
+                           hipStream_t s);
 // (br, bc) = (2, 2), (3, 3) or (2, 3); with the windows of the apply kernels
 void csr_to_bsr_fill(const Csr &A, int br, int bc, BsrB &B, hipStream_t s);
 void csr_to_bsr3(const Csr &A, Bsr3 &B, hipStream_t s, int *dflag, const char *what);

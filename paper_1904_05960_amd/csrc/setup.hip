@@ -1532,10 +1532,16 @@ void csr_to_bsr_fill(const Csr &A, int br, int bc, BsrB &B, hipStream_t s) {
     KCHK();
   }
 #undef BSRB_ROWS
-  B.nwin = B.nblk > 0 ? (B.nblk + kBsrWin - 1) / kBsrWin : 0;
-  B.rb.alloc(B.nwin + 1, s);
-  k_bsrb_windows<<<grid_for(B.nwin + 1, 256), 256, 0, s>>>(B.nbr, B.rp.p, B.nwin, B.rb.p);
+  B.nwin = make_block_windows(B.rp.p, B.nbr, B.nblk, B.rb, s);
+}
+
+int64_t make_block_windows(const int *rp, int64_t nbr, int64_t nblk, DArr<int> &rb,
+                           hipStream_t s) {
+  const int64_t nwin = nblk > 0 ? (nblk + kBsrWin - 1) / kBsrWin : 0;
+  rb.alloc(nwin + 1, s);
+  k_bsrb_windows<<<grid_for(nwin + 1, 256), 256, 0, s>>>(nbr, rp, nwin, rb.p);
   KCHK();
+  return nwin;
 }
 
 void block_diag_inverse(const Csr &A, int nb, double *inv, hipStream_t s, int *dflag) {
