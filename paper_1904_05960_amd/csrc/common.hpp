@@ -177,7 +177,9 @@ void check_flags(const int *dflag, hipStream_t s, const char *where);
 
 // ------------------------------------------------------------------------------------
 // sparse setup kernels (spgemm.hip, setup.hip, amg_setup.hip)
-void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag);
+// `group` > 1: rows of A in groups of that many rows (2 or 3) that likely share one column
+// pattern; verified, and the groups then share their symbolic work, loads and hash tables
+void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag, int group = 1);
 void transpose(const Csr &A, Csr &T, bool values, hipStream_t s);
 // S = A - diag(w) * B restricted to entries of B kept by the drop rule.
 //   keep rule: nmax < 0 keeps all of B; otherwise per row the entries whose column c has

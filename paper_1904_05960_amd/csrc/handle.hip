@@ -933,7 +933,10 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
       same_entity_filter(L->Acf, L->cf.C.p, L->cf.F.p, rankL.p, AcfQ, s);
     }
     Csr Acor;
-    spgemm(lo.coupling == MGR_COUPLING_QUASI_IMPES ? AcfQ : L->Acf, M, Acor, s, flag);
+    // the C rows of a cell (one per C label) select the same F columns: the product
+    // shares their work when their patterns agree
+    spgemm(lo.coupling == MGR_COUPLING_QUASI_IMPES ? AcfQ : L->Acf, M, Acor, s, flag,
+           __builtin_popcount(present & ~lo.f_label_mask));
     if (jac_r) {
       // N = A_CF D_FF^{-1}; correction A_CF M + N A_FC - N A_FF M (Jacobi restriction)
       Csr N;

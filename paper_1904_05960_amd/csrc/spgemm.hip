@@ -786,7 +786,270 @@ void spgemm_symbolic(int64_t n, const int *arp, const int *aci, int64_t annz, co
   if (ub_out) *ub_out = std::move(ub);
 }
 
-void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
+// ---------------------------------------------------------------------------------
+// Products whose rows of A come in groups of R rows with one column pattern (the rows of a
+// cell in A_CF): the rows of a group select the same rows of B, so they share the symbolic
+// count, the loads of B and the hash table of output columns; each row keeps its own
+// accumulators, summed in the same ascending k as the scalar kernels, so C is the same to
+// the bit.
+namespace {
+template <int R>
+__global__ void k_group_same(int64_t ng, const int *__restrict__ arp, const int *__restrict__ aci,
+                             int *__restrict__ flag) {
+  const int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 16;
+  const int l = threadIdx.x & 15;
+  if (g >= ng) return;
+  const int64_t r0 = g * R;
+  const int s0 = arp[r0], len = arp[r0 + 1] - s0;
+  bool bad = false;
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int sr = arp[r0 + r];
+    if (arp[r0 + r + 1] - sr != len) bad = true;
+    else
+      for (int e = l; e < len; e += 16) bad |= aci[sr + e] != aci[s0 + e];
+  }
+  if (bad) atomicOr(flag, 1);
+}
+// the first row of every group; upper bounds of their products
+__global__ void k_group_rows(int64_t ng, int R, const int *__restrict__ arp,
+                             const int *__restrict__ aci, const int *__restrict__ brp,
+                             int *__restrict__ rows, int64_t *__restrict__ ub) {
+  constexpr int G = 16;
+  const int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int l = threadIdx.x & (G - 1);
+  if (g >= ng) return;
+  const int64_t i = g * R;
+  int64_t sum = 0;
+  for (int e = arp[i] + l; e < arp[i + 1]; e += G) {
+    const int k = aci[e];
+    sum += brp[k + 1] - brp[k];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, G);
+  if (l == 0) {
+    rows[g] = (int)i;
+    ub[i] = sum;
+  }
+}
+__global__ void k_group_bcast(int64_t ng, int R, int *__restrict__ cnt, int *__restrict__ mx) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int c = cnt[g * R];
+  for (int r = 1; r < R; ++r) cnt[g * R + r] = c;
+  atomicMax(mx, c);
+}
+
+template <int G, int R>
+__device__ __forceinline__ void num_group_g(int r0, const int *__restrict__ arp,
+                                            const int *__restrict__ aci,
+                                            const double *__restrict__ av,
+                                            const int *__restrict__ brp,
+                                            const int *__restrict__ bci,
+                                            const double *__restrict__ bv,
+                                            const int *__restrict__ crp, int *__restrict__ cci,
+                                            double *__restrict__ cv, int *keys, double *vals,
+                                            int *lk, int *ls, int ht, int *s_n, int *flag) {
+  const int l = threadIdx.x & (G - 1);
+  const unsigned mask = (unsigned)ht - 1;
+  for (int q = l; q < ht; q += G) {
+    keys[q] = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) vals[r * ht + q] = 0.0;
+  }
+  if (l == 0) *s_n = 0;
+  __builtin_amdgcn_wave_barrier();
+  const int as = arp[r0], ae = arp[r0 + 1];
+  int aoff[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) aoff[r] = arp[r0 + r] - as;
+  for (int c0 = as; c0 < ae; c0 += G) {
+    const int e = c0 + l;
+    int k = 0, b0 = 0, b1 = 0;
+    double a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = 0.0;
+    if (e < ae) {
+      k = aci[e];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = av[e + aoff[r]];
+      b0 = brp[k];
+      b1 = brp[k + 1];
+    }
+    const int cnt = min(G, ae - c0);
+    constexpr int PF = 8;
+    for (int t0 = 0; t0 < cnt; t0 += PF) {
+      int jj[PF], qa[PF], qb[PF];
+      double bb[PF], at[PF][R];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int tt = (t0 + u < cnt) ? t0 + u : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) at[u][r] = __shfl(a[r], tt, G);
+        qa[u] = __shfl(b0, tt, G);
+        qb[u] = (t0 + u < cnt) ? __shfl(b1, tt, G) : qa[u];
+        const int q = qa[u] + l;
+        const bool ok = q < qb[u];
+        jj[u] = ok ? bci[q] : -1;
+        bb[u] = ok ? bv[q] : 0.0;
+      }
+      unsigned sl[PF];
+      int seen[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) sl[u] = hslot(jj[u] >= 0 ? jj[u] : 0, mask);
+#pragma unroll
+      for (int u = 0; u < PF; ++u) seen[u] = jj[u] >= 0 ? keys[sl[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (jj[u] >= 0 && seen[u] != jj[u]) {
+          sl[u] = table_find_or_insert(keys, mask, jj[u]);
+          if (sl[u] > mask) atomicOr(flag, FLAG_PATTERN);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        if (t0 + u < cnt) {
+          if (jj[u] >= 0 && sl[u] <= mask) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              vals[r * ht + sl[u]] = __dadd_rn(vals[r * ht + sl[u]], __dmul_rn(at[u][r], bb[u]));
+          }
+          for (int q = qa[u] + G + l; q < qb[u]; q += G) {   // rows of B longer than G
+            const unsigned slot = table_find_or_insert(keys, mask, bci[q]);
+            if (slot > mask) { atomicOr(flag, FLAG_PATTERN); continue; }
+            const double bq = bv[q];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              vals[r * ht + slot] = __dadd_rn(vals[r * ht + slot], __dmul_rn(at[u][r], bq));
+          }
+        }
+        table_step_fence<true>();
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int q = l; q < ht; q += G) {
+    const int key = keys[q];
+    if (key != -1) {
+      const int t = atomicAdd(s_n, 1);
+      if (t < ht / 2) {
+        lk[t] = key;
+        ls[t] = q;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  const int m = *s_n;
+  bool bad = m > ht / 2;
+#pragma unroll
+  for (int r = 0; r < R; ++r) bad |= m != crp[r0 + r + 1] - crp[r0 + r];
+  if (bad) {
+    if (l == 0) atomicOr(flag, FLAG_PATTERN);
+    return;
+  }
+  for (int t = l; t < m; t += G) {
+    const int key = lk[t];
+    int rank = 0;
+    for (int u = 0; u < m; ++u) rank += (lk[u] < key);
+    const int q = ls[t];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = crp[r0 + r] + rank;
+      cci[pos] = key;
+      cv[pos] = vals[r * ht + q];
+    }
+  }
+}
+
+// one 64-lane workgroup = 64 / G groups, each with its key table of HT slots and R value
+// tables
+template <int G, int HT, int R>
+__global__ void __launch_bounds__(64) k_num_grp(int ngrp, const int *__restrict__ rows,
+                                                const int *__restrict__ arp,
+                                                const int *__restrict__ aci,
+                                                const double *__restrict__ av,
+                                                const int *__restrict__ brp,
+                                                const int *__restrict__ bci,
+                                                const double *__restrict__ bv,
+                                                const int *__restrict__ crp,
+                                                int *__restrict__ cci, double *__restrict__ cv,
+                                                int *flag) {
+  constexpr int NR = 64 / G;
+  __shared__ int keys[NR][HT];
+  __shared__ double vals[NR][R * HT];
+  __shared__ int lk[NR][HT / 2], ls[NR][HT / 2];
+  __shared__ int s_n[NR];
+  const int g = threadIdx.x / G;
+  const int idx = blockIdx.x * NR + g;
+  if (idx >= ngrp) return;
+  num_group_g<G, R>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g],
+                    lk[g], ls[g], HT, &s_n[g], flag);
+}
+
+// C = A B by groups of R rows when every group of A shares one column pattern and every
+// output row fits a table of 512 slots; false (nothing written to C) otherwise
+bool spgemm_grouped(const Csr &A, const Csr &B, Csr &C, int R, hipStream_t s, int *dflag) {
+  const int64_t n = A.n, ng = n / R;
+  if (R < 2 || R > 3 || n % R != 0 || ng == 0 || ng > 0x7fffffffLL) return false;
+  DArr<int> f(1, s);
+  fill<int>(f.p, 0, 1, s);
+  if (R == 2) k_group_same<2><<<grid_for(ng * 16, 256), 256, 0, s>>>(ng, A.rp.p, A.ci.p, f.p);
+  else k_group_same<3><<<grid_for(ng * 16, 256), 256, 0, s>>>(ng, A.rp.p, A.ci.p, f.p);
+  KCHK();
+  if (read_flag(f.p, s) != 0) return false;
+  DArr<int> rows(ng, s), cnt(n + 1, s), retry(ng, s), mx(1, s);
+  DArr<int64_t> ub(n, s);
+  k_group_rows<<<grid_for(ng * 16, 256), 256, 0, s>>>(ng, R, A.rp.p, A.ci.p, B.rp.p, rows.p, ub.p);
+  KCHK();
+  fill<int>(f.p, 0, 1, s);
+  fill<int>(mx.p, 0, 1, s);
+  const double meanA = (double)A.nnz / (double)std::max<int64_t>(n, 1);
+  const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
+  const double prods = meanA * meanB;
+  if (prods > 256)
+    k_sym_lds<64, 512><<<(unsigned)ng, 64, 0, s>>>(ng, rows.p, ub.p, A.rp.p, A.ci.p, B.rp.p,
+                                                   B.ci.p, cnt.p, retry.p, f.p);
+  else if (prods > 64)
+    k_sym_lds<32, 512><<<(unsigned)((ng + 1) / 2), 64, 0, s>>>(ng, rows.p, ub.p, A.rp.p, A.ci.p,
+                                                               B.rp.p, B.ci.p, cnt.p, retry.p, f.p);
+  else
+    k_sym_lds<16, 512><<<(unsigned)((ng + 3) / 4), 64, 0, s>>>(ng, rows.p, ub.p, A.rp.p, A.ci.p,
+                                                               B.rp.p, B.ci.p, cnt.p, retry.p, f.p);
+  KCHK();
+  k_group_bcast<<<grid_for(ng, 256), 256, 0, s>>>(ng, R, cnt.p, mx.p);
+  KCHK();
+  int hb[2];
+  const D2HPart parts[2] = {{&hb[0], f.p, sizeof(int)}, {&hb[1], mx.p, sizeof(int)}};
+  d2h_sync_parts(parts, 2, s);
+  if (hb[0] != 0 || hb[1] > 256) return false;   // a row needs a larger table
+  C.nnz = exclusive_scan_i32(cnt.p, C.rp.p, n, s);
+  C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
+  C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
+  if (C.nnz == 0) return true;
+  const int ht = hb[1] <= 64 ? 128 : hb[1] <= 128 ? 256 : 512;
+  // lanes per group: 16 while the rows of B mostly fit one pass, else 32 or 64
+  const int G = meanB > 48 ? 64 : meanB > 12 ? 32 : 16;
+#define GRP(GG, HH, RR)                                                                        \
+  if (G == GG && ht == HH && R == RR) {                                                        \
+    k_num_grp<GG, HH, RR><<<(unsigned)((ng + 64 / GG - 1) / (64 / GG)), 64, 0, s>>>(           \
+        (int)ng, rows.p, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p,   \
+        dflag);                                                                                \
+    KCHK();                                                                                    \
+    return true;                                                                               \
+  }
+  GRP(16, 128, 2) GRP(16, 256, 2) GRP(32, 128, 2) GRP(32, 256, 2) GRP(64, 128, 2) GRP(64, 256, 2)
+  GRP(16, 128, 3) GRP(16, 256, 3) GRP(32, 128, 3) GRP(32, 256, 3) GRP(64, 128, 3) GRP(64, 256, 3)
+  GRP(32, 512, 2) GRP(64, 512, 2) GRP(64, 512, 3)
+#undef GRP
+  // no instance for this shape: the scalar path (C's row pointers are rebuilt there)
+  C.ci.reset();
+  C.v.reset();
+  return false;
+}
+}  // namespace
+
+void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag, int group) {
   require(A.m == B.n, MGR_ERR_ARG, "spgemm: inner dimensions differ");
   const int64_t n = A.n;
   C.n = n;
@@ -799,6 +1062,8 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag) {
   }
   const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
   const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
+  const bool tiny_or_dense = (B.m <= TINY_M || B.m <= DMAX) && meanA * meanB >= 64.0;
+  if (group > 1 && !tiny_or_dense && spgemm_grouped(A, B, C, group, s, dflag)) return;
   if (B.m <= TINY_M && meanA * meanB >= 64.0 && B.n * B.m <= ((int64_t)1 << 24)) {
     const int mm = (int)B.m;
     DArr<double> bd(std::max<int64_t>(B.n * mm, 1), s);
