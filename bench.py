@@ -12,7 +12,7 @@ case (1,348,163 unknowns) is also timed and reported under "two_phase_64".
     python bench.py [--steps K] [--warmup W] [--workload three|two] [--size 96]
                     [--precision fp32|fp64]
                     [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
-                    [--global-smoother block_jacobi|block_gs|ilu] [--global-sweeps 3]
+                    [--global-smoother block_jacobi|block_gs|ilu] [--global-sweeps 4]
                     [--ilu-level 1] [--ilu-sweeps 3] [--ilu-tri-sweeps 3]
 
 Prints one JSON line.  The dominant kernel's duration is measured live with HIP events
@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--ilu-level", type=int, default=1)
     ap.add_argument("--ilu-sweeps", type=int, default=3)
     ap.add_argument("--ilu-tri-sweeps", type=int, default=3)
-    ap.add_argument("--global-sweeps", type=int, default=3)
+    ap.add_argument("--global-sweeps", type=int, default=4)
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
     ap.add_argument("--sat-nmax", type=int, default=None,

@@ -359,7 +359,7 @@ class Options:
         return o
 
 
-def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 3,
+def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 4,
                sat_nmax: int | None = None, global_smoother: str = "block_jacobi",
                **kw) -> Options:
     """Reduction order of Sec. 5.3: displacement first (one nodal AMG V-cycle, N_max = 4),
@@ -367,7 +367,7 @@ def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 3,
     hold only cell unknowns), pressure last (AMG).  `quasi_impes` uses the quasi-IMPES
     coupling on the saturation levels; `global_smoother` is 'block_jacobi' or 'block_gs'
     (multicolour block Gauss-Seidel); `global_sweeps` sets the block smoother's sweeps
-    (three: the block-Jacobi sweeps stand in for the single, stronger ILU(1) step of
+    (four: the block-Jacobi sweeps stand in for the single, stronger ILU(1) step of
     Sec. 6); `sat_nmax` >= 0 applies the dropping operator on the saturation levels too.
     By default the two-phase saturation level is Galerkin (eq. coarse_grid_pressure); the
     three-phase model, which the paper does not treat, drops with the paper's N_max = 4 on
