@@ -150,6 +150,11 @@ def make_opts(m, a, model, precision):
         if L.global_smoother == "ilu":
             L.ilu_level, L.ilu_sweeps = a.ilu_level, a.ilu_sweeps
             L.ilu_tri_sweeps = a.ilu_tri_sweeps
+        if L.global_smoother != "none":
+            if a.global_omega is not None:
+                L.global_omega = float(a.global_omega)
+            if a.sat_frelax_sweeps is not None and L.frelax == "jacobi":
+                L.frelax_sweeps = int(a.sat_frelax_sweeps)
     return opts
 
 
@@ -253,6 +258,11 @@ def main():
     ap.add_argument("--ilu-sweeps", type=int, default=3)
     ap.add_argument("--ilu-tri-sweeps", type=int, default=3)
     ap.add_argument("--global-sweeps", type=int, default=4)
+    ap.add_argument("--global-omega", type=float, default=None,
+                    help="weight of the block-Jacobi sweeps after the first (default: the "
+                         "plan's, 0.9)")
+    ap.add_argument("--sat-frelax-sweeps", type=int, default=None,
+                    help="Jacobi F-relaxation sweeps on the saturation levels (default 1)")
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
     ap.add_argument("--sat-nmax", type=int, default=None,
@@ -374,7 +384,9 @@ def main():
             "outer_matrix": "BSR 3x3 FP64" if c.outer_block == 3 else "CSR FP64",
             "global_smoother": f"{a.global_smoother} x{a.global_sweeps}" + (
                 f" (ILU({a.ilu_level}), {a.ilu_sweeps} factor sweeps, {a.ilu_tri_sweeps} "
-                f"triangular sweeps)" if a.global_smoother == "ilu" else ""),
+                f"triangular sweeps)" if a.global_smoother == "ilu" else "") + (
+                f", omega {a.global_omega if a.global_omega is not None else 0.9}"
+                if a.global_smoother == "block_jacobi" else ""),
             "dropping": dropping_text(a),
             "rtol": 1e-6, "parallelism": "single GPU",
         },

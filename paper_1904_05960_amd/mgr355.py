@@ -361,22 +361,27 @@ class Options:
 
 def paper_plan(model: str, quasi_impes: bool = False, global_sweeps: int = 4,
                sat_nmax: int | None = None, global_smoother: str = "block_jacobi",
-               **kw) -> Options:
+               global_omega: float | None = None, **kw) -> Options:
     """Reduction order of Sec. 5.3: displacement first (one nodal AMG V-cycle, N_max = 4),
     then the saturations (Jacobi, Galerkin, with the global block smoother on the levels that
     hold only cell unknowns), pressure last (AMG).  `quasi_impes` uses the quasi-IMPES
     coupling on the saturation levels; `global_smoother` is 'block_jacobi' or 'block_gs'
     (multicolour block Gauss-Seidel); `global_sweeps` sets the block smoother's sweeps
     (four: the block-Jacobi sweeps stand in for the single, stronger ILU(1) step of
-    Sec. 6); `sat_nmax` >= 0 applies the dropping operator on the saturation levels too.
+    Sec. 6) and `global_omega` the weight of the sweeps after the first (0.9 for block
+    Jacobi, 1 otherwise); `sat_nmax` >= 0 applies the dropping operator on the saturation
+    levels too.
     By default the two-phase saturation level is Galerkin (eq. coarse_grid_pressure); the
     three-phase model, which the paper does not treat, drops with the paper's N_max = 4 on
     both saturation levels: two Galerkin eliminations in a row leave a pressure grid with
     distance-3 fill that makes the AMG setup several times slower and its V-cycle weaker."""
     if sat_nmax is None:
         sat_nmax = 4 if model == "three" else -1
+    if global_omega is None:
+        global_omega = 0.9 if global_smoother == "block_jacobi" else 1.0
     sat = dict(nmax=sat_nmax, frelax="jacobi", global_smoother=global_smoother,
-               global_sweeps=global_sweeps, coupling="quasi_impes" if quasi_impes else "full")
+               global_sweeps=global_sweeps, global_omega=global_omega,
+               coupling="quasi_impes" if quasi_impes else "full")
     if model == "biot1":
         levels = [Level((0,), nmax=4, frelax="amg", frelax_block=3)]
     elif model == "two":

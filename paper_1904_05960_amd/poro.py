@@ -219,7 +219,8 @@ def smoother_options(kind: str, precision="fp32", coupling="quasi_impes") -> M.O
     running simulation it needs about half the FGMRES iterations of the full coupling."""
     qi = coupling == "quasi_impes"
     if kind == "block_jacobi":
-        return M.paper_plan("two", precision=precision, quasi_impes=qi, global_sweeps=3)
+        return M.paper_plan("two", precision=precision, quasi_impes=qi, global_sweeps=3,
+                            global_omega=1.0)
     if kind == "block_gs":
         return M.paper_plan("two", precision=precision, global_smoother="block_gs",
                             quasi_impes=qi, global_sweeps=3)
