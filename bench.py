@@ -146,6 +146,10 @@ def make_opts(m, a, model, precision):
     if a.coarse_size is not None:
         opts.amg_frelax = m.AMG(coarse_size=a.coarse_size)
         opts.amg_coarse = m.AMG(coarse_size=a.coarse_size)
+    if a.theta_frelax is not None:
+        opts.amg_frelax.theta0 = float(a.theta_frelax)
+    if a.theta_coarse is not None:
+        opts.amg_coarse.theta0 = float(a.theta_coarse)
     for L in opts.levels:
         if L.global_smoother == "ilu":
             L.ilu_level, L.ilu_sweeps = a.ilu_level, a.ilu_sweeps
@@ -254,6 +258,10 @@ def main():
                     choices=["block_jacobi", "block_gs", "ilu"])
     ap.add_argument("--coarse-size", type=int, default=None,
                     help="AMG coarsest-grid size of both AMG hierarchies (default 256)")
+    ap.add_argument("--theta-frelax", type=float, default=None,
+                    help="strength threshold theta_0 of the displacement AMG (default 0.08)")
+    ap.add_argument("--theta-coarse", type=float, default=None,
+                    help="strength threshold theta_0 of the pressure AMG (default 0.08)")
     ap.add_argument("--ilu-level", type=int, default=1)
     ap.add_argument("--ilu-sweeps", type=int, default=3)
     ap.add_argument("--ilu-tri-sweeps", type=int, default=3)
