@@ -1062,7 +1062,9 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag, int g
   }
   const double meanB = (double)B.nnz / (double)std::max<int64_t>(B.n, 1);
   const double meanA = (double)A.nnz / (double)std::max<int64_t>(A.n, 1);
-  const bool tiny_or_dense = (B.m <= TINY_M || B.m <= DMAX) && meanA * meanB >= 64.0;
+  const bool tiny_or_dense = B.m <= DMAX && meanA * meanB >= 64.0 &&
+                             (B.m <= TINY_M || (double)B.m <= (B.m > 4096 ? 8.0 : 64.0) *
+                                                               meanA * meanB);
   if (group > 1 && !tiny_or_dense && spgemm_grouped(A, B, C, group, s, dflag)) return;
   if (B.m <= TINY_M && meanA * meanB >= 64.0 && B.n * B.m <= ((int64_t)1 << 24)) {
     const int mm = (int)B.m;
@@ -1090,7 +1092,11 @@ void spgemm(const Csr &A, const Csr &B, Csr &C, hipStream_t s, int *dflag, int g
     }
     return;
   }
-  if (B.m <= DMAX && meanA * meanB >= 64.0 && (double)B.m <= 64.0 * meanA * meanB) {
+  // dense accumulation pays when a row's products cover a good part of its columns; the
+  // widest tables (beyond 4096 columns, 72 KB of LDS: two workgroups per CU) only when the
+  // products are at least an eighth of the columns
+  const double dense_ratio = B.m > 4096 ? 8.0 : 64.0;
+  if (B.m <= DMAX && meanA * meanB >= 64.0 && (double)B.m <= dense_ratio * meanA * meanB) {
     // few output columns and many products per row: dense accumulation
     // tables sized to the column count: small ones leave room for several workgroups per CU
     DArr<int> cnt(n + 1, s);
