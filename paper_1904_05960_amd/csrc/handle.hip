@@ -1380,6 +1380,9 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   double host_buf[32];
   double *hb = noalloc ? host_buf : static_cast<double *>(pinned_scratch());
   const double bnorm = host_norm(b, n, W, hb, s);
+  // a zero initial guess makes the first residual b itself (b - A 0 = b exactly), so the
+  // first cycle starts without a product with A
+  bool x_zero = host_norm(x, n, W, hb, s) == 0.0;
   fgmres_result R{};
   if (res) { R.history = res->history; R.history_cap = res->history_cap; }
   auto push = [&](double v) {
@@ -1408,8 +1411,14 @@ mgr_status fgmres_impl(const mgr_csr *A, mgr_handle *M, const double *b, double 
   if (!noalloc)
     for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
   for (;;) {
-    matvec(x, b, W.r);  // r = b - A x
-    const double beta = host_norm(W.r, n, W, hb, s);
+    double beta = bnorm;
+    if (x_zero) {
+      HIPCHK(hipMemcpyAsync(W.r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      x_zero = false;
+    } else {
+      matvec(x, b, W.r);  // r = b - A x
+      beta = host_norm(W.r, n, W, hb, s);
+    }
     R.true_relres = beta / bnorm;
     push(beta / bnorm);
     if (beta <= tol) { R.converged = 1; break; }
