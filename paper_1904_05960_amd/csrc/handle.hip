@@ -1031,8 +1031,11 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     cast_values(dinvF.p, L->tdinvF, L->cf.nF, sz, s);
     // the level matrix itself is read by the V-cycle unless the F-relaxation is a solve that
     // starts from z = 0 (then the residual uses A_CF only)
-    const bool needs_A = lo.global_smoother != MGR_GSMOOTH_NONE || lo.frelax == MGR_FRELAX_JACOBI ||
-                         jac_r;
+    // the V-cycle reads A_l itself only in the ILU and block Gauss-Seidel smoothers: the
+    // block-Jacobi sweeps read its cell blocks, and every residual of the F-relaxation and
+    // the restriction reads the F rows and C rows gathered below (AF, AC) or A_CF
+    const bool needs_A = lo.global_smoother == MGR_GSMOOTH_ILU ||
+                         lo.global_smoother == MGR_GSMOOTH_BLOCK_GS;
     L->needs_A = needs_A;
     // rows F and rows C of A_l for the residuals of levels that are not compacted
     const bool need_sub = lo.frelax == MGR_FRELAX_JACOBI || lo.global_smoother != MGR_GSMOOTH_NONE ||
