@@ -35,6 +35,10 @@ struct CacheKey {
   }
 };
 std::mutex g_cache_mu;
+// Held while a V-cycle is captured into a graph.  A device-wide wait or a hipFree in one
+// thread while another thread captures invalidates that capture, so the paths that return
+// cached blocks to HIP take it first (always after g_cache_mu; a capture allocates nothing).
+std::mutex g_capture_mu;
 std::map<CacheKey, std::vector<void *>> g_cache;  // free blocks
 std::map<void *, size_t> g_live;                  // block -> bin size
 size_t g_cached_bytes = 0;
@@ -88,6 +92,7 @@ void *dalloc(size_t bytes, hipStream_t s) {
   g_miss_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    std::lock_guard<std::mutex> cg(g_capture_mu);
     (void)hipDeviceSynchronize();
     release_cache_locked();
     e = hipMalloc(&p, bin);
@@ -732,6 +737,7 @@ void apply_typed(mgr_handle *h, const double *v, double *z, hipStream_t s,
   if (h->opts.use_graph && !prof) {
     if (!h->gexec) {
       if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+      std::lock_guard<std::mutex> cg(g_capture_mu);
       HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
       try {
         apply_level<T>(h, 0, v0, z0, h->cap);
@@ -1712,6 +1718,7 @@ void mgr_set_allocator(void *(*alloc_fn)(size_t, void *, void *),
                        void (*free_fn)(void *, void *, void *), void *ctx) {
   {
     std::lock_guard<std::mutex> g(g_cache_mu);
+    std::lock_guard<std::mutex> cg(g_capture_mu);
     (void)hipDeviceSynchronize();
     release_cache_locked();
   }
@@ -1724,6 +1731,7 @@ const char *mgr_last_error(void) { return t_err.c_str(); }
 
 mgr_status mgr_release_cache(void) {
   std::lock_guard<std::mutex> g(g_cache_mu);
+  std::lock_guard<std::mutex> cg(g_capture_mu);
   (void)hipDeviceSynchronize();
   release_cache_locked();
   return MGR_OK;

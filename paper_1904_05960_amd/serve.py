@@ -259,7 +259,12 @@ def run_stream(server: Server, ens, order, rate: float, seed: int, newton: int,
 def summarize(recs, wall):
     lat = np.array([r["latency_ms"] for r in recs])
     ok = sum(1 for r in recs if r["status"] == 0)
-    return dict(requests=len(recs), ok=ok, solves_per_s=len(recs) / wall,
+    failed = {}
+    for r in recs:
+        if r["status"] != 0:
+            failed[str(r["status"])] = failed.get(str(r["status"]), 0) + 1
+    return dict(requests=len(recs), ok=ok, failed_by_status=failed,
+                solves_per_s=len(recs) / wall,
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                 mean_iters=float(np.mean([r["iters"] for r in recs])),
                 max_relres=float(max(r["true_relres"] for r in recs)),
