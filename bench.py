@@ -12,7 +12,7 @@ case (1,348,163 unknowns) is also timed and reported under "two_phase_64".
     python bench.py [--steps K] [--warmup W] [--workload three|two] [--size 96]
                     [--precision fp32|fp64]
                     [--plan paper|satfirst] [--drop-tol TAU] [--no-cpu-baseline]
-                    [--global-smoother block_jacobi|block_gs|ilu] [--global-sweeps 4]
+                    [--global-smoother block_jacobi|block_gs|ilu] [--global-sweeps 4] [--global-omega 0.9]
                     [--ilu-level 1] [--ilu-sweeps 3] [--ilu-tri-sweeps 3]
 
 Prints one JSON line.  The dominant kernel's duration is measured live with HIP events

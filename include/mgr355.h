@@ -428,6 +428,14 @@ typedef struct mgr_owned_csr mgr_owned_csr;
  * keeps entries that cancel.  Errors: ARG, UNSUPPORTED (a row beyond 2^21 entries). */
 mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int64_t sizes[3],
                       void *stream);
+/* The same product C = A B (pattern and values equal to mgr_spgemm's to the bit), computed
+ * `group` (2 or 3) consecutive rows of A at a time when every group's rows share one column
+ * pattern, as the C rows of a cell do in A_CF for the coarse-grid correction (Sec. 5.2):
+ * the group shares its symbolic count, the loads of B and the table of output columns.
+ * Groups whose patterns differ, or output rows beyond 256 entries, take the row-by-row
+ * path.  Errors: ARG (group not 1..3), as mgr_spgemm otherwise. */
+mgr_status mgr_spgemm_grouped(const mgr_csr *A, const mgr_csr *B, int32_t group,
+                              mgr_owned_csr **C, int64_t sizes[3], void *stream);
 /* C = A B for matrices made of full 3x3 blocks (nodal elasticity levels of the AMG that
  * relaxes the displacement block, Sec. 5.3), computed on the block patterns with the same
  * per-entry products, roundings and order as mgr_spgemm on the scalar matrices, so the

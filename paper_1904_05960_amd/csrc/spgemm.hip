@@ -1040,9 +1040,10 @@ bool spgemm_grouped(const Csr &A, const Csr &B, Csr &C, int R, hipStream_t s, in
   }
   GRP(16, 128, 2) GRP(16, 256, 2) GRP(32, 128, 2) GRP(32, 256, 2) GRP(64, 128, 2) GRP(64, 256, 2)
   GRP(16, 128, 3) GRP(16, 256, 3) GRP(32, 128, 3) GRP(32, 256, 3) GRP(64, 128, 3) GRP(64, 256, 3)
-  GRP(32, 512, 2) GRP(64, 512, 2) GRP(64, 512, 3)
+  GRP(16, 512, 2) GRP(32, 512, 2) GRP(64, 512, 2) GRP(32, 512, 3) GRP(64, 512, 3)
 #undef GRP
-  // no instance for this shape: the scalar path (C's row pointers are rebuilt there)
+  // no instance for this shape (16 lanes with three 512-slot value tables would need 64 KB
+  // of LDS): the scalar path (C's row pointers are rebuilt there)
   C.ci.reset();
   C.v.reset();
   return false;

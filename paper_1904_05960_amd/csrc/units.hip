@@ -50,6 +50,28 @@ mgr_status mgr_spgemm(const mgr_csr *A, const mgr_csr *B, mgr_owned_csr **C, int
   return MGR_OK;
 }
 
+mgr_status mgr_spgemm_grouped(const mgr_csr *A, const mgr_csr *B, int32_t group,
+                              mgr_owned_csr **C, int64_t sizes[3], void *stream) {
+  if (!A || !B || !C || !sizes || group < 1 || group > 3) return MGR_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    DArr<int> flag(1, s);
+    clear_flag(flag.p, s);
+    Csr a, b;
+    import_csr(A, a, s, flag.p);
+    import_csr(B, b, s, flag.p);
+    auto out = std::make_unique<mgr_owned_csr>();
+    out->s = s;
+    spgemm(a, b, out->M, s, flag.p, group);
+    check_flags(flag.p, s, "spgemm");
+    sizes_of(out->M, sizes);
+    *C = out.release();
+  } catch (const Error &e) {
+    return ufail(e);
+  }
+  return MGR_OK;
+}
+
 mgr_status mgr_spgemm_b3(const mgr_csr *A, const mgr_csr *B, int32_t diag_b, mgr_owned_csr **C,
                          int64_t sizes[3], void *stream) {
   if (!A || !B || !C || !sizes) return MGR_ERR_ARG;

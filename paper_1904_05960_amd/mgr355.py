@@ -180,6 +180,8 @@ def lib():
         "mgr_merge_drop": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), vp, C.c_int32, vp,
                                 C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_dense_inverse": (st, [vp, vp, C.c_int32, vp]),
+        "mgr_spgemm_grouped": (st, [C.POINTER(mgr_csr), C.POINTER(mgr_csr), C.c_int32,
+                                    C.POINTER(vp), C.POINTER(C.c_int64), vp]),
         "mgr_csr_to_bsr": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, vp, vp, vp,
                                 C.c_int64, C.POINTER(C.c_int64), vp]),
         "mgr_ilu": (st, [C.POINTER(mgr_csr), C.c_int32, C.c_int32, C.POINTER(vp),
@@ -582,6 +584,16 @@ def spgemm(A: Matrix, B: Matrix, stream=None):
     h = C.c_void_p()
     sz = (C.c_int64 * 3)()
     _check(lib().mgr_spgemm(C.byref(A.c), C.byref(B.c), C.byref(h), sz, _stream(stream)))
+    return _owned_to_host(h, sz, stream)
+
+
+def spgemm_grouped(A: Matrix, B: Matrix, group: int, stream=None):
+    """C = A B as spgemm, computed `group` rows of A at a time where the rows of a group share
+    their columns; returns host (indptr, indices, data, shape)."""
+    h = C.c_void_p()
+    sz = (C.c_int64 * 3)()
+    _check(lib().mgr_spgemm_grouped(C.byref(A.c), C.byref(B.c), int(group), C.byref(h), sz,
+                                    _stream(stream)))
     return _owned_to_host(h, sz, stream)
 
 

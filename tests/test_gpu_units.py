@@ -72,6 +72,52 @@ def test_spgemm_wide_row_pinned_order(ncols):
     assert_csr_equal(m.spgemm(dev(A), dev(B)), exp, f"pinned order, {ncols} columns")
 
 
+def grouped_csr(rng, ng, R, lens, ncols, differ=()):
+    """ng groups of R rows; the rows of a group share one sorted column set of lens[g]
+    entries (groups in `differ` get one other column in their last row), N(0,1) values."""
+    rows = []
+    for g in range(ng):
+        cols = np.sort(rng.choice(ncols, size=lens[g], replace=False))
+        for r in range(R):
+            c = cols
+            if g in differ and r == R - 1:
+                c = cols.copy()
+                c[0] = (c[0] + 1) % ncols if (c[0] + 1) % ncols not in cols else c[0]
+                c = np.sort(np.unique(np.append(c[1:], (cols[-1] + 7) % ncols)))
+            rows.append(c)
+    indptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([len(c) for c in rows], out=indptr[1:])
+    return CSR(indptr, np.concatenate(rows).astype(np.int64),
+               rng.standard_normal(indptr[-1]), (len(rows), ncols))
+
+
+@pytest.mark.parametrize("case", [
+    # (what, R, groups, entries per row of A, inner, B row lengths, columns of C)
+    ("R = 3, 16 lanes, outputs beyond 128 entries: no such table, row by row", 3, 300, 24,
+     4000, [8], 20000),
+    ("R = 3, 32 lanes, 512-slot tables", 3, 300, 16, 4000, [14], 20000),
+    ("R = 2, 16 lanes, 512-slot tables", 2, 200, 24, 3000, [8], 20000),
+    ("R = 3, 32 lanes, 256-slot tables", 3, 300, 8, 4000, [14], 20000),
+    ("R = 3, 16 lanes, 128-slot tables", 3, 300, 5, 4000, [10], 20000),
+    ("R = 2, 64 lanes, 512-slot tables", 2, 200, 4, 3000, [60], 20000),
+    ("R = 2, 32 lanes, rows of B beyond 32 entries", 2, 200, 6, 3000, [20, 20, 40], 20000),
+    ("R = 3, one group's rows differ: row by row", 3, 300, 12, 4000, [8], 20000),
+    ("R = 2, output rows beyond 256 entries: row by row", 2, 100, 30, 3000, [20], 40000),
+])
+def test_spgemm_grouped_equals_pinned_product(case):
+    """The grouped coarse-product path (the C rows of a cell share A_CF's columns): pattern
+    and values equal to the oracle's pinned-order product, bit for bit, and to mgr_spgemm."""
+    what, R, ng, la, k, blens, p = case
+    rng = np.random.default_rng(ng + la + k)
+    differ = (5,) if "differ" in what else ()
+    A = grouped_csr(rng, ng, R, [la] * ng, k, differ)
+    B = rows_csr(rng, [blens[i % len(blens)] for i in range(k)], p)
+    exp = spgemm(A, B)
+    got = m.spgemm_grouped(dev(A), dev(B), R)
+    assert_csr_equal(got, exp, f"grouped spgemm: {what}")
+    assert_csr_equal(m.spgemm(dev(A), dev(B)), exp, f"row-by-row spgemm: {what}")
+
+
 @pytest.mark.parametrize("case", [
     # (rows, inner, cols, density of A, density of B): which accumulation the product takes
     ("one lane per output column, 65..128 columns, rows of A beyond 64 entries", 150, 400,
