@@ -55,13 +55,22 @@ struct DArr {
   T *p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  bool own = true;   // false: a caller's array, read during one call and never freed here
   DArr() = default;
   DArr(size_t n_, hipStream_t s_) { alloc(n_, s_); }
   DArr(const DArr &) = delete;
   DArr &operator=(const DArr &) = delete;
-  DArr(DArr &&o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DArr(DArr &&o) noexcept : p(o.p), n(o.n), s(o.s), own(o.own) {
+    o.p = nullptr;
+    o.n = 0;
+    o.own = true;
+  }
   DArr &operator=(DArr &&o) noexcept {
-    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      reset();
+      p = o.p; n = o.n; s = o.s; own = o.own;
+      o.p = nullptr; o.n = 0; o.own = true;
+    }
     return *this;
   }
   ~DArr() { reset(); }
@@ -71,12 +80,20 @@ struct DArr {
     n = n_;
     p = n_ ? static_cast<T *>(dalloc(n_ * sizeof(T), s_)) : nullptr;
   }
+  void borrow(T *q, size_t n_, hipStream_t s_) {
+    reset();
+    p = q;
+    n = n_;
+    s = s_;
+    own = false;
+  }
   void reset() {
-    if (p) dfree(p, s);
+    if (p && own) dfree(p, s);
     p = nullptr;
     n = 0;
+    own = true;
   }
-  size_t bytes() const { return n * sizeof(T); }
+  size_t bytes() const { return own ? n * sizeof(T) : 0; }
   T *get() const { return p; }
 };
 
@@ -219,7 +236,9 @@ void extract_blocks(const Csr &A, const CfSplit &cf, Csr *Aff, Csr &Afc, Csr &Ac
 void scale_rows_div(Csr &M, const double *d, hipStream_t s);
 void check_nonzero(const double *d, int64_t n, int *dflag, hipStream_t s);
 void copy_csr(const Csr &A, Csr &B, hipStream_t s);
-void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag);
+// `borrow`: a scalar CSR's column and value arrays are used in place (the caller's arrays
+// must outlive B); otherwise copied
+void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag, bool borrow = false);
 uint64_t pattern_hash(const Csr &A, hipStream_t s);
 
 // AMG setup

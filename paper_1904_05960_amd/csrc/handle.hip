@@ -838,7 +838,13 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   const mgr_opts &o = h->opts;
   const size_t sz = esz(o);
   Csr cur;
-  import_csr(Ain, cur, s, flag);
+  // The caller's column and value arrays are read in place when nothing reads A after the
+  // setup (which ends with a synchronisation): level 0 keeps A only for the ILU and block
+  // Gauss-Seidel smoothers or with keep_setup, and without MGR levels the AMG owns it.
+  const bool borrow_A = o.nlevels > 0 && !o.keep_setup &&
+                        o.level[0].global_smoother != MGR_GSMOOTH_ILU &&
+                        o.level[0].global_smoother != MGR_GSMOOTH_BLOCK_GS;
+  import_csr(Ain, cur, s, flag, borrow_A);
   require(cur.n == cur.m, MGR_ERR_ARG, "A must be square");
   h->n = cur.n;
   h->pattern = pattern_hash(cur, s);
@@ -1563,8 +1569,10 @@ mgr_status mgr_setup(const mgr_csr *A, const int8_t *labels, const mgr_opts *opt
     HIPCHK(hipMemcpyAsync(h->labels0.p, labels, n, hipMemcpyDeviceToDevice, s));
     build(h.get(), A, labels);
   } catch (const Error &e) {
+    (void)hipStreamSynchronize(s);   // nothing in flight reads the caller's arrays
     return fail(e);
   } catch (const std::exception &e) {
+    (void)hipStreamSynchronize(s);
     t_err = e.what();
     return MGR_ERR_HIP;
   }
@@ -1581,8 +1589,8 @@ mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
             "matrix block size must be 0..3 and reserved 0");
     require(scalar_rows(*A) == h->n, MGR_ERR_PATTERN, "size differs from the original matrix");
     {
-      Csr tmp;
-      import_csr(A, tmp, s, h->dflag.p);
+      Csr tmp;   // read in place: the hash is read back before the arrays are let go
+      import_csr(A, tmp, s, h->dflag.p, A->block <= 1);
       require(pattern_hash(tmp, s) == h->pattern, MGR_ERR_PATTERN,
               "sparsity pattern differs from the original matrix");
     }
@@ -1602,8 +1610,10 @@ mgr_status mgr_setup_numeric(mgr_handle *h, const mgr_csr *A, void *stream) {
     HIPCHK(hipStreamSynchronize(s));
     h->valid = true;
   } catch (const Error &e) {
+    (void)hipStreamSynchronize(s);   // nothing in flight reads the caller's arrays
     return fail(e);
   } catch (const std::exception &e) {
+    (void)hipStreamSynchronize(s);
     t_err = e.what();
     return MGR_ERR_HIP;
   }

@@ -1098,7 +1098,7 @@ __global__ void k_bsr_expand(int64_t nbr, int bs, const int64_t *__restrict__ br
     }
 }
 
-void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
+void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag, bool borrow) {
   require(A->block >= 0 && A->block <= 3, MGR_ERR_ARG, "matrix block size must be 0..3");
   if (A->block > 1) {
     const int bs = A->block;
@@ -1131,12 +1131,17 @@ void import_csr(const mgr_csr *A, Csr &B, hipStream_t s, int *dflag) {
   B.m = A->ncols;
   B.nnz = nnz;
   B.rp.alloc(B.n + 1, s);
-  B.ci.alloc(nnz, s);
-  B.v.alloc(nnz, s);
   rowptr64_to_32(A->row_ptr, B.rp.p, B.n + 1, dflag, s);
-  if (nnz) {
-    HIPCHK(hipMemcpyAsync(B.ci.p, A->col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(B.v.p, A->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (borrow) {
+    B.ci.borrow(const_cast<int *>(A->col), nnz, s);
+    B.v.borrow(const_cast<double *>(A->val), nnz, s);
+  } else {
+    B.ci.alloc(nnz, s);
+    B.v.alloc(nnz, s);
+    if (nnz) {
+      HIPCHK(hipMemcpyAsync(B.ci.p, A->col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(B.v.p, A->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
   }
   check_flags(dflag, s, "matrix import");
 }
