@@ -167,7 +167,9 @@ void mgr_default_opts(mgr_opts *o);
  *   labels   n int8 labels in [0, 7] (unknown type of every row).
  *   opts     [host] options.
  *   out      [host] receives the new handle on success.
- * Synchronises `stream` (sizes of the coarse operators are data dependent).
+ * Synchronises `stream` (sizes of the coarse operators are data dependent), also when it
+ * fails.  A's arrays are read during the call only (the handle copies what it keeps), so
+ * the caller may free or overwrite them once mgr_setup returns.
  * Errors: ARG (labels outside [0,7], empty F or C set, bad options, A not square),
  * ZERO_PIVOT, UNSUPPORTED (a row of an intermediate product beyond 1 << 20 entries, a
  * dense solve beyond 4096 unknowns, a nodal level without full 3x3 blocks), ALLOC, HIP. */
