@@ -825,6 +825,32 @@ struct HelperStream {
   }
 };
 
+// The cell-block copies of the levels (the block-Jacobi sweeps' level matrices, A_CF of a
+// compacted level), read only by the apply.  A_CF's blocks are kept when at least 70 % of
+// their entries are entries of A_CF (FP32 blocks take 4 br bc + 4 bytes against 8 per CSR
+// entry).
+void convert_cell_blocks(const std::vector<MgrLevel *> &lv, size_t sz, hipStream_t s) {
+  for (MgrLevel *L : lv)
+    if (L->gsb_pending) {
+      const int nb = L->nb_gs;
+      csr_to_bsr_fill(L->A, nb, nb, L->gsb, s);
+      if (sz == 4) cast_values(L->gsb.v.p, L->tgsb, L->gsb.nblk * nb * nb, sz, s);
+      L->gsb_pending = false;
+    }
+  for (MgrLevel *L : lv)
+    if (L->cfb_pending) {
+      const int br = L->cfb.br, bc = L->cfb.bc;
+      csr_to_bsr_fill(L->Acf, br, bc, L->cfb, s);
+      const double slots = (double)L->cfb.nblk * br * bc;
+      if (slots > 0 && (double)L->Acf.nnz >= 0.7 * slots) {
+        if (sz == 4) cast_values(L->cfb.v.p, L->tcfb, L->cfb.nblk * br * bc, sz, s);
+      } else {
+        L->cfb = BsrB();
+      }
+      L->cfb_pending = false;
+    }
+}
+
 void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
   hipStream_t s = h->s;
   std::vector<hipEvent_t> events;
@@ -833,6 +859,7 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     ~EventGuard() { for (auto x : e) (void)hipEventDestroy(x); }
   } event_guard{events};
   HelperStream helper;       // the stream of the concurrent F-relaxation AMG setups
+  HelperStream conv;         // the stream of the cell-block copies (built with the coarse grid)
   Jobs jobs;                 // declared last: joined before the events and the stream go
   int *flag = h->dflag.p;
   const mgr_opts &o = h->opts;
@@ -1098,6 +1125,39 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     lab = std::move(labC);
     h->lv.push_back(std::move(L));
   }
+  // The cell-block copies are built by a thread of their own on a pooled stream while this
+  // thread sets up the coarse grid: the levels are complete, and the coarse-grid AMG (small
+  // kernels and read-backs) leaves most of the GPU free.
+  {
+    bool any = false;
+    for (auto &L : h->lv) any = any || L->gsb_pending || L->cfb_pending;
+    if (any) {
+      conv.acquire();
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      events.push_back(ev);
+      HIPCHK(hipEventRecord(ev, s));
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      std::vector<MgrLevel *> lvs;
+      for (auto &L : h->lv) lvs.push_back(L.get());
+      auto job = std::make_unique<AsyncAmg>();   // no hierarchy: `level` stays null
+      AsyncAmg *J = job.get();
+      hipStream_t s3 = conv.s;
+      job->th = std::thread([J, lvs, sz, dev, ev, s3]() {
+        try {
+          HIPCHK(hipSetDevice(dev));
+          t_trace_tag = "B";
+          HIPCHK(hipStreamWaitEvent(s3, ev, 0));
+          convert_cell_blocks(lvs, sz, s3);
+          HIPCHK(hipStreamSynchronize(s3));
+        } catch (...) {
+          J->err = std::current_exception();
+        }
+      });
+      jobs.v.push_back(std::move(job));
+    }
+  }
   // coarsest grid
   trace("mgr levels done");
   const int64_t nc = cur.n;
@@ -1117,31 +1177,10 @@ void build(mgr_handle *h, const mgr_csr *Ain, const int8_t *labels_in) {
     if (o.keep_setup) h->coarseA = std::move(keep);
   }
   h->coarse_labels = std::move(lab);
-  // the cell-block copies of the levels (nothing in the setup reads them)
-  for (auto &L : h->lv)
-    if (L->gsb_pending) {
-      const int nb = L->nb_gs;
-      csr_to_bsr_fill(L->A, nb, nb, L->gsb, s);
-      if (sz == 4) cast_values(L->gsb.v.p, L->tgsb, L->gsb.nblk * nb * nb, sz, s);
-      L->gsb_pending = false;
-    }
-  // A_CF in cell blocks: kept when at least 70 % of the stored block entries are entries
-  // of A_CF (FP32 blocks take 4 br bc + 4 bytes against 8 per CSR entry)
-  for (auto &L : h->lv)
-    if (L->cfb_pending) {
-      const int br = L->cfb.br, bc = L->cfb.bc;
-      csr_to_bsr_fill(L->Acf, br, bc, L->cfb, s);
-      const double slots = (double)L->cfb.nblk * br * bc;
-      if (slots > 0 && (double)L->Acf.nnz >= 0.7 * slots) {
-        if (sz == 4) cast_values(L->cfb.v.p, L->tcfb, L->cfb.nblk * br * bc, sz, s);
-      } else {
-        L->cfb = BsrB();
-      }
-      L->cfb_pending = false;
-    }
   jobs.join();
   jobs.rethrow();
-  for (auto &j : jobs.v) j->level->amg = std::move(j->amg);
+  for (auto &j : jobs.v)
+    if (j->level) j->level->amg = std::move(j->amg);
   trace("  F-relaxation AMG joined");
   h->v0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
   h->z0.alloc(std::max<int64_t>(h->n, 1) * sz, s);
