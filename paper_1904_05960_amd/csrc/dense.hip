@@ -309,18 +309,17 @@ __global__ void __launch_bounds__(GJ_THREADS) k_gauss_jordan_blocked(double *__r
     if (t == 0) atomicOr(flag, FLAG_ZERO_PIVOT);
     return;
   }
-  // undo the interchanges: columns k and piv[k], last step first
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k) {
-      for (int i = t; i < n; i += GJ_THREADS) {
+  // undo the interchanges: columns k and piv[k], last step first; a thread swaps within
+  // its own rows only, in that order, so the steps need no barrier
+  for (int i = t; i < n; i += GJ_THREADS)
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = piv[k];
+      if (p != k) {
         const double x = A[(int64_t)i * n + k];
         A[(int64_t)i * n + k] = A[(int64_t)i * n + p];
         A[(int64_t)i * n + p] = x;
       }
     }
-    __syncthreads();
-  }
 }
 
 }  // namespace
