@@ -380,7 +380,9 @@ mgr_status mgr_server_wait(mgr_server *s, uint64_t ticket, mgr_result *res);
 /* 1 if done, 0 if pending, -1 if unknown. */
 int32_t mgr_server_poll(mgr_server *s, uint64_t ticket);
 mgr_status mgr_server_stats(mgr_server *s, mgr_server_stats_t *out);
-/* Finish every queued request, stop the workers and free the cached setups. */
+/* Finish every queued request, stop the workers and free the cached setups; the memory
+ * they held, and every other block the library's allocator keeps cached, goes back to HIP
+ * (as mgr_release_cache). */
 void mgr_server_destroy(mgr_server *s);
 
 /* ---------------------------------------------------------------------------------- */

@@ -487,6 +487,10 @@ void mgr_server_destroy(mgr_server *S) {
   for (auto &t : S->workers) t.join();
   for (auto &kv : S->cache) mgr_destroy(kv.second.h);
   delete S;
+  // The blocks of the server's setups and workspaces went back to the allocator's cache
+  // under the streams of its slots, which no longer exist: no later allocation would find
+  // them, so they are returned to HIP.
+  (void)mgr_release_cache();
 }
 
 }  // extern "C"
