@@ -159,6 +159,8 @@ def make_opts(m, a, model, precision):
                 L.global_omega = float(a.global_omega)
             if a.sat_frelax_sweeps is not None and L.frelax == "jacobi":
                 L.frelax_sweeps = int(a.sat_frelax_sweeps)
+            if a.sat_frelax_omega is not None and L.frelax == "jacobi":
+                L.frelax_omega = float(a.sat_frelax_omega)
     return opts
 
 
@@ -271,6 +273,8 @@ def main():
                          "plan's, 0.9)")
     ap.add_argument("--sat-frelax-sweeps", type=int, default=None,
                     help="Jacobi F-relaxation sweeps on the saturation levels (default 1)")
+    ap.add_argument("--sat-frelax-omega", type=float, default=None,
+                    help="weight of that Jacobi F-relaxation (default 1)")
     ap.add_argument("--drop-tol", type=float, default=None,
                     help="tolerance form of G on the displacement level instead of N_max = 4")
     ap.add_argument("--sat-nmax", type=int, default=None,
