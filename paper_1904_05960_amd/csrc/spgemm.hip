@@ -64,7 +64,8 @@ __device__ __forceinline__ int table_insert(int *keys, unsigned mask, int key) {
 }
 
 // Returns the slot of `key`, inserting it if absent; mask + 1 (out of range) if the table is
-// full, which the sizing rules out (tables hold at least twice the row's distinct count).
+// full, which the sizing rules out (tables hold at least twice the row's distinct count,
+// the grouped coarse product's at least four thirds of it).
 __device__ __forceinline__ unsigned table_find_or_insert(int *keys, unsigned mask, int key) {
   unsigned slot = hslot(key, mask);
   for (unsigned probe = 0; probe <= mask; ++probe) {
@@ -932,7 +933,7 @@ __device__ __forceinline__ void num_group_g(int r0, const int *__restrict__ arp,
     const int key = keys[q];
     if (key != -1) {
       const int t = atomicAdd(s_n, 1);
-      if (t < ht / 2) {
+      if (t < (3 * ht) / 4) {
         lk[t] = key;
         ls[t] = q;
       }
@@ -941,7 +942,7 @@ __device__ __forceinline__ void num_group_g(int r0, const int *__restrict__ arp,
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
   const int m = *s_n;
-  bool bad = m > ht / 2;
+  bool bad = m > (3 * ht) / 4;
 #pragma unroll
   for (int r = 0; r < R; ++r) bad |= m != crp[r0 + r + 1] - crp[r0 + r];
   if (bad) {
@@ -978,7 +979,7 @@ __global__ void __launch_bounds__(64) k_num_grp(int ngrp, const int *__restrict_
   constexpr int NR = 64 / G;
   __shared__ int keys[NR][HT];
   __shared__ double vals[NR][R * HT];
-  __shared__ int lk[NR][HT / 2], ls[NR][HT / 2];
+  __shared__ int lk[NR][3 * HT / 4], ls[NR][3 * HT / 4];
   __shared__ int s_n[NR];
   const int g = threadIdx.x / G;
   const int idx = blockIdx.x * NR + g;
@@ -1027,7 +1028,9 @@ bool spgemm_grouped(const Csr &A, const Csr &B, Csr &C, int R, hipStream_t s, in
   C.ci.alloc(std::max<int64_t>(C.nnz, 1), s);
   C.v.alloc(std::max<int64_t>(C.nnz, 1), s);
   if (C.nnz == 0) return true;
-  const int ht = hb[1] <= 64 ? 128 : hb[1] <= 128 ? 256 : 512;
+  // tables filled up to three quarters: half the LDS of a half-full table, so twice the
+  // groups share a CU (the kernel waits on its loads; the longer probe runs cost less)
+  const int ht = hb[1] <= 96 ? 128 : hb[1] <= 192 ? 256 : 512;
   // lanes per group: 16 while the rows of B mostly fit one pass, else 32 or 64
   const int G = meanB > 48 ? 64 : meanB > 12 ? 32 : 16;
 #define GRP(GG, HH, RR)                                                                        \
