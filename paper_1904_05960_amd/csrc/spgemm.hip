@@ -361,10 +361,12 @@ __global__ void __launch_bounds__(64) k_num_global(int nrows, const int *__restr
   num_row_g<64, false>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, lv, ht, &s_n, flag);
 }
 
-// block-product row buckets: output blocks <= 32, <= 64, <= 128, <= 256, longer (global
-// tables), then <= 32 and <= 64 for rows whose steps carry many items (wide)
-constexpr int NBUCKET = 7;
-constexpr int B_GLOBAL = 4;
+// block-product row buckets by output blocks: <= 12, <= 24, <= 32 (16 lanes), <= 64 (32),
+// <= 128, <= 256 (64), longer (global tables); then the first four again for rows whose
+// steps carry many items (wide: 64 lanes, the same tables)
+constexpr int NBUCKET = 11;
+constexpr int B_GLOBAL = 6;
+constexpr int B_WIDE = 7;
 
 __global__ void k_max_len(int nrows, const int *__restrict__ rows, const int *__restrict__ crp,
                           int *__restrict__ out) {
@@ -1193,7 +1195,7 @@ __device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp,
                            const int *__restrict__ bci, const double *__restrict__ bv,
                            const int *__restrict__ crp, int *__restrict__ cci,
                            double *__restrict__ cv, int *keys, double *vals, int *lk, int *ls,
-                           int ht, int *s_n, int *flag) {
+                           int ht, int cap, int *s_n, int *flag) {
   const int l = threadIdx.x & (G - 1);
   const unsigned mask = (unsigned)ht - 1;
   for (int q = l; q < ht; q += G) keys[q] = -1;
@@ -1326,7 +1328,7 @@ __device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp,
     const int key = keys[q];
     if (key != -1) {
       const int t = atomicAdd(s_n, 1);
-      if (t < ht / 2) {
+      if (t < cap) {
         lk[t] = key;
         ls[t] = q;
       }
@@ -1336,7 +1338,7 @@ __device__ __forceinline__ void num_row_b3(int row, const int *__restrict__ arp,
   __builtin_amdgcn_wave_barrier();
   const int m = *s_n;
   const int base = crp[row];
-  if (m > ht / 2 || m != crp[row + 1] - base) {
+  if (m > cap || m != crp[row + 1] - base) {
     if (l == 0) atomicOr(flag, FLAG_PATTERN);
     return;
   }
@@ -1362,15 +1364,17 @@ __global__ void __launch_bounds__(64) k_num_b3(int nrows, const int *__restrict_
                                                const int *__restrict__ crp, int *__restrict__ cci,
                                                double *__restrict__ cv, int *flag) {
   constexpr int NR = 64 / G;
+  // tables filled up to three quarters (rows of at most 3 HT / 4 blocks)
+  constexpr int CAP = 3 * HT / 4;
   __shared__ int keys[NR][HT];
   __shared__ double vals[NR][9 * HT];
-  __shared__ int lk[NR][HT / 2], ls[NR][HT / 2];
+  __shared__ int lk[NR][CAP], ls[NR][CAP];
   __shared__ int s_n[NR];
   const int g = threadIdx.x / G;
   const int idx = blockIdx.x * NR + g;
   if (idx >= nrows) return;
   num_row_b3<G, DIAGB, true>(rows[idx], arp, aci, av, brp, bci, bv, crp, cci, cv, keys[g], vals[g],
-                       lk[g], ls[g], HT, &s_n[g], flag);
+                       lk[g], ls[g], HT, CAP, &s_n[g], flag);
 }
 
 template <bool DIAGB>
@@ -1388,7 +1392,7 @@ __global__ void __launch_bounds__(64) k_num_b3_global(
   int *ls = lk + ht / 2;
   double *vals = scratch_d + (int64_t)blockIdx.x * 9 * ht;
   num_row_b3<64, DIAGB, false>(row, arp, aci, av, brp, bci, bv, crp, cci, cv, keys, vals, lk, ls, ht,
-                        &s_n, flag);
+                        ht / 2, &s_n, flag);
 }
 
 // block rows by output block count: <= 32, <= 64, <= 128, <= 256, longer.  A row of the
@@ -1402,10 +1406,12 @@ __global__ void k_bucket_b3(int64_t n, const int *__restrict__ crp, const int *_
   int b = -1;
   if (i < n) {
     const int len = crp[i + 1] - crp[i];
-    if (len > 0) b = len <= 32 ? 0 : len <= 64 ? 1 : len <= 128 ? 2 : len <= 256 ? 3 : B_GLOBAL;
-    if (!diagb && b >= 0 && b <= 1) {
+    if (len > 0)
+      b = len <= 12 ? 0 : len <= 24 ? 1 : len <= 32 ? 2 : len <= 64 ? 3 : len <= 128 ? 4
+        : len <= 256 ? 5 : B_GLOBAL;
+    if (!diagb && b >= 0 && b <= 3) {
       const int64_t items = 3 * ub[i], steps = arp[i + 1] - arp[i];
-      if (items > (b == 0 ? 32 : 64) * steps) b += 5;
+      if (items > (b <= 2 ? 32 : 64) * steps) b += B_WIDE;
     }
   }
   for (int k = 0; k < NBUCKET; ++k) {
@@ -1447,9 +1453,10 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
     return;
   }
   DArr<int64_t> ub;
-  // rows by output block count; LDS tables of twice that (<= 21 KB per 64-lane workgroup,
-  // so that several workgroups share a CU), rows beyond 256 blocks in global memory (read
-  // back with the symbolic totals)
+  // rows by output block count; LDS tables of twice it, or of four thirds of it for rows of
+  // up to 24 blocks (the short rows of A T take 16-slot tables, 5 KB per 64-lane workgroup,
+  // so that three times as many workgroups share a CU as with 64 slots), rows beyond 256
+  // blocks in global memory (read back with the symbolic totals)
   DArr<int> lists((size_t)NBUCKET * n, s), counts(NBUCKET, s);
   int hc[NBUCKET] = {};
   SymBucket bk;
@@ -1467,12 +1474,18 @@ void spgemm_b3(const Bsr3 &A, const Bsr3 &B, bool diagb, Bsr3 &C, hipStream_t s,
   C.ci.alloc(std::max<int64_t>(C.nnzb, 1), s);
   C.v.alloc(std::max<int64_t>(9 * C.nnzb, 1), s);
   if (C.nnzb == 0) return;
-  if (hc[0] > 0) launch_num_b3<16, 64>(diagb, hc[0], lists.p, A, B, C, dflag, s);
-  if (hc[1] > 0) launch_num_b3<32, 128>(diagb, hc[1], lists.p + (size_t)n, A, B, C, dflag, s);
-  if (hc[2] > 0) launch_num_b3<64, 256>(diagb, hc[2], lists.p + (size_t)2 * n, A, B, C, dflag, s);
-  if (hc[3] > 0) launch_num_b3<64, 512>(diagb, hc[3], lists.p + (size_t)3 * n, A, B, C, dflag, s);
-  if (hc[5] > 0) launch_num_b3<64, 64>(diagb, hc[5], lists.p + (size_t)5 * n, A, B, C, dflag, s);
-  if (hc[6] > 0) launch_num_b3<64, 128>(diagb, hc[6], lists.p + (size_t)6 * n, A, B, C, dflag, s);
+  const int *lp = lists.p;
+  const size_t N = (size_t)n;
+  if (hc[0] > 0) launch_num_b3<16, 16>(diagb, hc[0], lp, A, B, C, dflag, s);
+  if (hc[1] > 0) launch_num_b3<16, 32>(diagb, hc[1], lp + N, A, B, C, dflag, s);
+  if (hc[2] > 0) launch_num_b3<16, 64>(diagb, hc[2], lp + 2 * N, A, B, C, dflag, s);
+  if (hc[3] > 0) launch_num_b3<32, 128>(diagb, hc[3], lp + 3 * N, A, B, C, dflag, s);
+  if (hc[4] > 0) launch_num_b3<64, 256>(diagb, hc[4], lp + 4 * N, A, B, C, dflag, s);
+  if (hc[5] > 0) launch_num_b3<64, 512>(diagb, hc[5], lp + 5 * N, A, B, C, dflag, s);
+  if (hc[B_WIDE] > 0) launch_num_b3<64, 16>(diagb, hc[B_WIDE], lp + 7 * N, A, B, C, dflag, s);
+  if (hc[B_WIDE + 1] > 0) launch_num_b3<64, 32>(diagb, hc[B_WIDE + 1], lp + 8 * N, A, B, C, dflag, s);
+  if (hc[B_WIDE + 2] > 0) launch_num_b3<64, 64>(diagb, hc[B_WIDE + 2], lp + 9 * N, A, B, C, dflag, s);
+  if (hc[B_WIDE + 3] > 0) launch_num_b3<64, 128>(diagb, hc[B_WIDE + 3], lp + 10 * N, A, B, C, dflag, s);
   if (hc[B_GLOBAL] > 0) {
     const int nbig = hc[B_GLOBAL];
     const int *big = lists.p + (size_t)B_GLOBAL * n;

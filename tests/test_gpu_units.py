@@ -173,10 +173,16 @@ def block_csr(rng, lens, nbc, diag_only=False):
 
 @pytest.mark.parametrize("case", [
     # (block rows of A, blocks per row of A, inner block dim, blocks per row of B, block cols)
-    ("short rows", 40, (1, 12), 30, (0, 6), 25),
+    ("short rows (tables of 16 and 32 slots)", 40, (1, 12), 30, (0, 6), 25),
+    ("outputs of at most 12 blocks, mostly all 12 (16-slot tables three quarters full)", 40,
+     (4, 8), 30, (3, 6), 12),
+    ("outputs of at most 24 blocks, mostly all 24 (32-slot tables three quarters full)", 30,
+     (6, 12), 40, (4, 8), 24),
     ("output rows of 33..256 blocks (larger LDS tables)", 24, (8, 40), 400, (4, 9), 3000),
     ("output rows beyond 256 blocks (global tables)", 6, (40, 60), 800, (8, 12), 6000),
     ("many items per step, outputs <= 32 blocks (wide groups)", 30, (5, 20), 50, (12, 20), 30),
+    ("many items per step, outputs <= 12 blocks (wide groups)", 30, (2, 8), 50, (11, 12), 12),
+    ("many items per step, outputs 13..24 blocks (wide groups)", 30, (2, 8), 50, (14, 20), 24),
     ("many items per step, outputs 33..64 blocks (wide groups)", 30, (5, 20), 50, (22, 40), 60),
 ])
 @pytest.mark.parametrize("diag_b", [False, True])
