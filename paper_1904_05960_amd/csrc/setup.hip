@@ -371,7 +371,9 @@ __device__ void merge_row_serial(int64_t row, const int *__restrict__ arp,
   if (!MODE) cnt[row] = c;
 }
 
-// The same merge by G lanes per row with both rows staged in LDS (up to 8 G entries each).
+// The same merge by G lanes per row with both rows staged in LDS (up to 128 entries each:
+// 25 KB per 256-thread workgroup for 16 lanes per row, 12.5 KB for 32, so that a CU holds
+// its full 32 wavefronts of the 32-lane form).
 // An entry's output position is its rank in the union: an entry of A is preceded by the
 // entries of A before it and by the entries of B that are kept, not in A and of smaller
 // column; a kept entry of B that is not in A, by the entries of A of smaller column and
@@ -390,7 +392,7 @@ __global__ void __launch_bounds__(256) k_merge_rows(int64_t n, const int *__rest
                                                     const int *__restrict__ srp,
                                                     int *__restrict__ sci,
                                                     double *__restrict__ sv) {
-  constexpr int RPB = 256 / G, MCAP = 8 * G;
+  constexpr int RPB = 256 / G, MCAP = 128;
   __shared__ int s_a[RPB][MCAP], s_b[RPB][MCAP], s_ob[RPB][MCAP + 1];
   const int g = threadIdx.x / G, l = threadIdx.x & (G - 1);
   const int64_t row = blockIdx.x * (int64_t)RPB + g;

@@ -244,8 +244,9 @@ def test_merge_drop_random(nmax):
     ("16 lanes per row, two rows beyond 128 entries", 300,
      lambda i: 200 if i in (7, 100) else 3 + i % 4,
      lambda i: 150 if i in (7, 100) else 2 + i % 6),
-    ("32 lanes per row, a row beyond 256 entries", 500,
-     lambda i: 300 if i == 3 else 40, lambda i: 400 if i == 3 else 40),
+    ("32 lanes per row, rows beyond 128 entries", 500,
+     lambda i: 300 if i == 3 else (200 if i == 10 else 40),
+     lambda i: 400 if i == 3 else (150 if i == 10 else 40)),
 ])
 @pytest.mark.parametrize("nmax", [-1, 4])
 @pytest.mark.parametrize("scaled", [False, True])
