@@ -1381,9 +1381,10 @@ constexpr int kBsrWin = 512;   // blocks per stream window of the cell-block ker
 // The count pass writes the number of representatives; the fill pass scatters every value
 // into its block (the blocks are zeroed beforehand) and the representatives write the
 // block columns.  No lane works serially over a cell.  Cells beyond BCAP entries are
-// merged from global memory by one lane.
+// merged from global memory by one lane (256 staged entries: 17 KB per workgroup, so that a
+// CU holds 32 wavefronts; the cells of 7-point flow levels and of A_CF hold at most 72).
 constexpr int BG_LANES = 16;
-constexpr int BCAP = 512;
+constexpr int BCAP = 256;
 
 // first position in s[lo, hi) whose value is >= key
 __device__ inline int lds_lower_bound(const int *s, int lo, int hi, int key) {

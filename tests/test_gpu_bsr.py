@@ -195,13 +195,13 @@ def bsr_by_definition(indptr, cols, vals, br, bc=None):
 def test_csr_to_bsr_matches_definition(br, bc):
     """The cell-block storage of the block-Jacobi sweeps and of A_CF, bit for bit: block
     columns, row pointers and every value (absent entries zero, explicit zeros kept), on
-    cells of 0 .. 13 blocks, full cells of 40, 60, 90 and 170 blocks (below and beyond the
-    512 entries staged in LDS; beyond are merged from global memory) and ragged, empty and
+    cells of 0 .. 13 blocks, full cells of 25, 40, 60, 90 and 170 blocks (below and beyond the
+    256 entries staged in LDS; beyond are merged from global memory) and ragged, empty and
     one-row cells; (2, 3) on a rectangular matrix."""
     rng = np.random.default_rng(40 + 10 * br + bc)
     ncell = 700
     ngroup = 700 if br == bc else 560
-    ip, ci, v, m_cols = cell_matrix(rng, ncell, br, {5: 90, 6: 170, 300: 40, 699: 60}, bc, ngroup)
+    ip, ci, v, m_cols = cell_matrix(rng, ncell, br, {5: 90, 6: 170, 7: 25, 300: 40, 699: 60}, bc, ngroup)
     A = m.Matrix.from_host(ip, ci, v, ncols=m_cols)
     brp, bci, bv = m.csr_to_bsr(A, br, bc)
     erp, eci, ev = bsr_by_definition(ip, ci, v, br, bc)
