@@ -1033,8 +1033,9 @@ bool spgemm_grouped(const Csr &A, const Csr &B, Csr &C, int R, hipStream_t s, in
   // tables filled up to three quarters: half the LDS of a half-full table, so twice the
   // groups share a CU (the kernel waits on its loads; the longer probe runs cost less)
   const int ht = hb[1] <= 96 ? 128 : hb[1] <= 192 ? 256 : 512;
-  // lanes per group: 16 while the rows of B mostly fit one pass, else 32 or 64
-  const int G = meanB > 48 ? 64 : meanB > 12 ? 32 : 16;
+  // lanes per group: 16 while the rows of B average at most 16 entries (longer rows take a
+  // second pass), else 32 or 64
+  const int G = meanB > 48 ? 64 : meanB > 16 ? 32 : 16;
 #define GRP(GG, HH, RR)                                                                        \
   if (G == GG && ht == HH && R == RR) {                                                        \
     k_num_grp<GG, HH, RR><<<(unsigned)((ng + 64 / GG - 1) / (64 / GG)), 64, 0, s>>>(           \

@@ -95,11 +95,12 @@ def grouped_csr(rng, ng, R, lens, ncols, differ=()):
     # (what, R, groups, entries per row of A, inner, B row lengths, columns of C)
     ("R = 3, 16 lanes, outputs beyond 192 entries: no such table, row by row", 3, 300, 26,
      4000, [8], 20000),
-    ("R = 3, 32 lanes, 512-slot tables", 3, 300, 16, 4000, [14], 20000),
+    ("R = 3, 32 lanes, 512-slot tables", 3, 300, 12, 4000, [18], 20000),
     ("R = 2, 16 lanes, 512-slot tables", 2, 200, 26, 3000, [8], 20000),
-    ("R = 3, 32 lanes, 256-slot tables", 3, 300, 8, 4000, [14], 20000),
+    ("R = 3, 32 lanes, 256-slot tables", 3, 300, 6, 4000, [18], 20000),
     ("R = 3, 16 lanes, 128-slot tables", 3, 300, 5, 4000, [10], 20000),
-    ("R = 3, 32 lanes, 128-slot tables filled to three quarters", 3, 300, 6, 4000, [16], 20000),
+    ("R = 3, 32 lanes, 128-slot tables filled to three quarters", 3, 300, 4, 4000, [24], 20000),
+    ("R = 3, 16 lanes, rows of B beyond 16 entries", 3, 300, 5, 4000, [8, 24], 20000),
     ("R = 2, 64 lanes, 512-slot tables", 2, 200, 4, 3000, [60], 20000),
     ("R = 2, 32 lanes, rows of B beyond 32 entries", 2, 200, 6, 3000, [20, 20, 40], 20000),
     ("R = 3, one group's rows differ: row by row", 3, 300, 12, 4000, [8], 20000),
